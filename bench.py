@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput of the generalized-Poisson PCG solver on one MI355X.
+
+Workload (default): molecule-like solute in a density-dependent (sccs)
+cavity, free boundaries, 96^3 grid, h = 0.3 bohr, 24 Gaussian charges
+(sigma in U[0.6, 1.2], q in U[-1, 1] shifted to net 0, centres in a 6-bohr
+ball, seed 2), mixed precision (FP32 FFT passes and vectors, FP64 inner
+products and solution), stop at ||r||/||r_0|| <= 1e-6.
+
+One step = one complete solve on inputs already resident in HBM: the
+per-request fields (sqrt(eps), q), the PCG iterations to the stop decision
+and the energy.  The plan (Green's spectrum, buffers) is built once before
+the timed region.
+
+Prints ONE JSON line: solves/s as `value`, plus Mgridpts*iter/s, p50/p99
+latency, the FP64 one-at-a-time comparator, the roofline of the dominant
+pass (timed live with HIP events on the solve stream) and the oracle timed
+on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv", "direction", "update")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=96)
+    ap.add_argument("--h", type=float, default=0.3)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
+    ap.add_argument("--fp64-steps", type=int, default=5,
+                    help="solves of the FP64 one-at-a-time comparator (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pass-times", action="store_true",
+                    help="also time every pass separately (extra solves)")
+    return ap.parse_args()
+
+
+def timed_solves(torch, plan, rho, eps, phi, tol, steps):
+    lat = []
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        st = plan.solve_generalized(rho, eps, phi, tol)
+        lat.append(time.perf_counter() - s0)
+        if st != 0:
+            raise RuntimeError("solve failed with status %d" % st)
+        iters.append(plan.info()["iterations"])
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat, iters
+
+
+def cpu_baseline(prob, tol):
+    """The oracle as it stands, one full solve of the same workload."""
+    from oracle import green, pcg
+    workers = min(16, os.cpu_count() or 1)
+    solver = green.VacuumSolver(prob.shape, prob.h, prob.bc, workers=workers)
+    t0 = time.perf_counter()
+    res = pcg.pcg_solve(prob.rho, prob.eps, prob.h, prob.bc, tol=tol, solver=solver)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": "one full FP64 solve of the same workload (%d iterations, %.1f s, "
+                      "scipy.fft workers=%d)" % (res.iterations, dt, workers),
+            "mgridpts_iter_per_s": prob.npoints * res.iterations / dt / 1e6}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported "
+              "(requests shard one plan per GPU, see DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    from paper_1509_00680_amd import gps, workloads as W
+
+    prob = W.molecule(args.n, args.h, seed=args.seed)
+    rho = torch.from_numpy(prob.rho).cuda()
+    eps = torch.from_numpy(prob.eps).cuda()
+    phi = torch.empty_like(rho)
+    plan = gps.Plan(prob.shape, prob.h, prob.bc, precision=args.precision)
+
+    for _ in range(args.warmup):
+        plan.solve_generalized(rho, eps, phi, args.tol)
+    # timed region; the dominant pass is bracketed by HIP events on the solve stream
+    plan.set_timing("zconv")
+    wall, lat, iters = timed_solves(torch, plan, rho, eps, phi, args.tol, args.steps)
+    tz = plan.timing()
+    plan.set_timing(None)
+
+    info = plan.info()
+    mean_iters = float(np.mean(iters))
+    solves_per_s = args.steps / wall
+    lat_ms = np.array(lat) * 1e3
+
+    avg_ms = tz["total_ms"] / max(1, tz["launches"])
+    achieved = tz["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+
+    pass_ms = {}
+    if args.pass_times:
+        for k in PASSES:
+            plan.set_timing(k)
+            timed_solves(torch, plan, rho, eps, phi, args.tol, 2)
+            t = plan.timing()
+            pass_ms[k] = {"avg_us": 1e3 * t["total_ms"] / max(1, t["launches"]),
+                          "gbs": t["bytes_per_launch"] / (t["total_ms"] / max(1, t["launches"])
+                                                          * 1e-3) / 1e9
+                          if t["total_ms"] > 0 else 0.0}
+        plan.set_timing(None)
+
+    fp64 = None
+    if args.fp64_steps > 0:
+        p64 = gps.Plan(prob.shape, prob.h, prob.bc, precision="fp64")
+        p64.solve_generalized(rho, eps, phi, args.tol)
+        w64, l64, it64 = timed_solves(torch, p64, rho, eps, phi, args.tol, args.fp64_steps)
+        fp64 = {"solves_per_s": args.fp64_steps / w64,
+                "p99_ms": float(np.percentile(np.array(l64) * 1e3, 99)),
+                "iters_per_solve": float(np.mean(it64))}
+        p64.close()
+
+    out = {
+        "metric": "PCG solves/s and Mgridpts·iter/s at 1e-6 rel. residual; p50/p99 latency",
+        "value": solves_per_s,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "molecule%d_sccs_free" % args.n, "grid": list(prob.shape),
+                   "h": prob.h, "bc": prob.bc, "n_charges": 24, "seed": args.seed,
+                   "tol": args.tol, "precision": args.precision
+                   + (" (fp32 bulk, fp64 dots/solution)" if args.precision == "mixed" else "")},
+        "mgridpts_iter_per_s": prob.npoints * sum(iters) / wall / 1e6,
+        "iters_per_solve": mean_iters,
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "energy": info["energy"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "z pass (forward FFT, Green's spectrum, inverse FFT)",
+                     "avg_us": avg_ms * 1e3, "bytes_per_launch": tz["bytes_per_launch"],
+                     "launches": tz["launches"]},
+        "fp64_one_at_a_time": fp64,
+    }
+    if pass_ms:
+        out["passes"] = pass_ms
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.tol)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

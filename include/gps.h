@@ -1,0 +1,200 @@
+/*
+ * gps.h -- generalized Poisson / Poisson-Boltzmann solver for AMD MI355X (gfx950).
+ *
+ * Method: Fisicaro, Genovese, Andreussi, Marzari, Goedecker, "A generalized
+ * Poisson and Poisson-Boltzmann solver for electrostatic environments",
+ * J. Chem. Phys. 144, 014103 (2016), arXiv:1509.00680.
+ *
+ *   gps_solve_generalized  Eq. GPe  div(eps grad phi) = -4 pi rho, solved by
+ *                          Algorithm PCG (Sec. II.B) with the preconditioner
+ *                          of Eq. PCGdef (the vacuum Poisson solver scaled by
+ *                          sqrt(eps)) and the operator identity of Eq. corr.
+ *   gps_solve_pb           Eq. PBe with the ionic charge of Eqs. rhoions,
+ *                          ionsconcPB / ionsconcMPB / maxconc (Sec. III):
+ *                          linear regime through Eq. corrPB inside PCG,
+ *                          nonlinear regime through Algorithm SCPBimproved.
+ *
+ * Units: Hartree atomic units (bohr, Ha, e).  phi in Ha/e, rho in e/bohr^3.
+ *
+ * Grid and layout: every field is a C array double[nz][ny][nx] (x fastest)
+ * on an orthorhombic cell-centred grid of spacing h; point (i, j, k) is at
+ * ((i - (nx-1)/2) h, (j - (ny-1)/2) h, (k - (nz-1)/2) h).
+ *
+ * Memory: every field pointer passed to a solve is a DEVICE pointer (HIP
+ * global memory of the device current at gps_plan_create) holding
+ * nx*ny*nz doubles.  The caller owns rho, eps, gamma and phi; the plan owns
+ * every internal buffer and frees it in gps_plan_destroy.  Solves are
+ * enqueued on the plan's stream (gps_options.stream, default: the null
+ * stream) and return after the stream has finished them.
+ *
+ * Threading: a plan is not thread-safe; distinct plans are independent.
+ *
+ * Errors: functions return a gps_status; nothing throws across this ABI.
+ * On GPS_E_NOT_CONVERGED / GPS_E_BREAKDOWN phi holds the last iterate and
+ * gps_last_info describes the solve.
+ */
+#ifndef GPS_H
+#define GPS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Boundary conditions of the vacuum Poisson solver (Sec. II.C):
+ *   FREE      isolated system, zero-padded (Hockney) convolution with the
+ *             cell-averaged 1/|r| kernel;
+ *   SURFACE   periodic along x and y, isolated along z;
+ *   PERIODIC  periodic along x, y and z (rho must be neutral for Poisson). */
+typedef enum { GPS_BC_FREE = 0, GPS_BC_SURFACE = 1, GPS_BC_PERIODIC = 2 } gps_bc;
+
+/* Arithmetic of the bulk work (FFT passes and PCG vectors).  Inner products,
+ * the solution accumulator, the Green's-function tables and the stencil are
+ * FP64 in both modes. */
+typedef enum { GPS_PREC_FP64 = 0, GPS_PREC_MIXED = 1 } gps_precision;
+
+typedef enum {
+  GPS_OK = 0,
+  GPS_E_INVALID = 1,        /* bad argument, eps <= 0, non-neutral periodic rho */
+  GPS_E_NOMEM = 2,          /* device allocation failed */
+  GPS_E_NOT_CONVERGED = 3,  /* maxit (or outer_maxit) reached */
+  GPS_E_BREAKDOWN = 4,      /* (v, r) <= 0 or (p, Ap) >= 0 in PCG */
+  GPS_E_NONFINITE = 5,      /* NaN/Inf in the inputs or during the iteration */
+  GPS_E_DEVICE = 6,         /* HIP runtime error */
+  GPS_E_UNSUPPORTED = 7     /* FFT length with a prime factor other than 2,3,5,7 or > 1024 */
+} gps_status;
+
+typedef struct gps_plan gps_plan;
+
+typedef struct {
+  int precision;     /* gps_precision, default GPS_PREC_FP64 */
+  int fd_order;      /* even order of the central differences of q (2..16), default 16 */
+  int maxit;         /* PCG iteration cap, default 1000 */
+  int check_every;   /* iterations enqueued between host convergence polls, default 8 */
+  void *stream;      /* hipStream_t the solves run on; NULL = null stream */
+} gps_options;
+
+/* Electrolyte of Sec. III (Eqs. rhoions, ionsconcPB, ionsconcMPB, maxconc).
+ * Z, c_bulk (bohr^-3) and c_max (bohr^-3) are HOST arrays of nspecies
+ * (1..4) entries; c_max NULL selects the Boltzmann law, otherwise the steric
+ * law with the bracket read as (exp(-Z_j phi/kT) - 1).  gamma is a DEVICE
+ * field in [0, 1] (ion accessibility); NULL selects (eps - 1)/(eps_bulk - 1).
+ * linear != 0 solves the linear regime (Eq. corrPB: kappa2 =
+ * (4 pi/kT) sum_i Z_i^2 c_i gamma inside PCG); otherwise Algorithm
+ * SCPBimproved with mixing eta and at most outer_maxit outer steps. */
+typedef struct {
+  int nspecies;
+  const double *Z;
+  const double *c_bulk;
+  const double *c_max;
+  double kT;           /* Ha */
+  const double *gamma;
+  double eps_bulk;
+  int linear;
+  double eta;
+  int outer_maxit;
+} gps_ions;
+
+typedef struct {
+  int status;            /* gps_status of the last solve */
+  int iterations;        /* PCG iterations (sum over outer steps for nonlinear PB) */
+  int outer_iterations;  /* nonlinear PB outer steps, 0 otherwise */
+  int history_len;       /* entries available through gps_last_history */
+  double rnorm0;         /* ||r_0||_2 = ||4 pi rho||_2 */
+  double rel_residual;   /* final ||r||_2 / ||r_0||_2 of the (last) PCG solve */
+  double energy;         /* (1/2) h^3 sum rho phi */
+  double outer_residual; /* ||rho^ions_k - rho^ions_{k-1}||_2 / ||rho||_2 (nonlinear PB) */
+} gps_info;
+
+/* Create a plan for an nx x ny x nz grid of spacing h (bohr) and boundary
+ * condition bc.  Computes the Green's-function spectrum on the device (FP64)
+ * and allocates the work buffers.  Errors: GPS_E_INVALID (n < 2, h <= 0 or
+ * not finite, unknown bc, out == NULL), GPS_E_UNSUPPORTED (an FFT length
+ * -- 2n on free axes, n on periodic axes -- with a prime factor > 7 or
+ * longer than 1024), GPS_E_NOMEM, GPS_E_DEVICE.  *out is NULL on error. */
+gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan **out);
+
+/* Replace the plan's options (NULL fields keep defaults: see gps_options).
+ * Errors: GPS_E_INVALID for an odd or out-of-range fd_order, maxit < 1,
+ * check_every < 1, unknown precision. */
+gps_status gps_plan_set_options(gps_plan *plan, const gps_options *opt);
+gps_status gps_plan_get_options(const gps_plan *plan, gps_options *opt);
+
+/* Device bytes held by the plan (tables + work buffers of both precisions
+ * allocated so far). */
+size_t gps_plan_device_bytes(const gps_plan *plan);
+
+void gps_plan_destroy(gps_plan *plan);
+
+/* Solve div(eps grad phi) = -4 pi rho (Eq. GPe) to ||r||_2 <= tol ||4 pi rho||_2
+ * (Algorithm PCG; r the PCG residual).  rho, eps: device, read only;
+ * phi: device, written.  Errors: GPS_E_INVALID (null pointer, tol <= 0,
+ * eps <= 0 anywhere, periodic rho with |sum rho| > 1e-10 sum |rho|),
+ * GPS_E_NONFINITE, GPS_E_NOT_CONVERGED, GPS_E_BREAKDOWN, GPS_E_DEVICE. */
+gps_status gps_solve_generalized(gps_plan *plan, const double *rho, const double *eps,
+                                 double *phi, double tol);
+
+/* Solve the Poisson-Boltzmann problem (Eq. PBe) for electrolyte ions.
+ * linear: tol as in gps_solve_generalized.  Nonlinear: Algorithm
+ * SCPBimproved, stopping when ||rho^ions_k - rho^ions_{k-1}||_2 <= tol ||rho||_2;
+ * each inner PCG stops at ||r||_2 <= 4 pi tol ||rho||_2, except the first two
+ * outer steps which stop at 1e-2 of their initial residual.  Errors: as
+ * gps_solve_generalized, plus GPS_E_INVALID for a bad electrolyte
+ * (nspecies outside 1..4, kT <= 0, c <= 0, c_max <= c, eta outside (0, 1],
+ * eps_bulk <= 1 when gamma is NULL) and GPS_E_NONFINITE when the ionic
+ * charge overflows (Boltzmann law at large |phi|/kT). */
+gps_status gps_solve_pb(gps_plan *plan, const double *rho, const double *eps,
+                        const gps_ions *ions, double *phi, double tol);
+
+/* Vacuum Poisson solver of the plan (Eq. SPe, Sec. II.C): u = G_bc f, i.e.
+ * lap u = -4 pi f under the plan's boundary condition, with the plan's
+ * Green's function (the preconditioner of every PCG iteration without the
+ * sqrt(eps) scaling).  Arithmetic in the plan's bulk precision.  f, u:
+ * device double[nz][ny][nx]; f is read, u written (they may not alias).
+ * Periodic: the k = 0 component of f is dropped (u has zero mean).
+ * Errors: GPS_E_INVALID (null pointer), GPS_E_NOMEM, GPS_E_DEVICE. */
+gps_status gps_solve_vacuum(gps_plan *plan, const double *f, double *u);
+
+/* Information about the last solve of this plan. */
+gps_status gps_last_info(const gps_plan *plan, gps_info *out);
+
+/* Per-iteration history of the last PCG solve: for iteration k, out[4k+0] =
+ * (v_k, r_k), out[4k+1] = beta_k, out[4k+2] = alpha_k, out[4k+3] = ||r_{k+1}||^2.
+ * Copies min(max_entries, history_len) entries to the HOST array out;
+ * returns GPS_E_INVALID for a null plan/out. */
+gps_status gps_last_history(const gps_plan *plan, double *out, int max_entries);
+
+/* Kernel timing (instrumentation for measurement).  kind selects one pass of
+ * the PCG iteration; while it is set, every solve brackets each launch of
+ * that pass with HIP events on the plan's stream and accumulates the elapsed
+ * time of the launches that did work (iterations before the stop decision).
+ * GPS_K_NONE switches timing off.  Setting a kind clears the totals.
+ * Errors: GPS_E_INVALID (null plan, unknown kind). */
+typedef enum {
+  GPS_K_NONE = 0,
+  GPS_K_XFWD = 1,       /* x pass: r/sqrt(eps), pairwise real-to-complex */
+  GPS_K_YFWD = 2,       /* y pass, forward */
+  GPS_K_ZCONV = 3,      /* z pass: forward, times the Green's spectrum, inverse */
+  GPS_K_YINV = 4,       /* y pass, inverse */
+  GPS_K_XINV = 5,       /* x pass: complex-to-real, v = u/sqrt(eps), (v, r) */
+  GPS_K_DIRECTION = 6,  /* p, Ap update and (p, Ap) */
+  GPS_K_UPDATE = 7      /* phi, r update and ||r||^2 */
+} gps_kernel_kind;
+gps_status gps_plan_set_timing(gps_plan *plan, int kind);
+
+/* Totals of the timed pass since the last gps_plan_set_timing: *total_ms
+ * (sum of launch durations), *launches, and *bytes_per_launch, the pass's
+ * algorithmic HBM bytes per launch (every input read once, every output
+ * written once) for the precision of the last solve.  Any output pointer may
+ * be NULL.  Errors: GPS_E_INVALID (null plan). */
+gps_status gps_plan_timing(const gps_plan *plan, double *total_ms, long long *launches,
+                           double *bytes_per_launch);
+
+const char *gps_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPS_H */

@@ -1,0 +1,887 @@
+// Plan, solve drivers and the C ABI of libgps (include/gps.h).
+//
+// A plan owns, for one grid and boundary condition: the FFT factorisations
+// and twiddles of the three axes, the Green's-function spectrum (FP64 and
+// FP32 copies, computed on the device at plan time) and, per precision, the
+// buffers of one problem in flight.  A solve enqueues the PCG iterations on
+// the plan's stream; alpha, beta and the stop decision stay on the device,
+// and the host only polls the state every `check_every` iterations.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gps.h"
+#include "gps_internal.h"
+#include "gps_launch.h"
+
+using namespace gps;
+
+namespace {
+
+struct DevError {
+  hipError_t e;
+};
+
+inline void ck(hipError_t e) {
+  if (e != hipSuccess) throw DevError{e};
+}
+
+struct NoMem {};
+
+template <typename P>
+void dalloc(P** p, size_t bytes, size_t* total) {
+  *p = nullptr;
+  if (bytes == 0) return;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    throw NoMem{};
+  }
+  *total += bytes;
+}
+
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+bool factorize(int n, RadixPlan* rp) {
+  rp->n = n;
+  rp->nstages = 0;
+  int m = n;
+  auto push = [&](int r) {
+    if (rp->nstages >= kMaxStages) return false;
+    rp->radix[rp->nstages++] = r;
+    return true;
+  };
+  while (m % 4 == 0) { if (!push(4)) return false; m /= 4; }
+  if (m % 2 == 0) { if (!push(2)) return false; m /= 2; }
+  for (int r : {3, 5, 7}) {
+    while (m % r == 0) { if (!push(r)) return false; m /= r; }
+  }
+  return m == 1 && n <= kMaxLen && n >= 1;
+}
+
+int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Per-precision buffers of one problem in flight.
+template <typename T> struct Res {
+  bool ready = false;
+  Slot<T> slot{};            // host copy of the device slot
+  Slot<T>* d_slot = nullptr;
+  SolveState* h_state = nullptr;   // pinned
+  double* h_parts = nullptr;       // pinned, >= 4 * groups
+  int hist_cap = 0;
+  double* lap64 = nullptr;         // periodic spectral Laplacian of sqrt(eps)
+  cplx<double>* work64q = nullptr; // FP64 work for the spectral q (mixed + periodic)
+};
+
+}  // namespace
+
+struct TimedLaunch {
+  int k;
+  hipEvent_t start, stop;
+};
+
+struct gps_plan {
+  int device = 0;
+  // kernel timing (gps_plan_set_timing)
+  int timing_kind = GPS_K_NONE;
+  double timing_ms = 0.0;
+  long long timing_launches = 0;
+  double timing_bytes = 0.0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<TimedLaunch> ev_pending;
+  size_t ev_used = 0;
+  Geom g{};
+  int bc = 0;
+  gps_options opt{};
+  RadixPlan rp[3]{};
+  double* tw64[3]{};
+  float* tw32[3]{};
+  double* green64 = nullptr;
+  float* green32 = nullptr;
+  double* lap64t = nullptr;     // spectral Laplacian table (periodic)
+  float* lap32t = nullptr;
+  Res<float> r32;
+  Res<double> r64;
+  size_t bytes = 0;
+  gps_info info{};
+  std::vector<double> hist;
+  long long npts() const { return (long long)g.nx * g.ny * g.nz; }
+  hipStream_t stream() const { return reinterpret_cast<hipStream_t>(opt.stream); }
+  template <typename T> Res<T>& res();
+  template <typename T> const T* green() const;
+  template <typename T> const T* lap() const;
+  template <typename T> const cplx<T>* tw(int axis) const;
+};
+template <> Res<float>& gps_plan::res<float>() { return r32; }
+template <> Res<double>& gps_plan::res<double>() { return r64; }
+template <> const float* gps_plan::green<float>() const { return green32; }
+template <> const double* gps_plan::green<double>() const { return green64; }
+template <> const float* gps_plan::lap<float>() const { return lap32t; }
+template <> const double* gps_plan::lap<double>() const { return lap64t; }
+template <> const cplx<float>* gps_plan::tw<float>(int a) const {
+  return reinterpret_cast<const cplx<float>*>(tw32[a]);
+}
+template <> const cplx<double>* gps_plan::tw<double>(int a) const {
+  return reinterpret_cast<const cplx<double>*>(tw64[a]);
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// pass parameter builders
+// ---------------------------------------------------------------------------
+template <typename T>
+XParams<T> xparams(const gps_plan* pl, int nrows, int rows_per_plane, int Lin, int Lout,
+                   long long plane_stride, long long in_row_stride) {
+  XParams<T> p{};
+  p.g = pl->g;
+  p.rp = pl->rp[0];
+  p.tw = pl->tw<T>(0);
+  p.Lin = Lin;
+  p.Lout = Lout;
+  const int npairs = (nrows + 1) / 2;
+  const int cap = std::max(1, TileCap<T>::elems / pl->g.Lx);
+  const int want = std::max(1, npairs / 1024);
+  p.P = pow2_floor(std::min(cap, want));
+  p.lgP = ilog2(p.P);
+  p.nrows = nrows;
+  p.rows_per_plane = rows_per_plane;
+  p.plane_stride = plane_stride;
+  p.in_row_stride = in_row_stride;
+  return p;
+}
+
+template <typename T>
+SParams<T> sparams(const gps_plan* pl, int axis, int L, int Lin, int Lout, int npencils,
+                   int per_group, long long group_stride, long long elem_stride) {
+  SParams<T> p{};
+  p.rp = pl->rp[axis];
+  p.tw = pl->tw<T>(axis);
+  p.L = L;
+  p.Lin = Lin;
+  p.Lout = Lout;
+  const int cap = std::max(1, TileCap<T>::elems / L);
+  p.B = pow2_floor(std::min(TileCap<T>::max_batch, cap));
+  p.lgB = ilog2(p.B);
+  p.npencils = npencils;
+  p.per_group = per_group;
+  p.group_stride = group_stride;
+  p.elem_stride = elem_stride;
+  p.Kx = pl->g.Kx;
+  p.Ly = pl->g.Ly;
+  p.Lz = pl->g.Lz;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// plan-time Green's-function spectrum (FP64 on the device)
+// ---------------------------------------------------------------------------
+void build_green(gps_plan* pl) {
+  const Geom& g = pl->g;
+  hipStream_t s = pl->stream();
+  const size_t ntab = (size_t)(g.Lz / 2 + 1) * (g.Ly / 2 + 1) * g.Kx;
+  dalloc(&pl->green64, ntab * sizeof(double), &pl->bytes);
+  dalloc(&pl->green32, ntab * sizeof(float), &pl->bytes);
+  const double norm = 1.0 / ((double)g.Lx * g.Ly * g.Lz);
+  if (pl->bc == GPS_BC_FREE) {
+    // K(m) on the full padded grid -> 3D FFT (FP64) -> fold and scale by h^3/N
+    const size_t nfull = (size_t)g.Lz * g.Ly * g.Kx;
+    size_t tmp_bytes = 0;
+    cplx<double>* full = nullptr;
+    dalloc(&full, nfull * sizeof(cplx<double>), &tmp_bytes);
+    XParams<double> xp = xparams<double>(pl, g.Ly * g.Lz, g.Ly, g.Lx, g.Lx,
+                                         (long long)g.Ly * g.Kx, g.Lx);
+    xp.work = full;
+    launch_xfwd<double>(XF_GEN_FREE, xp, s);
+    SParams<double> yp = sparams<double>(pl, 1, g.Ly, g.Ly, g.Ly, g.Lz * g.Kx, g.Kx,
+                                         (long long)g.Ly * g.Kx, g.Kx);
+    yp.work = full;
+    launch_strided<double>(ST_FWD, yp, s);
+    SParams<double> zp = sparams<double>(pl, 2, g.Lz, g.Lz, g.Lz / 2 + 1, g.Ly * g.Kx,
+                                         g.Ly * g.Kx, 0, (long long)g.Ly * g.Kx);
+    zp.work = full;
+    launch_strided<double>(ST_FWD, zp, s);
+    launch_compress_table(full, g.Kx, g.Ly, g.Lz, g.h * g.h * g.h * norm, pl->green64,
+                          pl->green32, s);
+    ck(hipGetLastError());
+    ck(hipStreamSynchronize(s));
+    dfree(full);
+  } else if (pl->bc == GPS_BC_SURFACE) {
+    const int Lyh = g.Ly / 2 + 1;
+    const size_t nc = (size_t)g.Kx * Lyh;
+    size_t tmp_bytes = 0;
+    cplx<double>* buf = nullptr;
+    dalloc(&buf, nc * g.Lz * sizeof(cplx<double>), &tmp_bytes);
+    // k_par = 0 kernel shifted by 2 pi Lz h (positive definite tent)
+    launch_surface_gen(buf, g.Kx, Lyh, g.Lz, g.nx, g.ny, g.h, 2.0 * kPi * g.Lz * g.h, s);
+    SParams<double> zp = sparams<double>(pl, 2, g.Lz, g.Lz, g.Lz / 2 + 1, (int)nc, (int)nc, 0,
+                                         (long long)nc);
+    zp.work = buf;
+    launch_strided<double>(ST_FWD, zp, s);
+    launch_surface_compress(buf, g.Kx, Lyh, g.Lz, g.h * norm, pl->green64, pl->green32, s);
+    ck(hipGetLastError());
+    ck(hipStreamSynchronize(s));
+    dfree(buf);
+  } else {
+    launch_periodic_table(g, 0, pl->green64, pl->green32, s);
+    dalloc(&pl->lap64t, ntab * sizeof(double), &pl->bytes);
+    dalloc(&pl->lap32t, ntab * sizeof(float), &pl->bytes);
+    launch_periodic_table(g, 1, pl->lap64t, pl->lap32t, s);
+    ck(hipGetLastError());
+    ck(hipStreamSynchronize(s));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-precision solve resources
+// ---------------------------------------------------------------------------
+template <typename T>
+void ensure_res(gps_plan* pl, bool need_ion) {
+  Res<T>& R = pl->res<T>();
+  const long long n = pl->npts();
+  const int nvg = vec_groups(n);
+  const Geom& g = pl->g;
+  const int nxg = (g.ny * g.nz + 1) / 2 + 1;   // x-pass groups <= row pairs
+  if (!R.ready) {
+    Slot<T>& s = R.slot;
+    s = Slot<T>{};
+    const size_t nb = (size_t)n * sizeof(T);
+    dalloc(&s.r, nb, &pl->bytes);
+    dalloc(&s.v, nb, &pl->bytes);
+    dalloc(&s.p, nb, &pl->bytes);
+    dalloc(&s.ap, nb, &pl->bytes);
+    dalloc(&s.isq, nb, &pl->bytes);
+    dalloc(&s.qk, nb, &pl->bytes);
+    if (pl->bc == GPS_BC_PERIODIC) dalloc(&s.s, nb, &pl->bytes);
+    dalloc(&s.sq64, (size_t)n * sizeof(double), &pl->bytes);
+    dalloc(&s.work, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<T>), &pl->bytes);
+    dalloc(&s.part_init, (size_t)4 * nvg * sizeof(double), &pl->bytes);
+    dalloc(&s.part_rr, (size_t)nvg * sizeof(double), &pl->bytes);
+    dalloc(&s.part_delta[0], (size_t)nxg * sizeof(double), &pl->bytes);
+    s.part_delta[1] = s.part_delta[0];
+    dalloc(&s.part_pap, (size_t)nvg * sizeof(double), &pl->bytes);
+    dalloc(&s.part_mu, (size_t)nxg * sizeof(double), &pl->bytes);
+    dalloc(&s.part_aux, (size_t)2 * nvg * sizeof(double), &pl->bytes);
+    dalloc(&s.st, sizeof(SolveState), &pl->bytes);
+    dalloc(&R.d_slot, sizeof(Slot<T>), &pl->bytes);
+    if (pl->bc == GPS_BC_PERIODIC) {
+      dalloc(&R.lap64, (size_t)n * sizeof(double), &pl->bytes);
+      if (sizeof(T) != sizeof(double))
+        dalloc(&R.work64q, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<double>), &pl->bytes);
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&R.h_state), sizeof(SolveState)) != hipSuccess)
+      throw NoMem{};
+    if (hipHostMalloc(reinterpret_cast<void**>(&R.h_parts), (size_t)4 * nvg * sizeof(double)) !=
+        hipSuccess)
+      throw NoMem{};
+    R.ready = true;
+  }
+  if (R.hist_cap < pl->opt.maxit + 1) {
+    dfree(R.slot.hist);
+    dalloc(&R.slot.hist, (size_t)4 * (pl->opt.maxit + 1) * sizeof(double), &pl->bytes);
+    R.hist_cap = pl->opt.maxit + 1;
+  }
+  if (need_ion && !R.slot.ion) dalloc(&R.slot.ion, (size_t)n * sizeof(T), &pl->bytes);
+  R.slot.hist_cap = R.hist_cap;
+  R.slot.maxit = pl->opt.maxit;
+}
+
+template <typename T>
+void free_res(gps_plan* pl) {
+  Res<T>& R = pl->res<T>();
+  Slot<T>& s = R.slot;
+  dfree(s.r); dfree(s.v); dfree(s.p); dfree(s.ap); dfree(s.isq); dfree(s.qk); dfree(s.s);
+  dfree(s.ion); dfree(s.sq64); dfree(s.work); dfree(s.part_init); dfree(s.part_rr);
+  dfree(s.part_delta[0]); dfree(s.part_pap); dfree(s.part_mu); dfree(s.part_aux); dfree(s.hist);
+  dfree(s.st); dfree(R.d_slot); dfree(R.lap64); dfree(R.work64q);
+  if (R.h_state) (void)hipHostFree(R.h_state);
+  if (R.h_parts) (void)hipHostFree(R.h_parts);
+  R = Res<T>{};
+}
+
+template <typename T>
+void push_slot(gps_plan* pl) {
+  Res<T>& R = pl->res<T>();
+  ck(hipMemcpyAsync(R.d_slot, &R.slot, sizeof(Slot<T>), hipMemcpyHostToDevice, pl->stream()));
+}
+
+template <typename T>
+SolveState read_state(gps_plan* pl) {
+  Res<T>& R = pl->res<T>();
+  ck(hipMemcpyAsync(R.h_state, R.slot.st, sizeof(SolveState), hipMemcpyDeviceToHost,
+                    pl->stream()));
+  ck(hipStreamSynchronize(pl->stream()));
+  return *R.h_state;
+}
+
+// Host sum, in index order, of `count` partials spaced by `stride`.
+template <typename T>
+double read_sum(gps_plan* pl, const double* dparts, int groups, int stride, int comp) {
+  Res<T>& R = pl->res<T>();
+  ck(hipMemcpyAsync(R.h_parts, dparts, (size_t)groups * stride * sizeof(double),
+                    hipMemcpyDeviceToHost, pl->stream()));
+  ck(hipStreamSynchronize(pl->stream()));
+  double s = 0.0;
+  for (int i = 0; i < groups; ++i) s += R.h_parts[(size_t)i * stride + comp];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+hipEvent_t next_event(gps_plan* pl) {
+  if (pl->ev_used == pl->ev_pool.size()) {
+    hipEvent_t e;
+    ck(hipEventCreate(&e));
+    pl->ev_pool.push_back(e);
+  }
+  return pl->ev_pool[pl->ev_used++];
+}
+
+struct TimerScope {
+  gps_plan* pl;
+  bool on;
+  TimedLaunch tl{};
+  TimerScope(gps_plan* p, int kind, int k) : pl(p), on(p->timing_kind == kind) {
+    if (on) {
+      tl.k = k;
+      tl.start = next_event(pl);
+      tl.stop = next_event(pl);
+      ck(hipEventRecord(tl.start, pl->stream()));
+    }
+  }
+  ~TimerScope() {
+    if (on) {
+      (void)hipEventRecord(tl.stop, pl->stream());
+      pl->ev_pending.push_back(tl);
+    }
+  }
+};
+
+// After a host sync: add the launches of iterations that did work.
+void collect_timing(gps_plan* pl, int iters_done) {
+  for (const TimedLaunch& t : pl->ev_pending) {
+    if (t.k < iters_done) {
+      float ms = 0.f;
+      ck(hipEventElapsedTime(&ms, t.start, t.stop));
+      pl->timing_ms += ms;
+      pl->timing_launches += 1;
+    }
+  }
+  pl->ev_pending.clear();
+  pl->ev_used = 0;
+}
+
+// Algorithmic bytes of one launch of pass `kind` (inputs read once, outputs
+// written once), bulk element size s.
+double pass_bytes(const gps_plan* pl, int kind, size_t s) {
+  const Geom& g = pl->g;
+  const double n = (double)pl->npts();
+  const double c = 2.0 * s;
+  const double rows = (double)g.ny * g.nz;
+  const double wbox = (double)g.nz * g.Ly * g.Kx;   // complex elements of the work buffer
+  const double tab = (double)(g.Lz / 2 + 1) * (g.Ly / 2 + 1) * g.Kx;
+  const int periodic = pl->bc == GPS_BC_PERIODIC;
+  switch (kind) {
+    case GPS_K_XFWD: return 2.0 * n * s + rows * g.Kx * c;
+    case GPS_K_YFWD: return (double)g.nz * g.Kx * g.ny * c + wbox * c;
+    case GPS_K_ZCONV: return 2.0 * wbox * c + tab * s;
+    case GPS_K_YINV: return wbox * c + (double)g.nz * g.Kx * g.ny * c;
+    case GPS_K_XINV: return rows * g.Kx * c + 3.0 * n * s;
+    case GPS_K_DIRECTION: return (7.0 + periodic) * n * s;
+    case GPS_K_UPDATE: return 4.0 * n * s + 16.0 * n;
+    default: return 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one PCG iteration for the problems of a batch (all of one plan)
+// ---------------------------------------------------------------------------
+template <typename T>
+void enqueue_iteration(gps_plan* pl, const Slot<T>* d_slots, const Batch& b, int check_neutral) {
+  const Geom& g = pl->g;
+  hipStream_t s = pl->stream();
+  const long long n = pl->npts();
+  const int periodic = pl->bc == GPS_BC_PERIODIC;
+  XParams<T> xp = xparams<T>(pl, g.ny * g.nz, g.ny, g.nx, g.nx, (long long)g.Ly * g.Kx, g.nx);
+  xp.slots = d_slots;
+  xp.batch = b;
+  xp.n_vec_parts = vec_groups(n);
+  xp.periodic_mean = periodic;
+  xp.check_neutral = check_neutral;
+  const int k0 = b.k[0];
+  { TimerScope t(pl, GPS_K_XFWD, k0); launch_xfwd<T>(XF_SOLVE, xp, s); }
+  SParams<T> yf = sparams<T>(pl, 1, g.Ly, g.ny, g.Ly, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
+                             g.Kx);
+  yf.slots = d_slots;
+  yf.batch = b;
+  { TimerScope t(pl, GPS_K_YFWD, k0); launch_strided<T>(ST_FWD, yf, s); }
+  SParams<T> zc = sparams<T>(pl, 2, g.Lz, g.nz, g.nz, g.Ly * g.Kx, g.Ly * g.Kx, 0,
+                             (long long)g.Ly * g.Kx);
+  zc.slots = d_slots;
+  zc.batch = b;
+  zc.table = pl->green<T>();
+  zc.k0_from_slot = periodic;
+  { TimerScope t(pl, GPS_K_ZCONV, k0); launch_strided<T>(ST_CONV, zc, s); }
+  SParams<T> yi = sparams<T>(pl, 1, g.Ly, g.Ly, g.ny, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
+                             g.Kx);
+  yi.slots = d_slots;
+  yi.batch = b;
+  { TimerScope t(pl, GPS_K_YINV, k0); launch_strided<T>(ST_INV, yi, s); }
+  { TimerScope t(pl, GPS_K_XINV, k0); launch_xinv<T>(0 /*XI_SOLVE*/, xp, s); }
+  { TimerScope t(pl, GPS_K_DIRECTION, k0);
+    launch_direction<T>(d_slots, b, n, xpass_groups(xp), periodic, s); }
+  { TimerScope t(pl, GPS_K_UPDATE, k0); launch_update<T>(d_slots, b, n, s); }
+}
+
+// Spectral Laplacian of sqrt(eps) (periodic q) with the FP64 FFT passes.
+template <typename T>
+void spectral_laplacian(gps_plan* pl) {
+  Res<T>& R = pl->res<T>();
+  const Geom& g = pl->g;
+  hipStream_t s = pl->stream();
+  cplx<double>* work = R.work64q ? R.work64q : reinterpret_cast<cplx<double>*>(R.slot.work);
+  XParams<double> xp = xparams<double>(pl, g.ny * g.nz, g.ny, g.nx, g.nx,
+                                       (long long)g.Ly * g.Kx, g.nx);
+  xp.in_real = R.slot.sq64;
+  xp.out_real = R.lap64;
+  xp.work = work;
+  launch_xfwd<double>(XF_REAL, xp, s);
+  SParams<double> yf = sparams<double>(pl, 1, g.Ly, g.ny, g.Ly, g.nz * g.Kx, g.Kx,
+                                       (long long)g.Ly * g.Kx, g.Kx);
+  yf.work = work;
+  launch_strided<double>(ST_FWD, yf, s);
+  SParams<double> zc = sparams<double>(pl, 2, g.Lz, g.nz, g.nz, g.Ly * g.Kx, g.Ly * g.Kx, 0,
+                                       (long long)g.Ly * g.Kx);
+  zc.work = work;
+  zc.table = pl->lap64t;
+  launch_strided<double>(ST_CONV, zc, s);
+  SParams<double> yi = sparams<double>(pl, 1, g.Ly, g.Ly, g.ny, g.nz * g.Kx, g.Kx,
+                                       (long long)g.Ly * g.Kx, g.Kx);
+  yi.work = work;
+  launch_strided<double>(ST_INV, yi, s);
+  launch_xinv<double>(1 /*XI_REAL*/, xp, s);
+}
+
+// u = G f with the bulk-precision FFT passes (no sqrt(eps) scaling).
+template <typename T>
+void vacuum_apply(gps_plan* pl, const double* f, double* u) {
+  ensure_res<T>(pl, false);
+  Res<T>& R = pl->res<T>();
+  const Geom& g = pl->g;
+  hipStream_t s = pl->stream();
+  cplx<T>* work = R.slot.work;
+  XParams<T> xp = xparams<T>(pl, g.ny * g.nz, g.ny, g.nx, g.nx, (long long)g.Ly * g.Kx, g.nx);
+  xp.in_real = f;
+  xp.out_real = u;
+  xp.work = work;
+  launch_xfwd<T>(XF_REAL, xp, s);
+  SParams<T> yf = sparams<T>(pl, 1, g.Ly, g.ny, g.Ly, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
+                             g.Kx);
+  yf.work = work;
+  launch_strided<T>(ST_FWD, yf, s);
+  SParams<T> zc = sparams<T>(pl, 2, g.Lz, g.nz, g.nz, g.Ly * g.Kx, g.Ly * g.Kx, 0,
+                             (long long)g.Ly * g.Kx);
+  zc.work = work;
+  zc.table = pl->green<T>();
+  launch_strided<T>(ST_CONV, zc, s);
+  SParams<T> yi = sparams<T>(pl, 1, g.Ly, g.Ly, g.ny, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
+                             g.Kx);
+  yi.work = work;
+  launch_strided<T>(ST_INV, yi, s);
+  launch_xinv<T>(1 /*XI_REAL*/, xp, s);
+  ck(hipGetLastError());
+  ck(hipStreamSynchronize(s));
+}
+
+// Run PCG iterations until the device-side state says done.
+template <typename T>
+SolveState run_pcg(gps_plan* pl, int check_neutral) {
+  Res<T>& R = pl->res<T>();
+  Batch b{};
+  b.n = 1;
+  b.slot[0] = 0;
+  int k = 0;
+  SolveState st{};
+  for (;;) {
+    for (int j = 0; j < pl->opt.check_every; ++j) {
+      b.k[0] = k++;
+      enqueue_iteration<T>(pl, R.d_slot, b, check_neutral);
+    }
+    ck(hipGetLastError());
+    st = read_state<T>(pl);
+    if (pl->timing_kind != GPS_K_NONE) {
+      collect_timing(pl, st.done ? st.iters : k);
+      pl->timing_bytes = pass_bytes(pl, pl->timing_kind, sizeof(T));
+    }
+    if (st.done || k > pl->opt.maxit + 1) break;
+  }
+  return st;
+}
+
+template <typename T>
+void reset_state(gps_plan* pl) {
+  Res<T>& R = pl->res<T>();
+  ck(hipMemsetAsync(R.slot.st, 0, sizeof(SolveState), pl->stream()));
+}
+
+template <typename T>
+void finish_info(gps_plan* pl, const SolveState& st, const double* rho, int total_iters) {
+  Res<T>& R = pl->res<T>();
+  const long long n = pl->npts();
+  Batch b{};
+  b.n = 1;
+  launch_energy<T>(R.d_slot, b, rho, n, pl->stream());
+  ck(hipGetLastError());
+  const double e = read_sum<T>(pl, R.slot.part_aux, vec_groups(n), 2, 0);
+  pl->info.energy = 0.5 * pl->g.h * pl->g.h * pl->g.h * e;
+  pl->info.iterations = total_iters;
+  pl->info.rnorm0 = std::sqrt(st.rr0);
+  pl->info.rel_residual = st.rr0 > 0 ? std::sqrt(st.rr / st.rr0) : 0.0;
+  const int nh = std::min(st.iters, R.hist_cap);
+  pl->hist.assign((size_t)4 * nh, 0.0);
+  if (nh > 0)
+    ck(hipMemcpy(pl->hist.data(), R.slot.hist, (size_t)4 * nh * sizeof(double),
+                 hipMemcpyDeviceToHost));
+  pl->info.history_len = nh;
+}
+
+struct Electrolyte {
+  bool present = false;
+  bool linear = false;
+  IonParams ip{};
+  double kappa_coef = 0.0;
+  int outer_maxit = 0;
+};
+
+template <typename T>
+gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double* phi,
+                      double tol, const Electrolyte& el) {
+  const bool nonlinear = el.present && !el.linear;
+  ensure_res<T>(pl, nonlinear);
+  Res<T>& R = pl->res<T>();
+  hipStream_t s = pl->stream();
+  const long long n = pl->npts();
+  const int periodic = pl->bc == GPS_BC_PERIODIC;
+  Slot<T>& sl = R.slot;
+  sl.phi = phi;
+  sl.g0 = 0.0;
+  sl.abs_thr = 0.0;
+  sl.rel_thr = tol;
+  push_slot<T>(pl);
+  reset_state<T>(pl);
+  Batch b{};
+  b.n = 1;
+  launch_init<T>(R.d_slot, b, rho, eps, n, s);
+  if (nonlinear) launch_zero_ion<T>(R.d_slot, b, n, s);
+  const double kcoef = (el.present && el.linear) ? el.kappa_coef : 0.0;
+  const double* lap = nullptr;
+  if (periodic) {
+    spectral_laplacian<T>(pl);
+    lap = R.lap64;
+  }
+  launch_qfield<T>(R.d_slot, b, pl->g, pl->opt.fd_order / 2, lap, kcoef, eps, el.ip.gamma,
+                   el.ip.eps_bulk, s);
+  ck(hipGetLastError());
+  if (periodic && kcoef != 0.0) {
+    // k = 0 multiplier of the preconditioner: 4 pi / mean(kappa2/eps)
+    const double sum = read_sum<T>(pl, sl.part_aux, vec_groups(n), 2, 0);
+    const double mean = sum / double(n);
+    const Geom& g = pl->g;
+    sl.g0 = mean > 0 ? 4.0 * kPi / mean / ((double)g.Lx * g.Ly * g.Lz) : 0.0;
+    push_slot<T>(pl);
+  }
+  std::memset(&pl->info, 0, sizeof(pl->info));
+  if (!nonlinear) {
+    const SolveState st = run_pcg<T>(pl, periodic && !el.present);
+    finish_info<T>(pl, st, rho, st.iters);
+    pl->info.status = st.status;
+    return (gps_status)st.status;
+  }
+  // Algorithm SCPBimproved
+  const double rho_norm = std::sqrt(read_sum<T>(pl, sl.part_init, vec_groups(n), 4, 3));
+  int total = 0;
+  SolveState st{};
+  gps_status result = GPS_E_NOT_CONVERGED;
+  double outer_res = 0.0;
+  int outer = 0;
+  for (int k = 1; k <= el.outer_maxit; ++k) {
+    outer = k;
+    sl.abs_thr = kFourPi * tol * rho_norm;
+    sl.rel_thr = k <= 2 ? 1e-2 : 0.0;
+    push_slot<T>(pl);
+    reset_state<T>(pl);
+    st = run_pcg<T>(pl, 0);
+    total += st.iters;
+    if (st.status != GPS_OK) {
+      result = (gps_status)st.status;
+      break;
+    }
+    IonParams ip = el.ip;
+    ip.eps = eps;
+    launch_ion_update<T>(R.d_slot, b, n, ip, k == 1, s);
+    ck(hipGetLastError());
+    const double d2 = read_sum<T>(pl, sl.part_init, vec_groups(n), 4, 3);
+    outer_res = rho_norm > 0 ? std::sqrt(d2) / rho_norm : std::sqrt(d2);
+    if (!std::isfinite(d2)) {
+      result = GPS_E_NONFINITE;
+      break;
+    }
+    if (std::sqrt(d2) <= tol * rho_norm) {
+      result = GPS_OK;
+      break;
+    }
+  }
+  finish_info<T>(pl, st, rho, total);
+  pl->info.outer_iterations = outer;
+  pl->info.outer_residual = outer_res;
+  pl->info.status = result;
+  return result;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* gps_status_string(int st) {
+  switch (st) {
+    case GPS_OK: return "ok";
+    case GPS_E_INVALID: return "invalid argument";
+    case GPS_E_NOMEM: return "out of device memory";
+    case GPS_E_NOT_CONVERGED: return "not converged";
+    case GPS_E_BREAKDOWN: return "PCG breakdown";
+    case GPS_E_NONFINITE: return "non-finite value";
+    case GPS_E_DEVICE: return "HIP runtime error";
+    case GPS_E_UNSUPPORTED: return "unsupported size";
+    default: return "unknown status";
+  }
+}
+
+static void plan_release(gps_plan* pl) {
+  if (!pl) return;
+  for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
+  pl->ev_pool.clear();
+  free_res<float>(pl);
+  free_res<double>(pl);
+  for (int a = 0; a < 3; ++a) {
+    dfree(pl->tw64[a]);
+    dfree(pl->tw32[a]);
+  }
+  dfree(pl->green64);
+  dfree(pl->green32);
+  dfree(pl->lap64t);
+  dfree(pl->lap32t);
+}
+
+gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan** out) {
+  if (!out) return GPS_E_INVALID;
+  *out = nullptr;
+  if (nx < 2 || ny < 2 || nz < 2 || !(h > 0.0) || !std::isfinite(h)) return GPS_E_INVALID;
+  if (bc != GPS_BC_FREE && bc != GPS_BC_SURFACE && bc != GPS_BC_PERIODIC) return GPS_E_INVALID;
+  gps_plan* pl = new (std::nothrow) gps_plan();
+  if (!pl) return GPS_E_NOMEM;
+  pl->bc = bc;
+  pl->opt.precision = GPS_PREC_FP64;
+  pl->opt.fd_order = 16;
+  pl->opt.maxit = 1000;
+  pl->opt.check_every = 8;
+  pl->opt.stream = nullptr;
+  Geom& g = pl->g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.h = h;
+  g.periodic_x = bc != GPS_BC_FREE;
+  g.periodic_y = bc != GPS_BC_FREE;
+  g.periodic_z = bc == GPS_BC_PERIODIC;
+  g.Lx = g.periodic_x ? nx : 2 * nx;
+  g.Ly = g.periodic_y ? ny : 2 * ny;
+  g.Lz = g.periodic_z ? nz : 2 * nz;
+  g.Kx = g.Lx / 2 + 1;
+  const int L[3] = {g.Lx, g.Ly, g.Lz};
+  for (int a = 0; a < 3; ++a) {
+    if (!factorize(L[a], &pl->rp[a])) {
+      delete pl;
+      return GPS_E_UNSUPPORTED;
+    }
+  }
+  try {
+    if (hipGetDevice(&pl->device) != hipSuccess) throw DevError{hipErrorNoDevice};
+    for (int a = 0; a < 3; ++a) {
+      std::vector<double> t64(2 * (size_t)L[a]);
+      std::vector<float> t32(2 * (size_t)L[a]);
+      for (int m = 0; m < L[a]; ++m) {
+        const double ang = 2.0 * kPi * (double)m / (double)L[a];
+        t64[2 * m] = std::cos(ang);
+        t64[2 * m + 1] = -std::sin(ang);
+        t32[2 * m] = (float)t64[2 * m];
+        t32[2 * m + 1] = (float)t64[2 * m + 1];
+      }
+      dalloc(&pl->tw64[a], t64.size() * sizeof(double), &pl->bytes);
+      dalloc(&pl->tw32[a], t32.size() * sizeof(float), &pl->bytes);
+      ck(hipMemcpy(pl->tw64[a], t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
+      ck(hipMemcpy(pl->tw32[a], t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    build_green(pl);
+  } catch (const NoMem&) {
+    plan_release(pl);
+    delete pl;
+    return GPS_E_NOMEM;
+  } catch (const DevError&) {
+    plan_release(pl);
+    delete pl;
+    return GPS_E_DEVICE;
+  }
+  *out = pl;
+  return GPS_OK;
+}
+
+gps_status gps_plan_set_options(gps_plan* pl, const gps_options* o) {
+  if (!pl || !o) return GPS_E_INVALID;
+  if (o->precision != GPS_PREC_FP64 && o->precision != GPS_PREC_MIXED) return GPS_E_INVALID;
+  if (o->fd_order < 2 || o->fd_order > 16 || (o->fd_order & 1)) return GPS_E_INVALID;
+  if (o->maxit < 1 || o->check_every < 1) return GPS_E_INVALID;
+  pl->opt = *o;
+  return GPS_OK;
+}
+
+gps_status gps_plan_get_options(const gps_plan* pl, gps_options* o) {
+  if (!pl || !o) return GPS_E_INVALID;
+  *o = pl->opt;
+  return GPS_OK;
+}
+
+size_t gps_plan_device_bytes(const gps_plan* pl) { return pl ? pl->bytes : 0; }
+
+void gps_plan_destroy(gps_plan* pl) {
+  if (!pl) return;
+  plan_release(pl);
+  delete pl;
+}
+
+static gps_status run_guarded(gps_plan* pl, bool mixed, const double* rho, const double* eps,
+                              double* phi, double tol, const Electrolyte& el) {
+  try {
+    if (mixed) return solve_impl<float>(pl, rho, eps, phi, tol, el);
+    return solve_impl<double>(pl, rho, eps, phi, tol, el);
+  } catch (const NoMem&) {
+    return GPS_E_NOMEM;
+  } catch (const DevError&) {
+    return GPS_E_DEVICE;
+  }
+}
+
+gps_status gps_solve_generalized(gps_plan* pl, const double* rho, const double* eps, double* phi,
+                                 double tol) {
+  if (!pl || !rho || !eps || !phi || !(tol > 0.0) || !std::isfinite(tol)) return GPS_E_INVALID;
+  Electrolyte el;
+  return run_guarded(pl, pl->opt.precision == GPS_PREC_MIXED, rho, eps, phi, tol, el);
+}
+
+gps_status gps_solve_pb(gps_plan* pl, const double* rho, const double* eps, const gps_ions* ions,
+                        double* phi, double tol) {
+  if (!pl || !rho || !eps || !phi || !ions || !(tol > 0.0) || !std::isfinite(tol))
+    return GPS_E_INVALID;
+  if (ions->nspecies < 1 || ions->nspecies > 4 || !ions->Z || !ions->c_bulk) return GPS_E_INVALID;
+  if (!(ions->kT > 0.0)) return GPS_E_INVALID;
+  if (!ions->gamma && !(ions->eps_bulk > 1.0)) return GPS_E_INVALID;
+  Electrolyte el;
+  el.present = true;
+  el.linear = ions->linear != 0;
+  IonParams& ip = el.ip;
+  ip.nspecies = ions->nspecies;
+  ip.kT = ions->kT;
+  ip.eta = ions->eta;
+  ip.eps_bulk = ions->eps_bulk;
+  ip.gamma = ions->gamma;
+  ip.steric = ions->c_max != nullptr;
+  double z2c = 0.0;
+  for (int i = 0; i < ions->nspecies; ++i) {
+    const double c = ions->c_bulk[i];
+    if (!(c > 0.0) || !std::isfinite(ions->Z[i])) return GPS_E_INVALID;
+    ip.Z[i] = ions->Z[i];
+    ip.c[i] = c;
+    ip.a[i] = 0.0;
+    if (ip.steric) {
+      const double cm = ions->c_max[i];
+      if (!(cm > c)) return GPS_E_INVALID;
+      ip.a[i] = c / cm;
+    }
+    z2c += ions->Z[i] * ions->Z[i] * c;
+  }
+  el.kappa_coef = kFourPi / ions->kT * z2c;
+  if (!el.linear) {
+    if (!(ions->eta > 0.0 && ions->eta <= 1.0) || ions->outer_maxit < 1) return GPS_E_INVALID;
+    if (pl->bc == GPS_BC_PERIODIC) return GPS_E_UNSUPPORTED;
+    el.outer_maxit = ions->outer_maxit;
+  }
+  return run_guarded(pl, pl->opt.precision == GPS_PREC_MIXED, rho, eps, phi, tol, el);
+}
+
+gps_status gps_solve_vacuum(gps_plan* pl, const double* f, double* u) {
+  if (!pl || !f || !u) return GPS_E_INVALID;
+  try {
+    if (pl->opt.precision == GPS_PREC_MIXED) vacuum_apply<float>(pl, f, u);
+    else vacuum_apply<double>(pl, f, u);
+  } catch (const NoMem&) {
+    return GPS_E_NOMEM;
+  } catch (const DevError&) {
+    return GPS_E_DEVICE;
+  }
+  return GPS_OK;
+}
+
+gps_status gps_plan_set_timing(gps_plan* pl, int kind) {
+  if (!pl || kind < GPS_K_NONE || kind > GPS_K_UPDATE) return GPS_E_INVALID;
+  pl->timing_kind = kind;
+  pl->timing_ms = 0.0;
+  pl->timing_launches = 0;
+  pl->timing_bytes = 0.0;
+  pl->ev_pending.clear();
+  pl->ev_used = 0;
+  return GPS_OK;
+}
+
+gps_status gps_plan_timing(const gps_plan* pl, double* total_ms, long long* launches,
+                           double* bytes_per_launch) {
+  if (!pl) return GPS_E_INVALID;
+  if (total_ms) *total_ms = pl->timing_ms;
+  if (launches) *launches = pl->timing_launches;
+  if (bytes_per_launch) *bytes_per_launch = pl->timing_bytes;
+  return GPS_OK;
+}
+
+gps_status gps_last_info(const gps_plan* pl, gps_info* out) {
+  if (!pl || !out) return GPS_E_INVALID;
+  *out = pl->info;
+  return GPS_OK;
+}
+
+gps_status gps_last_history(const gps_plan* pl, double* out, int max_entries) {
+  if (!pl || !out || max_entries < 0) return GPS_E_INVALID;
+  const int n = std::min(max_entries, pl->info.history_len);
+  std::memcpy(out, pl->hist.data(), (size_t)4 * n * sizeof(double));
+  return GPS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Device helpers shared by the kernels of libgps: complex arithmetic,
+// deterministic FP64 block reductions, slot lookup.
+#pragma once
+
+#include "gps_internal.h"
+
+namespace gps {
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmk(T x, T y) { cplx<T> c; c.x = x; c.y = y; return c; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return cmk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return cmk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return cmk(a.x * s, a.y * s); }
+
+// Sum of v over the work-group, identical in every thread.  Fixed reduction
+// tree (wavefront butterfly, then waves in index order): the result depends
+// only on the inputs, never on timing.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double wsum[kThreads / 64];
+  __shared__ double total;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) wsum[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) s += wsum[w];
+    total = s;
+  }
+  __syncthreads();
+  double r = total;
+  __syncthreads();   // the shared words may be reused by the next call
+  return r;
+}
+
+// Deterministic sum of n partials spaced by `stride` doubles.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n,
+                                               int stride = 1) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) s += part[(size_t)i * stride];
+  return block_sum(s);
+}
+
+// One work-group-uniform flag broadcast from thread 0.
+__device__ __forceinline__ int wg_read_flag(const int* p) {
+  __shared__ int f;
+  if (threadIdx.x == 0) f = *reinterpret_cast<const volatile int*>(p);
+  __syncthreads();
+  int r = f;
+  __syncthreads();
+  return r;
+}
+
+}  // namespace gps

@@ -1,0 +1,104 @@
+// Internal declarations shared by the HIP translation units of libgps.
+// Not part of the public ABI (see include/gps.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace gps {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kFourPi = 4.0 * kPi;
+
+// Threads per work-group for every kernel of the library.
+constexpr int kThreads = 256;
+// LDS tile of an FFT pass, in complex elements (32 KiB FP32, 63 KiB FP64:
+// with the reduction scratch a work-group stays under 64 KiB of LDS).
+template <typename T> struct TileCap;
+template <> struct TileCap<float> { static constexpr int elems = 4096; static constexpr int max_batch = 16; };
+template <> struct TileCap<double> { static constexpr int elems = 4032; static constexpr int max_batch = 8; };
+
+// Elements per thread of the pointwise kernels; a work-group covers
+// kThreads * kVec consecutive grid points.
+constexpr int kVec = 8;
+
+// Work-groups (and FP64 partials) of a pointwise kernel over n points.
+__host__ __device__ inline int vec_groups(long long n) {
+  return (int)((n + (long long)kThreads * kVec - 1) / ((long long)kThreads * kVec));
+}
+
+constexpr int kMaxStages = 16;
+constexpr int kMaxLen = 1024;        // longest supported FFT length
+constexpr int kMaxBatch = 32;        // problems per batched launch
+
+template <typename T> struct cplx { T x, y; };
+
+// Mixed-radix factorisation of one FFT length (radices 2, 3, 4, 5, 7).
+struct RadixPlan {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+};
+
+// Convergence / status words of one solve, resident in device memory.
+struct SolveState {
+  int done;          // 1 once the solve has stopped (any reason)
+  int status;        // gps_status value once done
+  int iters;         // iterations completed
+  int err;           // input-check flags raised by the init kernel
+  double rr0;        // ||r_0||^2
+  double thr2;       // stop threshold on ||r||^2
+  double rr;         // last ||r||^2
+  double rho_sum;    // sum rho, sum |rho| and sum rho^2 of the right-hand side
+  double rho_abs;
+  double rho_sq;
+};
+
+// Input-check flags (SolveState::err)
+constexpr int kErrEpsNonPositive = 1;
+constexpr int kErrNonFinite = 2;
+
+// Device-resident pointers of one problem in flight.  T is the bulk type
+// (float in mixed precision, double in plain FP64).
+template <typename T> struct Slot {
+  T *r, *v, *p, *ap;          // PCG vectors
+  T *isq;                     // 1/sqrt(eps)
+  T *qk;                      // q + kappa2 (fixed operator diagonal)
+  T *s;                       // sqrt(eps) (periodic mean term; may be null)
+  T *ion, *ion_prev;          // ionic charge (nonlinear PB only)
+  double *phi;                // solution accumulator (FP64)
+  double *sq64;               // sqrt(eps) in FP64 (stencil input)
+  cplx<T> *work;              // FFT work buffer  nz * Ly * Kx
+  double *part_init;          // 4 partial sums per init work-group
+  double *part_rr;            // ||r||^2 partials
+  double *part_delta[2];      // (v, r) partials, by iteration parity
+  double *part_pap;           // (p, Ap) partials
+  double *part_mu;            // sum r/sqrt(eps) partials (periodic)
+  double *part_aux;           // ionic-update / energy partials (2 per WG)
+  double *hist;               // per-iteration history: delta, beta, alpha, ||r||^2
+  SolveState *st;
+  double g0;                  // periodic k = 0 multiplier of the preconditioner
+  double abs_thr;             // absolute stop threshold on ||r||
+  double rel_thr;             // relative stop threshold on ||r|| / ||r_0||
+  int maxit;
+  int hist_cap;
+};
+
+// Problems of one batched launch: blockIdx.y indexes these arrays.
+struct Batch {
+  int n;
+  int slot[kMaxBatch];        // index into the device slot table
+  int k[kMaxBatch];           // iteration number of that problem
+};
+
+// Geometry of one plan, passed by value to kernels.
+struct Geom {
+  int nx, ny, nz;             // box
+  int Lx, Ly, Lz;             // FFT lengths
+  int Kx;                     // Lx/2 + 1
+  int periodic_x, periodic_y, periodic_z;
+  double h;
+};
+
+}  // namespace gps

@@ -1,0 +1,103 @@
+// Host-side launchers of the libgps kernels (internal).
+#pragma once
+
+#include "gps_internal.h"
+
+namespace gps {
+
+// ---- FFT passes -----------------------------------------------------------
+
+// Pass along x: pairs of real rows -> one complex FFT of length Lx.
+// Row `row` of the input is in[row * in_row_stride + x], x < Lin; the output
+// row goes to work[(row / rows_per_plane) * plane_stride + (row % rows_per_plane) * Kx + k].
+enum XfwdMode { XF_SOLVE = 0, XF_REAL = 1, XF_GEN_FREE = 2 };
+template <typename T> struct XParams {
+  Geom g;
+  RadixPlan rp;
+  const cplx<T>* tw;        // twiddles of length Lx
+  int Lin;                  // loaded row length (rest zero)
+  int Lout;                 // stored row length (inverse pass)
+  int P, lgP;               // row pairs per work-group (power of two)
+  int nrows;                // number of real rows
+  int rows_per_plane;
+  long long plane_stride;   // complex elements between output planes
+  long long in_row_stride;  // real elements between input rows
+  // XF_REAL / XF_GEN_FREE / XI_REAL: explicit buffers (single problem)
+  const double* in_real;
+  double* out_real;
+  cplx<T>* work;
+  // XF_SOLVE / XI_SOLVE: the problems of the batch
+  const Slot<T>* slots;
+  Batch batch;
+  int n_vec_parts;          // partial sums written by the vector kernels
+  int periodic_mean;        // accumulate sum r/sqrt(eps) (periodic)
+  int check_neutral;        // periodic Poisson: reject non-neutral rho
+};
+
+template <typename T> void launch_xfwd(int mode, const XParams<T>& p, hipStream_t s);
+template <typename T> void launch_xinv(int mode, const XParams<T>& p, hipStream_t s);
+template <typename T> int xpass_groups(const XParams<T>& p);
+
+// Pass along a strided axis: pencils p of length L with elements at
+// base(p) + t * elem_stride, base(p) = (p / per_group) * group_stride + p % per_group.
+enum StridedMode { ST_FWD = 0, ST_INV = 1, ST_CONV = 2 };
+template <typename T> struct SParams {
+  RadixPlan rp;
+  const cplx<T>* tw;
+  int L, Lin, Lout;
+  int B, lgB;
+  int npencils;
+  int per_group;
+  long long group_stride;
+  long long elem_stride;
+  // ST_CONV: multiply by a real, even table folded to (Lz/2+1)(Ly/2+1)Kx
+  const T* table;
+  int Kx, Ly, Lz;
+  int k0_from_slot;         // periodic: the k = 0 multiplier is slot.g0
+  cplx<T>* work;            // explicit buffer, or null to use the slots
+  const Slot<T>* slots;
+  Batch batch;
+};
+template <typename T> void launch_strided(int mode, const SParams<T>& p, hipStream_t s);
+
+// ---- plan-time tables -------------------------------------------------------
+void launch_compress_table(const cplx<double>* full, int Kx, int Ly, int Lz, double scale,
+                           double* t64, float* t32, hipStream_t s);
+void launch_surface_gen(cplx<double>* buf, int Kx, int Lyh, int Lz, int nx, int ny, double h,
+                        double k0_offset, hipStream_t s);
+void launch_surface_compress(const cplx<double>* buf, int Kx, int Lyh, int Lz, double scale,
+                             double* t64, float* t32, hipStream_t s);
+void launch_periodic_table(const Geom& g, int laplacian, double* t64, float* t32, hipStream_t s);
+
+// ---- per-solve vector kernels -------------------------------------------------
+struct IonParams {
+  int nspecies;
+  double Z[4];
+  double c[4];
+  double a[4];              // c / c_max (0 for Boltzmann)
+  int steric;
+  double kT;
+  double eta;
+  double eps_bulk;
+  const double* gamma;      // null: (eps - 1)/(eps_bulk - 1)
+  const double* eps;
+};
+
+template <typename T> void launch_init(const Slot<T>* slots, const Batch& b, const double* rho,
+                                       const double* eps, long long n, hipStream_t s);
+template <typename T> void launch_qfield(const Slot<T>* slots, const Batch& b, const Geom& g,
+                                         int fd_half, const double* lap_sq, double kappa_coef,
+                                         const double* eps, const double* gamma,
+                                         double eps_bulk, hipStream_t s);
+template <typename T> void launch_direction(const Slot<T>* slots, const Batch& b, long long n,
+                                            int n_xparts, int periodic, hipStream_t s);
+template <typename T> void launch_update(const Slot<T>* slots, const Batch& b, long long n,
+                                         hipStream_t s);
+template <typename T> void launch_ion_update(const Slot<T>* slots, const Batch& b, long long n,
+                                             const IonParams& ip, int first, hipStream_t s);
+template <typename T> void launch_energy(const Slot<T>* slots, const Batch& b, const double* rho,
+                                         long long n, hipStream_t s);
+template <typename T> void launch_zero_ion(const Slot<T>* slots, const Batch& b, long long n,
+                                           hipStream_t s);
+
+}  // namespace gps

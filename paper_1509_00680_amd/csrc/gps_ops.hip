@@ -1,0 +1,521 @@
+// Pointwise and stencil kernels of the PCG solver (Algorithm PCG with the
+// operator identity of Eq. corr / Eq. corrPB) and the ionic update of
+// Algorithm SCPBimproved, plus the plan-time spectrum tables.
+//
+// Reductions are deterministic: every work-group writes one FP64 partial per
+// quantity, and the consuming kernel sums the partials in a fixed order in
+// every work-group that needs the scalar (no atomics, no cross-group fences).
+#include "gps_device.h"
+#include "gps_launch.h"
+#include "gps.h"
+
+namespace gps {
+
+
+// ---------------------------------------------------------------------------
+// plan-time spectra
+// ---------------------------------------------------------------------------
+// t[kz][ky][kx] = scale * Re full[kz][ky][kx], kz <= Lz/2, ky <= Ly/2 (the
+// spectrum of a real kernel that is even along every axis).
+__global__ void k_compress_table(const cplx<double>* __restrict__ full, int Kx, int Ly, int Lz,
+                                 double scale, double* __restrict__ t64, float* __restrict__ t32) {
+  const int Lyh = Ly / 2 + 1, Lzh = Lz / 2 + 1;
+  const long long n = (long long)Lzh * Lyh * Kx;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int kx = (int)(i % Kx);
+    const int ky = (int)((i / Kx) % Lyh);
+    const int kz = (int)(i / ((long long)Kx * Lyh));
+    const double v = full[((size_t)kz * Ly + ky) * Kx + kx].x * scale;
+    t64[i] = v;
+    t32[i] = (float)v;
+  }
+}
+
+void launch_compress_table(const cplx<double>* full, int Kx, int Ly, int Lz, double scale,
+                           double* t64, float* t32, hipStream_t s) {
+  const long long n = (long long)(Lz / 2 + 1) * (Ly / 2 + 1) * Kx;
+  const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
+  hipLaunchKernelGGL(k_compress_table, dim3(grid), dim3(kThreads), 0, s, full, Kx, Ly, Lz, scale,
+                     t64, t32);
+}
+
+// Surface boundaries: for each in-plane wavevector (kx, ky folded) the cell
+// average over z of the 1D Green's function, on the cyclic padded axis:
+//   k > 0 : (2 pi/k) exp(-k |z|)          k = 0 : 2 pi (Lz h - |z|)
+// buf[m][c], c = ky * Kx + kx, m in [0, Lz).
+__global__ void k_surface_gen(cplx<double>* __restrict__ buf, int Kx, int Lyh, int Lz, int nx,
+                              int ny, double h, double k0_offset) {
+  const long long nc = (long long)Kx * Lyh;
+  const long long n = nc * Lz;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(i % nc);
+    const int m = (int)(i / nc);
+    const int kx = c % Kx, ky = c / Kx;
+    const double gx = 2.0 * kPi * kx / (nx * h), gy = 2.0 * kPi * ky / (ny * h);
+    const double k = sqrt(gx * gx + gy * gy);
+    const int nz = Lz / 2;
+    const int am = m <= nz ? m : Lz - m;
+    double g;
+    if (k == 0.0) {
+      g = (am == 0 ? -2.0 * kPi * h / 4.0 : -2.0 * kPi * h * am) + k0_offset;
+    } else if (am == 0) {
+      g = 4.0 * kPi / (k * k * h) * (-expm1(-k * h / 2.0));
+    } else {
+      g = 2.0 * kPi / (k * k * h) * exp(-k * (am * h - h / 2.0)) * (-expm1(-k * h));
+    }
+    buf[i] = cmk(g, 0.0);
+  }
+}
+
+void launch_surface_gen(cplx<double>* buf, int Kx, int Lyh, int Lz, int nx, int ny, double h,
+                        double k0_offset, hipStream_t s) {
+  const long long n = (long long)Kx * Lyh * Lz;
+  const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
+  hipLaunchKernelGGL(k_surface_gen, dim3(grid), dim3(kThreads), 0, s, buf, Kx, Lyh, Lz, nx, ny, h,
+                     k0_offset);
+}
+
+// t[kz][ky][kx] = scale * Re buf[kz][ky * Kx + kx], kz <= Lz/2
+__global__ void k_surface_compress(const cplx<double>* __restrict__ buf, int Kx, int Lyh, int Lz,
+                                   double scale, double* __restrict__ t64,
+                                   float* __restrict__ t32) {
+  const long long nc = (long long)Kx * Lyh;
+  const long long n = nc * (Lz / 2 + 1);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = buf[i].x * scale;
+    t64[i] = v;
+    t32[i] = (float)v;
+  }
+}
+
+void launch_surface_compress(const cplx<double>* buf, int Kx, int Lyh, int Lz, double scale,
+                             double* t64, float* t32, hipStream_t s) {
+  const long long n = (long long)Kx * Lyh * (Lz / 2 + 1);
+  const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
+  hipLaunchKernelGGL(k_surface_compress, dim3(grid), dim3(kThreads), 0, s, buf, Kx, Lyh, Lz, scale,
+                     t64, t32);
+}
+
+// Periodic boundaries: 4 pi/|k|^2 (Green) or -|k|^2 (Laplacian), divided by
+// the number of points (the inverse transform is unnormalised).  k = 0 -> 0.
+__global__ void k_periodic_table(Geom g, int laplacian, double* __restrict__ t64,
+                                 float* __restrict__ t32) {
+  const int Lyh = g.Ly / 2 + 1, Lzh = g.Lz / 2 + 1;
+  const long long n = (long long)Lzh * Lyh * g.Kx;
+  const double norm = 1.0 / ((double)g.Lx * g.Ly * g.Lz);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int kx = (int)(i % g.Kx);
+    const int ky = (int)((i / g.Kx) % Lyh);
+    const int kz = (int)(i / ((long long)g.Kx * Lyh));
+    const double ax = 2.0 * kPi * kx / (g.Lx * g.h);
+    const double ay = 2.0 * kPi * ky / (g.Ly * g.h);
+    const double az = 2.0 * kPi * kz / (g.Lz * g.h);
+    const double k2 = ax * ax + ay * ay + az * az;
+    double v;
+    if (laplacian) v = -k2 * norm;
+    else v = k2 > 0.0 ? 4.0 * kPi / k2 * norm : 0.0;
+    t64[i] = v;
+    t32[i] = (float)v;
+  }
+}
+
+void launch_periodic_table(const Geom& g, int laplacian, double* t64, float* t32, hipStream_t s) {
+  const long long n = (long long)(g.Lz / 2 + 1) * (g.Ly / 2 + 1) * g.Kx;
+  const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
+  hipLaunchKernelGGL(k_periodic_table, dim3(grid), dim3(kThreads), 0, s, g, laplacian, t64, t32);
+}
+
+// ---------------------------------------------------------------------------
+// per-solve initialisation: sqrt(eps), 1/sqrt(eps), r0 = -4 pi rho, phi = 0
+// partials (4 per group): ||r0||^2, sum rho, sum |rho|, sum rho^2
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_init(const Slot<T>* __restrict__ slots, Batch b,
+                                                   const double* __restrict__ rho,
+                                                   const double* __restrict__ eps, long long n) {
+  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int err = 0;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) {
+      const double rv = rho[i], ev = eps[i];
+      if (!(ev > 0.0)) err |= kErrEpsNonPositive;
+      if (!isfinite(rv) || !isfinite(ev)) err |= kErrNonFinite;
+      const double sq = sqrt(ev);
+      sl.sq64[i] = sq;
+      sl.isq[i] = T(1.0 / sq);
+      if (sl.s) sl.s[i] = T(sq);
+      const T r0 = T(-kFourPi * rv);
+      sl.r[i] = r0;
+      sl.phi[i] = 0.0;
+      a0 += double(r0) * double(r0);
+      a1 += rv;
+      a2 += fabs(rv);
+      a3 += rv * rv;
+    }
+  }
+  if (err) atomicOr(&sl.st->err, err);
+  a0 = block_sum(a0);
+  a1 = block_sum(a1);
+  a2 = block_sum(a2);
+  a3 = block_sum(a3);
+  if (threadIdx.x == 0) {
+    double* pp = sl.part_init + (size_t)blockIdx.x * 4;
+    pp[0] = a0;
+    pp[1] = a1;
+    pp[2] = a2;
+    pp[3] = a3;
+  }
+}
+
+template <typename T>
+void launch_init(const Slot<T>* slots, const Batch& b, const double* rho, const double* eps,
+                 long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_init<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, rho,
+                     eps, n);
+}
+
+// ---------------------------------------------------------------------------
+// q + kappa2:  q = sqrt(eps) * lap_h sqrt(eps)  (Eq. corr), lap_h the order-2M
+// central difference (edge-replicated ghosts on free axes, wrapped on
+// periodic ones) or, when lap_sq is given, the spectral Laplacian computed by
+// the FFT passes.  kappa2 = kappa_coef * gamma (Eq. corrPB).
+// ---------------------------------------------------------------------------
+struct FdWeights { double c[9]; };
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_qfield(const Slot<T>* __restrict__ slots, Batch b,
+                                                     Geom g, int M, FdWeights w,
+                                                     const double* __restrict__ lap_sq,
+                                                     double kappa_coef,
+                                                     const double* __restrict__ eps,
+                                                     const double* __restrict__ gamma,
+                                                     double eps_bulk) {
+  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const long long n = (long long)g.nx * g.ny * g.nz;
+  const long long plane = (long long)g.nx * g.ny;
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  const double* __restrict__ sq = sl.sq64;
+  const double ih2 = 1.0 / (g.h * g.h);
+  double kacc = 0.0;   // sum kappa2 / eps (periodic k = 0 multiplier)
+#pragma unroll 1
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i >= n) break;
+    const int x = (int)(i % g.nx);
+    const int y = (int)((i / g.nx) % g.ny);
+    const int z = (int)(i / plane);
+    const double sc = sq[i];
+    double lap;
+    if (lap_sq) {
+      lap = lap_sq[i];
+    } else {
+      double acc = 3.0 * w.c[0] * sc;
+      const long long zo = (long long)z * plane, yo = (long long)y * g.nx;
+      for (int m = 1; m <= M; ++m) {
+        int xp = x + m, xm = x - m, yp = y + m, ym = y - m, zp = z + m, zm = z - m;
+        if (g.periodic_x) { xp %= g.nx; xm = ((xm % g.nx) + g.nx) % g.nx; }
+        else { xp = min(xp, g.nx - 1); xm = max(xm, 0); }
+        if (g.periodic_y) { yp %= g.ny; ym = ((ym % g.ny) + g.ny) % g.ny; }
+        else { yp = min(yp, g.ny - 1); ym = max(ym, 0); }
+        if (g.periodic_z) { zp %= g.nz; zm = ((zm % g.nz) + g.nz) % g.nz; }
+        else { zp = min(zp, g.nz - 1); zm = max(zm, 0); }
+        const double sxx = sq[zo + yo + xp] + sq[zo + yo + xm];
+        const double syy = sq[zo + (long long)yp * g.nx + x] + sq[zo + (long long)ym * g.nx + x];
+        const double szz = sq[(long long)zp * plane + yo + x] + sq[(long long)zm * plane + yo + x];
+        acc += w.c[m] * (sxx + syy + szz);
+      }
+      lap = acc * ih2;
+    }
+    double qv = sc * lap;
+    if (kappa_coef != 0.0) {
+      const double gm = gamma ? gamma[i] : (eps[i] - 1.0) / (eps_bulk - 1.0);
+      const double k2 = kappa_coef * gm;
+      qv += k2;
+      kacc += k2 / eps[i];
+    }
+    sl.qk[i] = T(qv);
+  }
+  kacc = block_sum(kacc);
+  if (threadIdx.x == 0) {
+    sl.part_aux[(size_t)blockIdx.x * 2] = kacc;
+    sl.part_aux[(size_t)blockIdx.x * 2 + 1] = 0.0;
+  }
+}
+
+static FdWeights fd_weights(int M) {
+  FdWeights w{};
+  double fM = 1.0;
+  for (int i = 2; i <= M; ++i) fM *= i;
+  double sum = 0.0;
+  for (int j = 1; j <= M; ++j) {
+    double fa = 1.0, fb = 1.0;
+    for (int i = 2; i <= M - j; ++i) fa *= i;
+    for (int i = 2; i <= M + j; ++i) fb *= i;
+    const double c = 2.0 * ((j + 1) % 2 == 0 ? 1.0 : -1.0) * fM * fM / (double(j) * j * fa * fb);
+    w.c[j] = c;
+    sum += c;
+  }
+  w.c[0] = -2.0 * sum;
+  return w;
+}
+
+template <typename T>
+void launch_qfield(const Slot<T>* slots, const Batch& b, const Geom& g, int fd_half,
+                   const double* lap_sq, double kappa_coef, const double* eps,
+                   const double* gamma, double eps_bulk, hipStream_t s) {
+  const long long n = (long long)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL((k_qfield<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, g,
+                     fd_half, fd_weights(fd_half), lap_sq, kappa_coef, eps, gamma, eps_bulk);
+}
+
+// ---------------------------------------------------------------------------
+// direction update (Algorithm PCG with Eq. corr):
+//   delta = (v, r) from the x-pass partials;  beta = delta / delta_prev
+//   A v = -(q + kappa2) v - 4 pi (r - sqrt(eps) mean(r/sqrt(eps)))  [periodic]
+//   p = v + beta p;  Ap = A v + beta Ap;  partial (p, Ap)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_direction(const Slot<T>* __restrict__ slots, Batch b,
+                                                        long long n, int n_xparts, int periodic) {
+  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const int k = b.k[blockIdx.y];
+  if (wg_read_flag(&sl.st->done)) return;
+  const double delta = sum_partials(sl.part_delta[0], n_xparts);
+  if (!(delta > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sl.st->status = isfinite(delta) ? GPS_E_BREAKDOWN : GPS_E_NONFINITE;
+      sl.st->iters = k;
+      sl.st->done = 1;
+    }
+    return;
+  }
+  double beta = 0.0;
+  if (k > 0) beta = delta / sl.hist[(size_t)(k - 1) * 4 + 0];
+  double mu = 0.0;
+  if (periodic) mu = sum_partials(sl.part_mu, n_xparts) / double(n);
+  const T tb = T(beta), tmu = T(mu), fpi = T(kFourPi);
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) {
+      const T v = sl.v[i], r = sl.r[i], q = sl.qk[i];
+      T rr = r;
+      if (periodic) rr = r - sl.s[i] * tmu;
+      const T av = -q * v - fpi * rr;
+      T pn, apn;
+      if (k == 0) {
+        pn = v;
+        apn = av;
+      } else {
+        pn = v + tb * sl.p[i];
+        apn = av + tb * sl.ap[i];
+      }
+      sl.p[i] = pn;
+      sl.ap[i] = apn;
+      acc += double(pn) * double(apn);
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) sl.part_pap[blockIdx.x] = acc;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && k < sl.hist_cap) {
+    sl.hist[(size_t)k * 4 + 0] = delta;
+    sl.hist[(size_t)k * 4 + 1] = beta;
+  }
+}
+
+template <typename T>
+void launch_direction(const Slot<T>* slots, const Batch& b, long long n, int n_xparts,
+                      int periodic, hipStream_t s) {
+  hipLaunchKernelGGL((k_direction<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, n,
+                     n_xparts, periodic);
+}
+
+// ---------------------------------------------------------------------------
+// solution update: alpha = delta/(p, Ap); phi += alpha p; r -= alpha Ap;
+// partial ||r||^2
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update(const Slot<T>* __restrict__ slots, Batch b,
+                                                     long long n) {
+  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const int k = b.k[blockIdx.y];
+  if (wg_read_flag(&sl.st->done)) return;
+  const int nparts = vec_groups(n);
+  const double pap = sum_partials(sl.part_pap, nparts);
+  if (!(pap < 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sl.st->status = isfinite(pap) ? GPS_E_BREAKDOWN : GPS_E_NONFINITE;
+      sl.st->iters = k;
+      sl.st->done = 1;
+    }
+    return;
+  }
+  const double delta = sl.hist[(size_t)k * 4 + 0];
+  const double alpha = delta / pap;
+  const T ta = T(alpha);
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) {
+      sl.phi[i] += alpha * double(sl.p[i]);
+      const T rn = sl.r[i] - ta * sl.ap[i];
+      sl.r[i] = rn;
+      acc += double(rn) * double(rn);
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) sl.part_rr[blockIdx.x] = acc;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && k < sl.hist_cap) sl.hist[(size_t)k * 4 + 2] = alpha;
+}
+
+template <typename T>
+void launch_update(const Slot<T>* slots, const Batch& b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_update<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, n);
+}
+
+// ---------------------------------------------------------------------------
+// ionic update of Algorithm SCPBimproved (Eqs. rhoions, ionsconcPB/MPB):
+//   new = gamma sum_i Z_i c_i e^{x_i} / D,  x_i = -Z_i phi / kT,
+//   D = 1 (Boltzmann) or 1 + sum_j a_j (e^{x_j} - 1) (steric), evaluated with
+//   numerator and denominator scaled by e^{-xm}, xm = max(0, max_j x_j);
+//   ion <- eta new + (1 - eta) ion;  r -= 4 pi (ion_new - ion_old), i.e. the
+//   next right-hand side r' + rho^ions_k - rho^ions_{k-1} in residual form.
+// partials (4 per group): ||r||^2, 0, 0, ||ion_new - ion_old||^2
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ion_update(const Slot<T>* __restrict__ slots,
+                                                         Batch b, long long n, IonParams ip) {
+  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  double a0 = 0.0, a3 = 0.0;
+  const T fpi = T(kFourPi);
+#pragma unroll 1
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i >= n) break;
+    const double phi = sl.phi[i];
+    const double gm = ip.gamma ? ip.gamma[i] : (ip.eps[i] - 1.0) / (ip.eps_bulk - 1.0);
+    double xs[4];
+    double xm = 0.0;
+    for (int sp = 0; sp < ip.nspecies; ++sp) {
+      xs[sp] = -ip.Z[sp] * phi / ip.kT;
+      xm = fmax(xm, xs[sp]);
+    }
+    double num = 0.0, fresh;
+    if (ip.steric) {
+      double den = 1.0;
+      double asum = 0.0;
+      den = 0.0;
+      for (int sp = 0; sp < ip.nspecies; ++sp) {
+        const double e = exp(xs[sp] - xm);
+        num += ip.Z[sp] * ip.c[sp] * e;
+        den += ip.a[sp] * e;
+        asum += ip.a[sp];
+      }
+      den += exp(-xm) * (1.0 - asum);
+      fresh = gm * num / den;
+    } else {
+      for (int sp = 0; sp < ip.nspecies; ++sp) num += ip.Z[sp] * ip.c[sp] * exp(xs[sp]);
+      fresh = gm * num;
+    }
+    const T old = sl.ion[i];
+    const T nw = T(ip.eta * fresh + (1.0 - ip.eta) * double(old));
+    sl.ion[i] = nw;
+    const T d = nw - old;
+    const T rn = sl.r[i] - fpi * d;
+    sl.r[i] = rn;
+    a0 += double(rn) * double(rn);
+    a3 += double(d) * double(d);
+  }
+  a0 = block_sum(a0);
+  a3 = block_sum(a3);
+  if (threadIdx.x == 0) {
+    double* pp = sl.part_init + (size_t)blockIdx.x * 4;
+    pp[0] = a0;
+    pp[1] = 0.0;
+    pp[2] = 0.0;
+    pp[3] = a3;
+  }
+}
+
+template <typename T>
+void launch_ion_update(const Slot<T>* slots, const Batch& b, long long n, const IonParams& ip,
+                       int, hipStream_t s) {
+  hipLaunchKernelGGL((k_ion_update<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b,
+                     n, ip);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_zero_ion(const Slot<T>* __restrict__ slots, Batch b,
+                                                       long long n) {
+  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) sl.ion[i] = T(0);
+  }
+}
+
+template <typename T>
+void launch_zero_ion(const Slot<T>* slots, const Batch& b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_zero_ion<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, n);
+}
+
+// ---------------------------------------------------------------------------
+// energy partials: sum rho phi (2 per group in part_aux: sum rho phi, 0)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_energy(const Slot<T>* __restrict__ slots, Batch b,
+                                                     const double* __restrict__ rho, long long n) {
+  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) acc += rho[i] * sl.phi[i];
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) {
+    sl.part_aux[(size_t)blockIdx.x * 2] = acc;
+    sl.part_aux[(size_t)blockIdx.x * 2 + 1] = 0.0;
+  }
+}
+
+template <typename T>
+void launch_energy(const Slot<T>* slots, const Batch& b, const double* rho, long long n,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((k_energy<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, rho, n);
+}
+
+#define GPS_INST(T)                                                                              \
+  template void launch_init<T>(const Slot<T>*, const Batch&, const double*, const double*,       \
+                               long long, hipStream_t);                                          \
+  template void launch_qfield<T>(const Slot<T>*, const Batch&, const Geom&, int, const double*,  \
+                                 double, const double*, const double*, double, hipStream_t);     \
+  template void launch_direction<T>(const Slot<T>*, const Batch&, long long, int, int,           \
+                                    hipStream_t);                                                \
+  template void launch_update<T>(const Slot<T>*, const Batch&, long long, hipStream_t);          \
+  template void launch_ion_update<T>(const Slot<T>*, const Batch&, long long, const IonParams&,  \
+                                     int, hipStream_t);                                          \
+  template void launch_zero_ion<T>(const Slot<T>*, const Batch&, long long, hipStream_t);        \
+  template void launch_energy<T>(const Slot<T>*, const Batch&, const double*, long long,         \
+                                 hipStream_t);
+GPS_INST(float)
+GPS_INST(double)
+#undef GPS_INST
+
+}  // namespace gps

@@ -1,0 +1,228 @@
+"""Thin ctypes binding of libgps (include/gps.h).
+
+Argument marshalling only: every step of a solve runs in the HIP kernels of
+libgps.so.  Functions keep the C names; `Plan` wraps a plan handle and
+accepts torch tensors (float64, on the GPU) whose device pointers it passes
+through.  Importing works without a GPU; loading the library fails loudly if
+it has not been built (there is no fallback path).
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgps.so")
+
+GPS_BC_FREE, GPS_BC_SURFACE, GPS_BC_PERIODIC = 0, 1, 2
+BC_CODES = {"free": GPS_BC_FREE, "surface": GPS_BC_SURFACE, "periodic": GPS_BC_PERIODIC}
+GPS_PREC_FP64, GPS_PREC_MIXED = 0, 1
+PRECISIONS = {"fp64": GPS_PREC_FP64, "mixed": GPS_PREC_MIXED}
+
+STATUS = {0: "GPS_OK", 1: "GPS_E_INVALID", 2: "GPS_E_NOMEM", 3: "GPS_E_NOT_CONVERGED",
+          4: "GPS_E_BREAKDOWN", 5: "GPS_E_NONFINITE", 6: "GPS_E_DEVICE", 7: "GPS_E_UNSUPPORTED"}
+GPS_OK, GPS_E_INVALID, GPS_E_NOMEM, GPS_E_NOT_CONVERGED = 0, 1, 2, 3
+GPS_E_BREAKDOWN, GPS_E_NONFINITE, GPS_E_DEVICE, GPS_E_UNSUPPORTED = 4, 5, 6, 7
+
+# every symbol include/gps.h declares
+EXPORTED = ("gps_plan_create", "gps_plan_set_options", "gps_plan_get_options",
+            "gps_plan_device_bytes", "gps_plan_destroy", "gps_solve_generalized",
+            "gps_solve_pb", "gps_solve_vacuum", "gps_last_info", "gps_last_history",
+            "gps_plan_set_timing", "gps_plan_timing", "gps_status_string")
+KERNEL_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "xinv": 5, "direction": 6,
+                "update": 7}
+
+
+class gps_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("fd_order", ctypes.c_int),
+                ("maxit", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class gps_ions(ctypes.Structure):
+    _fields_ = [("nspecies", ctypes.c_int), ("Z", ctypes.POINTER(ctypes.c_double)),
+                ("c_bulk", ctypes.POINTER(ctypes.c_double)),
+                ("c_max", ctypes.POINTER(ctypes.c_double)), ("kT", ctypes.c_double),
+                ("gamma", ctypes.c_void_p), ("eps_bulk", ctypes.c_double),
+                ("linear", ctypes.c_int), ("eta", ctypes.c_double),
+                ("outer_maxit", ctypes.c_int)]
+
+
+class gps_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("outer_iterations", ctypes.c_int), ("history_len", ctypes.c_int),
+                ("rnorm0", ctypes.c_double), ("rel_residual", ctypes.c_double),
+                ("energy", ctypes.c_double), ("outer_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libgps.so and declare the C signatures (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libgps.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    I = ctypes.c_int
+    lib.gps_plan_create.argtypes = [I, I, I, D, I, ctypes.POINTER(P)]
+    lib.gps_plan_create.restype = I
+    lib.gps_plan_set_options.argtypes = [P, ctypes.POINTER(gps_options)]
+    lib.gps_plan_set_options.restype = I
+    lib.gps_plan_get_options.argtypes = [P, ctypes.POINTER(gps_options)]
+    lib.gps_plan_get_options.restype = I
+    lib.gps_plan_device_bytes.argtypes = [P]
+    lib.gps_plan_device_bytes.restype = ctypes.c_size_t
+    lib.gps_plan_destroy.argtypes = [P]
+    lib.gps_plan_destroy.restype = None
+    lib.gps_solve_generalized.argtypes = [P, P, P, P, D]
+    lib.gps_solve_generalized.restype = I
+    lib.gps_solve_pb.argtypes = [P, P, P, ctypes.POINTER(gps_ions), P, D]
+    lib.gps_solve_pb.restype = I
+    lib.gps_solve_vacuum.argtypes = [P, P, P]
+    lib.gps_solve_vacuum.restype = I
+    lib.gps_last_info.argtypes = [P, ctypes.POINTER(gps_info)]
+    lib.gps_last_info.restype = I
+    lib.gps_last_history.argtypes = [P, ctypes.POINTER(D), I]
+    lib.gps_last_history.restype = I
+    lib.gps_plan_set_timing.argtypes = [P, I]
+    lib.gps_plan_set_timing.restype = I
+    lib.gps_plan_timing.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(D)]
+    lib.gps_plan_timing.restype = I
+    lib.gps_status_string.argtypes = [I]
+    lib.gps_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class GPSError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, STATUS.get(status, "?"), status))
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (float64, contiguous, on the GPU)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libgps takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libgps takes contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_field(t, shape):
+    import torch
+    if t.dtype != torch.float64 or tuple(t.shape) != tuple(shape):
+        raise ValueError("expected float64 tensor of shape %s, got %s %s"
+                         % (shape, t.dtype, tuple(t.shape)))
+
+
+def gps_plan_create(nx, ny, nz, h, bc):
+    lib = load()
+    out = ctypes.c_void_p()
+    st = lib.gps_plan_create(int(nx), int(ny), int(nz), float(h), int(bc), ctypes.byref(out))
+    return st, out
+
+
+def ions_struct(ions, gamma=None):
+    """gps_ions from a dict {Z, c_bulk, c_max, kT, eps_bulk, linear, eta, outer_maxit}."""
+    n = len(ions["Z"])
+    arr = ctypes.c_double * n
+    z = arr(*ions["Z"])
+    c = arr(*ions["c_bulk"])
+    cm = arr(*ions["c_max"]) if ions.get("c_max") is not None else None
+    s = gps_ions(n, z, c, cm, float(ions["kT"]), _ptr(gamma),
+                 float(ions.get("eps_bulk", 78.36)), int(bool(ions.get("linear", False))),
+                 float(ions.get("eta", 0.3)), int(ions.get("outer_maxit", 100)))
+    s._keep = (z, c, cm)     # keep the host arrays alive with the struct
+    return s
+
+
+class Plan:
+    """A libgps plan for one grid, spacing and boundary condition."""
+
+    def __init__(self, shape, h, bc, precision="fp64", fd_order=16, maxit=1000,
+                 check_every=8, stream=None):
+        nz, ny, nx = shape
+        self.shape = (nz, ny, nx)
+        self.h = float(h)
+        self.bc = bc
+        st, handle = gps_plan_create(nx, ny, nz, h, BC_CODES[bc])
+        if st != GPS_OK:
+            raise GPSError(st, "gps_plan_create(%d,%d,%d,%g,%s)" % (nx, ny, nz, h, bc))
+        self.handle = handle
+        self.set_options(precision, fd_order, maxit, check_every, stream)
+
+    def set_options(self, precision="fp64", fd_order=16, maxit=1000, check_every=8,
+                    stream=None):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        o = gps_options(PRECISIONS[precision], int(fd_order), int(maxit), int(check_every),
+                        ctypes.c_void_p(stream))
+        st = load().gps_plan_set_options(self.handle, ctypes.byref(o))
+        if st != GPS_OK:
+            raise GPSError(st, "gps_plan_set_options")
+
+    def device_bytes(self):
+        return int(load().gps_plan_device_bytes(self.handle))
+
+    def solve_generalized(self, rho, eps, phi, tol):
+        for t in (rho, eps, phi):
+            _check_field(t, self.shape)
+        return load().gps_solve_generalized(self.handle, _ptr(rho), _ptr(eps), _ptr(phi),
+                                            float(tol))
+
+    def solve_pb(self, rho, eps, ions, phi, tol, gamma=None):
+        for t in (rho, eps, phi):
+            _check_field(t, self.shape)
+        s = ions_struct(ions, gamma)
+        return load().gps_solve_pb(self.handle, _ptr(rho), _ptr(eps), ctypes.byref(s),
+                                   _ptr(phi), float(tol))
+
+    def solve_vacuum(self, f, u):
+        for t in (f, u):
+            _check_field(t, self.shape)
+        return load().gps_solve_vacuum(self.handle, _ptr(f), _ptr(u))
+
+    def info(self):
+        out = gps_info()
+        load().gps_last_info(self.handle, ctypes.byref(out))
+        return out.as_dict()
+
+    def history(self):
+        n = self.info()["history_len"]
+        buf = (ctypes.c_double * (4 * max(n, 1)))()
+        load().gps_last_history(self.handle, buf, n)
+        return [tuple(buf[4 * k: 4 * k + 4]) for k in range(n)]
+
+    def set_timing(self, kind):
+        """Time every launch of one pass ("zconv", ...; None switches off)."""
+        code = 0 if kind is None else KERNEL_KINDS[kind]
+        st = load().gps_plan_set_timing(self.handle, code)
+        if st != GPS_OK:
+            raise GPSError(st, "gps_plan_set_timing")
+
+    def timing(self):
+        ms, n, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+        load().gps_plan_timing(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b))
+        return {"total_ms": ms.value, "launches": n.value, "bytes_per_launch": b.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().gps_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,91 @@
+"""Error paths of the C ABI on the GPU, each forced from the host."""
+import numpy as np
+import pytest
+
+from paper_1509_00680_amd import workloads as W
+from paper_1509_00680_amd import gps
+from gpu_util import dev, host, empty, plan, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _prob():
+    return W.molecule(16, 0.5, seed=3, n_atoms=4, ball=2.0)
+
+
+def test_invalid_plan_arguments():
+    require_gpu()
+    for args in [(1, 8, 8, 0.5, 0), (8, 8, 8, 0.0, 0), (8, 8, 8, 0.5, 3), (8, 8, 8, float("nan"), 0)]:
+        st, h = gps.gps_plan_create(*args)
+        assert st == gps.GPS_E_INVALID and not h.value
+
+
+def test_unsupported_length():
+    require_gpu()
+    st, h = gps.gps_plan_create(11, 8, 8, 0.5, 0)   # 22 = 2 * 11
+    assert st == gps.GPS_E_UNSUPPORTED
+
+
+def test_nonpositive_eps_rejected():
+    require_gpu()
+    prob = _prob()
+    eps = prob.eps.copy()
+    eps[3, 4, 5] = 0.0
+    p = plan(prob.shape, prob.h, "free")
+    assert p.solve_generalized(dev(prob.rho), dev(eps), empty(prob.shape), 1e-8) == gps.GPS_E_INVALID
+
+
+def test_nan_rejected():
+    require_gpu()
+    prob = _prob()
+    rho = prob.rho.copy()
+    rho[1, 2, 3] = np.nan
+    p = plan(prob.shape, prob.h, "free")
+    assert p.solve_generalized(dev(rho), dev(prob.eps), empty(prob.shape), 1e-8) == gps.GPS_E_NONFINITE
+
+
+def test_maxit_reported():
+    require_gpu()
+    prob = _prob()
+    p = plan(prob.shape, prob.h, "free", maxit=2)
+    phi = empty(prob.shape)
+    assert p.solve_generalized(dev(prob.rho), dev(prob.eps), phi, 1e-12) == gps.GPS_E_NOT_CONVERGED
+    assert p.info()["iterations"] == 2
+    assert np.isfinite(host(phi)).all()
+
+
+def test_non_neutral_periodic_rejected():
+    require_gpu()
+    prob = W.molecule(16, 0.5, seed=3, n_atoms=4, ball=2.0, bc="periodic", net_charge=1.0)
+    p = plan(prob.shape, prob.h, "periodic")
+    assert p.solve_generalized(dev(prob.rho), dev(prob.eps), empty(prob.shape), 1e-8) == gps.GPS_E_INVALID
+
+
+def test_zero_charge():
+    require_gpu()
+    prob = _prob()
+    p = plan(prob.shape, prob.h, "free")
+    phi = dev(np.full(prob.shape, 7.0))
+    assert p.solve_generalized(dev(np.zeros(prob.shape)), dev(prob.eps), phi, 1e-8) == gps.GPS_OK
+    assert p.info()["iterations"] == 0 and not host(phi).any()
+
+
+def test_bad_electrolyte():
+    require_gpu()
+    prob = _prob()
+    p = plan(prob.shape, prob.h, "free")
+    ions = W.electrolyte_1to1(1e-4)
+    ions["kT"] = 0.0
+    assert p.solve_pb(dev(prob.rho), dev(prob.eps), ions, empty(prob.shape), 1e-6) == gps.GPS_E_INVALID
+
+
+def test_deterministic_bitwise():
+    require_gpu()
+    prob = _prob()
+    out = []
+    for _ in range(2):
+        p = plan(prob.shape, prob.h, "free", "mixed")
+        phi = empty(prob.shape)
+        assert p.solve_generalized(dev(prob.rho), dev(prob.eps), phi, 1e-6) == gps.GPS_OK
+        out.append(host(phi))
+    assert np.array_equal(out[0], out[1])
