@@ -21,20 +21,20 @@ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return cmk(a.x * s, 
 
 // Sum of v over the work-group, identical in every thread.  Fixed reduction
 // tree (wavefront butterfly, then waves in index order): the result depends
-// only on the inputs, never on timing.
+// only on the inputs, never on timing.  Any block size up to 1024 threads.
 __device__ __forceinline__ double block_sum(double v) {
-  __shared__ double wsum[kThreads / 64];
+  __shared__ double wsum[16];
   __shared__ double total;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  const int nwaves = (blockDim.x + 63) >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   if (lane == 0) wsum[wave] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) s += wsum[w];
+    for (int w = 0; w < nwaves; ++w) s += wsum[w];
     total = s;
   }
   __syncthreads();
@@ -47,7 +47,7 @@ __device__ __forceinline__ double block_sum(double v) {
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n,
                                                int stride = 1) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kThreads) s += part[(size_t)i * stride];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[(size_t)i * stride];
   return block_sum(s);
 }
 

@@ -12,9 +12,8 @@
 //   y pass   strided C2C, in place in the work buffer.
 //   z pass   strided C2C forward, multiply by the real even Green's
 //            spectrum, C2C inverse, all in one pass through LDS.
-#include "gps_device.h"
+#include "gps_iter.h"
 #include "gps_launch.h"
-#include "gps.h"
 
 namespace gps {
 
@@ -192,51 +191,6 @@ __device__ double cell_inverse_distance(int mx, int my, int mz) {
   const double r12 = r4 * r4 * r4;
   const double t6 = (2.0 * s6 - 15.0 * p42 + 180.0 * x2 * y2 * z2) / 1344.0 / (r12 * r);
   return 1.0 / r + t4 + t6;
-}
-
-// ---------------------------------------------------------------------------
-// iteration head: convergence decision at the start of PCG iteration k
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ bool iteration_head(const Slot<T>& sl, int k, int n_vec_parts, int check_neutral) {
-  if (wg_read_flag(&sl.st->done)) return false;
-  double rr, thr2 = 0.0, rsum = 0.0, rabs = 0.0;
-  int status = -1;
-  if (k == 0) {
-    rr = sum_partials(sl.part_init + 0, n_vec_parts, 4);
-    rsum = sum_partials(sl.part_init + 1, n_vec_parts, 4);
-    rabs = sum_partials(sl.part_init + 2, n_vec_parts, 4);
-    const int err = wg_read_flag(&sl.st->err);
-    thr2 = fmax(sl.abs_thr * sl.abs_thr, sl.rel_thr * sl.rel_thr * rr);
-    if (err & kErrNonFinite) status = GPS_E_NONFINITE;
-    else if (err & kErrEpsNonPositive) status = GPS_E_INVALID;
-    else if (check_neutral && fabs(rsum) > 1e-10 * rabs) status = GPS_E_INVALID;
-  } else {
-    rr = sum_partials(sl.part_rr, n_vec_parts);
-    thr2 = *reinterpret_cast<const volatile double*>(&sl.st->thr2);
-  }
-  if (status < 0) {
-    if (!isfinite(rr)) status = GPS_E_NONFINITE;
-    else if (rr <= thr2) status = GPS_OK;
-    else if (k >= sl.maxit) status = GPS_E_NOT_CONVERGED;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (k == 0) {
-      sl.st->rr0 = rr;
-      sl.st->thr2 = thr2;
-      sl.st->rho_sum = rsum;
-      sl.st->rho_abs = rabs;
-    } else if (k - 1 < sl.hist_cap) {
-      sl.hist[(size_t)(k - 1) * 4 + 3] = rr;
-    }
-    sl.st->iters = k;
-    sl.st->rr = rr;
-    if (status >= 0) {
-      sl.st->status = status;
-      sl.st->done = 1;
-    }
-  }
-  return status < 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -470,13 +424,21 @@ __global__ __launch_bounds__(kThreads) void k_strided(SParams<T> p) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T> int xpass_groups(const XParams<T>& p) {
+// Work-groups of the generic x passes (also the count of their partials).
+template <typename T> static int generic_xpass_groups(const XParams<T>& p) {
   const int npairs = (p.nrows + 1) / 2;
   return (npairs + p.P - 1) / p.P;
 }
 
+// Work-groups (= partial sums) of the solve-mode x passes, whichever family runs.
+template <typename T> int xpass_groups(const XParams<T>& p) {
+  if (fast_length(p.g.Lx)) return fast_xpass_groups(p.nrows);
+  return generic_xpass_groups(p);
+}
+
 template <typename T> void launch_xfwd(int mode, const XParams<T>& p, hipStream_t s) {
-  const dim3 grid(xpass_groups(p), p.slots ? p.batch.n : 1);
+  if (mode != XF_GEN_FREE && fast_length(p.g.Lx) && fast_xfwd<T>(mode, p, s)) return;
+  const dim3 grid(generic_xpass_groups(p), p.slots ? p.batch.n : 1);
   const size_t lds = (size_t)p.P * p.g.Lx * sizeof(cplx<T>);
   if (mode == XF_SOLVE) hipLaunchKernelGGL((k_xfwd<T, XF_SOLVE>), grid, dim3(kThreads), lds, s, p);
   else if (mode == XF_REAL) hipLaunchKernelGGL((k_xfwd<T, XF_REAL>), grid, dim3(kThreads), lds, s, p);
@@ -484,13 +446,15 @@ template <typename T> void launch_xfwd(int mode, const XParams<T>& p, hipStream_
 }
 
 template <typename T> void launch_xinv(int mode, const XParams<T>& p, hipStream_t s) {
-  const dim3 grid(xpass_groups(p), p.slots ? p.batch.n : 1);
+  if (fast_length(p.g.Lx) && fast_xinv<T>(mode, p, s)) return;
+  const dim3 grid(generic_xpass_groups(p), p.slots ? p.batch.n : 1);
   const size_t lds = (size_t)p.P * p.g.Lx * sizeof(cplx<T>);
   if (mode == XI_SOLVE) hipLaunchKernelGGL((k_xinv<T, XI_SOLVE>), grid, dim3(kThreads), lds, s, p);
   else hipLaunchKernelGGL((k_xinv<T, XI_REAL>), grid, dim3(kThreads), lds, s, p);
 }
 
 template <typename T> void launch_strided(int mode, const SParams<T>& p, hipStream_t s) {
+  if (fast_length(p.L) && fast_strided<T>(mode, p, s)) return;
   const dim3 grid((p.npencils + p.B - 1) / p.B, p.work ? 1 : p.batch.n);
   const size_t lds = (size_t)p.B * p.L * sizeof(cplx<T>);
   if (mode == ST_FWD) hipLaunchKernelGGL((k_strided<T, ST_FWD>), grid, dim3(kThreads), lds, s, p);

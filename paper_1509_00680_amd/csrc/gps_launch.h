@@ -60,6 +60,13 @@ template <typename T> struct SParams {
 };
 template <typename T> void launch_strided(int mode, const SParams<T>& p, hipStream_t s);
 
+// Two-level passes for the common lengths (32 ... 384); false if L has none.
+bool fast_length(int L);
+int fast_xpass_groups(int nrows);
+template <typename T> bool fast_strided(int mode, const SParams<T>& p, hipStream_t s);
+template <typename T> bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s);
+template <typename T> bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s);
+
 // ---- plan-time tables -------------------------------------------------------
 void launch_compress_table(const cplx<double>* full, int Kx, int Ly, int Lz, double scale,
                            double* t64, float* t32, hipStream_t s);
