@@ -71,7 +71,8 @@ typedef struct {
   int precision;     /* gps_precision, default GPS_PREC_FP64 */
   int fd_order;      /* even order of the central differences of q (2..16), default 16 */
   int maxit;         /* PCG iteration cap, default 1000 */
-  int check_every;   /* iterations enqueued between host convergence polls, default 8 */
+  int check_every;   /* PCG iterations per replayed graph (the finest host poll
+                        granularity), default 4 */
   void *stream;      /* hipStream_t the solves run on; NULL = null stream */
 } gps_options;
 
@@ -169,17 +170,20 @@ gps_status gps_last_history(const gps_plan *plan, double *out, int max_entries);
  * the PCG iteration; while it is set, every solve brackets each launch of
  * that pass with HIP events on the plan's stream and accumulates the elapsed
  * time of the launches that did work (iterations before the stop decision).
+ * Untimed solves replay the iterations as captured HIP graphs; timed solves
+ * launch the same kernels one by one (events inside a graph are not
+ * readable), so a timed solve is slower end to end than an untimed one.
  * GPS_K_NONE switches timing off.  Setting a kind clears the totals.
  * Errors: GPS_E_INVALID (null plan, unknown kind). */
 typedef enum {
   GPS_K_NONE = 0,
-  GPS_K_XFWD = 1,       /* x pass: r/sqrt(eps), pairwise real-to-complex */
+  GPS_K_XFWD = 1,       /* x pass: phi, r update of the previous iteration, r/sqrt(eps),
+                           pairwise real-to-complex */
   GPS_K_YFWD = 2,       /* y pass, forward */
   GPS_K_ZCONV = 3,      /* z pass: forward, times the Green's spectrum, inverse */
   GPS_K_YINV = 4,       /* y pass, inverse */
-  GPS_K_XINV = 5,       /* x pass: complex-to-real, v = u/sqrt(eps), (v, r) */
-  GPS_K_DIRECTION = 6,  /* p, Ap update and (p, Ap) */
-  GPS_K_UPDATE = 7      /* phi, r update and ||r||^2 */
+  GPS_K_XINV = 5,       /* x pass: complex-to-real, v = u/sqrt(eps), (v, r), ||r||^2 */
+  GPS_K_DIRECTION = 6   /* stop decision, p, Ap update and (p, Ap) */
 } gps_kernel_kind;
 gps_status gps_plan_set_timing(gps_plan *plan, int kind);
 

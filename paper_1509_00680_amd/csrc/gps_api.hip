@@ -21,6 +21,11 @@ using namespace gps;
 
 namespace {
 
+struct TimedLaunch {
+  int k;
+  hipEvent_t start, stop;
+};
+
 struct DevError {
   hipError_t e;
 };
@@ -88,14 +93,14 @@ template <typename T> struct Res {
   int hist_cap = 0;
   double* lap64 = nullptr;         // periodic spectral Laplacian of sqrt(eps)
   cplx<double>* work64q = nullptr; // FP64 work for the spectral q (mixed + periodic)
+  // graph of `chunk` PCG iterations (kernel arguments are replay-invariant:
+  // the iteration counter lives in the solve state)
+  hipGraphExec_t graph = nullptr;
+  int graph_neutral = -1, graph_timing = -1, graph_chunk = 0;
 };
 
 }  // namespace
 
-struct TimedLaunch {
-  int k;
-  hipEvent_t start, stop;
-};
 
 struct gps_plan {
   int device = 0;
@@ -107,6 +112,7 @@ struct gps_plan {
   std::vector<hipEvent_t> ev_pool;
   std::vector<TimedLaunch> ev_pending;
   size_t ev_used = 0;
+  hipStream_t cap_stream = nullptr;   // side stream used only to capture graphs
   Geom g{};
   int bc = 0;
   gps_options opt{};
@@ -273,7 +279,7 @@ void ensure_res(gps_plan* pl, bool need_ion) {
     dalloc(&s.sq64, (size_t)n * sizeof(double), &pl->bytes);
     dalloc(&s.work, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<T>), &pl->bytes);
     dalloc(&s.part_init, (size_t)4 * nvg * sizeof(double), &pl->bytes);
-    dalloc(&s.part_rr, (size_t)nvg * sizeof(double), &pl->bytes);
+    dalloc(&s.part_rr, (size_t)std::max(nvg, nxg) * sizeof(double), &pl->bytes);
     dalloc(&s.part_delta[0], (size_t)nxg * sizeof(double), &pl->bytes);
     s.part_delta[1] = s.part_delta[0];
     dalloc(&s.part_pap, (size_t)nvg * sizeof(double), &pl->bytes);
@@ -306,6 +312,7 @@ void ensure_res(gps_plan* pl, bool need_ion) {
 template <typename T>
 void free_res(gps_plan* pl) {
   Res<T>& R = pl->res<T>();
+  if (R.graph) (void)hipGraphExecDestroy(R.graph);
   Slot<T>& s = R.slot;
   dfree(s.r); dfree(s.v); dfree(s.p); dfree(s.ap); dfree(s.isq); dfree(s.qk); dfree(s.s);
   dfree(s.ion); dfree(s.sq64); dfree(s.work); dfree(s.part_init); dfree(s.part_rr);
@@ -355,38 +362,42 @@ hipEvent_t next_event(gps_plan* pl) {
   return pl->ev_pool[pl->ev_used++];
 }
 
+// Brackets one launch with two events on stream s (inside a graph capture
+// the records become graph nodes).
 struct TimerScope {
   gps_plan* pl;
+  hipStream_t s;
   bool on;
   TimedLaunch tl{};
-  TimerScope(gps_plan* p, int kind, int k) : pl(p), on(p->timing_kind == kind) {
+  TimerScope(gps_plan* p, hipStream_t st, int kind, int k)
+      : pl(p), s(st), on(p->timing_kind == kind) {
     if (on) {
       tl.k = k;
       tl.start = next_event(pl);
       tl.stop = next_event(pl);
-      ck(hipEventRecord(tl.start, pl->stream()));
+      ck(hipEventRecord(tl.start, s));
     }
   }
   ~TimerScope() {
     if (on) {
-      (void)hipEventRecord(tl.stop, pl->stream());
+      (void)hipEventRecord(tl.stop, s);
       pl->ev_pending.push_back(tl);
     }
   }
 };
 
-// After a host sync: add the launches of iterations that did work.
-void collect_timing(gps_plan* pl, int iters_done) {
-  for (const TimedLaunch& t : pl->ev_pending) {
-    if (t.k < iters_done) {
+// After a host sync: add the timed launches of iterations k_base + t.k that
+// did work (k < iters_done).
+void collect_timing(gps_plan* pl, const std::vector<TimedLaunch>& ev, int k_base,
+                    int iters_done) {
+  for (const TimedLaunch& t : ev) {
+    if (k_base + t.k < iters_done) {
       float ms = 0.f;
       ck(hipEventElapsedTime(&ms, t.start, t.stop));
       pl->timing_ms += ms;
       pl->timing_launches += 1;
     }
   }
-  pl->ev_pending.clear();
-  pl->ev_used = 0;
 }
 
 // Algorithmic bytes of one launch of pass `kind` (inputs read once, outputs
@@ -400,13 +411,12 @@ double pass_bytes(const gps_plan* pl, int kind, size_t s) {
   const double tab = (double)(g.Lz / 2 + 1) * (g.Ly / 2 + 1) * g.Kx;
   const int periodic = pl->bc == GPS_BC_PERIODIC;
   switch (kind) {
-    case GPS_K_XFWD: return 2.0 * n * s + rows * g.Kx * c;
+    case GPS_K_XFWD: return (5.0 * s + 16.0) * n + rows * g.Kx * c;   // with the fused update
     case GPS_K_YFWD: return (double)g.nz * g.Kx * g.ny * c + wbox * c;
     case GPS_K_ZCONV: return 2.0 * wbox * c + tab * s;
     case GPS_K_YINV: return wbox * c + (double)g.nz * g.Kx * g.ny * c;
     case GPS_K_XINV: return rows * g.Kx * c + 3.0 * n * s;
     case GPS_K_DIRECTION: return (7.0 + periodic) * n * s;
-    case GPS_K_UPDATE: return 4.0 * n * s + 16.0 * n;
     default: return 0.0;
   }
 }
@@ -415,9 +425,9 @@ double pass_bytes(const gps_plan* pl, int kind, size_t s) {
 // one PCG iteration for the problems of a batch (all of one plan)
 // ---------------------------------------------------------------------------
 template <typename T>
-void enqueue_iteration(gps_plan* pl, const Slot<T>* d_slots, const Batch& b, int check_neutral) {
+void enqueue_iteration(gps_plan* pl, const Slot<T>* d_slots, const Batch& b, int check_neutral,
+                       hipStream_t s, int k0) {
   const Geom& g = pl->g;
-  hipStream_t s = pl->stream();
   const long long n = pl->npts();
   const int periodic = pl->bc == GPS_BC_PERIODIC;
   XParams<T> xp = xparams<T>(pl, g.ny * g.nz, g.ny, g.nx, g.nx, (long long)g.Ly * g.Kx, g.nx);
@@ -425,30 +435,27 @@ void enqueue_iteration(gps_plan* pl, const Slot<T>* d_slots, const Batch& b, int
   xp.batch = b;
   xp.n_vec_parts = vec_groups(n);
   xp.periodic_mean = periodic;
-  xp.check_neutral = check_neutral;
-  const int k0 = b.k[0];
-  { TimerScope t(pl, GPS_K_XFWD, k0); launch_xfwd<T>(XF_SOLVE, xp, s); }
+  { TimerScope t(pl, s, GPS_K_XFWD, k0); launch_xfwd<T>(XF_SOLVE, xp, s); }
   SParams<T> yf = sparams<T>(pl, 1, g.Ly, g.ny, g.Ly, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
                              g.Kx);
   yf.slots = d_slots;
   yf.batch = b;
-  { TimerScope t(pl, GPS_K_YFWD, k0); launch_strided<T>(ST_FWD, yf, s); }
+  { TimerScope t(pl, s, GPS_K_YFWD, k0); launch_strided<T>(ST_FWD, yf, s); }
   SParams<T> zc = sparams<T>(pl, 2, g.Lz, g.nz, g.nz, g.Ly * g.Kx, g.Ly * g.Kx, 0,
                              (long long)g.Ly * g.Kx);
   zc.slots = d_slots;
   zc.batch = b;
   zc.table = pl->green<T>();
   zc.k0_from_slot = periodic;
-  { TimerScope t(pl, GPS_K_ZCONV, k0); launch_strided<T>(ST_CONV, zc, s); }
+  { TimerScope t(pl, s, GPS_K_ZCONV, k0); launch_strided<T>(ST_CONV, zc, s); }
   SParams<T> yi = sparams<T>(pl, 1, g.Ly, g.Ly, g.ny, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
                              g.Kx);
   yi.slots = d_slots;
   yi.batch = b;
-  { TimerScope t(pl, GPS_K_YINV, k0); launch_strided<T>(ST_INV, yi, s); }
-  { TimerScope t(pl, GPS_K_XINV, k0); launch_xinv<T>(0 /*XI_SOLVE*/, xp, s); }
-  { TimerScope t(pl, GPS_K_DIRECTION, k0);
-    launch_direction<T>(d_slots, b, n, xpass_groups(xp), periodic, s); }
-  { TimerScope t(pl, GPS_K_UPDATE, k0); launch_update<T>(d_slots, b, n, s); }
+  { TimerScope t(pl, s, GPS_K_YINV, k0); launch_strided<T>(ST_INV, yi, s); }
+  { TimerScope t(pl, s, GPS_K_XINV, k0); launch_xinv<T>(0 /*XI_SOLVE*/, xp, s); }
+  { TimerScope t(pl, s, GPS_K_DIRECTION, k0);
+    launch_direction<T>(d_slots, b, n, xpass_groups(xp), periodic, check_neutral, s); }
 }
 
 // Spectral Laplacian of sqrt(eps) (periodic q) with the FP64 FFT passes.
@@ -511,27 +518,85 @@ void vacuum_apply(gps_plan* pl, const double* f, double* u) {
   ck(hipStreamSynchronize(s));
 }
 
-// Run PCG iterations until the device-side state says done.
+// Capture `chunk` PCG iterations as one graph (rebuilt when the variant
+// changes: neutrality check, timed pass).
 template <typename T>
-SolveState run_pcg(gps_plan* pl, int check_neutral) {
+void build_graph(gps_plan* pl, int check_neutral, int chunk) {
   Res<T>& R = pl->res<T>();
+  if (R.graph && R.graph_neutral == check_neutral && R.graph_timing == pl->timing_kind &&
+      R.graph_chunk == chunk)
+    return;
+  if (R.graph) {
+    (void)hipGraphExecDestroy(R.graph);
+    R.graph = nullptr;
+  }
+  if (!pl->cap_stream) ck(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
   Batch b{};
   b.n = 1;
   b.slot[0] = 0;
-  int k = 0;
+  pl->ev_pending.clear();
+  ck(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int j = 0; j < chunk; ++j) enqueue_iteration<T>(pl, R.d_slot, b, check_neutral,
+                                                       pl->cap_stream, j);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
+  if (e != hipSuccess) throw DevError{e};
+  const hipError_t e2 = hipGraphInstantiate(&R.graph, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) throw DevError{e2};
+  R.graph_neutral = check_neutral;
+  R.graph_timing = pl->timing_kind;
+  R.graph_chunk = chunk;
+}
+
+// Run PCG iterations until the device-side state says done: replay the
+// iteration graph m times between host polls, m predicted from the recent
+// residual decay so that few replays run past convergence.
+template <typename T>
+SolveState run_pcg(gps_plan* pl, int check_neutral) {
+  Res<T>& R = pl->res<T>();
+  const int chunk = pl->opt.check_every;
+  // Timing needs readable events around single launches; events recorded
+  // inside a captured graph cannot be read back, so timed solves launch
+  // the same kernels directly on the stream.
+  const bool timing = pl->timing_kind != GPS_K_NONE;
+  if (!timing) build_graph<T>(pl, check_neutral, chunk);
+  Batch b{};
+  b.n = 1;
+  b.slot[0] = 0;
+  int k = 0;            // iterations enqueued
+  int m = 2;            // chunks before the next poll
+  double prev_rr = -1.0;
+  int prev_it = 0;
   SolveState st{};
   for (;;) {
-    for (int j = 0; j < pl->opt.check_every; ++j) {
-      b.k[0] = k++;
-      enqueue_iteration<T>(pl, R.d_slot, b, check_neutral);
+    if (timing) {
+      pl->ev_pending.clear();
+      pl->ev_used = 0;
+      for (int j = 0; j < m * chunk; ++j)
+        enqueue_iteration<T>(pl, R.d_slot, b, check_neutral, pl->stream(), j);
+      ck(hipGetLastError());
+    } else {
+      for (int r = 0; r < m; ++r) ck(hipGraphLaunch(R.graph, pl->stream()));
     }
-    ck(hipGetLastError());
+    const int k_base = k;
+    k += m * chunk;
     st = read_state<T>(pl);
-    if (pl->timing_kind != GPS_K_NONE) {
-      collect_timing(pl, st.done ? st.iters : k);
+    if (timing) {
+      collect_timing(pl, pl->ev_pending, k_base, st.done ? st.iters : k);
       pl->timing_bytes = pass_bytes(pl, pl->timing_kind, sizeof(T));
     }
     if (st.done || k > pl->opt.maxit + 1) break;
+    // predicted iterations left: log-linear extrapolation of ||r||^2
+    m = 2;
+    if (prev_rr > 0.0 && st.rr > 0.0 && st.iters > prev_it && st.rr < prev_rr) {
+      const double rate = std::log(st.rr / prev_rr) / double(st.iters - prev_it);
+      const double left = std::log(st.thr2 / st.rr) / rate;
+      m = (int)std::ceil(std::max(1.0, left) / chunk);
+      m = std::max(1, std::min(m, 8));
+    }
+    prev_rr = st.rr;
+    prev_it = st.iters;
   }
   return st;
 }
@@ -539,7 +604,9 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
 template <typename T>
 void reset_state(gps_plan* pl) {
   Res<T>& R = pl->res<T>();
-  ck(hipMemsetAsync(R.slot.st, 0, sizeof(SolveState), pl->stream()));
+  Batch b{};
+  b.n = 1;
+  launch_reset_state<T>(R.d_slot, b, pl->stream());
 }
 
 template <typename T>
@@ -681,6 +748,8 @@ static void plan_release(gps_plan* pl) {
   if (!pl) return;
   for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
   pl->ev_pool.clear();
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  pl->cap_stream = nullptr;
   free_res<float>(pl);
   free_res<double>(pl);
   for (int a = 0; a < 3; ++a) {
@@ -704,7 +773,7 @@ gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan** 
   pl->opt.precision = GPS_PREC_FP64;
   pl->opt.fd_order = 16;
   pl->opt.maxit = 1000;
-  pl->opt.check_every = 8;
+  pl->opt.check_every = 4;
   pl->opt.stream = nullptr;
   Geom& g = pl->g;
   g.nx = nx;
@@ -852,12 +921,17 @@ gps_status gps_solve_vacuum(gps_plan* pl, const double* f, double* u) {
 }
 
 gps_status gps_plan_set_timing(gps_plan* pl, int kind) {
-  if (!pl || kind < GPS_K_NONE || kind > GPS_K_UPDATE) return GPS_E_INVALID;
+  if (!pl || kind < GPS_K_NONE || kind > GPS_K_DIRECTION) return GPS_E_INVALID;
   pl->timing_kind = kind;
   pl->timing_ms = 0.0;
   pl->timing_launches = 0;
   pl->timing_bytes = 0.0;
   pl->ev_pending.clear();
+  // graphs record into pooled events: rebuild them with the new timing
+  if (pl->r32.graph) (void)hipGraphExecDestroy(pl->r32.graph);
+  if (pl->r64.graph) (void)hipGraphExecDestroy(pl->r64.graph);
+  pl->r32.graph = nullptr;
+  pl->r64.graph = nullptr;
   pl->ev_used = 0;
   return GPS_OK;
 }

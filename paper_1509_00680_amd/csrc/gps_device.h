@@ -51,6 +51,17 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
   return block_sum(s);
 }
 
+// Tile processed by work-group `bid` of a G-group launch.  Work-groups are
+// dealt round-robin to the 8 XCDs (each with its own L2); this bijection
+// gives every XCD a contiguous range of tiles, so tiles that share cache
+// lines (neighbouring pencils, rows of one plane) meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int G) {
+  constexpr int X = 8;
+  const int q = G / X, r = G % X;
+  const int xcd = bid % X, local = bid / X;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
 // One work-group-uniform flag broadcast from thread 0.
 __device__ __forceinline__ int wg_read_flag(const int* p) {
   __shared__ int f;

@@ -204,14 +204,14 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(XParams<T> p) {
   const int Lx = p.g.Lx, Kx = p.g.Kx, P = p.P, lgP = p.lgP, Lin = p.Lin;
   const int pair0 = blockIdx.x * P;
   cplx<T>* work = p.work;
-  const T* rin = nullptr;
-  const T* isq = nullptr;
   Slot<T> sl;
+  double alpha = 0.0;
+  bool upd = false;
   if constexpr (MODE == XF_SOLVE) {
     sl = p.slots[p.batch.slot[blockIdx.y]];
-    if (!iteration_head(sl, p.batch.k[blockIdx.y], p.n_vec_parts, p.check_neutral)) return;
-    rin = sl.r;
-    isq = sl.isq;
+    int k;
+    if (!xfwd_head(sl, p.n_vec_parts, &k, &alpha)) return;
+    upd = k > 0;
     work = sl.work;
   }
   double mu = 0.0;
@@ -221,14 +221,8 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(XParams<T> p) {
     const int ra = 2 * (pair0 + pp), rb = ra + 1;
     T a = T(0), b = T(0);
     if constexpr (MODE == XF_SOLVE) {
-      if (ra < p.nrows) {
-        const size_t o = (size_t)ra * p.in_row_stride + x;
-        a = rin[o] * isq[o];
-      }
-      if (rb < p.nrows) {
-        const size_t o = (size_t)rb * p.in_row_stride + x;
-        b = rin[o] * isq[o];
-      }
+      if (ra < p.nrows) a = solve_prologue(sl, (size_t)ra * p.in_row_stride + x, upd, alpha);
+      if (rb < p.nrows) b = solve_prologue(sl, (size_t)rb * p.in_row_stride + x, upd, alpha);
       mu += double(a) + double(b);
     } else if constexpr (MODE == XF_REAL) {
       if (ra < p.nrows) a = T(p.in_real[(size_t)ra * p.in_row_stride + x]);
@@ -320,7 +314,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(XParams<T> p) {
   }
   __syncthreads();
   lds_fft<T, true>(buf, Lx, lgP, p.rp, p.tw);
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0;
   for (int e = tid; e < P * Lout; e += kThreads) {
     const int pp = e / Lout;
     const int x = e - pp * Lout;
@@ -328,28 +322,22 @@ __global__ __launch_bounds__(kThreads) void k_xinv(XParams<T> p) {
     const cplx<T> z = buf[(x << lgP) + pp];
     if (ra < p.nrows) {
       const size_t o = (size_t)ra * p.in_row_stride + x;
-      if constexpr (MODE == XI_SOLVE) {
-        const T v = z.x * sl.isq[o];
-        sl.v[o] = v;
-        acc += double(v) * double(sl.r[o]);
-      } else {
-        p.out_real[o] = double(z.x);
-      }
+      if constexpr (MODE == XI_SOLVE) solve_epilogue(sl, o, z.x, acc, acc2);
+      else p.out_real[o] = double(z.x);
     }
     if (rb < p.nrows) {
       const size_t o = (size_t)rb * p.in_row_stride + x;
-      if constexpr (MODE == XI_SOLVE) {
-        const T v = z.y * sl.isq[o];
-        sl.v[o] = v;
-        acc += double(v) * double(sl.r[o]);
-      } else {
-        p.out_real[o] = double(z.y);
-      }
+      if constexpr (MODE == XI_SOLVE) solve_epilogue(sl, o, z.y, acc, acc2);
+      else p.out_real[o] = double(z.y);
     }
   }
   if constexpr (MODE == XI_SOLVE) {
-    const double s = block_sum(acc);
-    if (tid == 0) sl.part_delta[0][blockIdx.x] = s;
+    const double s1 = block_sum(acc);
+    const double s2 = block_sum(acc2);
+    if (tid == 0) {
+      sl.part_delta[0][blockIdx.x] = s1;
+      sl.part_rr[blockIdx.x] = s2;
+    }
   }
 }
 

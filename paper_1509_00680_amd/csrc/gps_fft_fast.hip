@@ -53,7 +53,7 @@ void k_fstrided(SParams<T> p) {
   }
   const int b = tid & (B - 1);
   const int q = tid / B;
-  const int pen = blockIdx.x * B + b;
+  const int pen = xcd_tile(blockIdx.x, gridDim.x) * B + b;
   const bool pv = pen < p.npencils;
   size_t base = 0;
   if (pv) {
@@ -158,16 +158,17 @@ void k_fxfwd(XParams<T> p) {
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int Kx = p.g.Kx, Lin = p.Lin;
-  const int pair0 = blockIdx.x * P;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int pair0 = tile * P;
   cplx<T>* work = p.work;
-  const T* rin = nullptr;
-  const T* isq = nullptr;
   Slot<T> sl;
+  double alpha = 0.0;
+  bool upd = false;
   if constexpr (MODE == XF_SOLVE) {
     sl = p.slots[p.batch.slot[blockIdx.y]];
-    if (!iteration_head(sl, p.batch.k[blockIdx.y], p.n_vec_parts, p.check_neutral)) return;
-    rin = sl.r;
-    isq = sl.isq;
+    int k;
+    if (!xfwd_head(sl, p.n_vec_parts, &k, &alpha)) return;
+    upd = k > 0;
     work = sl.work;
   }
   double mu = 0.0;
@@ -177,14 +178,8 @@ void k_fxfwd(XParams<T> p) {
     const int ra = 2 * (pair0 + pp), rb = ra + 1;
     T a = T(0), bb = T(0);
     if constexpr (MODE == XF_SOLVE) {
-      if (ra < p.nrows) {
-        const size_t o = (size_t)ra * p.in_row_stride + x;
-        a = rin[o] * isq[o];
-      }
-      if (rb < p.nrows) {
-        const size_t o = (size_t)rb * p.in_row_stride + x;
-        bb = rin[o] * isq[o];
-      }
+      if (ra < p.nrows) a = solve_prologue(sl, (size_t)ra * p.in_row_stride + x, upd, alpha);
+      if (rb < p.nrows) bb = solve_prologue(sl, (size_t)rb * p.in_row_stride + x, upd, alpha);
       mu += double(a) + double(bb);
     } else {
       if (ra < p.nrows) a = T(p.in_real[(size_t)ra * p.in_row_stride + x]);
@@ -246,7 +241,7 @@ void k_fxfwd(XParams<T> p) {
   if constexpr (MODE == XF_SOLVE) {
     if (p.periodic_mean) {
       const double s = block_sum(mu);
-      if (tid == 0) sl.part_mu[blockIdx.x] = s;
+      if (tid == 0) sl.part_mu[tile] = s;
     }
   }
 }
@@ -261,7 +256,8 @@ void k_fxinv(XParams<T> p) {
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int Kx = p.g.Kx, Lout = p.Lout;
-  const int pair0 = blockIdx.x * P;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int pair0 = tile * P;
   cplx<T>* work = p.work;
   Slot<T> sl;
   if constexpr (MODE == 0) {
@@ -318,7 +314,7 @@ void k_fxinv(XParams<T> p) {
     for (int nb = 0; nb < L1; ++nb) lds[(q + L2 * nb) * PITCH + pp] = x[nb];
   }
   __syncthreads();
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0;
   for (int e = tid; e < P * Lout; e += nt) {
     const int p2 = e / Lout;
     const int xx = e - p2 * Lout;
@@ -326,28 +322,22 @@ void k_fxinv(XParams<T> p) {
     const cplx<T> z = lds[xx * PITCH + p2];
     if (ra < p.nrows) {
       const size_t o = (size_t)ra * p.in_row_stride + xx;
-      if constexpr (MODE == 0) {
-        const T v = z.x * sl.isq[o];
-        sl.v[o] = v;
-        acc += double(v) * double(sl.r[o]);
-      } else {
-        p.out_real[o] = double(z.x);
-      }
+      if constexpr (MODE == 0) solve_epilogue(sl, o, z.x, acc, acc2);
+      else p.out_real[o] = double(z.x);
     }
     if (rb < p.nrows) {
       const size_t o = (size_t)rb * p.in_row_stride + xx;
-      if constexpr (MODE == 0) {
-        const T v = z.y * sl.isq[o];
-        sl.v[o] = v;
-        acc += double(v) * double(sl.r[o]);
-      } else {
-        p.out_real[o] = double(z.y);
-      }
+      if constexpr (MODE == 0) solve_epilogue(sl, o, z.y, acc, acc2);
+      else p.out_real[o] = double(z.y);
     }
   }
   if constexpr (MODE == 0) {
-    const double s = block_sum(acc);
-    if (tid == 0) sl.part_delta[0][blockIdx.x] = s;
+    const double s1 = block_sum(acc);
+    const double s2 = block_sum(acc2);
+    if (tid == 0) {
+      sl.part_delta[0][tile] = s1;
+      sl.part_rr[tile] = s2;
+    }
   }
 }
 

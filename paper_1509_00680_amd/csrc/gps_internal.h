@@ -47,6 +47,8 @@ struct SolveState {
   int status;        // gps_status value once done
   int iters;         // iterations completed
   int err;           // input-check flags raised by the init kernel
+  int k;             // current iteration (written by the x-forward pass)
+  int k_next;        // next iteration (written by the direction kernel)
   double rr0;        // ||r_0||^2
   double thr2;       // stop threshold on ||r||^2
   double rr;         // last ||r||^2
@@ -85,11 +87,12 @@ template <typename T> struct Slot {
   int hist_cap;
 };
 
-// Problems of one batched launch: blockIdx.y indexes these arrays.
+// Problems of one batched launch: blockIdx.y indexes these arrays.  Each
+// problem keeps its own iteration counter in its SolveState, so a launch
+// (or a replayed graph of launches) needs no per-iteration arguments.
 struct Batch {
   int n;
   int slot[kMaxBatch];        // index into the device slot table
-  int k[kMaxBatch];           // iteration number of that problem
 };
 
 // Geometry of one plan, passed by value to kernels.

@@ -29,9 +29,8 @@ template <typename T> struct XParams {
   // XF_SOLVE / XI_SOLVE: the problems of the batch
   const Slot<T>* slots;
   Batch batch;
-  int n_vec_parts;          // partial sums written by the vector kernels
+  int n_vec_parts;          // partial sums written by the direction kernel
   int periodic_mean;        // accumulate sum r/sqrt(eps) (periodic)
-  int check_neutral;        // periodic Poisson: reject non-neutral rho
 };
 
 template <typename T> void launch_xfwd(int mode, const XParams<T>& p, hipStream_t s);
@@ -90,6 +89,7 @@ struct IonParams {
   const double* eps;
 };
 
+template <typename T> void launch_reset_state(const Slot<T>* slots, const Batch& b, hipStream_t s);
 template <typename T> void launch_init(const Slot<T>* slots, const Batch& b, const double* rho,
                                        const double* eps, long long n, hipStream_t s);
 template <typename T> void launch_qfield(const Slot<T>* slots, const Batch& b, const Geom& g,
@@ -97,9 +97,8 @@ template <typename T> void launch_qfield(const Slot<T>* slots, const Batch& b, c
                                          const double* eps, const double* gamma,
                                          double eps_bulk, hipStream_t s);
 template <typename T> void launch_direction(const Slot<T>* slots, const Batch& b, long long n,
-                                            int n_xparts, int periodic, hipStream_t s);
-template <typename T> void launch_update(const Slot<T>* slots, const Batch& b, long long n,
-                                         hipStream_t s);
+                                            int n_xparts, int periodic, int check_neutral,
+                                            hipStream_t s);
 template <typename T> void launch_ion_update(const Slot<T>* slots, const Batch& b, long long n,
                                              const IonParams& ip, int first, hipStream_t s);
 template <typename T> void launch_energy(const Slot<T>* slots, const Batch& b, const double* rho,

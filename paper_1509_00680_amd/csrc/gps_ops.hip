@@ -5,9 +5,8 @@
 // Reductions are deterministic: every work-group writes one FP64 partial per
 // quantity, and the consuming kernel sums the partials in a fixed order in
 // every work-group that needs the scalar (no atomics, no cross-group fences).
-#include "gps_device.h"
+#include "gps_iter.h"
 #include "gps_launch.h"
-#include "gps.h"
 
 namespace gps {
 
@@ -127,6 +126,22 @@ void launch_periodic_table(const Geom& g, int laplacian, double* t64, float* t32
   const long long n = (long long)(g.Lz / 2 + 1) * (g.Ly / 2 + 1) * g.Kx;
   const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
   hipLaunchKernelGGL(k_periodic_table, dim3(grid), dim3(kThreads), 0, s, g, laplacian, t64, t32);
+}
+
+// ---------------------------------------------------------------------------
+// solve-state reset (a kernel rather than a memset, so it may sit in a graph)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_reset_state(const Slot<T>* __restrict__ slots, Batch b) {
+  if (threadIdx.x == 0) {
+    SolveState* st = slots[b.slot[blockIdx.x]].st;
+    *st = SolveState{};
+  }
+}
+
+template <typename T>
+void launch_reset_state(const Slot<T>* slots, const Batch& b, hipStream_t s) {
+  hipLaunchKernelGGL((k_reset_state<T>), dim3(b.n), dim3(64), 0, s, slots, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,26 +292,19 @@ void launch_qfield(const Slot<T>* slots, const Batch& b, const Geom& g, int fd_h
 }
 
 // ---------------------------------------------------------------------------
-// direction update (Algorithm PCG with Eq. corr):
-//   delta = (v, r) from the x-pass partials;  beta = delta / delta_prev
+// direction update (Algorithm PCG with Eq. corr), after the stop decision:
+//   beta = delta_k / delta_{k-1}  (0 at k = 0)
 //   A v = -(q + kappa2) v - 4 pi (r - sqrt(eps) mean(r/sqrt(eps)))  [periodic]
 //   p = v + beta p;  Ap = A v + beta Ap;  partial (p, Ap)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_direction(const Slot<T>* __restrict__ slots, Batch b,
-                                                        long long n, int n_xparts, int periodic) {
+                                                        long long n, int n_xparts, int periodic,
+                                                        int check_neutral) {
   const Slot<T> sl = slots[b.slot[blockIdx.y]];
-  const int k = b.k[blockIdx.y];
-  if (wg_read_flag(&sl.st->done)) return;
-  const double delta = sum_partials(sl.part_delta[0], n_xparts);
-  if (!(delta > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sl.st->status = isfinite(delta) ? GPS_E_BREAKDOWN : GPS_E_NONFINITE;
-      sl.st->iters = k;
-      sl.st->done = 1;
-    }
-    return;
-  }
+  int k;
+  double delta;
+  if (!direction_head(sl, n_xparts, vec_groups(n), check_neutral, &k, &delta)) return;
   double beta = 0.0;
   if (k > 0) beta = delta / sl.hist[(size_t)(k - 1) * 4 + 0];
   double mu = 0.0;
@@ -327,7 +335,7 @@ __global__ __launch_bounds__(kThreads) void k_direction(const Slot<T>* __restric
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) sl.part_pap[blockIdx.x] = acc;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && k < sl.hist_cap) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     sl.hist[(size_t)k * 4 + 0] = delta;
     sl.hist[(size_t)k * 4 + 1] = beta;
   }
@@ -335,54 +343,9 @@ __global__ __launch_bounds__(kThreads) void k_direction(const Slot<T>* __restric
 
 template <typename T>
 void launch_direction(const Slot<T>* slots, const Batch& b, long long n, int n_xparts,
-                      int periodic, hipStream_t s) {
+                      int periodic, int check_neutral, hipStream_t s) {
   hipLaunchKernelGGL((k_direction<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, n,
-                     n_xparts, periodic);
-}
-
-// ---------------------------------------------------------------------------
-// solution update: alpha = delta/(p, Ap); phi += alpha p; r -= alpha Ap;
-// partial ||r||^2
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_update(const Slot<T>* __restrict__ slots, Batch b,
-                                                     long long n) {
-  const Slot<T> sl = slots[b.slot[blockIdx.y]];
-  const int k = b.k[blockIdx.y];
-  if (wg_read_flag(&sl.st->done)) return;
-  const int nparts = vec_groups(n);
-  const double pap = sum_partials(sl.part_pap, nparts);
-  if (!(pap < 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sl.st->status = isfinite(pap) ? GPS_E_BREAKDOWN : GPS_E_NONFINITE;
-      sl.st->iters = k;
-      sl.st->done = 1;
-    }
-    return;
-  }
-  const double delta = sl.hist[(size_t)k * 4 + 0];
-  const double alpha = delta / pap;
-  const T ta = T(alpha);
-  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
-  double acc = 0.0;
-#pragma unroll
-  for (int j = 0; j < kVec; ++j) {
-    const long long i = base + (long long)j * kThreads;
-    if (i < n) {
-      sl.phi[i] += alpha * double(sl.p[i]);
-      const T rn = sl.r[i] - ta * sl.ap[i];
-      sl.r[i] = rn;
-      acc += double(rn) * double(rn);
-    }
-  }
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) sl.part_rr[blockIdx.x] = acc;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && k < sl.hist_cap) sl.hist[(size_t)k * 4 + 2] = alpha;
-}
-
-template <typename T>
-void launch_update(const Slot<T>* slots, const Batch& b, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_update<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, n);
+                     n_xparts, periodic, check_neutral);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,13 +465,13 @@ void launch_energy(const Slot<T>* slots, const Batch& b, const double* rho, long
 }
 
 #define GPS_INST(T)                                                                              \
+  template void launch_reset_state<T>(const Slot<T>*, const Batch&, hipStream_t);                \
   template void launch_init<T>(const Slot<T>*, const Batch&, const double*, const double*,       \
                                long long, hipStream_t);                                          \
   template void launch_qfield<T>(const Slot<T>*, const Batch&, const Geom&, int, const double*,  \
                                  double, const double*, const double*, double, hipStream_t);     \
-  template void launch_direction<T>(const Slot<T>*, const Batch&, long long, int, int,           \
+  template void launch_direction<T>(const Slot<T>*, const Batch&, long long, int, int, int,      \
                                     hipStream_t);                                                \
-  template void launch_update<T>(const Slot<T>*, const Batch&, long long, hipStream_t);          \
   template void launch_ion_update<T>(const Slot<T>*, const Batch&, long long, const IonParams&,  \
                                      int, hipStream_t);                                          \
   template void launch_zero_ion<T>(const Slot<T>*, const Batch&, long long, hipStream_t);        \

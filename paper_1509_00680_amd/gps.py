@@ -27,8 +27,7 @@ EXPORTED = ("gps_plan_create", "gps_plan_set_options", "gps_plan_get_options",
             "gps_plan_device_bytes", "gps_plan_destroy", "gps_solve_generalized",
             "gps_solve_pb", "gps_solve_vacuum", "gps_last_info", "gps_last_history",
             "gps_plan_set_timing", "gps_plan_timing", "gps_status_string")
-KERNEL_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "xinv": 5, "direction": 6,
-                "update": 7}
+KERNEL_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "xinv": 5, "direction": 6}
 
 
 class gps_options(ctypes.Structure):
