@@ -43,12 +43,25 @@ __device__ __forceinline__ double block_sum(double v) {
   return r;
 }
 
-// Deterministic sum of n partials spaced by `stride` doubles.
+// Deterministic sum of n partials spaced by `stride` doubles: four
+// independent loads in flight per thread, fixed combination order.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n,
                                                int stride = 1) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[(size_t)i * stride];
-  return block_sum(s);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int step = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 3 * step < n; i += 4 * step) {
+    const double a = part[(size_t)i * stride];
+    const double b = part[(size_t)(i + step) * stride];
+    const double c = part[(size_t)(i + 2 * step) * stride];
+    const double d = part[(size_t)(i + 3 * step) * stride];
+    s0 += a;
+    s1 += b;
+    s2 += c;
+    s3 += d;
+  }
+  for (; i < n; i += step) s0 += part[(size_t)i * stride];
+  return block_sum((s0 + s1) + (s2 + s3));
 }
 
 // Tile processed by work-group `bid` of a G-group launch.  Work-groups are

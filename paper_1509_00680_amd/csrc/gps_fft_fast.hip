@@ -148,18 +148,35 @@ void k_fstrided(SParams<T> p) {
 // ---------------------------------------------------------------------------
 // x passes (pairs of real rows packed as one complex row)
 // ---------------------------------------------------------------------------
-template <typename T, int L1, int L2, int MODE>
-__global__ __launch_bounds__(round64(kXPairs * L1))
+// A work-group transforms 2P consecutive rows.  Row lengths are compile-time
+// (PAD: the box holds L/2 points of the padded length L, else L), so every
+// loop has a fixed trip count and all global loads of a thread are issued
+// before the first one is used.
+template <int L1> constexpr int xthreads() { return round64(kXPairs * L1); }
+
+template <typename T>
+__device__ __forceinline__ size_t xrow_offset(const XParams<T>& p, int row, int Kx) {
+  return (size_t)(row / p.rows_per_plane) * p.plane_stride + (size_t)(row % p.rows_per_plane) * Kx;
+}
+
+template <typename T, int L1, int L2, int MODE, bool PAD>
+__global__ __launch_bounds__(xthreads<L1>())
 void k_fxfwd(XParams<T> p) {
   constexpr int P = kXPairs;
   constexpr int L = L1 * L2;
   constexpr int PITCH = P + 1;
+  constexpr int NT = xthreads<L1>();
+  constexpr int Lin = PAD ? L / 2 : L;
+  constexpr int Kx = L / 2 + 1;
+  constexpr int NIN = 2 * P * Lin;                 // real inputs of the tile
+  constexpr int EIN = (NIN + NT - 1) / NT;
+  constexpr int NOUT = P * Kx;                     // complex outputs per row parity
+  constexpr int EOUT = (NOUT + NT - 1) / NT;
   __shared__ cplx<T> lds[L * PITCH];
+  T* ldsr = reinterpret_cast<T*>(lds);
   const int tid = threadIdx.x;
-  const int nt = blockDim.x;
-  const int Kx = p.g.Kx, Lin = p.Lin;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int pair0 = tile * P;
+  const int row0 = tile * 2 * P;
   cplx<T>* work = p.work;
   Slot<T> sl;
   double alpha = 0.0;
@@ -171,25 +188,63 @@ void k_fxfwd(XParams<T> p) {
     upd = k > 0;
     work = sl.work;
   }
-  double mu = 0.0;
-  for (int e = tid; e < P * Lin; e += nt) {
-    const int pp = e / Lin;
-    const int x = e - pp * Lin;
-    const int ra = 2 * (pair0 + pp), rb = ra + 1;
-    T a = T(0), bb = T(0);
-    if constexpr (MODE == XF_SOLVE) {
-      if (ra < p.nrows) a = solve_prologue(sl, (size_t)ra * p.in_row_stride + x, upd, alpha);
-      if (rb < p.nrows) bb = solve_prologue(sl, (size_t)rb * p.in_row_stride + x, upd, alpha);
-      mu += double(a) + double(bb);
-    } else {
-      if (ra < p.nrows) a = T(p.in_real[(size_t)ra * p.in_row_stride + x]);
-      if (rb < p.nrows) bb = T(p.in_real[(size_t)rb * p.in_row_stride + x]);
+  // phase 1: all loads of this thread
+  T rv[EIN], sv[EIN], pv[EIN], av[EIN];
+  double fv[EIN];
+#pragma unroll
+  for (int i = 0; i < EIN; ++i) {
+    const int e = tid + i * NT;
+    const int row = e / Lin;
+    const int x = e - row * Lin;
+    const int grow = row0 + row;
+    rv[i] = T(0);
+    sv[i] = T(0);
+    if (e < NIN && grow < p.nrows) {
+      const size_t o = (size_t)grow * p.in_row_stride + x;
+      if constexpr (MODE == XF_SOLVE) {
+        rv[i] = sl.r[o];
+        sv[i] = sl.isq[o];
+        if (upd) {
+          pv[i] = sl.p[o];
+          av[i] = sl.ap[o];
+          fv[i] = sl.phi[o];
+        }
+      } else {
+        rv[i] = T(p.in_real[o]);
+      }
     }
-    lds[x * PITCH + pp] = cmk(a, bb);
   }
-  for (int e = tid; e < P * (L - Lin); e += nt) {
-    const int x = Lin + e / P;
-    lds[x * PITCH + (e % P)] = cmk(T(0), T(0));
+  // phase 2: update, scale, stage the rows in LDS
+  double mu = 0.0;
+#pragma unroll
+  for (int i = 0; i < EIN; ++i) {
+    const int e = tid + i * NT;
+    const int row = e / Lin;
+    const int x = e - row * Lin;
+    const int grow = row0 + row;
+    if (e < NIN) {
+      T a = rv[i];
+      if constexpr (MODE == XF_SOLVE) {
+        if (grow < p.nrows) {
+          const size_t o = (size_t)grow * p.in_row_stride + x;
+          if (upd) {
+            sl.phi[o] = fv[i] + alpha * double(pv[i]);
+            a = a - T(alpha) * av[i];
+            sl.r[o] = a;
+          }
+          a = a * sv[i];
+          mu += double(a);
+        }
+      }
+      ldsr[2 * (x * PITCH + (row >> 1)) + (row & 1)] = a;
+    }
+  }
+  if constexpr (PAD) {
+#pragma unroll
+    for (int i = 0; i < (P * (L - Lin) + NT - 1) / NT; ++i) {
+      const int e = tid + i * NT;
+      if (e < P * (L - Lin)) lds[(Lin + e / P) * PITCH + (e % P)] = cmk(T(0), T(0));
+    }
   }
   __syncthreads();
   const int pp = tid % P;
@@ -221,22 +276,21 @@ void k_fxfwd(XParams<T> p) {
     for (int k2 = 0; k2 < L2; ++k2) lds[(q + L1 * k2) * PITCH + pp] = y[k2];
   }
   __syncthreads();
-  for (int e = tid; e < P * Kx; e += nt) {
-    const int p2 = e / Kx;
-    const int kk = e - p2 * Kx;
-    const int ra = 2 * (pair0 + p2), rb = ra + 1;
-    const cplx<T> zk = lds[kk * PITCH + p2];
-    const int km = kk == 0 ? 0 : L - kk;
-    const cplx<T> zm = lds[km * PITCH + p2];
-    const T half = T(0.5);
-    const cplx<T> xa = cmk(half * (zk.x + zm.x), half * (zk.y - zm.y));
-    const cplx<T> xb = cmk(half * (zk.y + zm.y), half * (zm.x - zk.x));
-    if (ra < p.nrows)
-      work[(size_t)(ra / p.rows_per_plane) * p.plane_stride +
-           (size_t)(ra % p.rows_per_plane) * Kx + kk] = xa;
-    if (rb < p.nrows)
-      work[(size_t)(rb / p.rows_per_plane) * p.plane_stride +
-           (size_t)(rb % p.rows_per_plane) * Kx + kk] = xb;
+#pragma unroll
+  for (int i = 0; i < EOUT; ++i) {
+    const int e = tid + i * NT;
+    if (e < NOUT) {
+      const int p2 = e / Kx;
+      const int kk = e - p2 * Kx;
+      const int ra = row0 + 2 * p2, rb = ra + 1;
+      const cplx<T> zk = lds[kk * PITCH + p2];
+      const cplx<T> zm = lds[(kk == 0 ? 0 : L - kk) * PITCH + p2];
+      const T half = T(0.5);
+      if (ra < p.nrows)
+        work[xrow_offset(p, ra, Kx) + kk] = cmk(half * (zk.x + zm.x), half * (zk.y - zm.y));
+      if (rb < p.nrows)
+        work[xrow_offset(p, rb, Kx) + kk] = cmk(half * (zk.y + zm.y), half * (zm.x - zk.x));
+    }
   }
   if constexpr (MODE == XF_SOLVE) {
     if (p.periodic_mean) {
@@ -246,18 +300,24 @@ void k_fxfwd(XParams<T> p) {
   }
 }
 
-template <typename T, int L1, int L2, int MODE>   // MODE 0: solve epilogue, 1: plain store
-__global__ __launch_bounds__(round64(kXPairs * L1))
+template <typename T, int L1, int L2, int MODE, bool PAD>   // MODE 0: solve epilogue, 1: plain
+__global__ __launch_bounds__(xthreads<L1>())
 void k_fxinv(XParams<T> p) {
   constexpr int P = kXPairs;
   constexpr int L = L1 * L2;
   constexpr int PITCH = P + 1;
+  constexpr int NT = xthreads<L1>();
+  constexpr int Lout = PAD ? L / 2 : L;
+  constexpr int Kx = L / 2 + 1;
+  constexpr int NIN = P * Kx;
+  constexpr int EIN = (NIN + NT - 1) / NT;
+  constexpr int NOUT = 2 * P * Lout;
+  constexpr int EOUT = (NOUT + NT - 1) / NT;
   __shared__ cplx<T> lds[L * PITCH];
+  const T* ldsr = reinterpret_cast<const T*>(lds);
   const int tid = threadIdx.x;
-  const int nt = blockDim.x;
-  const int Kx = p.g.Kx, Lout = p.Lout;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int pair0 = tile * P;
+  const int row0 = tile * 2 * P;
   cplx<T>* work = p.work;
   Slot<T> sl;
   if constexpr (MODE == 0) {
@@ -265,24 +325,35 @@ void k_fxinv(XParams<T> p) {
     if (wg_read_flag(&sl.st->done)) return;
     work = sl.work;
   }
-  for (int e = tid; e < P * Kx; e += nt) {
+  cplx<T> xa[EIN], xb[EIN];
+#pragma unroll
+  for (int i = 0; i < EIN; ++i) {
+    const int e = tid + i * NT;
     const int p2 = e / Kx;
     const int kk = e - p2 * Kx;
-    const int ra = 2 * (pair0 + p2), rb = ra + 1;
-    cplx<T> xa = cmk(T(0), T(0)), xb = cmk(T(0), T(0));
-    if (ra < p.nrows)
-      xa = work[(size_t)(ra / p.rows_per_plane) * p.plane_stride +
-                (size_t)(ra % p.rows_per_plane) * Kx + kk];
-    if (rb < p.nrows)
-      xb = work[(size_t)(rb / p.rows_per_plane) * p.plane_stride +
-                (size_t)(rb % p.rows_per_plane) * Kx + kk];
-    if (kk == 0 || 2 * kk == L) {
-      xa.y = T(0);
-      xb.y = T(0);
+    const int ra = row0 + 2 * p2, rb = ra + 1;
+    xa[i] = cmk(T(0), T(0));
+    xb[i] = cmk(T(0), T(0));
+    if (e < NIN) {
+      if (ra < p.nrows) xa[i] = work[xrow_offset(p, ra, Kx) + kk];
+      if (rb < p.nrows) xb[i] = work[xrow_offset(p, rb, Kx) + kk];
     }
-    lds[kk * PITCH + p2] = cmk(xa.x - xb.y, xa.y + xb.x);
-    const int km = L - kk;
-    if (kk > 0 && km >= Kx) lds[km * PITCH + p2] = cmk(xa.x + xb.y, xb.x - xa.y);
+  }
+#pragma unroll
+  for (int i = 0; i < EIN; ++i) {
+    const int e = tid + i * NT;
+    if (e < NIN) {
+      const int p2 = e / Kx;
+      const int kk = e - p2 * Kx;
+      cplx<T> a = xa[i], b = xb[i];
+      if (kk == 0 || 2 * kk == L) {    // self-conjugate bins of a real row
+        a.y = T(0);
+        b.y = T(0);
+      }
+      lds[kk * PITCH + p2] = cmk(a.x - b.y, a.y + b.x);
+      const int km = L - kk;
+      if (kk > 0 && km >= Kx) lds[km * PITCH + p2] = cmk(a.x + b.y, b.x - a.y);
+    }
   }
   __syncthreads();
   const int pp = tid % P;
@@ -314,29 +385,51 @@ void k_fxinv(XParams<T> p) {
     for (int nb = 0; nb < L1; ++nb) lds[(q + L2 * nb) * PITCH + pp] = x[nb];
   }
   __syncthreads();
-  double acc = 0.0, acc2 = 0.0;
-  for (int e = tid; e < P * Lout; e += nt) {
-    const int p2 = e / Lout;
-    const int xx = e - p2 * Lout;
-    const int ra = 2 * (pair0 + p2), rb = ra + 1;
-    const cplx<T> z = lds[xx * PITCH + p2];
-    if (ra < p.nrows) {
-      const size_t o = (size_t)ra * p.in_row_stride + xx;
-      if constexpr (MODE == 0) solve_epilogue(sl, o, z.x, acc, acc2);
-      else p.out_real[o] = double(z.x);
-    }
-    if (rb < p.nrows) {
-      const size_t o = (size_t)rb * p.in_row_stride + xx;
-      if constexpr (MODE == 0) solve_epilogue(sl, o, z.y, acc, acc2);
-      else p.out_real[o] = double(z.y);
-    }
-  }
   if constexpr (MODE == 0) {
+    T sv[EOUT], rv[EOUT];
+#pragma unroll
+    for (int i = 0; i < EOUT; ++i) {
+      const int e = tid + i * NT;
+      const int row = e / Lout;
+      const int xx = e - row * Lout;
+      const int grow = row0 + row;
+      if (e < NOUT && grow < p.nrows) {
+        const size_t o = (size_t)grow * p.in_row_stride + xx;
+        sv[i] = sl.isq[o];
+        rv[i] = sl.r[o];
+      }
+    }
+    double acc = 0.0, acc2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < EOUT; ++i) {
+      const int e = tid + i * NT;
+      const int row = e / Lout;
+      const int xx = e - row * Lout;
+      const int grow = row0 + row;
+      if (e < NOUT && grow < p.nrows) {
+        const size_t o = (size_t)grow * p.in_row_stride + xx;
+        const T v = ldsr[2 * (xx * PITCH + (row >> 1)) + (row & 1)] * sv[i];
+        sl.v[o] = v;
+        acc += double(v) * double(rv[i]);
+        acc2 += double(rv[i]) * double(rv[i]);
+      }
+    }
     const double s1 = block_sum(acc);
     const double s2 = block_sum(acc2);
     if (tid == 0) {
       sl.part_delta[0][tile] = s1;
       sl.part_rr[tile] = s2;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < EOUT; ++i) {
+      const int e = tid + i * NT;
+      const int row = e / Lout;
+      const int xx = e - row * Lout;
+      const int grow = row0 + row;
+      if (e < NOUT && grow < p.nrows)
+        p.out_real[(size_t)grow * p.in_row_stride + xx] =
+            double(ldsr[2 * (xx * PITCH + (row >> 1)) + (row & 1)]);
     }
   }
 }
@@ -378,17 +471,25 @@ bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
   }
 }
 
+// x passes exist for full rows (Lin = L) and for half-padded rows (Lin = L/2).
 template <typename T>
 bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s) {
   if (mode != XF_SOLVE && mode != XF_REAL) return false;
+  const bool pad = 2 * p.Lin == p.g.Lx;
+  if (!pad && p.Lin != p.g.Lx) return false;
   const dim3 grid(fast_xpass_groups(p.nrows), p.slots ? p.batch.n : 1);
   switch (p.g.Lx) {
-#define GPS_CASE(LL, A, BB)                                                                    \
-  case LL: {                                                                                   \
-    const dim3 blk(round64(kXPairs * A));                                                      \
-    if (mode == XF_SOLVE) hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_SOLVE>), grid, blk, 0, s, p); \
-    else hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_REAL>), grid, blk, 0, s, p);                \
-    return true;                                                                               \
+#define GPS_CASE(LL, A, BB)                                                                      \
+  case LL: {                                                                                     \
+    const dim3 blk(xthreads<A>());                                                      \
+    if (mode == XF_SOLVE) {                                                                      \
+      if (pad) hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_SOLVE, true>), grid, blk, 0, s, p);      \
+      else hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_SOLVE, false>), grid, blk, 0, s, p);         \
+    } else {                                                                                     \
+      if (pad) hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_REAL, true>), grid, blk, 0, s, p);       \
+      else hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_REAL, false>), grid, blk, 0, s, p);          \
+    }                                                                                            \
+    return true;                                                                                 \
   }
     GPS_FAST_LENGTHS(GPS_CASE)
 #undef GPS_CASE
@@ -398,14 +499,21 @@ bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s) {
 
 template <typename T>
 bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s) {
+  const bool pad = 2 * p.Lout == p.g.Lx;
+  if (!pad && p.Lout != p.g.Lx) return false;
   const dim3 grid(fast_xpass_groups(p.nrows), p.slots ? p.batch.n : 1);
   switch (p.g.Lx) {
-#define GPS_CASE(LL, A, BB)                                                                    \
-  case LL: {                                                                                   \
-    const dim3 blk(round64(kXPairs * A));                                                      \
-    if (mode == 0) hipLaunchKernelGGL((k_fxinv<T, A, BB, 0>), grid, blk, 0, s, p);            \
-    else hipLaunchKernelGGL((k_fxinv<T, A, BB, 1>), grid, blk, 0, s, p);                      \
-    return true;                                                                               \
+#define GPS_CASE(LL, A, BB)                                                                      \
+  case LL: {                                                                                     \
+    const dim3 blk(xthreads<A>());                                                      \
+    if (mode == 0) {                                                                             \
+      if (pad) hipLaunchKernelGGL((k_fxinv<T, A, BB, 0, true>), grid, blk, 0, s, p);             \
+      else hipLaunchKernelGGL((k_fxinv<T, A, BB, 0, false>), grid, blk, 0, s, p);                \
+    } else {                                                                                     \
+      if (pad) hipLaunchKernelGGL((k_fxinv<T, A, BB, 1, true>), grid, blk, 0, s, p);             \
+      else hipLaunchKernelGGL((k_fxinv<T, A, BB, 1, false>), grid, blk, 0, s, p);                \
+    }                                                                                            \
+    return true;                                                                                 \
   }
     GPS_FAST_LENGTHS(GPS_CASE)
 #undef GPS_CASE
