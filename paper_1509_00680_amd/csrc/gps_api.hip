@@ -86,8 +86,8 @@ int ilog2(int v) {
 // Per-precision buffers of one problem in flight.
 template <typename T> struct Res {
   bool ready = false;
-  Slot<T> slot{};            // host copy of the device slot
-  Slot<T>* d_slot = nullptr;
+  SlotTable<T> tab{};        // passed by value to every kernel; entry 0 is this plan's problem
+  Slot<T>& slot() { return tab.s[0]; }
   SolveState* h_state = nullptr;   // pinned
   double* h_parts = nullptr;       // pinned, >= 4 * groups
   int hist_cap = 0;
@@ -266,7 +266,7 @@ void ensure_res(gps_plan* pl, bool need_ion) {
   const Geom& g = pl->g;
   const int nxg = (g.ny * g.nz + 1) / 2 + 1;   // x-pass groups <= row pairs
   if (!R.ready) {
-    Slot<T>& s = R.slot;
+    Slot<T>& s = R.slot();
     s = Slot<T>{};
     const size_t nb = (size_t)n * sizeof(T);
     dalloc(&s.r, nb, &pl->bytes);
@@ -286,7 +286,7 @@ void ensure_res(gps_plan* pl, bool need_ion) {
     dalloc(&s.part_mu, (size_t)nxg * sizeof(double), &pl->bytes);
     dalloc(&s.part_aux, (size_t)2 * nvg * sizeof(double), &pl->bytes);
     dalloc(&s.st, sizeof(SolveState), &pl->bytes);
-    dalloc(&R.d_slot, sizeof(Slot<T>), &pl->bytes);
+    dalloc(&s.phi, (size_t)n * sizeof(double), &pl->bytes);
     if (pl->bc == GPS_BC_PERIODIC) {
       dalloc(&R.lap64, (size_t)n * sizeof(double), &pl->bytes);
       if (sizeof(T) != sizeof(double))
@@ -300,39 +300,42 @@ void ensure_res(gps_plan* pl, bool need_ion) {
     R.ready = true;
   }
   if (R.hist_cap < pl->opt.maxit + 1) {
-    dfree(R.slot.hist);
-    dalloc(&R.slot.hist, (size_t)4 * (pl->opt.maxit + 1) * sizeof(double), &pl->bytes);
+    dfree(R.slot().hist);
+    dalloc(&R.slot().hist, (size_t)4 * (pl->opt.maxit + 1) * sizeof(double), &pl->bytes);
     R.hist_cap = pl->opt.maxit + 1;
   }
-  if (need_ion && !R.slot.ion) dalloc(&R.slot.ion, (size_t)n * sizeof(T), &pl->bytes);
-  R.slot.hist_cap = R.hist_cap;
-  R.slot.maxit = pl->opt.maxit;
+  bool changed = false;
+  if (need_ion && !R.slot().ion) {
+    dalloc(&R.slot().ion, (size_t)n * sizeof(T), &pl->bytes);
+    changed = true;
+  }
+  // the table is captured by value in graphs: rebuild them when it changes
+  if (changed || R.slot().hist_cap != R.hist_cap || R.slot().maxit != pl->opt.maxit) {
+    if (R.graph) (void)hipGraphExecDestroy(R.graph);
+    R.graph = nullptr;
+  }
+  R.slot().hist_cap = R.hist_cap;
+  R.slot().maxit = pl->opt.maxit;
 }
 
 template <typename T>
 void free_res(gps_plan* pl) {
   Res<T>& R = pl->res<T>();
   if (R.graph) (void)hipGraphExecDestroy(R.graph);
-  Slot<T>& s = R.slot;
+  Slot<T>& s = R.slot();
   dfree(s.r); dfree(s.v); dfree(s.p); dfree(s.ap); dfree(s.isq); dfree(s.qk); dfree(s.s);
   dfree(s.ion); dfree(s.sq64); dfree(s.work); dfree(s.part_init); dfree(s.part_rr);
   dfree(s.part_delta[0]); dfree(s.part_pap); dfree(s.part_mu); dfree(s.part_aux); dfree(s.hist);
-  dfree(s.st); dfree(R.d_slot); dfree(R.lap64); dfree(R.work64q);
+  dfree(s.st); dfree(s.phi); dfree(R.lap64); dfree(R.work64q);
   if (R.h_state) (void)hipHostFree(R.h_state);
   if (R.h_parts) (void)hipHostFree(R.h_parts);
   R = Res<T>{};
 }
 
 template <typename T>
-void push_slot(gps_plan* pl) {
-  Res<T>& R = pl->res<T>();
-  ck(hipMemcpyAsync(R.d_slot, &R.slot, sizeof(Slot<T>), hipMemcpyHostToDevice, pl->stream()));
-}
-
-template <typename T>
 SolveState read_state(gps_plan* pl) {
   Res<T>& R = pl->res<T>();
-  ck(hipMemcpyAsync(R.h_state, R.slot.st, sizeof(SolveState), hipMemcpyDeviceToHost,
+  ck(hipMemcpyAsync(R.h_state, R.slot().st, sizeof(SolveState), hipMemcpyDeviceToHost,
                     pl->stream()));
   ck(hipStreamSynchronize(pl->stream()));
   return *R.h_state;
@@ -425,37 +428,38 @@ double pass_bytes(const gps_plan* pl, int kind, size_t s) {
 // one PCG iteration for the problems of a batch (all of one plan)
 // ---------------------------------------------------------------------------
 template <typename T>
-void enqueue_iteration(gps_plan* pl, const Slot<T>* d_slots, const Batch& b, int check_neutral,
+void enqueue_iteration(gps_plan* pl, const SlotTable<T>& tab, const Batch& b, int check_neutral,
                        hipStream_t s, int k0) {
   const Geom& g = pl->g;
   const long long n = pl->npts();
   const int periodic = pl->bc == GPS_BC_PERIODIC;
   XParams<T> xp = xparams<T>(pl, g.ny * g.nz, g.ny, g.nx, g.nx, (long long)g.Ly * g.Kx, g.nx);
-  xp.slots = d_slots;
+  xp.tab = tab;
+  xp.has_slots = 1;
   xp.batch = b;
   xp.n_vec_parts = vec_groups(n);
   xp.periodic_mean = periodic;
   { TimerScope t(pl, s, GPS_K_XFWD, k0); launch_xfwd<T>(XF_SOLVE, xp, s); }
   SParams<T> yf = sparams<T>(pl, 1, g.Ly, g.ny, g.Ly, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
                              g.Kx);
-  yf.slots = d_slots;
+  yf.tab = tab;
   yf.batch = b;
   { TimerScope t(pl, s, GPS_K_YFWD, k0); launch_strided<T>(ST_FWD, yf, s); }
   SParams<T> zc = sparams<T>(pl, 2, g.Lz, g.nz, g.nz, g.Ly * g.Kx, g.Ly * g.Kx, 0,
                              (long long)g.Ly * g.Kx);
-  zc.slots = d_slots;
+  zc.tab = tab;
   zc.batch = b;
   zc.table = pl->green<T>();
   zc.k0_from_slot = periodic;
   { TimerScope t(pl, s, GPS_K_ZCONV, k0); launch_strided<T>(ST_CONV, zc, s); }
   SParams<T> yi = sparams<T>(pl, 1, g.Ly, g.Ly, g.ny, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
                              g.Kx);
-  yi.slots = d_slots;
+  yi.tab = tab;
   yi.batch = b;
   { TimerScope t(pl, s, GPS_K_YINV, k0); launch_strided<T>(ST_INV, yi, s); }
   { TimerScope t(pl, s, GPS_K_XINV, k0); launch_xinv<T>(0 /*XI_SOLVE*/, xp, s); }
   { TimerScope t(pl, s, GPS_K_DIRECTION, k0);
-    launch_direction<T>(d_slots, b, n, xpass_groups(xp), periodic, check_neutral, s); }
+    launch_direction<T>(tab, b, n, xpass_groups(xp), periodic, check_neutral, s); }
 }
 
 // Spectral Laplacian of sqrt(eps) (periodic q) with the FP64 FFT passes.
@@ -464,10 +468,10 @@ void spectral_laplacian(gps_plan* pl) {
   Res<T>& R = pl->res<T>();
   const Geom& g = pl->g;
   hipStream_t s = pl->stream();
-  cplx<double>* work = R.work64q ? R.work64q : reinterpret_cast<cplx<double>*>(R.slot.work);
+  cplx<double>* work = R.work64q ? R.work64q : reinterpret_cast<cplx<double>*>(R.slot().work);
   XParams<double> xp = xparams<double>(pl, g.ny * g.nz, g.ny, g.nx, g.nx,
                                        (long long)g.Ly * g.Kx, g.nx);
-  xp.in_real = R.slot.sq64;
+  xp.in_real = R.slot().sq64;
   xp.out_real = R.lap64;
   xp.work = work;
   launch_xfwd<double>(XF_REAL, xp, s);
@@ -494,7 +498,7 @@ void vacuum_apply(gps_plan* pl, const double* f, double* u) {
   Res<T>& R = pl->res<T>();
   const Geom& g = pl->g;
   hipStream_t s = pl->stream();
-  cplx<T>* work = R.slot.work;
+  cplx<T>* work = R.slot().work;
   XParams<T> xp = xparams<T>(pl, g.ny * g.nz, g.ny, g.nx, g.nx, (long long)g.Ly * g.Kx, g.nx);
   xp.in_real = f;
   xp.out_real = u;
@@ -536,7 +540,7 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk) {
   b.slot[0] = 0;
   pl->ev_pending.clear();
   ck(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-  for (int j = 0; j < chunk; ++j) enqueue_iteration<T>(pl, R.d_slot, b, check_neutral,
+  for (int j = 0; j < chunk; ++j) enqueue_iteration<T>(pl, R.tab, b, check_neutral,
                                                        pl->cap_stream, j);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
@@ -574,7 +578,7 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
       pl->ev_pending.clear();
       pl->ev_used = 0;
       for (int j = 0; j < m * chunk; ++j)
-        enqueue_iteration<T>(pl, R.d_slot, b, check_neutral, pl->stream(), j);
+        enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->stream(), j);
       ck(hipGetLastError());
     } else {
       for (int r = 0; r < m; ++r) ck(hipGraphLaunch(R.graph, pl->stream()));
@@ -602,22 +606,25 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
 }
 
 template <typename T>
-void reset_state(gps_plan* pl) {
+void reset_state(gps_plan* pl, double abs_thr, double rel_thr) {
   Res<T>& R = pl->res<T>();
   Batch b{};
   b.n = 1;
-  launch_reset_state<T>(R.d_slot, b, pl->stream());
+  launch_reset_state<T>(R.tab, b, abs_thr, rel_thr, pl->stream());
 }
 
 template <typename T>
-void finish_info(gps_plan* pl, const SolveState& st, const double* rho, int total_iters) {
+void finish_info(gps_plan* pl, const SolveState& st, const double* rho, double* phi_out,
+                 int total_iters) {
   Res<T>& R = pl->res<T>();
   const long long n = pl->npts();
+  ck(hipMemcpyAsync(phi_out, R.slot().phi, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice,
+                    pl->stream()));
   Batch b{};
   b.n = 1;
-  launch_energy<T>(R.d_slot, b, rho, n, pl->stream());
+  launch_energy<T>(R.tab, b, rho, n, pl->stream());
   ck(hipGetLastError());
-  const double e = read_sum<T>(pl, R.slot.part_aux, vec_groups(n), 2, 0);
+  const double e = read_sum<T>(pl, R.slot().part_aux, vec_groups(n), 2, 0);
   pl->info.energy = 0.5 * pl->g.h * pl->g.h * pl->g.h * e;
   pl->info.iterations = total_iters;
   pl->info.rnorm0 = std::sqrt(st.rr0);
@@ -625,7 +632,7 @@ void finish_info(gps_plan* pl, const SolveState& st, const double* rho, int tota
   const int nh = std::min(st.iters, R.hist_cap);
   pl->hist.assign((size_t)4 * nh, 0.0);
   if (nh > 0)
-    ck(hipMemcpy(pl->hist.data(), R.slot.hist, (size_t)4 * nh * sizeof(double),
+    ck(hipMemcpy(pl->hist.data(), R.slot().hist, (size_t)4 * nh * sizeof(double),
                  hipMemcpyDeviceToHost));
   pl->info.history_len = nh;
 }
@@ -647,43 +654,43 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
   hipStream_t s = pl->stream();
   const long long n = pl->npts();
   const int periodic = pl->bc == GPS_BC_PERIODIC;
-  Slot<T>& sl = R.slot;
-  sl.phi = phi;
-  sl.g0 = 0.0;
-  sl.abs_thr = 0.0;
-  sl.rel_thr = tol;
-  push_slot<T>(pl);
-  reset_state<T>(pl);
+  Slot<T>& sl = R.slot();
   Batch b{};
   b.n = 1;
-  launch_init<T>(R.d_slot, b, rho, eps, n, s);
-  if (nonlinear) launch_zero_ion<T>(R.d_slot, b, n, s);
+  // Algorithm SCPBimproved's inner threshold for outer step 1 (see below)
+  double rho_norm = 0.0;
+  if (nonlinear) {
+    // ||rho|| is needed before the first reset: one reduction on the host
+    launch_init<T>(R.tab, b, rho, eps, n, s);
+    ck(hipGetLastError());
+    rho_norm = std::sqrt(read_sum<T>(pl, sl.part_init, vec_groups(n), 4, 3));
+    reset_state<T>(pl, kFourPi * tol * rho_norm, 1e-2);
+  } else {
+    reset_state<T>(pl, 0.0, tol);
+  }
+  launch_init<T>(R.tab, b, rho, eps, n, s);
+  if (nonlinear) launch_zero_ion<T>(R.tab, b, n, s);
   const double kcoef = (el.present && el.linear) ? el.kappa_coef : 0.0;
   const double* lap = nullptr;
   if (periodic) {
     spectral_laplacian<T>(pl);
     lap = R.lap64;
   }
-  launch_qfield<T>(R.d_slot, b, pl->g, pl->opt.fd_order / 2, lap, kcoef, eps, el.ip.gamma,
+  launch_qfield<T>(R.tab, b, pl->g, pl->opt.fd_order / 2, lap, kcoef, eps, el.ip.gamma,
                    el.ip.eps_bulk, s);
-  ck(hipGetLastError());
   if (periodic && kcoef != 0.0) {
-    // k = 0 multiplier of the preconditioner: 4 pi / mean(kappa2/eps)
-    const double sum = read_sum<T>(pl, sl.part_aux, vec_groups(n), 2, 0);
-    const double mean = sum / double(n);
     const Geom& g = pl->g;
-    sl.g0 = mean > 0 ? 4.0 * kPi / mean / ((double)g.Lx * g.Ly * g.Lz) : 0.0;
-    push_slot<T>(pl);
+    launch_set_g0<T>(R.tab, b, n, 1.0 / ((double)g.Lx * g.Ly * g.Lz), s);
   }
+  ck(hipGetLastError());
   std::memset(&pl->info, 0, sizeof(pl->info));
   if (!nonlinear) {
     const SolveState st = run_pcg<T>(pl, periodic && !el.present);
-    finish_info<T>(pl, st, rho, st.iters);
+    finish_info<T>(pl, st, rho, phi, st.iters);
     pl->info.status = st.status;
     return (gps_status)st.status;
   }
   // Algorithm SCPBimproved
-  const double rho_norm = std::sqrt(read_sum<T>(pl, sl.part_init, vec_groups(n), 4, 3));
   int total = 0;
   SolveState st{};
   gps_status result = GPS_E_NOT_CONVERGED;
@@ -691,10 +698,7 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
   int outer = 0;
   for (int k = 1; k <= el.outer_maxit; ++k) {
     outer = k;
-    sl.abs_thr = kFourPi * tol * rho_norm;
-    sl.rel_thr = k <= 2 ? 1e-2 : 0.0;
-    push_slot<T>(pl);
-    reset_state<T>(pl);
+    if (k > 1) reset_state<T>(pl, kFourPi * tol * rho_norm, k <= 2 ? 1e-2 : 0.0);
     st = run_pcg<T>(pl, 0);
     total += st.iters;
     if (st.status != GPS_OK) {
@@ -703,7 +707,7 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
     }
     IonParams ip = el.ip;
     ip.eps = eps;
-    launch_ion_update<T>(R.d_slot, b, n, ip, k == 1, s);
+    launch_ion_update<T>(R.tab, b, n, ip, k == 1, s);
     ck(hipGetLastError());
     const double d2 = read_sum<T>(pl, sl.part_init, vec_groups(n), 4, 3);
     outer_res = rho_norm > 0 ? std::sqrt(d2) / rho_norm : std::sqrt(d2);
@@ -716,7 +720,7 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
       break;
     }
   }
-  finish_info<T>(pl, st, rho, total);
+  finish_info<T>(pl, st, rho, phi, total);
   pl->info.outer_iterations = outer;
   pl->info.outer_residual = outer_res;
   pl->info.status = result;

@@ -204,11 +204,10 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(XParams<T> p) {
   const int Lx = p.g.Lx, Kx = p.g.Kx, P = p.P, lgP = p.lgP, Lin = p.Lin;
   const int pair0 = blockIdx.x * P;
   cplx<T>* work = p.work;
-  Slot<T> sl;
+  const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
   double alpha = 0.0;
   bool upd = false;
   if constexpr (MODE == XF_SOLVE) {
-    sl = p.slots[p.batch.slot[blockIdx.y]];
     int k;
     if (!xfwd_head(sl, p.n_vec_parts, &k, &alpha)) return;
     upd = k > 0;
@@ -287,9 +286,8 @@ __global__ __launch_bounds__(kThreads) void k_xinv(XParams<T> p) {
   const int Lx = p.g.Lx, Kx = p.g.Kx, P = p.P, lgP = p.lgP, Lout = p.Lout;
   const int pair0 = blockIdx.x * P;
   cplx<T>* work = p.work;
-  Slot<T> sl;
+  const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
   if constexpr (MODE == XI_SOLVE) {
-    sl = p.slots[p.batch.slot[blockIdx.y]];
     if (wg_read_flag(&sl.st->done)) return;
     work = sl.work;
   }
@@ -350,12 +348,12 @@ __global__ __launch_bounds__(kThreads) void k_strided(SParams<T> p) {
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x;
   cplx<T>* work = p.work;
-  double g0 = 0.0;
+  const SolveState* st = nullptr;
   if (work == nullptr) {
-    const Slot<T>& sl = p.slots[p.batch.slot[blockIdx.y]];
+    const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
     if (wg_read_flag(&sl.st->done)) return;
     work = sl.work;
-    g0 = sl.g0;
+    st = sl.st;
   }
   const int B = p.B, lgB = p.lgB, L = p.L, Lin = p.Lin;
   const int pen0 = blockIdx.x * B;
@@ -390,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void k_strided(SParams<T> p) {
         const int kyf = min(ky, p.Ly - ky);
         const int kzf = min(t, p.Lz - t);
         T m = p.table[((size_t)kzf * Lyh + kyf) * p.Kx + kx];
-        if (p.k0_from_slot && pen == 0 && t == 0) m = T(g0);
+        if (p.k0_from_slot && pen == 0 && t == 0) m = T(st->g0);
         buf[e] = cscale(buf[e], m);
       }
     }
@@ -426,7 +424,7 @@ template <typename T> int xpass_groups(const XParams<T>& p) {
 
 template <typename T> void launch_xfwd(int mode, const XParams<T>& p, hipStream_t s) {
   if (mode != XF_GEN_FREE && fast_length(p.g.Lx) && fast_xfwd<T>(mode, p, s)) return;
-  const dim3 grid(generic_xpass_groups(p), p.slots ? p.batch.n : 1);
+  const dim3 grid(generic_xpass_groups(p), p.has_slots ? p.batch.n : 1);
   const size_t lds = (size_t)p.P * p.g.Lx * sizeof(cplx<T>);
   if (mode == XF_SOLVE) hipLaunchKernelGGL((k_xfwd<T, XF_SOLVE>), grid, dim3(kThreads), lds, s, p);
   else if (mode == XF_REAL) hipLaunchKernelGGL((k_xfwd<T, XF_REAL>), grid, dim3(kThreads), lds, s, p);
@@ -435,7 +433,7 @@ template <typename T> void launch_xfwd(int mode, const XParams<T>& p, hipStream_
 
 template <typename T> void launch_xinv(int mode, const XParams<T>& p, hipStream_t s) {
   if (fast_length(p.g.Lx) && fast_xinv<T>(mode, p, s)) return;
-  const dim3 grid(generic_xpass_groups(p), p.slots ? p.batch.n : 1);
+  const dim3 grid(generic_xpass_groups(p), p.has_slots ? p.batch.n : 1);
   const size_t lds = (size_t)p.P * p.g.Lx * sizeof(cplx<T>);
   if (mode == XI_SOLVE) hipLaunchKernelGGL((k_xinv<T, XI_SOLVE>), grid, dim3(kThreads), lds, s, p);
   else hipLaunchKernelGGL((k_xinv<T, XI_REAL>), grid, dim3(kThreads), lds, s, p);

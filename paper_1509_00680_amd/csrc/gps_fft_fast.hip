@@ -44,12 +44,11 @@ void k_fstrided(SParams<T> p) {
   __shared__ cplx<T> lds[L * PITCH];
   const int tid = threadIdx.x;
   cplx<T>* work = p.work;
-  double g0 = 0.0;
+  const SolveState* st = nullptr;
   if (work == nullptr) {
-    const Slot<T>& sl = p.slots[p.batch.slot[blockIdx.y]];
-    if (wg_read_flag(&sl.st->done)) return;
+    const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
     work = sl.work;
-    g0 = sl.g0;
+    st = sl.st;
   }
   const int b = tid & (B - 1);
   const int q = tid / B;
@@ -63,15 +62,20 @@ void k_fstrided(SParams<T> p) {
   const size_t es = (size_t)p.elem_stride;
   const cplx<T>* __restrict__ tw = p.tw;
 
+  // the stop flag is read after the tile loads are issued, so both travel
+  // together (a stopped solve wastes the loads, never a round trip)
   cplx<T> y[L2];
   if constexpr (MODE != ST_INV) {
+    cplx<T> x[L1];
     if (q < L2) {
-      cplx<T> x[L1];
 #pragma unroll
       for (int n1 = 0; n1 < L1; ++n1) {
         const int t = L2 * n1 + q;
         x[n1] = (pv && t < p.Lin) ? work[base + t * es] : cmk(T(0), T(0));
       }
+    }
+    if (st && wg_read_flag(&st->done)) return;
+    if (q < L2) {
       reg_fft<T, false, L1>(x);
 #pragma unroll
       for (int k1 = 1; k1 < L1; ++k1) x[k1] = cmul(x[k1], tw[q * k1]);
@@ -106,7 +110,7 @@ void k_fstrided(SParams<T> p) {
           const int kz = q + L1 * k2;
           const int kzf = min(kz, L - kz);
           T m = row[kzf * zs];
-          if (p.k0_from_slot && pen == 0 && kz == 0) m = T(g0);
+          if (p.k0_from_slot && pen == 0 && kz == 0) m = T(st->g0);
           y[k2] = cscale(y[k2], m);
         }
       }
@@ -120,6 +124,7 @@ void k_fstrided(SParams<T> p) {
         y[k2] = (pv && kk < p.Lin) ? work[base + kk * es] : cmk(T(0), T(0));
       }
     }
+    if (st && wg_read_flag(&st->done)) return;
   }
   // inverse transform (ST_CONV second half, ST_INV)
   if (q < L1) {
@@ -178,17 +183,11 @@ void k_fxfwd(XParams<T> p) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int row0 = tile * 2 * P;
   cplx<T>* work = p.work;
-  Slot<T> sl;
-  double alpha = 0.0;
-  bool upd = false;
-  if constexpr (MODE == XF_SOLVE) {
-    sl = p.slots[p.batch.slot[blockIdx.y]];
-    int k;
-    if (!xfwd_head(sl, p.n_vec_parts, &k, &alpha)) return;
-    upd = k > 0;
-    work = sl.work;
-  }
-  // phase 1: all loads of this thread
+  const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
+  if constexpr (MODE == XF_SOLVE) work = sl.work;
+  // phase 1: all loads of this thread, issued before the iteration head so
+  // that their latency and the head's (flag, partial sums) overlap; p, Ap and
+  // phi are loaded even at k = 0 (unused there)
   T rv[EIN], sv[EIN], pv[EIN], av[EIN];
   double fv[EIN];
 #pragma unroll
@@ -204,15 +203,20 @@ void k_fxfwd(XParams<T> p) {
       if constexpr (MODE == XF_SOLVE) {
         rv[i] = sl.r[o];
         sv[i] = sl.isq[o];
-        if (upd) {
-          pv[i] = sl.p[o];
-          av[i] = sl.ap[o];
-          fv[i] = sl.phi[o];
-        }
+        pv[i] = sl.p[o];
+        av[i] = sl.ap[o];
+        fv[i] = sl.phi[o];
       } else {
         rv[i] = T(p.in_real[o]);
       }
     }
+  }
+  double alpha = 0.0;
+  bool upd = false;
+  if constexpr (MODE == XF_SOLVE) {
+    int k;
+    if (!xfwd_head(sl, p.n_vec_parts, &k, &alpha)) return;
+    upd = k > 0;
   }
   // phase 2: update, scale, stage the rows in LDS
   double mu = 0.0;
@@ -319,12 +323,8 @@ void k_fxinv(XParams<T> p) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int row0 = tile * 2 * P;
   cplx<T>* work = p.work;
-  Slot<T> sl;
-  if constexpr (MODE == 0) {
-    sl = p.slots[p.batch.slot[blockIdx.y]];
-    if (wg_read_flag(&sl.st->done)) return;
-    work = sl.work;
-  }
+  const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
+  if constexpr (MODE == 0) work = sl.work;
   cplx<T> xa[EIN], xb[EIN];
 #pragma unroll
   for (int i = 0; i < EIN; ++i) {
@@ -338,6 +338,23 @@ void k_fxinv(XParams<T> p) {
       if (ra < p.nrows) xa[i] = work[xrow_offset(p, ra, Kx) + kk];
       if (rb < p.nrows) xb[i] = work[xrow_offset(p, rb, Kx) + kk];
     }
+  }
+  // epilogue operands are independent of the transform: load them now too
+  T sv[MODE == 0 ? EOUT : 1], rv[MODE == 0 ? EOUT : 1];
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int i = 0; i < EOUT; ++i) {
+      const int e = tid + i * NT;
+      const int row = e / Lout;
+      const int xx = e - row * Lout;
+      const int grow = row0 + row;
+      if (e < NOUT && grow < p.nrows) {
+        const size_t o = (size_t)grow * p.in_row_stride + xx;
+        sv[i] = sl.isq[o];
+        rv[i] = sl.r[o];
+      }
+    }
+    if (wg_read_flag(&sl.st->done)) return;
   }
 #pragma unroll
   for (int i = 0; i < EIN; ++i) {
@@ -386,19 +403,6 @@ void k_fxinv(XParams<T> p) {
   }
   __syncthreads();
   if constexpr (MODE == 0) {
-    T sv[EOUT], rv[EOUT];
-#pragma unroll
-    for (int i = 0; i < EOUT; ++i) {
-      const int e = tid + i * NT;
-      const int row = e / Lout;
-      const int xx = e - row * Lout;
-      const int grow = row0 + row;
-      if (e < NOUT && grow < p.nrows) {
-        const size_t o = (size_t)grow * p.in_row_stride + xx;
-        sv[i] = sl.isq[o];
-        rv[i] = sl.r[o];
-      }
-    }
     double acc = 0.0, acc2 = 0.0;
 #pragma unroll
     for (int i = 0; i < EOUT; ++i) {
@@ -477,7 +481,7 @@ bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s) {
   if (mode != XF_SOLVE && mode != XF_REAL) return false;
   const bool pad = 2 * p.Lin == p.g.Lx;
   if (!pad && p.Lin != p.g.Lx) return false;
-  const dim3 grid(fast_xpass_groups(p.nrows), p.slots ? p.batch.n : 1);
+  const dim3 grid(fast_xpass_groups(p.nrows), p.has_slots ? p.batch.n : 1);
   switch (p.g.Lx) {
 #define GPS_CASE(LL, A, BB)                                                                      \
   case LL: {                                                                                     \
@@ -501,7 +505,7 @@ template <typename T>
 bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s) {
   const bool pad = 2 * p.Lout == p.g.Lx;
   if (!pad && p.Lout != p.g.Lx) return false;
-  const dim3 grid(fast_xpass_groups(p.nrows), p.slots ? p.batch.n : 1);
+  const dim3 grid(fast_xpass_groups(p.nrows), p.has_slots ? p.batch.n : 1);
   switch (p.g.Lx) {
 #define GPS_CASE(LL, A, BB)                                                                      \
   case LL: {                                                                                     \

@@ -30,7 +30,6 @@ __host__ __device__ inline int vec_groups(long long n) {
 
 constexpr int kMaxStages = 16;
 constexpr int kMaxLen = 1024;        // longest supported FFT length
-constexpr int kMaxBatch = 32;        // problems per batched launch
 
 template <typename T> struct cplx { T x, y; };
 
@@ -55,6 +54,10 @@ struct SolveState {
   double rho_sum;    // sum rho, sum |rho| and sum rho^2 of the right-hand side
   double rho_abs;
   double rho_sq;
+  // per-solve parameters (set by the reset kernel)
+  double abs_thr;    // absolute stop threshold on ||r||
+  double rel_thr;    // relative stop threshold on ||r|| / ||r_0||
+  double g0;         // periodic k = 0 multiplier of the preconditioner
 };
 
 // Input-check flags (SolveState::err)
@@ -80,11 +83,16 @@ template <typename T> struct Slot {
   double *part_aux;           // ionic-update / energy partials (2 per WG)
   double *hist;               // per-iteration history: delta, beta, alpha, ||r||^2
   SolveState *st;
-  double g0;                  // periodic k = 0 multiplier of the preconditioner
-  double abs_thr;             // absolute stop threshold on ||r||
-  double rel_thr;             // relative stop threshold on ||r|| / ||r_0||
   int maxit;
   int hist_cap;
+};
+
+// Problems per launch.  The slot table travels by value in the kernel
+// arguments (constant memory), so a work-group finds its buffers without a
+// dependent global load, and a captured graph stays valid across solves.
+constexpr int kArgSlots = 1;
+template <typename T> struct SlotTable {
+  Slot<T> s[kArgSlots];
 };
 
 // Problems of one batched launch: blockIdx.y indexes these arrays.  Each
@@ -92,7 +100,7 @@ template <typename T> struct Slot {
 // (or a replayed graph of launches) needs no per-iteration arguments.
 struct Batch {
   int n;
-  int slot[kMaxBatch];        // index into the device slot table
+  int slot[kArgSlots];        // index into the slot table
 };
 
 // Geometry of one plan, passed by value to kernels.

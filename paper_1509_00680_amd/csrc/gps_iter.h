@@ -62,7 +62,7 @@ __device__ __forceinline__ bool direction_head(const Slot<T>& sl, int n_x_parts,
     rsum = sum_partials(sl.part_init + 1, n_vec_parts, 4);
     rabs = sum_partials(sl.part_init + 2, n_vec_parts, 4);
     const int err = wg_read_flag(&sl.st->err);
-    thr2 = fmax(sl.abs_thr * sl.abs_thr, sl.rel_thr * sl.rel_thr * rr);
+    thr2 = fmax(sl.st->abs_thr * sl.st->abs_thr, sl.st->rel_thr * sl.st->rel_thr * rr);
     if (err & kErrNonFinite) status = GPS_E_NONFINITE;
     else if (err & kErrEpsNonPositive) status = GPS_E_INVALID;
     else if (check_neutral && fabs(rsum) > 1e-10 * rabs) status = GPS_E_INVALID;

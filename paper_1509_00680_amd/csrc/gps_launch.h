@@ -27,7 +27,8 @@ template <typename T> struct XParams {
   double* out_real;
   cplx<T>* work;
   // XF_SOLVE / XI_SOLVE: the problems of the batch
-  const Slot<T>* slots;
+  SlotTable<T> tab;
+  int has_slots;
   Batch batch;
   int n_vec_parts;          // partial sums written by the direction kernel
   int periodic_mean;        // accumulate sum r/sqrt(eps) (periodic)
@@ -52,9 +53,9 @@ template <typename T> struct SParams {
   // ST_CONV: multiply by a real, even table folded to (Lz/2+1)(Ly/2+1)Kx
   const T* table;
   int Kx, Ly, Lz;
-  int k0_from_slot;         // periodic: the k = 0 multiplier is slot.g0
+  int k0_from_slot;         // periodic: the k = 0 multiplier is the solve state's g0
   cplx<T>* work;            // explicit buffer, or null to use the slots
-  const Slot<T>* slots;
+  SlotTable<T> tab;
   Batch batch;
 };
 template <typename T> void launch_strided(int mode, const SParams<T>& p, hipStream_t s);
@@ -89,21 +90,24 @@ struct IonParams {
   const double* eps;
 };
 
-template <typename T> void launch_reset_state(const Slot<T>* slots, const Batch& b, hipStream_t s);
-template <typename T> void launch_init(const Slot<T>* slots, const Batch& b, const double* rho,
+template <typename T> void launch_reset_state(const SlotTable<T>& tab, const Batch& b,
+                                              double abs_thr, double rel_thr, hipStream_t s);
+template <typename T> void launch_set_g0(const SlotTable<T>& tab, const Batch& b, long long n,
+                                         double norm, hipStream_t s);
+template <typename T> void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho,
                                        const double* eps, long long n, hipStream_t s);
-template <typename T> void launch_qfield(const Slot<T>* slots, const Batch& b, const Geom& g,
+template <typename T> void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g,
                                          int fd_half, const double* lap_sq, double kappa_coef,
                                          const double* eps, const double* gamma,
                                          double eps_bulk, hipStream_t s);
-template <typename T> void launch_direction(const Slot<T>* slots, const Batch& b, long long n,
+template <typename T> void launch_direction(const SlotTable<T>& tab, const Batch& b, long long n,
                                             int n_xparts, int periodic, int check_neutral,
                                             hipStream_t s);
-template <typename T> void launch_ion_update(const Slot<T>* slots, const Batch& b, long long n,
+template <typename T> void launch_ion_update(const SlotTable<T>& tab, const Batch& b, long long n,
                                              const IonParams& ip, int first, hipStream_t s);
-template <typename T> void launch_energy(const Slot<T>* slots, const Batch& b, const double* rho,
+template <typename T> void launch_energy(const SlotTable<T>& tab, const Batch& b, const double* rho,
                                          long long n, hipStream_t s);
-template <typename T> void launch_zero_ion(const Slot<T>* slots, const Batch& b, long long n,
+template <typename T> void launch_zero_ion(const SlotTable<T>& tab, const Batch& b, long long n,
                                            hipStream_t s);
 
 }  // namespace gps

@@ -132,16 +132,40 @@ void launch_periodic_table(const Geom& g, int laplacian, double* t64, float* t32
 // solve-state reset (a kernel rather than a memset, so it may sit in a graph)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_reset_state(const Slot<T>* __restrict__ slots, Batch b) {
+__global__ void k_reset_state(SlotTable<T> tab, Batch b, double abs_thr, double rel_thr) {
   if (threadIdx.x == 0) {
-    SolveState* st = slots[b.slot[blockIdx.x]].st;
-    *st = SolveState{};
+    SolveState* st = tab.s[b.slot[blockIdx.x]].st;
+    SolveState z{};
+    z.abs_thr = abs_thr;
+    z.rel_thr = rel_thr;
+    *st = z;
   }
 }
 
 template <typename T>
-void launch_reset_state(const Slot<T>* slots, const Batch& b, hipStream_t s) {
-  hipLaunchKernelGGL((k_reset_state<T>), dim3(b.n), dim3(64), 0, s, slots, b);
+void launch_reset_state(const SlotTable<T>& tab, const Batch& b, double abs_thr, double rel_thr,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((k_reset_state<T>), dim3(b.n), dim3(64), 0, s, tab, b, abs_thr, rel_thr);
+}
+
+// Periodic boundaries with ions: the k = 0 multiplier 4 pi / mean(kappa2/eps)
+// (divided by the transform size) from the partials of the q kernel.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_set_g0(SlotTable<T> tab, Batch b, int nparts,
+                                                     double npts, double norm) {
+  const Slot<T> sl = tab.s[b.slot[blockIdx.x]];
+  const double sum = sum_partials(sl.part_aux, nparts, 2);
+  if (threadIdx.x == 0) {
+    const double mean = sum / npts;
+    sl.st->g0 = mean > 0.0 ? 4.0 * kPi / mean * norm : 0.0;
+  }
+}
+
+template <typename T>
+void launch_set_g0(const SlotTable<T>& tab, const Batch& b, long long n, double norm,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((k_set_g0<T>), dim3(b.n), dim3(kThreads), 0, s, tab, b, vec_groups(n),
+                     double(n), norm);
 }
 
 // ---------------------------------------------------------------------------
@@ -149,10 +173,10 @@ void launch_reset_state(const Slot<T>* slots, const Batch& b, hipStream_t s) {
 // partials (4 per group): ||r0||^2, sum rho, sum |rho|, sum rho^2
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_init(const Slot<T>* __restrict__ slots, Batch b,
+__global__ __launch_bounds__(kThreads) void k_init(SlotTable<T> tab, Batch b,
                                                    const double* __restrict__ rho,
                                                    const double* __restrict__ eps, long long n) {
-  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
   const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   int err = 0;
@@ -191,9 +215,9 @@ __global__ __launch_bounds__(kThreads) void k_init(const Slot<T>* __restrict__ s
 }
 
 template <typename T>
-void launch_init(const Slot<T>* slots, const Batch& b, const double* rho, const double* eps,
+void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho, const double* eps,
                  long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_init<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, rho,
+  hipLaunchKernelGGL((k_init<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, rho,
                      eps, n);
 }
 
@@ -206,14 +230,14 @@ void launch_init(const Slot<T>* slots, const Batch& b, const double* rho, const 
 struct FdWeights { double c[9]; };
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_qfield(const Slot<T>* __restrict__ slots, Batch b,
+__global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b,
                                                      Geom g, int M, FdWeights w,
                                                      const double* __restrict__ lap_sq,
                                                      double kappa_coef,
                                                      const double* __restrict__ eps,
                                                      const double* __restrict__ gamma,
                                                      double eps_bulk) {
-  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long plane = (long long)g.nx * g.ny;
   const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
@@ -283,11 +307,11 @@ static FdWeights fd_weights(int M) {
 }
 
 template <typename T>
-void launch_qfield(const Slot<T>* slots, const Batch& b, const Geom& g, int fd_half,
+void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g, int fd_half,
                    const double* lap_sq, double kappa_coef, const double* eps,
                    const double* gamma, double eps_bulk, hipStream_t s) {
   const long long n = (long long)g.nx * g.ny * g.nz;
-  hipLaunchKernelGGL((k_qfield<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, g,
+  hipLaunchKernelGGL((k_qfield<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, g,
                      fd_half, fd_weights(fd_half), lap_sq, kappa_coef, eps, gamma, eps_bulk);
 }
 
@@ -298,10 +322,25 @@ void launch_qfield(const Slot<T>* slots, const Batch& b, const Geom& g, int fd_h
 //   p = v + beta p;  Ap = A v + beta Ap;  partial (p, Ap)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_direction(const Slot<T>* __restrict__ slots, Batch b,
-                                                        long long n, int n_xparts, int periodic,
+__global__ __launch_bounds__(kThreads) void k_direction(SlotTable<T> tab, Batch b, long long n,
+                                                        int n_xparts, int periodic,
                                                         int check_neutral) {
-  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  // operands first: their loads overlap the head's flag and partial-sum reads
+  T vv[kVec], rv[kVec], qv[kVec], pv[kVec], av[kVec], sv[kVec];
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) {
+      vv[j] = sl.v[i];
+      rv[j] = sl.r[i];
+      qv[j] = sl.qk[i];
+      pv[j] = sl.p[i];
+      av[j] = sl.ap[i];
+      sv[j] = periodic ? sl.s[i] : T(0);
+    }
+  }
   int k;
   double delta;
   if (!direction_head(sl, n_xparts, vec_groups(n), check_neutral, &k, &delta)) return;
@@ -310,23 +349,19 @@ __global__ __launch_bounds__(kThreads) void k_direction(const Slot<T>* __restric
   double mu = 0.0;
   if (periodic) mu = sum_partials(sl.part_mu, n_xparts) / double(n);
   const T tb = T(beta), tmu = T(mu), fpi = T(kFourPi);
-  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < kVec; ++j) {
     const long long i = base + (long long)j * kThreads;
     if (i < n) {
-      const T v = sl.v[i], r = sl.r[i], q = sl.qk[i];
-      T rr = r;
-      if (periodic) rr = r - sl.s[i] * tmu;
-      const T av = -q * v - fpi * rr;
+      const T av_ = -qv[j] * vv[j] - fpi * (periodic ? rv[j] - sv[j] * tmu : rv[j]);
       T pn, apn;
       if (k == 0) {
-        pn = v;
-        apn = av;
+        pn = vv[j];
+        apn = av_;
       } else {
-        pn = v + tb * sl.p[i];
-        apn = av + tb * sl.ap[i];
+        pn = vv[j] + tb * pv[j];
+        apn = av_ + tb * av[j];
       }
       sl.p[i] = pn;
       sl.ap[i] = apn;
@@ -342,9 +377,9 @@ __global__ __launch_bounds__(kThreads) void k_direction(const Slot<T>* __restric
 }
 
 template <typename T>
-void launch_direction(const Slot<T>* slots, const Batch& b, long long n, int n_xparts,
+void launch_direction(const SlotTable<T>& tab, const Batch& b, long long n, int n_xparts,
                       int periodic, int check_neutral, hipStream_t s) {
-  hipLaunchKernelGGL((k_direction<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, n,
+  hipLaunchKernelGGL((k_direction<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n,
                      n_xparts, periodic, check_neutral);
 }
 
@@ -358,9 +393,9 @@ void launch_direction(const Slot<T>* slots, const Batch& b, long long n, int n_x
 // partials (4 per group): ||r||^2, 0, 0, ||ion_new - ion_old||^2
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_ion_update(const Slot<T>* __restrict__ slots,
-                                                         Batch b, long long n, IonParams ip) {
-  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+__global__ __launch_bounds__(kThreads) void k_ion_update(SlotTable<T> tab, Batch b, long long n,
+                                                         IonParams ip) {
+  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
   const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
   double a0 = 0.0, a3 = 0.0;
   const T fpi = T(kFourPi);
@@ -414,16 +449,16 @@ __global__ __launch_bounds__(kThreads) void k_ion_update(const Slot<T>* __restri
 }
 
 template <typename T>
-void launch_ion_update(const Slot<T>* slots, const Batch& b, long long n, const IonParams& ip,
+void launch_ion_update(const SlotTable<T>& tab, const Batch& b, long long n, const IonParams& ip,
                        int, hipStream_t s) {
-  hipLaunchKernelGGL((k_ion_update<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b,
+  hipLaunchKernelGGL((k_ion_update<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b,
                      n, ip);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_zero_ion(const Slot<T>* __restrict__ slots, Batch b,
+__global__ __launch_bounds__(kThreads) void k_zero_ion(SlotTable<T> tab, Batch b,
                                                        long long n) {
-  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
   const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
 #pragma unroll
   for (int j = 0; j < kVec; ++j) {
@@ -433,17 +468,17 @@ __global__ __launch_bounds__(kThreads) void k_zero_ion(const Slot<T>* __restrict
 }
 
 template <typename T>
-void launch_zero_ion(const Slot<T>* slots, const Batch& b, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_zero_ion<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, n);
+void launch_zero_ion(const SlotTable<T>& tab, const Batch& b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_zero_ion<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n);
 }
 
 // ---------------------------------------------------------------------------
 // energy partials: sum rho phi (2 per group in part_aux: sum rho phi, 0)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_energy(const Slot<T>* __restrict__ slots, Batch b,
+__global__ __launch_bounds__(kThreads) void k_energy(SlotTable<T> tab, Batch b,
                                                      const double* __restrict__ rho, long long n) {
-  const Slot<T> sl = slots[b.slot[blockIdx.y]];
+  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
   const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
   double acc = 0.0;
 #pragma unroll
@@ -459,23 +494,26 @@ __global__ __launch_bounds__(kThreads) void k_energy(const Slot<T>* __restrict__
 }
 
 template <typename T>
-void launch_energy(const Slot<T>* slots, const Batch& b, const double* rho, long long n,
+void launch_energy(const SlotTable<T>& tab, const Batch& b, const double* rho, long long n,
                    hipStream_t s) {
-  hipLaunchKernelGGL((k_energy<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, slots, b, rho, n);
+  hipLaunchKernelGGL((k_energy<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, rho, n);
 }
 
 #define GPS_INST(T)                                                                              \
-  template void launch_reset_state<T>(const Slot<T>*, const Batch&, hipStream_t);                \
-  template void launch_init<T>(const Slot<T>*, const Batch&, const double*, const double*,       \
+  template void launch_reset_state<T>(const SlotTable<T>&, const Batch&, double, double,            \
+                                      hipStream_t);                                              \
+  template void launch_set_g0<T>(const SlotTable<T>&, const Batch&, long long, double,            \
+                                 hipStream_t);                                                   \
+  template void launch_init<T>(const SlotTable<T>&, const Batch&, const double*, const double*,       \
                                long long, hipStream_t);                                          \
-  template void launch_qfield<T>(const Slot<T>*, const Batch&, const Geom&, int, const double*,  \
+  template void launch_qfield<T>(const SlotTable<T>&, const Batch&, const Geom&, int, const double*,  \
                                  double, const double*, const double*, double, hipStream_t);     \
-  template void launch_direction<T>(const Slot<T>*, const Batch&, long long, int, int, int,      \
+  template void launch_direction<T>(const SlotTable<T>&, const Batch&, long long, int, int, int,      \
                                     hipStream_t);                                                \
-  template void launch_ion_update<T>(const Slot<T>*, const Batch&, long long, const IonParams&,  \
+  template void launch_ion_update<T>(const SlotTable<T>&, const Batch&, long long, const IonParams&,  \
                                      int, hipStream_t);                                          \
-  template void launch_zero_ion<T>(const Slot<T>*, const Batch&, long long, hipStream_t);        \
-  template void launch_energy<T>(const Slot<T>*, const Batch&, const double*, long long,         \
+  template void launch_zero_ion<T>(const SlotTable<T>&, const Batch&, long long, hipStream_t);        \
+  template void launch_energy<T>(const SlotTable<T>&, const Batch&, const double*, long long,         \
                                  hipStream_t);
 GPS_INST(float)
 GPS_INST(double)
