@@ -41,8 +41,15 @@ void k_fstrided(SParams<T> p) {
   constexpr int B = FastTile<T>::B;
   constexpr int L = L1 * L2;
   constexpr int PITCH = B + 1;
+  constexpr int NT = round64(B * L1);
   __shared__ cplx<T> lds[L * PITCH];
+  __shared__ cplx<T> twl[L];
   const int tid = threadIdx.x;
+  // twiddles to LDS: their loads are issued first and overlap the tile loads
+  cplx<T> twv[(L + NT - 1) / NT];
+#pragma unroll
+  for (int i = 0; i < (L + NT - 1) / NT; ++i)
+    if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
   cplx<T>* work = p.work;
   const SolveState* st = nullptr;
   if (work == nullptr) {
@@ -60,7 +67,7 @@ void k_fstrided(SParams<T> p) {
     base = (size_t)grp * p.group_stride + (pen - grp * p.per_group);
   }
   const size_t es = (size_t)p.elem_stride;
-  const cplx<T>* __restrict__ tw = p.tw;
+  const cplx<T>* tw = twl;
 
   // the stop flag is read after the tile loads are issued, so both travel
   // together (a stopped solve wastes the loads, never a round trip)
@@ -74,7 +81,28 @@ void k_fstrided(SParams<T> p) {
         x[n1] = (pv && t < p.Lin) ? work[base + t * es] : cmk(T(0), T(0));
       }
     }
-    if (st && wg_read_flag(&st->done)) return;
+    // spectrum multipliers of the z pass: prefetched with the tile
+    T gm[MODE == ST_CONV ? L2 : 1];
+    if constexpr (MODE == ST_CONV) {
+      if (pv && q < L1) {
+        const int Lyh = p.Ly / 2 + 1;
+        const int ky = pen / p.Kx;
+        const int kx = pen - ky * p.Kx;
+        const int kyf = min(ky, p.Ly - ky);
+        const T* __restrict__ row = p.table + (size_t)kyf * p.Kx + kx;
+        const size_t zs = (size_t)Lyh * p.Kx;
+#pragma unroll
+        for (int k2 = 0; k2 < L2; ++k2) {
+          const int kz = q + L1 * k2;
+          gm[k2] = row[min(kz, L - kz) * zs];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < (L + NT - 1) / NT; ++i)
+      if (tid + i * NT < L) twl[tid + i * NT] = twv[i];
+    if (st && wg_read_flag(&st->done)) return;   // (includes a barrier)
+    if (st == nullptr) __syncthreads();
     if (q < L2) {
       reg_fft<T, false, L1>(x);
 #pragma unroll
@@ -99,17 +127,10 @@ void k_fstrided(SParams<T> p) {
       return;
     } else {
       if (pv && q < L1) {
-        const int Lyh = p.Ly / 2 + 1;
-        const int ky = pen / p.Kx;
-        const int kx = pen - ky * p.Kx;
-        const int kyf = min(ky, p.Ly - ky);
-        const T* __restrict__ row = p.table + (size_t)kyf * p.Kx + kx;
-        const size_t zs = (size_t)Lyh * p.Kx;
 #pragma unroll
         for (int k2 = 0; k2 < L2; ++k2) {
           const int kz = q + L1 * k2;
-          const int kzf = min(kz, L - kz);
-          T m = row[kzf * zs];
+          T m = gm[k2];
           if (p.k0_from_slot && pen == 0 && kz == 0) m = T(st->g0);
           y[k2] = cscale(y[k2], m);
         }
@@ -124,7 +145,11 @@ void k_fstrided(SParams<T> p) {
         y[k2] = (pv && kk < p.Lin) ? work[base + kk * es] : cmk(T(0), T(0));
       }
     }
-    if (st && wg_read_flag(&st->done)) return;
+#pragma unroll
+    for (int i = 0; i < (L + NT - 1) / NT; ++i)
+      if (tid + i * NT < L) twl[tid + i * NT] = twv[i];
+    if (st && wg_read_flag(&st->done)) return;   // (includes a barrier)
+    if (st == nullptr) __syncthreads();
   }
   // inverse transform (ST_CONV second half, ST_INV)
   if (q < L1) {
@@ -178,6 +203,7 @@ void k_fxfwd(XParams<T> p) {
   constexpr int NOUT = P * Kx;                     // complex outputs per row parity
   constexpr int EOUT = (NOUT + NT - 1) / NT;
   __shared__ cplx<T> lds[L * PITCH];
+  __shared__ cplx<T> twl[L];
   T* ldsr = reinterpret_cast<T*>(lds);
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -185,6 +211,11 @@ void k_fxfwd(XParams<T> p) {
   cplx<T>* work = p.work;
   const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
   if constexpr (MODE == XF_SOLVE) work = sl.work;
+  constexpr int ETW = (L + NT - 1) / NT;
+  cplx<T> twv[ETW];
+#pragma unroll
+  for (int i = 0; i < ETW; ++i)
+    if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
   // phase 1: all loads of this thread, issued before the iteration head so
   // that their latency and the head's (flag, partial sums) overlap; p, Ap and
   // phi are loaded even at k = 0 (unused there)
@@ -250,10 +281,13 @@ void k_fxfwd(XParams<T> p) {
       if (e < P * (L - Lin)) lds[(Lin + e / P) * PITCH + (e % P)] = cmk(T(0), T(0));
     }
   }
+#pragma unroll
+  for (int i = 0; i < ETW; ++i)
+    if (tid + i * NT < L) twl[tid + i * NT] = twv[i];
   __syncthreads();
   const int pp = tid % P;
   const int q = tid / P;
-  const cplx<T>* __restrict__ tw = p.tw;
+  const cplx<T>* tw = twl;
   cplx<T> x[L1];
   if (q < L2) {
 #pragma unroll
@@ -318,6 +352,7 @@ void k_fxinv(XParams<T> p) {
   constexpr int NOUT = 2 * P * Lout;
   constexpr int EOUT = (NOUT + NT - 1) / NT;
   __shared__ cplx<T> lds[L * PITCH];
+  __shared__ cplx<T> twl[L];
   const T* ldsr = reinterpret_cast<const T*>(lds);
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -325,6 +360,11 @@ void k_fxinv(XParams<T> p) {
   cplx<T>* work = p.work;
   const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
   if constexpr (MODE == 0) work = sl.work;
+  constexpr int ETW = (L + NT - 1) / NT;
+  cplx<T> twv[ETW];
+#pragma unroll
+  for (int i = 0; i < ETW; ++i)
+    if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
   cplx<T> xa[EIN], xb[EIN];
 #pragma unroll
   for (int i = 0; i < EIN; ++i) {
@@ -372,10 +412,13 @@ void k_fxinv(XParams<T> p) {
       if (kk > 0 && km >= Kx) lds[km * PITCH + p2] = cmk(a.x + b.y, b.x - a.y);
     }
   }
+#pragma unroll
+  for (int i = 0; i < ETW; ++i)
+    if (tid + i * NT < L) twl[tid + i * NT] = twv[i];
   __syncthreads();
   const int pp = tid % P;
   const int q = tid / P;
-  const cplx<T>* __restrict__ tw = p.tw;
+  const cplx<T>* tw = twl;
   cplx<T> y[L2];
   if (q < L1) {
 #pragma unroll
