@@ -46,9 +46,52 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=5,
                     help="solves of the FP64 one-at-a-time comparator (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pass-times", action="store_true",
-                    help="also time every pass separately (extra solves)")
+    ap.add_argument("--no-pass-times", action="store_true",
+                    help="skip the per-pass kernel times (extra eager solves)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum wall time of the oracle sample (whole solves)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (10 times) and exit: the "
+                         "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "copies": 10}))
+
+
+def kernel_source_digest():
+    """sha256 over the HIP sources (names and contents, sorted by name)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1509_00680_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE passes
+    (scaled by a plain copy's counts), or None once the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def timed_solves(torch, plan, rho, eps, phi, tol, steps):
@@ -67,22 +110,32 @@ def timed_solves(torch, plan, rho, eps, phi, tol, steps):
     return time.perf_counter() - t0, lat, iters
 
 
-def cpu_baseline(prob, tol):
-    """The oracle as it stands, one full solve of the same workload."""
+def cpu_baseline(prob, tol, min_seconds):
+    """The oracle as it stands: whole FP64 solves of the same workload, repeated
+    until at least `min_seconds` have passed."""
     from oracle import green, pcg
     workers = min(16, os.cpu_count() or 1)
     solver = green.VacuumSolver(prob.shape, prob.h, prob.bc, workers=workers)
+    solves, iters = 0, 0
     t0 = time.perf_counter()
-    res = pcg.pcg_solve(prob.rho, prob.eps, prob.h, prob.bc, tol=tol, solver=solver)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
-            "sample": "one full FP64 solve of the same workload (%d iterations, %.1f s, "
-                      "scipy.fft workers=%d)" % (res.iterations, dt, workers),
-            "mgridpts_iter_per_s": prob.npoints * res.iterations / dt / 1e6}
+    while True:
+        res = pcg.pcg_solve(prob.rho, prob.eps, prob.h, prob.bc, tol=tol, solver=solver)
+        solves += 1
+        iters += res.iterations
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+    return {"value": solves / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": "%d full FP64 solves of the same workload (%d iterations each, %.1f s, "
+                      "scipy.fft workers=%d)" % (solves, res.iterations, dt, workers),
+            "mgridpts_iter_per_s": prob.npoints * iters / dt / 1e6}
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported "
               "(requests shard one plan per GPU, see DESIGN.md)" % args.gpus, file=sys.stderr)
@@ -118,7 +171,7 @@ def main():
     achieved = tz["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
 
     pass_ms = {}
-    if args.pass_times:
+    if not args.no_pass_times:
         for k in PASSES:
             plan.set_timing(k)
             timed_solves(torch, plan, rho, eps, phi, args.tol, 2)
@@ -162,7 +215,9 @@ def main():
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "energy": info["energy"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("traffic_zpass_molecule96_free_mixed.json")
+                     if (args.n, args.precision) == (96, "mixed") else None,
                      "kernel": "z pass (forward FFT, Green's spectrum, inverse FFT)",
                      "avg_us": avg_ms * 1e3, "bytes_per_launch": tz["bytes_per_launch"],
                      "launches": tz["launches"]},
@@ -171,7 +226,7 @@ def main():
     if pass_ms:
         out["passes"] = pass_ms
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.tol)
+        out["cpu_baseline"] = cpu_baseline(prob, args.tol, args.cpu_seconds)
     print(json.dumps(out))
 
 

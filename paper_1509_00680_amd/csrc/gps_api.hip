@@ -19,6 +19,11 @@
 
 using namespace gps;
 
+gps::LaunchEvents& gps::launch_events() {
+  static thread_local LaunchEvents ev{nullptr, nullptr};
+  return ev;
+}
+
 namespace {
 
 struct TimedLaunch {
@@ -365,25 +370,24 @@ hipEvent_t next_event(gps_plan* pl) {
   return pl->ev_pool[pl->ev_used++];
 }
 
-// Brackets one launch with two events on stream s (inside a graph capture
-// the records become graph nodes).
+// Binds two events to the next launch on stream s: the events take the
+// kernel's own start and end timestamps (not the time the stream spent
+// reaching it).  Only eager launches are timed.
 struct TimerScope {
   gps_plan* pl;
-  hipStream_t s;
   bool on;
   TimedLaunch tl{};
-  TimerScope(gps_plan* p, hipStream_t st, int kind, int k)
-      : pl(p), s(st), on(p->timing_kind == kind) {
+  TimerScope(gps_plan* p, hipStream_t, int kind, int k) : pl(p), on(p->timing_kind == kind) {
     if (on) {
       tl.k = k;
       tl.start = next_event(pl);
       tl.stop = next_event(pl);
-      ck(hipEventRecord(tl.start, s));
+      launch_events() = LaunchEvents{tl.start, tl.stop};
     }
   }
   ~TimerScope() {
     if (on) {
-      (void)hipEventRecord(tl.stop, s);
+      launch_events() = LaunchEvents{nullptr, nullptr};
       pl->ev_pending.push_back(tl);
     }
   }

@@ -426,26 +426,26 @@ template <typename T> void launch_xfwd(int mode, const XParams<T>& p, hipStream_
   if (mode != XF_GEN_FREE && fast_length(p.g.Lx) && fast_xfwd<T>(mode, p, s)) return;
   const dim3 grid(generic_xpass_groups(p), p.has_slots ? p.batch.n : 1);
   const size_t lds = (size_t)p.P * p.g.Lx * sizeof(cplx<T>);
-  if (mode == XF_SOLVE) hipLaunchKernelGGL((k_xfwd<T, XF_SOLVE>), grid, dim3(kThreads), lds, s, p);
-  else if (mode == XF_REAL) hipLaunchKernelGGL((k_xfwd<T, XF_REAL>), grid, dim3(kThreads), lds, s, p);
-  else hipLaunchKernelGGL((k_xfwd<T, XF_GEN_FREE>), grid, dim3(kThreads), lds, s, p);
+  if (mode == XF_SOLVE) GPS_LAUNCH((k_xfwd<T, XF_SOLVE>), grid, dim3(kThreads), lds, s, p);
+  else if (mode == XF_REAL) GPS_LAUNCH((k_xfwd<T, XF_REAL>), grid, dim3(kThreads), lds, s, p);
+  else GPS_LAUNCH((k_xfwd<T, XF_GEN_FREE>), grid, dim3(kThreads), lds, s, p);
 }
 
 template <typename T> void launch_xinv(int mode, const XParams<T>& p, hipStream_t s) {
   if (fast_length(p.g.Lx) && fast_xinv<T>(mode, p, s)) return;
   const dim3 grid(generic_xpass_groups(p), p.has_slots ? p.batch.n : 1);
   const size_t lds = (size_t)p.P * p.g.Lx * sizeof(cplx<T>);
-  if (mode == XI_SOLVE) hipLaunchKernelGGL((k_xinv<T, XI_SOLVE>), grid, dim3(kThreads), lds, s, p);
-  else hipLaunchKernelGGL((k_xinv<T, XI_REAL>), grid, dim3(kThreads), lds, s, p);
+  if (mode == XI_SOLVE) GPS_LAUNCH((k_xinv<T, XI_SOLVE>), grid, dim3(kThreads), lds, s, p);
+  else GPS_LAUNCH((k_xinv<T, XI_REAL>), grid, dim3(kThreads), lds, s, p);
 }
 
 template <typename T> void launch_strided(int mode, const SParams<T>& p, hipStream_t s) {
   if (fast_length(p.L) && fast_strided<T>(mode, p, s)) return;
   const dim3 grid((p.npencils + p.B - 1) / p.B, p.work ? 1 : p.batch.n);
   const size_t lds = (size_t)p.B * p.L * sizeof(cplx<T>);
-  if (mode == ST_FWD) hipLaunchKernelGGL((k_strided<T, ST_FWD>), grid, dim3(kThreads), lds, s, p);
-  else if (mode == ST_INV) hipLaunchKernelGGL((k_strided<T, ST_INV>), grid, dim3(kThreads), lds, s, p);
-  else hipLaunchKernelGGL((k_strided<T, ST_CONV>), grid, dim3(kThreads), lds, s, p);
+  if (mode == ST_FWD) GPS_LAUNCH((k_strided<T, ST_FWD>), grid, dim3(kThreads), lds, s, p);
+  else if (mode == ST_INV) GPS_LAUNCH((k_strided<T, ST_INV>), grid, dim3(kThreads), lds, s, p);
+  else GPS_LAUNCH((k_strided<T, ST_CONV>), grid, dim3(kThreads), lds, s, p);
 }
 
 template int xpass_groups<float>(const XParams<float>&);

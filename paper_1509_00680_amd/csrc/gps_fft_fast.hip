@@ -507,9 +507,9 @@ bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
 #define GPS_CASE(LL, A, BB)                                                                    \
   case LL: {                                                                                   \
     const dim3 blk(round64(B * A));                                                            \
-    if (mode == ST_FWD) hipLaunchKernelGGL((k_fstrided<T, A, BB, ST_FWD>), grid, blk, 0, s, p);  \
-    else if (mode == ST_INV) hipLaunchKernelGGL((k_fstrided<T, A, BB, ST_INV>), grid, blk, 0, s, p); \
-    else hipLaunchKernelGGL((k_fstrided<T, A, BB, ST_CONV>), grid, blk, 0, s, p);             \
+    if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD>), grid, blk, 0, s, p);  \
+    else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV>), grid, blk, 0, s, p); \
+    else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV>), grid, blk, 0, s, p);             \
     return true;                                                                               \
   }
     GPS_FAST_LENGTHS(GPS_CASE)
@@ -530,11 +530,11 @@ bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s) {
   case LL: {                                                                                     \
     const dim3 blk(xthreads<A>());                                                      \
     if (mode == XF_SOLVE) {                                                                      \
-      if (pad) hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_SOLVE, true>), grid, blk, 0, s, p);      \
-      else hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_SOLVE, false>), grid, blk, 0, s, p);         \
+      if (pad) GPS_LAUNCH((k_fxfwd<T, A, BB, XF_SOLVE, true>), grid, blk, 0, s, p);      \
+      else GPS_LAUNCH((k_fxfwd<T, A, BB, XF_SOLVE, false>), grid, blk, 0, s, p);         \
     } else {                                                                                     \
-      if (pad) hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_REAL, true>), grid, blk, 0, s, p);       \
-      else hipLaunchKernelGGL((k_fxfwd<T, A, BB, XF_REAL, false>), grid, blk, 0, s, p);          \
+      if (pad) GPS_LAUNCH((k_fxfwd<T, A, BB, XF_REAL, true>), grid, blk, 0, s, p);       \
+      else GPS_LAUNCH((k_fxfwd<T, A, BB, XF_REAL, false>), grid, blk, 0, s, p);          \
     }                                                                                            \
     return true;                                                                                 \
   }
@@ -554,11 +554,11 @@ bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s) {
   case LL: {                                                                                     \
     const dim3 blk(xthreads<A>());                                                      \
     if (mode == 0) {                                                                             \
-      if (pad) hipLaunchKernelGGL((k_fxinv<T, A, BB, 0, true>), grid, blk, 0, s, p);             \
-      else hipLaunchKernelGGL((k_fxinv<T, A, BB, 0, false>), grid, blk, 0, s, p);                \
+      if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, 0, true>), grid, blk, 0, s, p);             \
+      else GPS_LAUNCH((k_fxinv<T, A, BB, 0, false>), grid, blk, 0, s, p);                \
     } else {                                                                                     \
-      if (pad) hipLaunchKernelGGL((k_fxinv<T, A, BB, 1, true>), grid, blk, 0, s, p);             \
-      else hipLaunchKernelGGL((k_fxinv<T, A, BB, 1, false>), grid, blk, 0, s, p);                \
+      if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, 1, true>), grid, blk, 0, s, p);             \
+      else GPS_LAUNCH((k_fxinv<T, A, BB, 1, false>), grid, blk, 0, s, p);                \
     }                                                                                            \
     return true;                                                                                 \
   }

@@ -1,9 +1,35 @@
 // Host-side launchers of the libgps kernels (internal).
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "gps_internal.h"
 
 namespace gps {
+
+// ---- timed launches ---------------------------------------------------------
+
+// Events that the next launch made on this host thread binds to its dispatch
+// (start and end of the kernel's execution, the timestamps a kernel trace
+// reports); cleared by that launch.  Both null: plain launch.
+struct LaunchEvents {
+  hipEvent_t start;
+  hipEvent_t stop;
+};
+LaunchEvents& launch_events();
+
+#define GPS_LAUNCH(kern, grid, blk, shm, strm, ...)                                     \
+  do {                                                                                  \
+    ::gps::LaunchEvents& gps_ev_ = ::gps::launch_events();                              \
+    if (gps_ev_.start) {                                                                \
+      const ::gps::LaunchEvents gps_e_ = gps_ev_;                                       \
+      gps_ev_ = ::gps::LaunchEvents{nullptr, nullptr};                                  \
+      hipExtLaunchKernelGGL(kern, grid, blk, shm, strm, gps_e_.start, gps_e_.stop, 0,   \
+                            __VA_ARGS__);                                               \
+    } else {                                                                            \
+      hipLaunchKernelGGL(kern, grid, blk, shm, strm, __VA_ARGS__);                      \
+    }                                                                                   \
+  } while (0)
 
 // ---- FFT passes -----------------------------------------------------------
 

@@ -35,7 +35,7 @@ void launch_compress_table(const cplx<double>* full, int Kx, int Ly, int Lz, dou
                            double* t64, float* t32, hipStream_t s) {
   const long long n = (long long)(Lz / 2 + 1) * (Ly / 2 + 1) * Kx;
   const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
-  hipLaunchKernelGGL(k_compress_table, dim3(grid), dim3(kThreads), 0, s, full, Kx, Ly, Lz, scale,
+  GPS_LAUNCH(k_compress_table, dim3(grid), dim3(kThreads), 0, s, full, Kx, Ly, Lz, scale,
                      t64, t32);
 }
 
@@ -72,7 +72,7 @@ void launch_surface_gen(cplx<double>* buf, int Kx, int Lyh, int Lz, int nx, int 
                         double k0_offset, hipStream_t s) {
   const long long n = (long long)Kx * Lyh * Lz;
   const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
-  hipLaunchKernelGGL(k_surface_gen, dim3(grid), dim3(kThreads), 0, s, buf, Kx, Lyh, Lz, nx, ny, h,
+  GPS_LAUNCH(k_surface_gen, dim3(grid), dim3(kThreads), 0, s, buf, Kx, Lyh, Lz, nx, ny, h,
                      k0_offset);
 }
 
@@ -94,7 +94,7 @@ void launch_surface_compress(const cplx<double>* buf, int Kx, int Lyh, int Lz, d
                              double* t64, float* t32, hipStream_t s) {
   const long long n = (long long)Kx * Lyh * (Lz / 2 + 1);
   const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
-  hipLaunchKernelGGL(k_surface_compress, dim3(grid), dim3(kThreads), 0, s, buf, Kx, Lyh, Lz, scale,
+  GPS_LAUNCH(k_surface_compress, dim3(grid), dim3(kThreads), 0, s, buf, Kx, Lyh, Lz, scale,
                      t64, t32);
 }
 
@@ -125,7 +125,7 @@ __global__ void k_periodic_table(Geom g, int laplacian, double* __restrict__ t64
 void launch_periodic_table(const Geom& g, int laplacian, double* t64, float* t32, hipStream_t s) {
   const long long n = (long long)(g.Lz / 2 + 1) * (g.Ly / 2 + 1) * g.Kx;
   const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
-  hipLaunchKernelGGL(k_periodic_table, dim3(grid), dim3(kThreads), 0, s, g, laplacian, t64, t32);
+  GPS_LAUNCH(k_periodic_table, dim3(grid), dim3(kThreads), 0, s, g, laplacian, t64, t32);
 }
 
 // ---------------------------------------------------------------------------
@@ -145,7 +145,7 @@ __global__ void k_reset_state(SlotTable<T> tab, Batch b, double abs_thr, double 
 template <typename T>
 void launch_reset_state(const SlotTable<T>& tab, const Batch& b, double abs_thr, double rel_thr,
                         hipStream_t s) {
-  hipLaunchKernelGGL((k_reset_state<T>), dim3(b.n), dim3(64), 0, s, tab, b, abs_thr, rel_thr);
+  GPS_LAUNCH((k_reset_state<T>), dim3(b.n), dim3(64), 0, s, tab, b, abs_thr, rel_thr);
 }
 
 // Periodic boundaries with ions: the k = 0 multiplier 4 pi / mean(kappa2/eps)
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_set_g0(SlotTable<T> tab, Batch b, 
 template <typename T>
 void launch_set_g0(const SlotTable<T>& tab, const Batch& b, long long n, double norm,
                    hipStream_t s) {
-  hipLaunchKernelGGL((k_set_g0<T>), dim3(b.n), dim3(kThreads), 0, s, tab, b, vec_groups(n),
+  GPS_LAUNCH((k_set_g0<T>), dim3(b.n), dim3(kThreads), 0, s, tab, b, vec_groups(n),
                      double(n), norm);
 }
 
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotTable<T> tab, Batch b,
 template <typename T>
 void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho, const double* eps,
                  long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_init<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, rho,
+  GPS_LAUNCH((k_init<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, rho,
                      eps, n);
 }
 
@@ -311,7 +311,7 @@ void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g, int f
                    const double* lap_sq, double kappa_coef, const double* eps,
                    const double* gamma, double eps_bulk, hipStream_t s) {
   const long long n = (long long)g.nx * g.ny * g.nz;
-  hipLaunchKernelGGL((k_qfield<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, g,
+  GPS_LAUNCH((k_qfield<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, g,
                      fd_half, fd_weights(fd_half), lap_sq, kappa_coef, eps, gamma, eps_bulk);
 }
 
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_direction(SlotTable<T> tab, Batch 
 template <typename T>
 void launch_direction(const SlotTable<T>& tab, const Batch& b, long long n, int n_xparts,
                       int periodic, int check_neutral, hipStream_t s) {
-  hipLaunchKernelGGL((k_direction<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n,
+  GPS_LAUNCH((k_direction<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n,
                      n_xparts, periodic, check_neutral);
 }
 
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(kThreads) void k_ion_update(SlotTable<T> tab, Batch
 template <typename T>
 void launch_ion_update(const SlotTable<T>& tab, const Batch& b, long long n, const IonParams& ip,
                        int, hipStream_t s) {
-  hipLaunchKernelGGL((k_ion_update<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b,
+  GPS_LAUNCH((k_ion_update<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b,
                      n, ip);
 }
 
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void k_zero_ion(SlotTable<T> tab, Batch b
 
 template <typename T>
 void launch_zero_ion(const SlotTable<T>& tab, const Batch& b, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_zero_ion<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n);
+  GPS_LAUNCH((k_zero_ion<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -496,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_energy(SlotTable<T> tab, Batch b,
 template <typename T>
 void launch_energy(const SlotTable<T>& tab, const Batch& b, const double* rho, long long n,
                    hipStream_t s) {
-  hipLaunchKernelGGL((k_energy<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, rho, n);
+  GPS_LAUNCH((k_energy<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, rho, n);
 }
 
 #define GPS_INST(T)                                                                              \
