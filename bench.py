@@ -50,6 +50,16 @@ def parse():
                     help="skip the per-pass kernel times (extra eager solves)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum wall time of the oracle sample (whole solves)")
+    ap.add_argument("--workload", default="molecule", choices=("molecule", "serving"),
+                    help="molecule: one 96^3 solve per step (default); serving: a request "
+                         "stream through the serving loop")
+    ap.add_argument("--requests", type=int, default=512, help="serving: stream length")
+    ap.add_argument("--max-active", type=int, default=4, help="serving: concurrent solves")
+    ap.add_argument("--budget-frac", type=float, default=0.75,
+                    help="serving: admission budget as a fraction of the distinct plans' "
+                         "total resident bytes")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="serving: arrival rate as a fraction of the closed-loop capacity")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (10 times) and exit: the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -131,6 +141,128 @@ def cpu_baseline(prob, tol, min_seconds):
             "mgridpts_iter_per_s": prob.npoints * iters / dt / 1e6}
 
 
+def run_stream(torch, gps, srv, reqs, arrivals, phis):
+    """Submits reqs[i] at arrivals[i] seconds (open loop) and returns the
+    results and the wall time from the first submission to the last result."""
+    results = [None] * len(reqs)
+    pending = {}
+    t0 = time.perf_counter()
+    for i, (prm, rho, eps) in enumerate(reqs):
+        while True:
+            dt = t0 + arrivals[i] - time.perf_counter()
+            if dt <= 0:
+                break
+            for k, t in list(pending.items()):
+                r = srv.poll(t)
+                if r is not None:
+                    results[k] = r
+                    del pending[k]
+            time.sleep(min(dt, 2e-4))
+        st, t = srv.submit(rho, eps, phis[i], prm["h"], prm["bc"], prm["tol"],
+                           ions=prm["ions"], sync=False)
+        if st != gps.GPS_OK:
+            raise RuntimeError("submit failed: %s" % gps.STATUS[st])
+        pending[i] = t
+    for k, t in pending.items():
+        results[k] = srv.wait(t)
+    return results
+
+
+def serving_bench(args, torch, gps, W):
+    """Continuous-batching serving of a seeded request stream: open-loop
+    Poisson arrivals at a fraction of the closed-loop capacity; latency is
+    arrival (submission) to result ready."""
+    prms, gaps = W.serving_stream_params(args.requests, seed=5)
+    reqs = []
+    for prm in prms:
+        rho, eps = W.request_fields_torch(prm, "cuda")
+        reqs.append((prm, rho, eps))
+    phis = [torch.empty_like(r) for _, r, _ in reqs]
+    phis64 = [torch.empty_like(r) for _, r, _ in reqs]
+    torch.cuda.synchronize()
+    fps = {}
+    for prm in prms:
+        n = prm["n"]
+        fps[(n, prm["bc"])] = gps.plan_footprint((n, n, n), prm["bc"], "mixed")
+    total = sum(tb + b for tb, b, _ in fps.values())
+    budget = max(int(args.budget_frac * total), max(tb + b + t for tb, b, t in fps.values()))
+    npts = [prm["n"] ** 3 for prm in prms]
+
+    def closed_loop(srv, count, out):
+        t0 = time.perf_counter()
+        ts = []
+        for i in range(count):
+            prm, rho, eps = reqs[i]
+            st, t = srv.submit(rho, eps, out[i], prm["h"], prm["bc"], prm["tol"],
+                               ions=prm["ions"], sync=False)
+            ts.append(t)
+        for t in ts:
+            srv.wait(t)
+        return count / (time.perf_counter() - t0)
+
+    def summarize(results, srv):
+        lat = np.array([r["done_ms"] - r["submit_ms"] for r in results])
+        bad = [r["status"] for r in results if r["status"] != gps.GPS_OK]
+        wall = (max(r["done_ms"] for r in results) - min(r["submit_ms"] for r in results)) / 1e3
+        iters = sum(r["iterations"] for r in results)
+        return {"solves_per_s": len(results) / wall, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "wall_s": wall,
+                "mgridpts_iter_per_s": sum(n * r["iterations"] for n, r in zip(npts, results))
+                / wall / 1e6, "iterations": iters, "failed": len(bad), "stats": srv.stats()}
+
+    warm = min(64, len(reqs))
+    srv = gps.Server(budget_bytes=budget, max_active=args.max_active, precision="mixed")
+    closed_loop(srv, warm, phis)                       # plans, graphs
+    capacity = closed_loop(srv, warm, phis)
+    rate = args.load * capacity
+    arrivals = np.cumsum(gaps / rate)
+    res_mixed = run_stream(torch, gps, srv, reqs, arrivals, phis)
+    mixed = summarize(res_mixed, srv)
+    srv.close()
+
+    srv64 = gps.Server(budget_bytes=0, max_active=1, precision="fp64")
+    closed_loop(srv64, warm, phis64)
+    cap64 = closed_loop(srv64, warm, phis64)
+    res64 = run_stream(torch, gps, srv64, reqs, arrivals, phis64)
+    fp64 = summarize(res64, srv64)
+    srv64.close()
+    fp64["closed_loop_solves_per_s"] = cap64
+
+    dphi = 0.0
+    for i, (prm, _, _) in enumerate(reqs):
+        a, b = phis[i], phis64[i]
+        if prm["bc"] == "periodic":
+            a, b = a - a.mean(), b - b.mean()
+        dphi = max(dphi, float((a - b).abs().max()))
+    torch.cuda.synchronize()
+    kinds = {}
+    for prm in prms:
+        kinds[prm["kind"]] = kinds.get(prm["kind"], 0) + 1
+    return {
+        "metric": "serving solves/s at 1e-6 rel. residual; p50/p99 latency (arrival to result)",
+        "value": mixed["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 2 * warm, "ms_per_step": 1e3 / mixed["solves_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving_stream_%d" % len(reqs), "grids": list(W.SERVING_GRIDS),
+                   "box_bohr": W.SERVING_BOX, "bc": "free/surface/periodic", "kinds": kinds,
+                   "seed": 5, "tol": 1e-6, "max_active": args.max_active,
+                   "budget_bytes": budget, "distinct_plans_bytes": total,
+                   "arrival_rate_per_s": rate, "closed_loop_capacity_per_s": capacity,
+                   "precision": "mixed (fp32 bulk, fp64 dots/solution)"},
+        "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"],
+        "mgridpts_iter_per_s": mixed["mgridpts_iter_per_s"],
+        "failed": mixed["failed"], "server": mixed["stats"],
+        "fp64_one_at_a_time": dict({k: fp64[k] for k in ("solves_per_s", "p50_ms", "p99_ms",
+                                                          "closed_loop_solves_per_s", "failed")},
+                                   budget_bytes="unlimited", max_active=1,
+                                   arrival_rate_per_s=rate),
+        "max_abs_dphi_vs_fp64": dphi,
+        "max_rel_energy_diff_vs_fp64": max(abs(a["energy"] / b["energy"] - 1.0)
+                                           for a, b in zip(res_mixed, res64) if b["energy"]),
+    }
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -144,6 +276,9 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     from paper_1509_00680_amd import gps, workloads as W
+    if args.workload == "serving":
+        print(json.dumps(serving_bench(args, torch, gps, W)))
+        return
 
     prob = W.molecule(args.n, args.h, seed=args.seed)
     rho = torch.from_numpy(prob.rho).cuda()

@@ -62,7 +62,8 @@ typedef enum {
   GPS_E_BREAKDOWN = 4,      /* (v, r) <= 0 or (p, Ap) >= 0 in PCG */
   GPS_E_NONFINITE = 5,      /* NaN/Inf in the inputs or during the iteration */
   GPS_E_DEVICE = 6,         /* HIP runtime error */
-  GPS_E_UNSUPPORTED = 7     /* FFT length with a prime factor other than 2,3,5,7 or > 1024 */
+  GPS_E_UNSUPPORTED = 7,    /* FFT length with a prime factor other than 2,3,5,7 or > 1024 */
+  GPS_PENDING = 8           /* serving: the request is still queued or running */
 } gps_status;
 
 typedef struct gps_plan gps_plan;
@@ -106,6 +107,7 @@ typedef struct {
   double rel_residual;   /* final ||r||_2 / ||r_0||_2 of the (last) PCG solve */
   double energy;         /* (1/2) h^3 sum rho phi */
   double outer_residual; /* ||rho^ions_k - rho^ions_{k-1}||_2 / ||rho||_2 (nonlinear PB) */
+  int device_error;      /* hipError_t of the HIP call that failed (GPS_E_DEVICE), else 0 */
 } gps_info;
 
 /* Create a plan for an nx x ny x nz grid of spacing h (bohr) and boundary
@@ -125,6 +127,25 @@ gps_status gps_plan_get_options(const gps_plan *plan, gps_options *opt);
 /* Device bytes held by the plan (tables + work buffers of both precisions
  * allocated so far). */
 size_t gps_plan_device_bytes(const gps_plan *plan);
+
+/* Device bytes of a plan for an nx x ny x nz grid with boundary condition bc:
+ * *tables, held from gps_plan_create to gps_plan_destroy (twiddles, Green's
+ * spectrum); *buffers, the per-solve buffers that one solve in `precision`
+ * with iteration cap maxit allocates (nonlinear_pb != 0: a nonlinear
+ * Poisson-Boltzmann solve, which adds the ionic-charge field) and
+ * gps_plan_release_buffers frees; *transient, held only while gps_plan_create
+ * builds the Green's spectrum (FP64 padded spectrum for free and surface BC).
+ * After one solve gps_plan_device_bytes reports *tables + *buffers.  Any
+ * output pointer may be NULL.  Errors: GPS_E_INVALID (n < 2, maxit < 1,
+ * unknown bc or precision). */
+gps_status gps_plan_footprint(int nx, int ny, int nz, int bc, int precision, int maxit,
+                              int nonlinear_pb, size_t *tables, size_t *buffers,
+                              size_t *transient);
+
+/* Free the plan's per-solve buffers (both precisions) and its captured
+ * iteration graphs, keeping the tables; the next solve allocates them again.
+ * Errors: GPS_E_INVALID (null plan). */
+gps_status gps_plan_release_buffers(gps_plan *plan);
 
 void gps_plan_destroy(gps_plan *plan);
 
@@ -167,9 +188,11 @@ gps_status gps_last_info(const gps_plan *plan, gps_info *out);
 gps_status gps_last_history(const gps_plan *plan, double *out, int max_entries);
 
 /* Kernel timing (instrumentation for measurement).  kind selects one pass of
- * the PCG iteration; while it is set, every solve brackets each launch of
- * that pass with HIP events on the plan's stream and accumulates the elapsed
- * time of the launches that did work (iterations before the stop decision).
+ * the PCG iteration; while it is set, every solve times each launch of
+ * that pass: two HIP events bound to the launch on the plan's stream
+ * (hipExtLaunchKernel) take the kernel's start and end timestamps, and the
+ * elapsed times of the launches that did work (iterations before the stop
+ * decision) are accumulated.
  * Untimed solves replay the iterations as captured HIP graphs; timed solves
  * launch the same kernels one by one (events inside a graph are not
  * readable), so a timed solve is slower end to end than an untimed one.
@@ -196,6 +219,111 @@ gps_status gps_plan_timing(const gps_plan *plan, double *total_ms, long long *la
                            double *bytes_per_launch);
 
 const char *gps_status_string(int status);
+
+/* ---- serving ---------------------------------------------------------------
+ * A server runs independent solves that arrive over time (continuous
+ * batching).  Each request is a full problem of its own: grid, spacing,
+ * boundary condition, fields and, optionally, an electrolyte.  max_active
+ * worker threads each own a HIP stream (non-blocking, default priority) and
+ * take the oldest waiting request as soon as they are free and it is
+ * admitted.  The solves of different workers then run on the device at the
+ * same time.  Plans (Green's spectrum, work buffers, captured iteration
+ * graphs) stay resident between requests and are reused by any request of
+ * the same nx, ny, nz, h and bc.
+ *
+ * Admission is by device footprint (gps_plan_footprint).  A request is
+ * admitted when the bytes that the server's plans hold, plus what its own solve
+ * adds (new tables, buffers and the transient of a new plan; only the
+ * buffers if a resident plan has released them), fit in budget_bytes.  To make
+ * room, idle plans release their buffers (gps_plan_release_buffers) and then
+ * are destroyed, least recently used first in both steps.  Otherwise the request waits until
+ * a running solve finishes.  Requests are taken in arrival order, except that
+ * a waiting request among the next 16 whose plan is resident and idle may go
+ * ahead of older ones that need a new plan.  No request is passed over more
+ * than 8 times.
+ *
+ * A result is the same whether its request runs alone or among others.  Each
+ * solve uses one plan, and the kernels reduce in a fixed order.
+ *
+ * Fields are device pointers, as for the plan calls.  They must hold their
+ * final values when gps_server_submit is called (the workers' streams do not
+ * wait for work on the caller's streams).  The caller keeps rho, eps, phi (and
+ * gamma) valid and unmodified until the request's result has been returned
+ * by gps_server_poll or gps_server_wait; phi is complete by then. */
+typedef struct gps_server gps_server;
+
+typedef struct {
+  size_t budget_bytes;  /* device bytes the server's plans may hold, transients
+                           included; 0 = no limit */
+  int max_active;       /* solves in flight at once, 1..16 (default 4) */
+  int precision;        /* gps_precision of every solve (default GPS_PREC_MIXED) */
+  int fd_order;         /* as gps_options (default 16) */
+  int maxit;            /* as gps_options (default 1000) */
+} gps_server_options;
+
+typedef struct {
+  int nx, ny, nz;
+  double h;
+  int bc;
+  const double *rho;    /* device, read */
+  const double *eps;    /* device, read */
+  double *phi;          /* device, written */
+  const gps_ions *ions; /* NULL: generalized Poisson (gps_solve_generalized);
+                           else Poisson-Boltzmann (gps_solve_pb).  The struct
+                           and its host arrays are copied at submission. */
+  double tol;
+} gps_request;
+
+typedef struct {
+  int status;            /* gps_status of the solve */
+  int iterations;
+  int outer_iterations;
+  double rel_residual;
+  double energy;
+  double submit_ms;      /* server clock: ms since gps_server_create */
+  double start_ms;       /* admitted and taken by a worker */
+  double done_ms;        /* phi written and the worker's stream idle */
+  int worker;            /* index of the worker that ran it */
+  int plan_reused;       /* 1 if an existing resident plan served it */
+  int device_error;      /* as gps_info.device_error */
+} gps_result;
+
+typedef struct {
+  size_t bytes_in_use;   /* resident plans plus admitted transients */
+  size_t bytes_peak;
+  int plans_resident;
+  int plans_created;
+  int plans_evicted;     /* destroyed to make room */
+  int buffers_released;  /* idle plans whose buffers were released to make room */
+  int max_in_flight;     /* largest number of solves running at once */
+  long long submitted;
+  long long completed;
+} gps_server_stats;
+
+/* Start a server on the current device.  opt may be NULL (defaults).
+ * Errors: GPS_E_INVALID (out NULL, max_active outside 1..16, bad precision,
+ * fd_order or maxit), GPS_E_DEVICE. */
+gps_status gps_server_create(const gps_server_options *opt, gps_server **out);
+
+/* Queue a request; *ticket identifies it.  Errors: GPS_E_INVALID (null
+ * pointers, n < 2, h <= 0, unknown bc, tol <= 0, ions with nspecies outside
+ * 1..4 or null arrays), GPS_E_NOMEM (the request alone exceeds the budget).
+ * Problems found while solving (bad electrolyte, eps <= 0, ...) are reported
+ * in the result's status. */
+gps_status gps_server_submit(gps_server *srv, const gps_request *req, long long *ticket);
+
+/* GPS_PENDING while the request is queued or running.  GPS_OK once it has
+ * finished: *out is filled and the ticket is released.  GPS_E_INVALID for an
+ * unknown or released ticket. */
+gps_status gps_server_poll(gps_server *srv, long long ticket, gps_result *out);
+
+/* As gps_server_poll, but blocks until the request has finished. */
+gps_status gps_server_wait(gps_server *srv, long long ticket, gps_result *out);
+
+gps_status gps_server_get_stats(gps_server *srv, gps_server_stats *out);
+
+/* Finish every submitted request, then free the plans and the workers. */
+void gps_server_destroy(gps_server *srv);
 
 #ifdef __cplusplus
 }

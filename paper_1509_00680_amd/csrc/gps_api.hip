@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -25,6 +26,11 @@ gps::LaunchEvents& gps::launch_events() {
 }
 
 namespace {
+
+// Serializes stream capture against plan creation and destruction across
+// host threads (allocation, frees and stream teardown must not overlap another
+// thread's capture).
+std::mutex g_plan_mu;
 
 struct TimedLaunch {
   int k;
@@ -91,6 +97,7 @@ int ilog2(int v) {
 // Per-precision buffers of one problem in flight.
 template <typename T> struct Res {
   bool ready = false;
+  size_t bytes = 0;          // device bytes of this precision's buffers
   SlotTable<T> tab{};        // passed by value to every kernel; entry 0 is this plan's problem
   Slot<T>& slot() { return tab.s[0]; }
   SolveState* h_state = nullptr;   // pinned
@@ -206,7 +213,7 @@ SParams<T> sparams(const gps_plan* pl, int axis, int L, int Lin, int Lout, int n
 // ---------------------------------------------------------------------------
 void build_green(gps_plan* pl) {
   const Geom& g = pl->g;
-  hipStream_t s = pl->stream();
+  hipStream_t s = pl->cap_stream;
   const size_t ntab = (size_t)(g.Lz / 2 + 1) * (g.Ly / 2 + 1) * g.Kx;
   dalloc(&pl->green64, ntab * sizeof(double), &pl->bytes);
   dalloc(&pl->green32, ntab * sizeof(float), &pl->bytes);
@@ -265,6 +272,7 @@ void build_green(gps_plan* pl) {
 // ---------------------------------------------------------------------------
 template <typename T>
 void ensure_res(gps_plan* pl, bool need_ion) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
   Res<T>& R = pl->res<T>();
   const long long n = pl->npts();
   const int nvg = vec_groups(n);
@@ -274,28 +282,28 @@ void ensure_res(gps_plan* pl, bool need_ion) {
     Slot<T>& s = R.slot();
     s = Slot<T>{};
     const size_t nb = (size_t)n * sizeof(T);
-    dalloc(&s.r, nb, &pl->bytes);
-    dalloc(&s.v, nb, &pl->bytes);
-    dalloc(&s.p, nb, &pl->bytes);
-    dalloc(&s.ap, nb, &pl->bytes);
-    dalloc(&s.isq, nb, &pl->bytes);
-    dalloc(&s.qk, nb, &pl->bytes);
-    if (pl->bc == GPS_BC_PERIODIC) dalloc(&s.s, nb, &pl->bytes);
-    dalloc(&s.sq64, (size_t)n * sizeof(double), &pl->bytes);
-    dalloc(&s.work, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<T>), &pl->bytes);
-    dalloc(&s.part_init, (size_t)4 * nvg * sizeof(double), &pl->bytes);
-    dalloc(&s.part_rr, (size_t)std::max(nvg, nxg) * sizeof(double), &pl->bytes);
-    dalloc(&s.part_delta[0], (size_t)nxg * sizeof(double), &pl->bytes);
+    dalloc(&s.r, nb, &R.bytes);
+    dalloc(&s.v, nb, &R.bytes);
+    dalloc(&s.p, nb, &R.bytes);
+    dalloc(&s.ap, nb, &R.bytes);
+    dalloc(&s.isq, nb, &R.bytes);
+    dalloc(&s.qk, nb, &R.bytes);
+    if (pl->bc == GPS_BC_PERIODIC) dalloc(&s.s, nb, &R.bytes);
+    dalloc(&s.sq64, (size_t)n * sizeof(double), &R.bytes);
+    dalloc(&s.work, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<T>), &R.bytes);
+    dalloc(&s.part_init, (size_t)4 * nvg * sizeof(double), &R.bytes);
+    dalloc(&s.part_rr, (size_t)std::max(nvg, nxg) * sizeof(double), &R.bytes);
+    dalloc(&s.part_delta[0], (size_t)nxg * sizeof(double), &R.bytes);
     s.part_delta[1] = s.part_delta[0];
-    dalloc(&s.part_pap, (size_t)nvg * sizeof(double), &pl->bytes);
-    dalloc(&s.part_mu, (size_t)nxg * sizeof(double), &pl->bytes);
-    dalloc(&s.part_aux, (size_t)2 * nvg * sizeof(double), &pl->bytes);
-    dalloc(&s.st, sizeof(SolveState), &pl->bytes);
-    dalloc(&s.phi, (size_t)n * sizeof(double), &pl->bytes);
+    dalloc(&s.part_pap, (size_t)nvg * sizeof(double), &R.bytes);
+    dalloc(&s.part_mu, (size_t)nxg * sizeof(double), &R.bytes);
+    dalloc(&s.part_aux, (size_t)2 * nvg * sizeof(double), &R.bytes);
+    dalloc(&s.st, sizeof(SolveState), &R.bytes);
+    dalloc(&s.phi, (size_t)n * sizeof(double), &R.bytes);
     if (pl->bc == GPS_BC_PERIODIC) {
-      dalloc(&R.lap64, (size_t)n * sizeof(double), &pl->bytes);
+      dalloc(&R.lap64, (size_t)n * sizeof(double), &R.bytes);
       if (sizeof(T) != sizeof(double))
-        dalloc(&R.work64q, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<double>), &pl->bytes);
+        dalloc(&R.work64q, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<double>), &R.bytes);
     }
     if (hipHostMalloc(reinterpret_cast<void**>(&R.h_state), sizeof(SolveState)) != hipSuccess)
       throw NoMem{};
@@ -305,13 +313,14 @@ void ensure_res(gps_plan* pl, bool need_ion) {
     R.ready = true;
   }
   if (R.hist_cap < pl->opt.maxit + 1) {
+    if (R.slot().hist) R.bytes -= (size_t)4 * R.hist_cap * sizeof(double);
     dfree(R.slot().hist);
-    dalloc(&R.slot().hist, (size_t)4 * (pl->opt.maxit + 1) * sizeof(double), &pl->bytes);
+    dalloc(&R.slot().hist, (size_t)4 * (pl->opt.maxit + 1) * sizeof(double), &R.bytes);
     R.hist_cap = pl->opt.maxit + 1;
   }
   bool changed = false;
   if (need_ion && !R.slot().ion) {
-    dalloc(&R.slot().ion, (size_t)n * sizeof(T), &pl->bytes);
+    dalloc(&R.slot().ion, (size_t)n * sizeof(T), &R.bytes);
     changed = true;
   }
   // the table is captured by value in graphs: rebuild them when it changes
@@ -543,6 +552,7 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk) {
   b.n = 1;
   b.slot[0] = 0;
   pl->ev_pending.clear();
+  std::lock_guard<std::mutex> lk(g_plan_mu);
   ck(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
   for (int j = 0; j < chunk; ++j) enqueue_iteration<T>(pl, R.tab, b, check_neutral,
                                                        pl->cap_stream, j);
@@ -635,9 +645,11 @@ void finish_info(gps_plan* pl, const SolveState& st, const double* rho, double* 
   pl->info.rel_residual = st.rr0 > 0 ? std::sqrt(st.rr / st.rr0) : 0.0;
   const int nh = std::min(st.iters, R.hist_cap);
   pl->hist.assign((size_t)4 * nh, 0.0);
-  if (nh > 0)
-    ck(hipMemcpy(pl->hist.data(), R.slot().hist, (size_t)4 * nh * sizeof(double),
-                 hipMemcpyDeviceToHost));
+  if (nh > 0) {
+    ck(hipMemcpyAsync(pl->hist.data(), R.slot().hist, (size_t)4 * nh * sizeof(double),
+                      hipMemcpyDeviceToHost, pl->stream()));
+    ck(hipStreamSynchronize(pl->stream()));
+  }
   pl->info.history_len = nh;
 }
 
@@ -748,6 +760,7 @@ const char* gps_status_string(int st) {
     case GPS_E_NONFINITE: return "non-finite value";
     case GPS_E_DEVICE: return "HIP runtime error";
     case GPS_E_UNSUPPORTED: return "unsupported size";
+    case GPS_PENDING: return "pending";
     default: return "unknown status";
   }
 }
@@ -802,24 +815,32 @@ gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan** 
       return GPS_E_UNSUPPORTED;
     }
   }
+  std::lock_guard<std::mutex> lk(g_plan_mu);
   try {
     if (hipGetDevice(&pl->device) != hipSuccess) throw DevError{hipErrorNoDevice};
+    // plan-time work runs on the plan's own non-blocking stream, never on the
+    // legacy null stream (which would synchronize with other threads' streams)
+    ck(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    std::vector<double> t64[3];
+    std::vector<float> t32[3];
     for (int a = 0; a < 3; ++a) {
-      std::vector<double> t64(2 * (size_t)L[a]);
-      std::vector<float> t32(2 * (size_t)L[a]);
+      t64[a].resize(2 * (size_t)L[a]);
+      t32[a].resize(2 * (size_t)L[a]);
       for (int m = 0; m < L[a]; ++m) {
         const double ang = 2.0 * kPi * (double)m / (double)L[a];
-        t64[2 * m] = std::cos(ang);
-        t64[2 * m + 1] = -std::sin(ang);
-        t32[2 * m] = (float)t64[2 * m];
-        t32[2 * m + 1] = (float)t64[2 * m + 1];
+        t64[a][2 * m] = std::cos(ang);
+        t64[a][2 * m + 1] = -std::sin(ang);
+        t32[a][2 * m] = (float)t64[a][2 * m];
+        t32[a][2 * m + 1] = (float)t64[a][2 * m + 1];
       }
-      dalloc(&pl->tw64[a], t64.size() * sizeof(double), &pl->bytes);
-      dalloc(&pl->tw32[a], t32.size() * sizeof(float), &pl->bytes);
-      ck(hipMemcpy(pl->tw64[a], t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
-      ck(hipMemcpy(pl->tw32[a], t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+      dalloc(&pl->tw64[a], t64[a].size() * sizeof(double), &pl->bytes);
+      dalloc(&pl->tw32[a], t32[a].size() * sizeof(float), &pl->bytes);
+      ck(hipMemcpyAsync(pl->tw64[a], t64[a].data(), t64[a].size() * sizeof(double),
+                        hipMemcpyHostToDevice, pl->cap_stream));
+      ck(hipMemcpyAsync(pl->tw32[a], t32[a].data(), t32[a].size() * sizeof(float),
+                        hipMemcpyHostToDevice, pl->cap_stream));
     }
-    build_green(pl);
+    build_green(pl);   // synchronizes cap_stream (the host twiddles outlive the copies)
   } catch (const NoMem&) {
     plan_release(pl);
     delete pl;
@@ -848,22 +869,71 @@ gps_status gps_plan_get_options(const gps_plan* pl, gps_options* o) {
   return GPS_OK;
 }
 
-size_t gps_plan_device_bytes(const gps_plan* pl) { return pl ? pl->bytes : 0; }
+size_t gps_plan_device_bytes(const gps_plan* pl) {
+  return pl ? pl->bytes + pl->r32.bytes + pl->r64.bytes : 0;
+}
+
+gps_status gps_plan_release_buffers(gps_plan* pl) {
+  if (!pl) return GPS_E_INVALID;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  free_res<float>(pl);
+  free_res<double>(pl);
+  return GPS_OK;
+}
+
+gps_status gps_plan_footprint(int nx, int ny, int nz, int bc, int precision, int maxit,
+                              int nonlinear_pb, size_t* tables, size_t* buffers,
+                              size_t* transient) {
+  if (nx < 2 || ny < 2 || nz < 2 || maxit < 1) return GPS_E_INVALID;
+  if (bc != GPS_BC_FREE && bc != GPS_BC_SURFACE && bc != GPS_BC_PERIODIC) return GPS_E_INVALID;
+  if (precision != GPS_PREC_FP64 && precision != GPS_PREC_MIXED) return GPS_E_INVALID;
+  // the same sizes as gps_plan_create, build_green and ensure_res
+  const bool px = bc != GPS_BC_FREE, pz = bc == GPS_BC_PERIODIC;
+  const size_t Lx = px ? nx : 2 * (size_t)nx, Ly = px ? ny : 2 * (size_t)ny;
+  const size_t Lz = pz ? nz : 2 * (size_t)nz, Kx = Lx / 2 + 1;
+  const size_t n = (size_t)nx * ny * nz;
+  const size_t s = precision == GPS_PREC_MIXED ? sizeof(float) : sizeof(double);
+  const size_t ntab = (Lz / 2 + 1) * (Ly / 2 + 1) * Kx;
+  const size_t nvg = (size_t)vec_groups((long long)n);
+  const size_t nxg = ((size_t)ny * nz + 1) / 2 + 1;
+  const size_t wbox = (size_t)nz * Ly * Kx;
+  size_t tb = 2 * (Lx + Ly + Lz) * (sizeof(double) + sizeof(float));         // twiddles
+  tb += ntab * (sizeof(double) + sizeof(float));                              // Green table
+  if (pz) tb += ntab * (sizeof(double) + sizeof(float));                      // Laplacian table
+  size_t b = 6 * n * s + (pz ? n * s : 0) + n * sizeof(double);                     // vectors, sq64
+  b += wbox * 2 * s;                                                          // work buffer
+  b += (4 * nvg + std::max(nvg, nxg) + nxg + nvg + nxg + 2 * nvg) * sizeof(double);
+  b += sizeof(SolveState) + n * sizeof(double);                               // state, phi
+  if (pz) b += n * sizeof(double) + (s != sizeof(double) ? wbox * 2 * sizeof(double) : 0);
+  b += 4 * ((size_t)maxit + 1) * sizeof(double);                              // history
+  if (nonlinear_pb) b += n * s;                                               // ionic charge
+  size_t t = 0;
+  if (bc == GPS_BC_FREE) t = Lz * Ly * Kx * 2 * sizeof(double);
+  else if (bc == GPS_BC_SURFACE) t = Kx * (Ly / 2 + 1) * Lz * 2 * sizeof(double);
+  if (tables) *tables = tb;
+  if (buffers) *buffers = b;
+  if (transient) *transient = t;
+  return GPS_OK;
+}
 
 void gps_plan_destroy(gps_plan* pl) {
   if (!pl) return;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
   plan_release(pl);
   delete pl;
 }
 
 static gps_status run_guarded(gps_plan* pl, bool mixed, const double* rho, const double* eps,
                               double* phi, double tol, const Electrolyte& el) {
+  pl->info.device_error = 0;
   try {
     if (mixed) return solve_impl<float>(pl, rho, eps, phi, tol, el);
     return solve_impl<double>(pl, rho, eps, phi, tol, el);
   } catch (const NoMem&) {
     return GPS_E_NOMEM;
-  } catch (const DevError&) {
+  } catch (const DevError& d) {
+    pl->info.device_error = (int)d.e;
+    pl->info.status = GPS_E_DEVICE;
     return GPS_E_DEVICE;
   }
 }

@@ -18,15 +18,19 @@ GPS_PREC_FP64, GPS_PREC_MIXED = 0, 1
 PRECISIONS = {"fp64": GPS_PREC_FP64, "mixed": GPS_PREC_MIXED}
 
 STATUS = {0: "GPS_OK", 1: "GPS_E_INVALID", 2: "GPS_E_NOMEM", 3: "GPS_E_NOT_CONVERGED",
-          4: "GPS_E_BREAKDOWN", 5: "GPS_E_NONFINITE", 6: "GPS_E_DEVICE", 7: "GPS_E_UNSUPPORTED"}
+          4: "GPS_E_BREAKDOWN", 5: "GPS_E_NONFINITE", 6: "GPS_E_DEVICE", 7: "GPS_E_UNSUPPORTED",
+          8: "GPS_PENDING"}
 GPS_OK, GPS_E_INVALID, GPS_E_NOMEM, GPS_E_NOT_CONVERGED = 0, 1, 2, 3
 GPS_E_BREAKDOWN, GPS_E_NONFINITE, GPS_E_DEVICE, GPS_E_UNSUPPORTED = 4, 5, 6, 7
+GPS_PENDING = 8
 
 # every symbol include/gps.h declares
 EXPORTED = ("gps_plan_create", "gps_plan_set_options", "gps_plan_get_options",
             "gps_plan_device_bytes", "gps_plan_destroy", "gps_solve_generalized",
             "gps_solve_pb", "gps_solve_vacuum", "gps_last_info", "gps_last_history",
-            "gps_plan_set_timing", "gps_plan_timing", "gps_status_string")
+            "gps_plan_set_timing", "gps_plan_timing", "gps_status_string",
+            "gps_plan_footprint", "gps_plan_release_buffers", "gps_server_create", "gps_server_submit", "gps_server_poll",
+            "gps_server_wait", "gps_server_get_stats", "gps_server_destroy")
 KERNEL_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "xinv": 5, "direction": 6}
 
 
@@ -49,7 +53,43 @@ class gps_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
                 ("outer_iterations", ctypes.c_int), ("history_len", ctypes.c_int),
                 ("rnorm0", ctypes.c_double), ("rel_residual", ctypes.c_double),
-                ("energy", ctypes.c_double), ("outer_residual", ctypes.c_double)]
+                ("energy", ctypes.c_double), ("outer_residual", ctypes.c_double),
+                ("device_error", ctypes.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class gps_server_options(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int),
+                ("precision", ctypes.c_int), ("fd_order", ctypes.c_int), ("maxit", ctypes.c_int)]
+
+
+class gps_request(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("h", ctypes.c_double), ("bc", ctypes.c_int), ("rho", ctypes.c_void_p),
+                ("eps", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("ions", ctypes.POINTER(gps_ions)), ("tol", ctypes.c_double)]
+
+
+class gps_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("outer_iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("energy", ctypes.c_double), ("submit_ms", ctypes.c_double),
+                ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
+                ("worker", ctypes.c_int), ("plan_reused", ctypes.c_int),
+                ("device_error", ctypes.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class gps_server_stats(ctypes.Structure):
+    _fields_ = [("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t),
+                ("plans_resident", ctypes.c_int), ("plans_created", ctypes.c_int),
+                ("plans_evicted", ctypes.c_int), ("buffers_released", ctypes.c_int),
+                ("max_in_flight", ctypes.c_int),
+                ("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -96,6 +136,24 @@ def load(path=LIB_PATH):
     lib.gps_plan_timing.restype = I
     lib.gps_status_string.argtypes = [I]
     lib.gps_status_string.restype = ctypes.c_char_p
+    SZ = ctypes.POINTER(ctypes.c_size_t)
+    lib.gps_plan_footprint.argtypes = [I, I, I, I, I, I, I, SZ, SZ, SZ]
+    lib.gps_plan_release_buffers.argtypes = [P]
+    lib.gps_plan_release_buffers.restype = I
+    lib.gps_plan_footprint.restype = I
+    lib.gps_server_create.argtypes = [ctypes.POINTER(gps_server_options), ctypes.POINTER(P)]
+    lib.gps_server_create.restype = I
+    lib.gps_server_submit.argtypes = [P, ctypes.POINTER(gps_request),
+                                      ctypes.POINTER(ctypes.c_longlong)]
+    lib.gps_server_submit.restype = I
+    lib.gps_server_poll.argtypes = [P, ctypes.c_longlong, ctypes.POINTER(gps_result)]
+    lib.gps_server_poll.restype = I
+    lib.gps_server_wait.argtypes = [P, ctypes.c_longlong, ctypes.POINTER(gps_result)]
+    lib.gps_server_wait.restype = I
+    lib.gps_server_get_stats.argtypes = [P, ctypes.POINTER(gps_server_stats)]
+    lib.gps_server_get_stats.restype = I
+    lib.gps_server_destroy.argtypes = [P]
+    lib.gps_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -174,6 +232,11 @@ class Plan:
     def device_bytes(self):
         return int(load().gps_plan_device_bytes(self.handle))
 
+    def release_buffers(self):
+        st = load().gps_plan_release_buffers(self.handle)
+        if st != GPS_OK:
+            raise GPSError(st, "gps_plan_release_buffers")
+
     def solve_generalized(self, rho, eps, phi, tol):
         for t in (rho, eps, phi):
             _check_field(t, self.shape)
@@ -219,6 +282,89 @@ class Plan:
         if getattr(self, "handle", None):
             load().gps_plan_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_footprint(shape, bc, precision="mixed", maxit=1000, nonlinear_pb=False):
+    """(tables, buffers, transient) device bytes of a plan (gps_plan_footprint)."""
+    nz, ny, nx = shape
+    tb, b, t = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    st = load().gps_plan_footprint(int(nx), int(ny), int(nz), BC_CODES[bc], PRECISIONS[precision],
+                                   int(maxit), int(bool(nonlinear_pb)), ctypes.byref(tb),
+                                   ctypes.byref(b), ctypes.byref(t))
+    if st != GPS_OK:
+        raise GPSError(st, "gps_plan_footprint")
+    return tb.value, b.value, t.value
+
+
+class Server:
+    """A libgps server (gps_server_*): queued solves on resident plans.
+
+    submit() keeps references to the request's tensors until its result has
+    been taken by poll() or wait()."""
+
+    def __init__(self, budget_bytes=0, max_active=4, precision="mixed", fd_order=16,
+                 maxit=1000):
+        o = gps_server_options(int(budget_bytes), int(max_active), PRECISIONS[precision],
+                               int(fd_order), int(maxit))
+        h = ctypes.c_void_p()
+        st = load().gps_server_create(ctypes.byref(o), ctypes.byref(h))
+        if st != GPS_OK:
+            raise GPSError(st, "gps_server_create")
+        self.handle = h
+        self._live = {}
+
+    def submit(self, rho, eps, phi, h, bc, tol, ions=None, gamma=None, sync=True):
+        """Queue one solve; returns (status, ticket).  With sync, the current
+        torch stream is synchronized first so that the inputs are complete."""
+        shape = tuple(rho.shape)
+        for t in (rho, eps, phi):
+            _check_field(t, shape)
+        if sync:
+            import torch
+            torch.cuda.current_stream().synchronize()
+        nz, ny, nx = shape
+        s = ions_struct(ions, gamma) if ions is not None else None
+        req = gps_request(nx, ny, nz, float(h), BC_CODES[bc], _ptr(rho), _ptr(eps), _ptr(phi),
+                          ctypes.pointer(s) if s is not None else None, float(tol))
+        ticket = ctypes.c_longlong()
+        st = load().gps_server_submit(self.handle, ctypes.byref(req), ctypes.byref(ticket))
+        if st == GPS_OK:
+            self._live[ticket.value] = (rho, eps, phi, gamma)
+        return st, ticket.value
+
+    def _take(self, fn, ticket):
+        out = gps_result()
+        st = fn(self.handle, ctypes.c_longlong(ticket), ctypes.byref(out))
+        if st == GPS_OK:
+            self._live.pop(ticket, None)
+            return out.as_dict()
+        if st == GPS_PENDING:
+            return None
+        raise GPSError(st, "gps_server result of ticket %d" % ticket)
+
+    def poll(self, ticket):
+        """Result dict once finished, else None."""
+        return self._take(load().gps_server_poll, ticket)
+
+    def wait(self, ticket):
+        return self._take(load().gps_server_wait, ticket)
+
+    def stats(self):
+        out = gps_server_stats()
+        load().gps_server_get_stats(self.handle, ctypes.byref(out))
+        return out.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().gps_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
 
     def __del__(self):
         try:

@@ -257,21 +257,64 @@ SERVING_GRIDS = (32, 48, 64, 96, 128)
 SERVING_BOX = 19.2
 
 
-def serving_request(rng, grids=SERVING_GRIDS, box=SERVING_BOX, tol=1e-6):
-    """One request: grid, BC, solute and kind drawn from rng."""
+def serving_params(rng, grids=SERVING_GRIDS, box=SERVING_BOX, tol=1e-6):
+    """Draws one request's parameters: grid, BC, kind, solute (in this order)."""
     n = int(rng.choice(grids))
     bc = (BC_FREE, BC_SURFACE, BC_PERIODIC)[int(rng.integers(3))]
     n_atoms = int(rng.integers(4, 49))
     kind = ("gpe", "pb_linear")[int(rng.integers(2))]
-    h = box / n
     centres, sig, q = random_solute(rng, n_atoms, 3.0, 0.0)
-    shape = (n, n, n)
-    rho = gaussian_sum(shape, h, centres, sig, q, bc=bc, discrete_norm=True)
-    cav = gaussian_sum(shape, h, centres, sig, np.ones(n_atoms), bc=bc)
-    eps = sccs_eps(cav)
     ions = electrolyte_1to1(debye_concentration(10.0), linear=True) if kind == "pb_linear" else None
-    return Problem("req_n%d_%s_%s" % (n, bc, kind), shape, h, bc, rho, eps, tol,
-                   ions=ions, kind=kind, meta={"n_atoms": n_atoms})
+    return {"n": n, "h": box / n, "bc": bc, "kind": kind, "n_atoms": n_atoms,
+            "centres": centres, "sigmas": sig, "charges": q, "ions": ions, "tol": tol}
+
+
+def serving_request(rng, grids=SERVING_GRIDS, box=SERVING_BOX, tol=1e-6):
+    """One request: grid, BC, solute and kind drawn from rng."""
+    return request_problem(serving_params(rng, grids, box, tol))
+
+
+def request_problem(prm):
+    """Fields of a request on the host (numpy)."""
+    n, h, bc = prm["n"], prm["h"], prm["bc"]
+    shape = (n, n, n)
+    rho = gaussian_sum(shape, h, prm["centres"], prm["sigmas"], prm["charges"], bc=bc,
+                       discrete_norm=True)
+    cav = gaussian_sum(shape, h, prm["centres"], prm["sigmas"], np.ones(prm["n_atoms"]), bc=bc)
+    eps = sccs_eps(cav)
+    return Problem("req_n%d_%s_%s" % (n, bc, prm["kind"]), shape, h, bc, rho, eps, prm["tol"],
+                   ions=prm["ions"], kind=prm["kind"], meta={"n_atoms": prm["n_atoms"]})
+
+
+def request_fields_torch(prm, device):
+    """(rho, eps) of a request as float64 torch tensors on `device`: the same
+    recipe as request_problem, evaluated by torch (for large request streams)."""
+    import torch
+    n, h, bc = prm["n"], prm["h"], prm["bc"]
+    ax = (torch.arange(n, dtype=torch.float64, device=device) - (n - 1) / 2.0) * h
+    px, py, pz = periodic_flags(bc)
+    length = n * h
+
+    def mi(d, periodic):
+        return d - length * torch.round(d / length) if periodic else d
+
+    rho = torch.zeros((n, n, n), dtype=torch.float64, device=device)
+    cav = torch.zeros_like(rho)
+    for c, s, w in zip(prm["centres"], prm["sigmas"], prm["charges"]):
+        k = 1.0 / (2.0 * s * s)
+        ex = torch.exp(-mi(ax - c[0], px) ** 2 * k)
+        ey = torch.exp(-mi(ax - c[1], py) ** 2 * k)
+        ez = torch.exp(-mi(ax - c[2], pz) ** 2 * k)
+        e = ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
+        rho += (w / (h ** 3 * e.sum())) * e
+        cav += (2 * math.pi * s * s) ** -1.5 * e
+    eps = torch.full_like(cav, EPS_WATER)
+    eps[cav > RHO_MAX_SCCS] = 1.0
+    mid = (cav <= RHO_MAX_SCCS) & (cav >= RHO_MIN_SCCS)
+    zeta = 2 * math.pi * torch.log(RHO_MAX_SCCS / cav[mid]) / math.log(RHO_MAX_SCCS / RHO_MIN_SCCS)
+    w = (zeta - torch.sin(zeta)) / (2 * math.pi)
+    eps[mid] = torch.exp(math.log(EPS_WATER) * w)
+    return rho, eps
 
 
 def serving_stream(n_requests=512, seed=5, rate=None, **kw):
@@ -282,3 +325,11 @@ def serving_stream(n_requests=512, seed=5, rate=None, **kw):
     if rate is not None:
         gaps = gaps / rate
     return reqs, np.cumsum(gaps)
+
+
+def serving_stream_params(n_requests=512, seed=5, **kw):
+    """Parameters of the same stream as serving_stream (no fields) and the
+    unit-rate inter-arrival gaps (divide by the rate)."""
+    rng = np.random.default_rng(seed)
+    prms = [serving_params(rng, **kw) for _ in range(n_requests)]
+    return prms, rng.exponential(1.0, n_requests)

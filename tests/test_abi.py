@@ -58,3 +58,36 @@ def test_null_plan_rejected(lib):
     assert lib.gps_last_info(None, None) == gps.GPS_E_INVALID
     assert lib.gps_plan_device_bytes(None) == 0
     lib.gps_plan_destroy(None)
+
+
+def test_footprint_host_side(lib):
+    tb, b, t = gps.plan_footprint((96, 96, 96), "free", "mixed")
+    tb64, b64, _ = gps.plan_footprint((96, 96, 96), "free", "fp64")
+    tbn, bnl, tnl = gps.plan_footprint((96, 96, 96), "free", "mixed", nonlinear_pb=True)
+    n = 96 ** 3
+    assert bnl - b == 4 * n                      # FP32 ionic-charge field
+    assert tnl == t == 192 * 192 * 97 * 16       # FP64 padded half spectrum while planning
+    assert tb == tbn == tb64                     # tables do not depend on the precision
+    assert tb > 97 ** 3 * 12                     # FP64 + FP32 folded Green table
+    assert b64 > b
+    # the FP32 work buffer (96 x 192 x 97 complex) and 6 FP32 vectors dominate
+    assert b > 96 * 192 * 97 * 8 + 6 * 4 * n
+    tbp, bp, tp = gps.plan_footprint((32, 32, 32), "periodic", "mixed")
+    assert tp == 0 and bp > 0 and tbp > 0
+    with pytest.raises(gps.GPSError):
+        gps.plan_footprint((1, 8, 8), "free")
+
+
+def test_server_argument_checks_need_no_device(lib):
+    t = ctypes.c_longlong()
+    assert lib.gps_server_create(None, None) == gps.GPS_E_INVALID
+    bad = gps.gps_server_options(0, 0, 1, 16, 100)          # max_active 0
+    h = ctypes.c_void_p()
+    assert lib.gps_server_create(ctypes.byref(bad), ctypes.byref(h)) == gps.GPS_E_INVALID
+    assert lib.gps_server_submit(None, None, ctypes.byref(t)) == gps.GPS_E_INVALID
+    assert lib.gps_server_poll(None, 1, None) == gps.GPS_E_INVALID
+    assert lib.gps_server_wait(None, 1, None) == gps.GPS_E_INVALID
+    assert lib.gps_server_get_stats(None, None) == gps.GPS_E_INVALID
+    lib.gps_server_destroy(None)
+    assert lib.gps_plan_release_buffers(None) == gps.GPS_E_INVALID
+    assert lib.gps_status_string(8) == b"pending"

@@ -1,0 +1,145 @@
+"""Serving (gps_server_*): a stream of independent requests of different grids,
+boundary conditions and kinds, admitted by device footprint and run
+concurrently on several streams.  Each result must equal, bit for bit, the
+same request solved alone on a fresh plan; one request is checked against the
+FP64 oracle; footprints agree with what plans actually hold."""
+import numpy as np
+import pytest
+
+from oracle import pcg
+from paper_1509_00680_amd import gps
+from paper_1509_00680_amd import workloads as W
+from gpu_util import dev, host, empty, plan, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = (16, 24, 32)
+BOX = 9.6
+
+
+def _requests(n, seed):
+    prms, _ = W.serving_stream_params(n, seed=seed, grids=GRIDS, box=BOX)
+    out = []
+    for prm in prms:
+        prob = W.request_problem(prm)
+        out.append((prob, dev(prob.rho), dev(prob.eps)))
+    return out
+
+
+def _solve_alone(prob, rho, eps, precision="mixed"):
+    p = plan(prob.shape, prob.h, prob.bc, precision)
+    phi = empty(prob.shape)
+    if prob.ions is None:
+        st = p.solve_generalized(rho, eps, phi, prob.tol)
+    else:
+        st = p.solve_pb(rho, eps, prob.ions, phi, prob.tol)
+    info = p.info()
+    p.close()
+    return st, phi, info
+
+
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic"])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_footprint_matches_plan_bytes(bc, precision):
+    require_gpu()
+    prob = W.molecule(24, 0.4, seed=3, n_atoms=6, ball=2.0, bc=bc)
+    p = plan(prob.shape, prob.h, bc, precision)
+    phi = empty(prob.shape)
+    print("footprint", bc, precision, flush=True)
+    assert p.solve_generalized(dev(prob.rho), dev(prob.eps), phi, 1e-6) == gps.GPS_OK
+    tables, buffers, _ = gps.plan_footprint(prob.shape, bc, precision)
+    assert p.device_bytes() == tables + buffers
+    phi0 = host(phi)
+    p.release_buffers()
+    assert p.device_bytes() == tables
+    # the buffers come back on the next solve, with the same result
+    assert p.solve_generalized(dev(prob.rho), dev(prob.eps), phi, 1e-6) == gps.GPS_OK
+    assert p.device_bytes() == tables + buffers
+    assert np.array_equal(host(phi), phi0)
+    if bc != "periodic":
+        ions = W.electrolyte_1to1(W.debye_concentration(3.0), eta=0.3)
+        assert p.solve_pb(dev(prob.rho * 1e-3), dev(prob.eps), ions, phi, 1e-5) == gps.GPS_OK
+        _, buffers_nl, _ = gps.plan_footprint(prob.shape, bc, precision, nonlinear_pb=True)
+        assert p.device_bytes() == tables + buffers_nl
+
+
+def test_mix_equals_alone_bitwise():
+    torch = require_gpu()
+    reqs = _requests(18, seed=7)
+    fp = {(p.shape, p.bc): gps.plan_footprint(p.shape, p.bc, "mixed") for p, _, _ in reqs}
+    # every request fits alone, the distinct plans together do not
+    budget = (max(tb + b + t for tb, b, t in fp.values())
+              + sum(tb + b for tb, b, _ in fp.values()) // 4)
+    assert sum(tb + b for tb, b, _ in fp.values()) > budget
+    srv = gps.Server(budget_bytes=budget, max_active=4, precision="mixed")
+    phis, tickets = [], []
+    print("serving mix of", len(reqs), "requests, budget", budget, flush=True)
+    for prob, rho, eps in reqs:
+        phi = torch.full(prob.shape, float("nan"), dtype=torch.float64, device="cuda")
+        st, t = srv.submit(rho, eps, phi, prob.h, prob.bc, prob.tol, ions=prob.ions)
+        assert st == gps.GPS_OK
+        phis.append(phi)
+        tickets.append(t)
+    results = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    assert stats["completed"] == len(reqs)
+    assert stats["max_in_flight"] >= 2
+    assert stats["bytes_peak"] <= budget
+    assert stats["plans_evicted"] + stats["buffers_released"] >= 1   # the budget binds
+    for (prob, rho, eps), phi, res in zip(reqs, phis, results):
+        print("alone", prob.name, flush=True)
+        st, phi1, info = _solve_alone(prob, rho, eps)
+        assert res["status"] == st == gps.GPS_OK, (prob.name, res, st)
+        assert res["iterations"] == info["iterations"]
+        assert res["energy"] == info["energy"]
+        assert torch.equal(phi, phi1), prob.name
+        assert res["submit_ms"] <= res["start_ms"] <= res["done_ms"]
+
+
+def test_served_request_matches_oracle():
+    require_gpu()
+    prm = W.serving_params(np.random.default_rng(3), grids=(24,), box=BOX)
+    prm["bc"], prm["kind"], prm["ions"] = "periodic", "gpe", None
+    prob = W.request_problem(prm)
+    ref = pcg.pcg_solve(prob.rho, prob.eps, prob.h, "periodic", tol=1e-10)
+    srv = gps.Server(max_active=2, precision="mixed")
+    phi = empty(prob.shape)
+    print("served periodic request vs oracle", flush=True)
+    st, t = srv.submit(dev(prob.rho), dev(prob.eps), phi, prob.h, prob.bc, 1e-6)
+    assert st == gps.GPS_OK
+    res = srv.wait(t)
+    srv.close()
+    assert res["status"] == gps.GPS_OK
+    got = host(phi)
+    # periodic GPe: unique up to a constant
+    d = (got - got.mean()) - (ref.phi - ref.phi.mean())
+    assert np.abs(d).max() <= 1e-5
+    e_ref = pcg.electrostatic_energy(prob.rho, ref.phi, prob.h)
+    assert abs(res["energy"] / e_ref - 1.0) <= 1e-6
+
+
+def test_server_errors_and_polling():
+    torch = require_gpu()
+    prob = W.molecule(16, 0.5, seed=1, n_atoms=4, ball=2.0)
+    rho, eps = dev(prob.rho), dev(prob.eps)
+    small = gps.plan_footprint((16, 16, 16), "free", "mixed")
+    srv = gps.Server(budget_bytes=sum(small), max_active=1, precision="mixed")
+    big = torch.zeros((32, 32, 32), dtype=torch.float64, device="cuda")
+    st, _ = srv.submit(big, big, big.clone(), 0.5, "free", 1e-6)
+    assert st == gps.GPS_E_NOMEM                    # can never fit the budget
+    phi = empty(prob.shape)
+    st, t = srv.submit(rho, eps, phi, prob.h, "free", 1e-6)
+    assert st == gps.GPS_OK
+    # a grid whose padded FFT length (22) has the factor 11: failed in the result
+    odd = torch.ones((11, 11, 11), dtype=torch.float64, device="cuda")
+    st, t_bad = srv.submit(odd * 0.0, odd, odd.clone(), 0.5, "free", 1e-6)
+    assert st == gps.GPS_OK
+    res = srv.wait(t)
+    assert res["status"] == gps.GPS_OK
+    assert srv.wait(t_bad)["status"] == gps.GPS_E_UNSUPPORTED
+    with pytest.raises(gps.GPSError):
+        srv.poll(t)                                 # released ticket
+    stats = srv.stats()
+    srv.close()
+    assert stats["submitted"] == stats["completed"] == 2
