@@ -2,6 +2,8 @@
 // deterministic FP64 block reductions, slot lookup.
 #pragma once
 
+#include <type_traits>
+
 #include "gps_internal.h"
 
 namespace gps {
@@ -73,6 +75,15 @@ __device__ __forceinline__ int xcd_tile(int bid, int G) {
   const int q = G / X, r = G % X;
   const int xcd = bid % X, local = bid / X;
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+// Element at a 32-bit byte offset from a work-group-uniform base pointer.
+// The address is then the scalar base plus a 32-bit vector offset, with no
+// 64-bit vector arithmetic.  Callers guarantee offsets below 4 GiB.
+template <typename V>
+__device__ __forceinline__ V& at_bytes(V* base, unsigned off) {
+  return *reinterpret_cast<V*>(reinterpret_cast<
+      typename std::conditional<std::is_const<V>::value, const char, char>::type*>(base) + off);
 }
 
 // One work-group-uniform flag broadcast from thread 0.

@@ -61,12 +61,15 @@ void k_fstrided(SParams<T> p) {
   const int q = tid / B;
   const int pen = xcd_tile(blockIdx.x, gridDim.x) * B + b;
   const bool pv = pen < p.npencils;
-  size_t base = 0;
+  // 32-bit byte offsets: the longest compile-time length is 384, so every
+  // buffer these passes index is below 4 GiB
+  constexpr unsigned CB = sizeof(cplx<T>);
+  unsigned base = 0;
   if (pv) {
     const int grp = pen / p.per_group;
-    base = (size_t)grp * p.group_stride + (pen - grp * p.per_group);
+    base = CB * ((unsigned)grp * (unsigned)p.group_stride + (unsigned)(pen - grp * p.per_group));
   }
-  const size_t es = (size_t)p.elem_stride;
+  const unsigned es = CB * (unsigned)p.elem_stride;
   const cplx<T>* tw = twl;
 
   // the stop flag is read after the tile loads are issued, so both travel
@@ -78,7 +81,7 @@ void k_fstrided(SParams<T> p) {
 #pragma unroll
       for (int n1 = 0; n1 < L1; ++n1) {
         const int t = L2 * n1 + q;
-        x[n1] = (pv && t < p.Lin) ? work[base + t * es] : cmk(T(0), T(0));
+        x[n1] = (pv && t < p.Lin) ? at_bytes(work, base + (unsigned)t * es) : cmk(T(0), T(0));
       }
     }
     // spectrum multipliers of the z pass: prefetched with the tile
@@ -89,12 +92,12 @@ void k_fstrided(SParams<T> p) {
         const int ky = pen / p.Kx;
         const int kx = pen - ky * p.Kx;
         const int kyf = min(ky, p.Ly - ky);
-        const T* __restrict__ row = p.table + (size_t)kyf * p.Kx + kx;
-        const size_t zs = (size_t)Lyh * p.Kx;
+        const unsigned row = (unsigned)sizeof(T) * (unsigned)(kyf * p.Kx + kx);
+        const unsigned zs = (unsigned)sizeof(T) * (unsigned)(Lyh * p.Kx);
 #pragma unroll
         for (int k2 = 0; k2 < L2; ++k2) {
           const int kz = q + L1 * k2;
-          gm[k2] = row[min(kz, L - kz) * zs];
+          gm[k2] = at_bytes(p.table, row + (unsigned)min(kz, L - kz) * zs);
         }
       }
     }
@@ -121,7 +124,7 @@ void k_fstrided(SParams<T> p) {
 #pragma unroll
         for (int k2 = 0; k2 < L2; ++k2) {
           const int kk = q + L1 * k2;
-          if (kk < p.Lout) work[base + kk * es] = y[k2];
+          if (kk < p.Lout) at_bytes(work, base + (unsigned)kk * es) = y[k2];
         }
       }
       return;
@@ -142,7 +145,7 @@ void k_fstrided(SParams<T> p) {
 #pragma unroll
       for (int k2 = 0; k2 < L2; ++k2) {
         const int kk = q + L1 * k2;
-        y[k2] = (pv && kk < p.Lin) ? work[base + kk * es] : cmk(T(0), T(0));
+        y[k2] = (pv && kk < p.Lin) ? at_bytes(work, base + (unsigned)kk * es) : cmk(T(0), T(0));
       }
     }
 #pragma unroll
@@ -169,7 +172,7 @@ void k_fstrided(SParams<T> p) {
 #pragma unroll
       for (int nb = 0; nb < L1; ++nb) {
         const int t = q + L2 * nb;
-        if (t < p.Lout) work[base + t * es] = x[nb];
+        if (t < p.Lout) at_bytes(work, base + (unsigned)t * es) = x[nb];
       }
     }
   }
@@ -184,9 +187,14 @@ void k_fstrided(SParams<T> p) {
 // before the first one is used.
 template <int L1> constexpr int xthreads() { return round64(kXPairs * L1); }
 
+// Element idx of a buffer with a work-group-uniform base, addressed through a
+// 32-bit byte offset (the buffers of the compile-time lengths are < 4 GiB).
+#define GPS_AT(ptr, idx) at_bytes((ptr), (unsigned)(idx) * (unsigned)sizeof(*(ptr)))
+
 template <typename T>
-__device__ __forceinline__ size_t xrow_offset(const XParams<T>& p, int row, int Kx) {
-  return (size_t)(row / p.rows_per_plane) * p.plane_stride + (size_t)(row % p.rows_per_plane) * Kx;
+__device__ __forceinline__ unsigned xrow_offset(const XParams<T>& p, int row, int Kx) {
+  return (unsigned)(row / p.rows_per_plane) * (unsigned)p.plane_stride +
+         (unsigned)(row % p.rows_per_plane) * (unsigned)Kx;
 }
 
 template <typename T, int L1, int L2, int MODE, bool PAD>
@@ -230,15 +238,15 @@ void k_fxfwd(XParams<T> p) {
     rv[i] = T(0);
     sv[i] = T(0);
     if (e < NIN && grow < p.nrows) {
-      const size_t o = (size_t)grow * p.in_row_stride + x;
+      const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)x;
       if constexpr (MODE == XF_SOLVE) {
-        rv[i] = sl.r[o];
-        sv[i] = sl.isq[o];
-        pv[i] = sl.p[o];
-        av[i] = sl.ap[o];
-        fv[i] = sl.phi[o];
+        rv[i] = GPS_AT(sl.r, o);
+        sv[i] = GPS_AT(sl.isq, o);
+        pv[i] = GPS_AT(sl.p, o);
+        av[i] = GPS_AT(sl.ap, o);
+        fv[i] = GPS_AT(sl.phi, o);
       } else {
-        rv[i] = T(p.in_real[o]);
+        rv[i] = T(GPS_AT(p.in_real, o));
       }
     }
   }
@@ -261,11 +269,11 @@ void k_fxfwd(XParams<T> p) {
       T a = rv[i];
       if constexpr (MODE == XF_SOLVE) {
         if (grow < p.nrows) {
-          const size_t o = (size_t)grow * p.in_row_stride + x;
+          const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)x;
           if (upd) {
-            sl.phi[o] = fv[i] + alpha * double(pv[i]);
+            GPS_AT(sl.phi, o) = fv[i] + alpha * double(pv[i]);
             a = a - T(alpha) * av[i];
-            sl.r[o] = a;
+            GPS_AT(sl.r, o) = a;
           }
           a = a * sv[i];
           mu += double(a);
@@ -325,9 +333,9 @@ void k_fxfwd(XParams<T> p) {
       const cplx<T> zm = lds[(kk == 0 ? 0 : L - kk) * PITCH + p2];
       const T half = T(0.5);
       if (ra < p.nrows)
-        work[xrow_offset(p, ra, Kx) + kk] = cmk(half * (zk.x + zm.x), half * (zk.y - zm.y));
+        GPS_AT(work, xrow_offset(p, ra, Kx) + kk) = cmk(half * (zk.x + zm.x), half * (zk.y - zm.y));
       if (rb < p.nrows)
-        work[xrow_offset(p, rb, Kx) + kk] = cmk(half * (zk.y + zm.y), half * (zm.x - zk.x));
+        GPS_AT(work, xrow_offset(p, rb, Kx) + kk) = cmk(half * (zk.y + zm.y), half * (zm.x - zk.x));
     }
   }
   if constexpr (MODE == XF_SOLVE) {
@@ -375,8 +383,8 @@ void k_fxinv(XParams<T> p) {
     xa[i] = cmk(T(0), T(0));
     xb[i] = cmk(T(0), T(0));
     if (e < NIN) {
-      if (ra < p.nrows) xa[i] = work[xrow_offset(p, ra, Kx) + kk];
-      if (rb < p.nrows) xb[i] = work[xrow_offset(p, rb, Kx) + kk];
+      if (ra < p.nrows) xa[i] = GPS_AT(work, xrow_offset(p, ra, Kx) + kk);
+      if (rb < p.nrows) xb[i] = GPS_AT(work, xrow_offset(p, rb, Kx) + kk);
     }
   }
   // epilogue operands are independent of the transform: load them now too
@@ -389,9 +397,9 @@ void k_fxinv(XParams<T> p) {
       const int xx = e - row * Lout;
       const int grow = row0 + row;
       if (e < NOUT && grow < p.nrows) {
-        const size_t o = (size_t)grow * p.in_row_stride + xx;
-        sv[i] = sl.isq[o];
-        rv[i] = sl.r[o];
+        const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)xx;
+        sv[i] = GPS_AT(sl.isq, o);
+        rv[i] = GPS_AT(sl.r, o);
       }
     }
     if (wg_read_flag(&sl.st->done)) return;
@@ -454,9 +462,9 @@ void k_fxinv(XParams<T> p) {
       const int xx = e - row * Lout;
       const int grow = row0 + row;
       if (e < NOUT && grow < p.nrows) {
-        const size_t o = (size_t)grow * p.in_row_stride + xx;
+        const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)xx;
         const T v = ldsr[2 * (xx * PITCH + (row >> 1)) + (row & 1)] * sv[i];
-        sl.v[o] = v;
+        GPS_AT(sl.v, o) = v;
         acc += double(v) * double(rv[i]);
         acc2 += double(rv[i]) * double(rv[i]);
       }
@@ -475,7 +483,7 @@ void k_fxinv(XParams<T> p) {
       const int xx = e - row * Lout;
       const int grow = row0 + row;
       if (e < NOUT && grow < p.nrows)
-        p.out_real[(size_t)grow * p.in_row_stride + xx] =
+        GPS_AT(p.out_real, (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)xx) =
             double(ldsr[2 * (xx * PITCH + (row >> 1)) + (row & 1)]);
     }
   }

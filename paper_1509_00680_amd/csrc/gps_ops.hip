@@ -229,9 +229,12 @@ void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho, con
 // ---------------------------------------------------------------------------
 struct FdWeights { double c[9]; };
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b,
-                                                     Geom g, int M, FdWeights w,
+// One work-group covers kThreads * kVec consecutive points.  Work-groups are
+// mapped XCD-contiguously, so each XCD's L2 holds one z-slab and its +-M halo
+// planes instead of the whole field.
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, Geom g,
+                                                     FdWeights w,
                                                      const double* __restrict__ lap_sq,
                                                      double kappa_coef,
                                                      const double* __restrict__ eps,
@@ -240,9 +243,11 @@ __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b,
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
   const long long n = (long long)g.nx * g.ny * g.nz;
   const long long plane = (long long)g.nx * g.ny;
-  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  const long long base =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
   const double* __restrict__ sq = sl.sq64;
   const double ih2 = 1.0 / (g.h * g.h);
+  const long long sx = 1, sy = g.nx, sz = plane;
   double kacc = 0.0;   // sum kappa2 / eps (periodic k = 0 multiplier)
 #pragma unroll 1
   for (int j = 0; j < kVec; ++j) {
@@ -257,19 +262,31 @@ __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b,
       lap = lap_sq[i];
     } else {
       double acc = 3.0 * w.c[0] * sc;
-      const long long zo = (long long)z * plane, yo = (long long)y * g.nx;
-      for (int m = 1; m <= M; ++m) {
-        int xp = x + m, xm = x - m, yp = y + m, ym = y - m, zp = z + m, zm = z - m;
-        if (g.periodic_x) { xp %= g.nx; xm = ((xm % g.nx) + g.nx) % g.nx; }
-        else { xp = min(xp, g.nx - 1); xm = max(xm, 0); }
-        if (g.periodic_y) { yp %= g.ny; ym = ((ym % g.ny) + g.ny) % g.ny; }
-        else { yp = min(yp, g.ny - 1); ym = max(ym, 0); }
-        if (g.periodic_z) { zp %= g.nz; zm = ((zm % g.nz) + g.nz) % g.nz; }
-        else { zp = min(zp, g.nz - 1); zm = max(zm, 0); }
-        const double sxx = sq[zo + yo + xp] + sq[zo + yo + xm];
-        const double syy = sq[zo + (long long)yp * g.nx + x] + sq[zo + (long long)ym * g.nx + x];
-        const double szz = sq[(long long)zp * plane + yo + x] + sq[(long long)zm * plane + yo + x];
-        acc += w.c[m] * (sxx + syy + szz);
+      if (x >= M && x < g.nx - M && y >= M && y < g.ny - M && z >= M && z < g.nz - M) {
+        // interior: no ghost handling
+#pragma unroll
+        for (int m = 1; m <= M; ++m) {
+          const double sxx = sq[i + m * sx] + sq[i - m * sx];
+          const double syy = sq[i + m * sy] + sq[i - m * sy];
+          const double szz = sq[i + m * sz] + sq[i - m * sz];
+          acc += w.c[m] * (sxx + syy + szz);
+        }
+      } else {
+        const long long zo = (long long)z * plane, yo = (long long)y * g.nx;
+#pragma unroll
+        for (int m = 1; m <= M; ++m) {
+          int xp = x + m, xm = x - m, yp = y + m, ym = y - m, zp = z + m, zm = z - m;
+          if (g.periodic_x) { xp %= g.nx; xm = ((xm % g.nx) + g.nx) % g.nx; }
+          else { xp = min(xp, g.nx - 1); xm = max(xm, 0); }
+          if (g.periodic_y) { yp %= g.ny; ym = ((ym % g.ny) + g.ny) % g.ny; }
+          else { yp = min(yp, g.ny - 1); ym = max(ym, 0); }
+          if (g.periodic_z) { zp %= g.nz; zm = ((zm % g.nz) + g.nz) % g.nz; }
+          else { zp = min(zp, g.nz - 1); zm = max(zm, 0); }
+          const double sxx = sq[zo + yo + xp] + sq[zo + yo + xm];
+          const double syy = sq[zo + (long long)yp * g.nx + x] + sq[zo + (long long)ym * g.nx + x];
+          const double szz = sq[(long long)zp * plane + yo + x] + sq[(long long)zm * plane + yo + x];
+          acc += w.c[m] * (sxx + syy + szz);
+        }
       }
       lap = acc * ih2;
     }
@@ -311,8 +328,18 @@ void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g, int f
                    const double* lap_sq, double kappa_coef, const double* eps,
                    const double* gamma, double eps_bulk, hipStream_t s) {
   const long long n = (long long)g.nx * g.ny * g.nz;
-  GPS_LAUNCH((k_qfield<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, g,
-                     fd_half, fd_weights(fd_half), lap_sq, kappa_coef, eps, gamma, eps_bulk);
+  const dim3 grid(vec_groups(n), b.n);
+  const FdWeights w = fd_weights(fd_half);
+#define GPS_QF(MM)                                                                        \
+  case MM:                                                                                \
+    GPS_LAUNCH((k_qfield<T, MM>), grid, dim3(kThreads), 0, s, tab, b, g, w, lap_sq,       \
+               kappa_coef, eps, gamma, eps_bulk);                                         \
+    break;
+  switch (fd_half) {
+    GPS_QF(1) GPS_QF(2) GPS_QF(3) GPS_QF(4) GPS_QF(5) GPS_QF(6) GPS_QF(7) GPS_QF(8)
+    default: break;
+  }
+#undef GPS_QF
 }
 
 // ---------------------------------------------------------------------------

@@ -199,11 +199,17 @@ def molecule(n=96, h=0.3, seed=2, n_atoms=24, ball=6.0, net_charge=0.0, tol=1e-6
 
 
 def charged_solute_mpb(n=160, h=0.3, seed=4, n_atoms=48, ball=6.0, net_charge=4.0,
-                       molar=1.0, eta=0.3, tol=1e-6, steric=True):
-    """Nonlinear PB: charged solute, 1:1 electrolyte, accessibility from eps."""
+                       molar=1.0, eta=0.15, tol=1e-6, steric=True, outer_maxit=200):
+    """Nonlinear PB: charged solute, 1:1 electrolyte, accessibility from eps.
+
+    eta = 0.15: in this 48-bohr box at 1 M the plain linear mixing of the
+    self-consistent loop settles into a non-contracting cycle for eta >= 0.2
+    (the screening response of the box-scale mode is about -10); 0.15
+    converges in about 50 outer steps."""
     p = molecule(n, h, seed, n_atoms, ball, net_charge, tol)
     c = molar * MOLAR_BOHR3
-    ions = electrolyte_1to1(c, c_max=steric_cmax() if steric else None, eta=eta)
+    ions = electrolyte_1to1(c, c_max=steric_cmax() if steric else None, eta=eta,
+                            outer_maxit=outer_maxit)
     return Problem("mpb%d_s%d" % (n, seed), p.shape, h, BC_FREE, p.rho, p.eps, tol,
                    ions=ions, kind="pb_nonlinear", meta=p.meta)
 

@@ -122,7 +122,7 @@ def test_nonlinear_pb_matches_oracle(precision, steric):
     if not steric:       # the Boltzmann law overflows at full charge (see below)
         prob.rho = prob.rho * 0.1
     oi = oracle_ions(prob.ions)
-    ref = pb.scpb_improved(prob.rho, prob.eps, prob.h, "free", oi, 1e-9, eta=0.3)
+    ref = pb.scpb_improved(prob.rho, prob.eps, prob.h, "free", oi, 1e-9, eta=prob.ions["eta"])
     assert ref.converged
     p = plan(prob.shape, prob.h, "free", precision)
     phi = empty(prob.shape)
@@ -144,7 +144,8 @@ def test_boltzmann_overflow_reported():
     require_gpu()
     prob = W.charged_solute_mpb(n=24, h=0.5, n_atoms=8, ball=2.0, net_charge=1.0,
                                 molar=0.1, steric=False)
-    ref = pb.scpb_improved(prob.rho, prob.eps, prob.h, "free", oracle_ions(prob.ions), 1e-9)
+    ref = pb.scpb_improved(prob.rho, prob.eps, prob.h, "free", oracle_ions(prob.ions), 1e-9,
+                           eta=prob.ions["eta"])
     assert ref.status == "nonfinite"
     p = plan(prob.shape, prob.h, "free", "fp64")
     st = p.solve_pb(dev(prob.rho), dev(prob.eps), prob.ions, empty(prob.shape), 1e-9)

@@ -107,7 +107,7 @@ def test_nonlinear_pb_outer_convergence_mpb():
     p = W.charged_solute_mpb(n=32, h=0.5, n_atoms=12, ball=3.0, net_charge=2.0)
     io = p.ions
     ions = pb.Electrolyte(io["Z"], io["c_bulk"], io["kT"], c_max=io["c_max"])
-    res = pb.scpb_improved(p.rho, p.eps, p.h, "free", ions, 1e-8, eta=io["eta"])
+    res = pb.scpb_improved(p.rho, p.eps, p.h, "free", ions, 1e-8, eta=0.3)
     assert res.converged and res.outer < 60
     # late inner solves are cheap (warm start through the carried residual)
     assert res.inner_iterations[-1] <= max(res.inner_iterations[:3])
