@@ -86,14 +86,11 @@ __device__ __forceinline__ V& at_bytes(V* base, unsigned off) {
       typename std::conditional<std::is_const<V>::value, const char, char>::type*>(base) + off);
 }
 
-// One work-group-uniform flag broadcast from thread 0.
-__device__ __forceinline__ int wg_read_flag(const int* p) {
-  __shared__ int f;
-  if (threadIdx.x == 0) f = *reinterpret_cast<const volatile int*>(p);
-  __syncthreads();
-  int r = f;
-  __syncthreads();
-  return r;
-}
+// Stop flag of a solve, for the passes that run while no kernel writes it
+// (the y, z and x-inverse passes: the flag's writers, the direction kernel and
+// the x-forward head, come earlier in stream order).  A plain load: its value
+// is the same for every wavefront of the launch, so it needs no broadcast, and
+// it waits for nothing but itself.
+__device__ __forceinline__ int solve_stopped(const SolveState* st) { return st->done; }
 
 }  // namespace gps

@@ -209,7 +209,9 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(XParams<T> p) {
   bool upd = false;
   if constexpr (MODE == XF_SOLVE) {
     int k;
-    if (!xfwd_head(sl, p.n_vec_parts, &k, &alpha)) return;
+    XHead hd;
+    xfwd_head_load(sl, p.n_vec_parts, hd);
+    if (!xfwd_head_finish(sl, p.n_vec_parts, hd, &k, &alpha)) return;
     upd = k > 0;
     work = sl.work;
   }
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(XParams<T> p) {
   cplx<T>* work = p.work;
   const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
   if constexpr (MODE == XI_SOLVE) {
-    if (wg_read_flag(&sl.st->done)) return;
+    if (solve_stopped(sl.st)) return;
     work = sl.work;
   }
   for (int e = tid; e < P * Kx; e += kThreads) {
@@ -351,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void k_strided(SParams<T> p) {
   const SolveState* st = nullptr;
   if (work == nullptr) {
     const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
-    if (wg_read_flag(&sl.st->done)) return;
+    if (solve_stopped(sl.st)) return;
     work = sl.work;
     st = sl.st;
   }

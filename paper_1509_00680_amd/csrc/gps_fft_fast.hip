@@ -35,7 +35,13 @@ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return cmk(a.x, -a.y); }
 // ---------------------------------------------------------------------------
 // strided passes
 // ---------------------------------------------------------------------------
-template <typename T, int L1, int L2, int MODE>
+// A work-group transforms NTILE adjacent tiles of B pencils.  Every global load
+// of all its tiles is issued first, so the later tiles' loads are in flight
+// while the first tile is transformed.  PAD: the pencil holds L/2 data points
+// (Hockney zero padding): the forward and z passes read, and the inverse and z
+// passes write, only the first L/2 elements, and the zero half is a
+// compile-time constant.
+template <typename T, int L1, int L2, int MODE, bool PAD, int NTILE>
 __global__ __launch_bounds__(round64(FastTile<T>::B * L1))
 void k_fstrided(SParams<T> p) {
   constexpr int B = FastTile<T>::B;
@@ -59,120 +65,152 @@ void k_fstrided(SParams<T> p) {
   }
   const int b = tid & (B - 1);
   const int q = tid / B;
-  const int pen = xcd_tile(blockIdx.x, gridDim.x) * B + b;
-  const bool pv = pen < p.npencils;
+  const int tile0 = xcd_tile(blockIdx.x, gridDim.x) * NTILE;
   // 32-bit byte offsets: the longest compile-time length is 384, so every
   // buffer these passes index is below 4 GiB
   constexpr unsigned CB = sizeof(cplx<T>);
-  unsigned base = 0;
-  if (pv) {
-    const int grp = pen / p.per_group;
-    base = CB * ((unsigned)grp * (unsigned)p.group_stride + (unsigned)(pen - grp * p.per_group));
-  }
   const unsigned es = CB * (unsigned)p.elem_stride;
-  const cplx<T>* tw = twl;
-
-  // the stop flag is read after the tile loads are issued, so both travel
-  // together (a stopped solve wastes the loads, never a round trip)
-  cplx<T> y[L2];
-  if constexpr (MODE != ST_INV) {
-    cplx<T> x[L1];
-    if (q < L2) {
+  int pen[NTILE];
+  bool pv[NTILE];
+  unsigned base[NTILE];
 #pragma unroll
-      for (int n1 = 0; n1 < L1; ++n1) {
-        const int t = L2 * n1 + q;
-        x[n1] = (pv && t < p.Lin) ? at_bytes(work, base + (unsigned)t * es) : cmk(T(0), T(0));
-      }
+  for (int t = 0; t < NTILE; ++t) {
+    pen[t] = (tile0 + t) * B + b;
+    pv[t] = pen[t] < p.npencils;
+    base[t] = 0;
+    if (pv[t]) {
+      const int grp = pen[t] / p.per_group;
+      base[t] = CB * ((unsigned)grp * (unsigned)p.group_stride +
+                      (unsigned)(pen[t] - grp * p.per_group));
     }
-    // spectrum multipliers of the z pass: prefetched with the tile
-    T gm[MODE == ST_CONV ? L2 : 1];
-    if constexpr (MODE == ST_CONV) {
-      if (pv && q < L1) {
-        const int Lyh = p.Ly / 2 + 1;
-        const int ky = pen / p.Kx;
-        const int kx = pen - ky * p.Kx;
-        const int kyf = min(ky, p.Ly - ky);
-        const unsigned row = (unsigned)sizeof(T) * (unsigned)(kyf * p.Kx + kx);
-        const unsigned zs = (unsigned)sizeof(T) * (unsigned)(Lyh * p.Kx);
+  }
+  // data extents: PAD bounds the input of the forward and z passes and the
+  // output of the inverse and z passes
+  const int lin = (PAD && MODE != ST_INV) ? L / 2 : p.Lin;
+  const int lout = (PAD && MODE != ST_FWD) ? L / 2 : p.Lout;
+
+  // ---- phase 1: every load of every tile (the stop flag is read after them,
+  // so both travel together: a stopped solve wastes the loads, never a round
+  // trip) ----
+  cplx<T> xin[MODE != ST_INV ? NTILE : 1][L1];
+  cplx<T> yin[MODE == ST_INV ? NTILE : 1][L2];
+  T gm[MODE == ST_CONV ? NTILE : 1][MODE == ST_CONV ? L2 : 1];
 #pragma unroll
-        for (int k2 = 0; k2 < L2; ++k2) {
-          const int kz = q + L1 * k2;
-          gm[k2] = at_bytes(p.table, row + (unsigned)min(kz, L - kz) * zs);
+  for (int t = 0; t < NTILE; ++t) {
+    if constexpr (MODE != ST_INV) {
+      if (q < L2) {
+#pragma unroll
+        for (int n1 = 0; n1 < L1; ++n1) {
+          const int e = L2 * n1 + q;
+          const bool in = PAD ? (n1 < L1 / 2) : (e < lin);
+          xin[t][n1] = (pv[t] && in) ? at_bytes(work, base[t] + (unsigned)e * es)
+                                     : cmk(T(0), T(0));
         }
       }
-    }
+      if constexpr (MODE == ST_CONV) {
+        // spectrum multipliers of the z pass: prefetched with the tile
+        if (pv[t] && q < L1) {
+          const int Lyh = p.Ly / 2 + 1;
+          const int ky = pen[t] / p.Kx;
+          const int kx = pen[t] - ky * p.Kx;
+          const int kyf = min(ky, p.Ly - ky);
+          const unsigned row = (unsigned)sizeof(T) * (unsigned)(kyf * p.Kx + kx);
+          const unsigned zs = (unsigned)sizeof(T) * (unsigned)(Lyh * p.Kx);
 #pragma unroll
-    for (int i = 0; i < (L + NT - 1) / NT; ++i)
-      if (tid + i * NT < L) twl[tid + i * NT] = twv[i];
-    if (st && wg_read_flag(&st->done)) return;   // (includes a barrier)
-    if (st == nullptr) __syncthreads();
-    if (q < L2) {
-      reg_fft<T, false, L1>(x);
-#pragma unroll
-      for (int k1 = 1; k1 < L1; ++k1) x[k1] = cmul(x[k1], tw[q * k1]);
-#pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) lds[(q * L1 + k1) * PITCH + b] = x[k1];
-    }
-    __syncthreads();
-    if (q < L1) {
-#pragma unroll
-      for (int n2 = 0; n2 < L2; ++n2) y[n2] = lds[(n2 * L1 + q) * PITCH + b];
-      reg_fft<T, false, L2>(y);                 // y[k2] = X[q + L1 k2]
-    }
-    if constexpr (MODE == ST_FWD) {
-      if (pv && q < L1) {
+          for (int k2 = 0; k2 < L2; ++k2) {
+            const int kz = q + L1 * k2;
+            gm[t][k2] = at_bytes(p.table, row + (unsigned)min(kz, L - kz) * zs);
+          }
+        }
+      }
+    } else {
+      if (q < L1) {
 #pragma unroll
         for (int k2 = 0; k2 < L2; ++k2) {
           const int kk = q + L1 * k2;
-          if (kk < p.Lout) at_bytes(work, base + (unsigned)kk * es) = y[k2];
+          yin[t][k2] = (pv[t] && kk < lin) ? at_bytes(work, base[t] + (unsigned)kk * es)
+                                           : cmk(T(0), T(0));
         }
       }
-      return;
-    } else {
-      if (pv && q < L1) {
-#pragma unroll
-        for (int k2 = 0; k2 < L2; ++k2) {
-          const int kz = q + L1 * k2;
-          T m = gm[k2];
-          if (p.k0_from_slot && pen == 0 && kz == 0) m = T(st->g0);
-          y[k2] = cscale(y[k2], m);
-        }
-      }
-      __syncthreads();                          // step-2 reads of lds are done
     }
-  } else {
-    if (q < L1) {
-#pragma unroll
-      for (int k2 = 0; k2 < L2; ++k2) {
-        const int kk = q + L1 * k2;
-        y[k2] = (pv && kk < p.Lin) ? at_bytes(work, base + (unsigned)kk * es) : cmk(T(0), T(0));
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < (L + NT - 1) / NT; ++i)
-      if (tid + i * NT < L) twl[tid + i * NT] = twv[i];
-    if (st && wg_read_flag(&st->done)) return;   // (includes a barrier)
-    if (st == nullptr) __syncthreads();
   }
-  // inverse transform (ST_CONV second half, ST_INV)
-  if (q < L1) {
-    reg_fft<T, true, L2>(y);                    // y[n_a] = Z[q][n_a]
 #pragma unroll
-    for (int na = 1; na < L2; ++na) y[na] = cmul(y[na], cconj(tw[na * q]));
-#pragma unroll
-    for (int na = 0; na < L2; ++na) lds[(na * L1 + q) * PITCH + b] = y[na];
-  }
+  for (int i = 0; i < (L + NT - 1) / NT; ++i)
+    if (tid + i * NT < L) twl[tid + i * NT] = twv[i];
+  if (st && solve_stopped(st)) return;
   __syncthreads();
-  if (q < L2) {
-    cplx<T> x[L1];
+  const cplx<T>* tw = twl;
+
+  // ---- phase 2: transform the tiles one after the other ----
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) x[k1] = lds[(q * L1 + k1) * PITCH + b];
-    reg_fft<T, true, L1>(x);                    // x[n_b] = out[q + L2 n_b]
-    if (pv) {
+  for (int t = 0; t < NTILE; ++t) {
+    if (t > 0) __syncthreads();                 // previous tile's LDS reads are done
+    cplx<T> y[L2];
+    if constexpr (MODE != ST_INV) {
+      if (q < L2) {
+        cplx<T> x[L1];
 #pragma unroll
-      for (int nb = 0; nb < L1; ++nb) {
-        const int t = q + L2 * nb;
-        if (t < p.Lout) at_bytes(work, base + (unsigned)t * es) = x[nb];
+        for (int n1 = 0; n1 < L1; ++n1) x[n1] = xin[t][n1];
+        reg_fft<T, false, L1>(x);
+#pragma unroll
+        for (int k1 = 1; k1 < L1; ++k1) x[k1] = cmul(x[k1], tw[q * k1]);
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) lds[(q * L1 + k1) * PITCH + b] = x[k1];
+      }
+      __syncthreads();
+      if (q < L1) {
+#pragma unroll
+        for (int n2 = 0; n2 < L2; ++n2) y[n2] = lds[(n2 * L1 + q) * PITCH + b];
+        reg_fft<T, false, L2>(y);               // y[k2] = X[q + L1 k2]
+      }
+      if constexpr (MODE == ST_FWD) {
+        if (pv[t] && q < L1) {
+#pragma unroll
+          for (int k2 = 0; k2 < L2; ++k2) {
+            const int kk = q + L1 * k2;
+            if (kk < lout) at_bytes(work, base[t] + (unsigned)kk * es) = y[k2];
+          }
+        }
+        continue;
+      } else {
+        if (pv[t] && q < L1) {
+#pragma unroll
+          for (int k2 = 0; k2 < L2; ++k2) {
+            const int kz = q + L1 * k2;
+            T m = gm[t][k2];
+            if (p.k0_from_slot && pen[t] == 0 && kz == 0) m = T(st->g0);
+            y[k2] = cscale(y[k2], m);
+          }
+        }
+        __syncthreads();                        // step-2 reads of lds are done
+      }
+    } else {
+      if (q < L1) {
+#pragma unroll
+        for (int k2 = 0; k2 < L2; ++k2) y[k2] = yin[t][k2];
+      }
+    }
+    // inverse transform (ST_CONV second half, ST_INV)
+    if (q < L1) {
+      reg_fft<T, true, L2>(y);                  // y[n_a] = Z[q][n_a]
+#pragma unroll
+      for (int na = 1; na < L2; ++na) y[na] = cmul(y[na], cconj(tw[na * q]));
+#pragma unroll
+      for (int na = 0; na < L2; ++na) lds[(na * L1 + q) * PITCH + b] = y[na];
+    }
+    __syncthreads();
+    if (q < L2) {
+      cplx<T> x[L1];
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) x[k1] = lds[(q * L1 + k1) * PITCH + b];
+      reg_fft<T, true, L1>(x);                  // x[n_b] = out[q + L2 n_b]
+      if (pv[t]) {
+#pragma unroll
+        for (int nb = 0; nb < L1; ++nb) {
+          const int e = q + L2 * nb;
+          const bool out = PAD ? (nb < L1 / 2) : (e < lout);
+          if (out) at_bytes(work, base[t] + (unsigned)e * es) = x[nb];
+        }
       }
     }
   }
@@ -224,9 +262,12 @@ void k_fxfwd(XParams<T> p) {
 #pragma unroll
   for (int i = 0; i < ETW; ++i)
     if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
-  // phase 1: all loads of this thread, issued before the iteration head so
-  // that their latency and the head's (flag, partial sums) overlap; p, Ap and
-  // phi are loaded even at k = 0 (unused there)
+  // the head's own loads (state words, (p, Ap) partials) go first, then every
+  // operand load of this thread: the head waits only for its loads, and the
+  // operands arrive while it decides.  p, Ap and phi are loaded even at k = 0
+  // (unused there).
+  XHead hd;
+  if constexpr (MODE == XF_SOLVE) xfwd_head_load(sl, p.n_vec_parts, hd);
   T rv[EIN], sv[EIN], pv[EIN], av[EIN];
   double fv[EIN];
 #pragma unroll
@@ -254,7 +295,7 @@ void k_fxfwd(XParams<T> p) {
   bool upd = false;
   if constexpr (MODE == XF_SOLVE) {
     int k;
-    if (!xfwd_head(sl, p.n_vec_parts, &k, &alpha)) return;
+    if (!xfwd_head_finish(sl, p.n_vec_parts, hd, &k, &alpha)) return;
     upd = k > 0;
   }
   // phase 2: update, scale, stage the rows in LDS
@@ -402,7 +443,7 @@ void k_fxinv(XParams<T> p) {
         rv[i] = GPS_AT(sl.r, o);
       }
     }
-    if (wg_read_flag(&sl.st->done)) return;
+    if (solve_stopped(sl.st)) return;
   }
 #pragma unroll
   for (int i = 0; i < EIN; ++i) {
@@ -507,17 +548,32 @@ bool fast_length(int L) {
 
 int fast_xpass_groups(int nrows) { return ((nrows + 1) / 2 + kXPairs - 1) / kXPairs; }
 
+// Tiles per work-group of the strided passes.
+constexpr int kStridedTiles = 1;
+
 template <typename T>
 bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
   constexpr int B = FastTile<T>::B;
-  const dim3 grid((p.npencils + B - 1) / B, p.work ? 1 : p.batch.n);
+  constexpr int NTL = kStridedTiles;
+  // PAD when the pencil's data half is L/2: forward reads, z pass reads and
+  // writes, inverse writes that half only
+  const bool pad = (mode == ST_FWD && 2 * p.Lin == p.L) ||
+                   (mode == ST_CONV && 2 * p.Lin == p.L && p.Lout == p.Lin) ||
+                   (mode == ST_INV && 2 * p.Lout == p.L && p.Lin == p.L);
+  const dim3 grid((p.npencils + B * NTL - 1) / (B * NTL), p.work ? 1 : p.batch.n);
   switch (p.L) {
 #define GPS_CASE(LL, A, BB)                                                                    \
   case LL: {                                                                                   \
     const dim3 blk(round64(B * A));                                                            \
-    if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD>), grid, blk, 0, s, p);  \
-    else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV>), grid, blk, 0, s, p); \
-    else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV>), grid, blk, 0, s, p);             \
+    if (pad) {                                                                                 \
+      if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD, true, NTL>), grid, blk, 0, s, p);   \
+      else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV, true, NTL>), grid, blk, 0, s, p); \
+      else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, true, NTL>), grid, blk, 0, s, p);             \
+    } else {                                                                                   \
+      if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD, false, NTL>), grid, blk, 0, s, p);  \
+      else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV, false, NTL>), grid, blk, 0, s, p); \
+      else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, false, NTL>), grid, blk, 0, s, p);            \
+    }                                                                                          \
     return true;                                                                               \
   }
     GPS_FAST_LENGTHS(GPS_CASE)

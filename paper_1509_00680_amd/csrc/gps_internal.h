@@ -58,6 +58,7 @@ struct SolveState {
   double abs_thr;    // absolute stop threshold on ||r||
   double rel_thr;    // relative stop threshold on ||r|| / ||r_0||
   double g0;         // periodic k = 0 multiplier of the preconditioner
+  double delta[2];   // delta_k = (v_k, r_k) at index k & 1 (direction kernel)
 };
 
 // Input-check flags (SolveState::err)

@@ -177,7 +177,10 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotTable<T> tab, Batch b,
                                                    const double* __restrict__ rho,
                                                    const double* __restrict__ eps, long long n) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
-  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  // XCD-contiguous chunks: each XCD works on the same 1/8 of the grid as the
+  // x passes, so fields written by one kernel are read from the same L2
+  const long long base =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   int err = 0;
 #pragma unroll
@@ -348,33 +351,38 @@ void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g, int f
 //   A v = -(q + kappa2) v - 4 pi (r - sqrt(eps) mean(r/sqrt(eps)))  [periodic]
 //   p = v + beta p;  Ap = A v + beta Ap;  partial (p, Ap)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int periodic>
 __global__ __launch_bounds__(kThreads) void k_direction(SlotTable<T> tab, Batch b, long long n,
-                                                        int n_xparts, int periodic,
-                                                        int check_neutral) {
+                                                        int n_xparts, int check_neutral) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
-  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
-  // operands first: their loads overlap the head's flag and partial-sum reads
+  // head inputs first (one round), then the operands, which arrive while the
+  // head reduces and decides
+  DHead h;
+  direction_head_load(sl, n_xparts, periodic, h);
+  // XCD-contiguous chunks: each XCD works on the same 1/8 of the grid as the
+  // x passes, so fields written by one kernel are read from the same L2
+  const long long base =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
+  // branch-free loads (clamped index; results past n are never stored), so
+  // that they issue back to back and nothing waits for them before use
   T vv[kVec], rv[kVec], qv[kVec], pv[kVec], av[kVec], sv[kVec];
 #pragma unroll
   for (int j = 0; j < kVec; ++j) {
     const long long i = base + (long long)j * kThreads;
-    if (i < n) {
-      vv[j] = sl.v[i];
-      rv[j] = sl.r[i];
-      qv[j] = sl.qk[i];
-      pv[j] = sl.p[i];
-      av[j] = sl.ap[i];
-      sv[j] = periodic ? sl.s[i] : T(0);
-    }
+    const long long ic = i < n ? i : n - 1;
+    vv[j] = sl.v[ic];
+    rv[j] = sl.r[ic];
+    qv[j] = sl.qk[ic];
+    pv[j] = sl.p[ic];
+    av[j] = sl.ap[ic];
+    sv[j] = periodic ? sl.s[ic] : T(0);
   }
   int k;
-  double delta;
-  if (!direction_head(sl, n_xparts, vec_groups(n), check_neutral, &k, &delta)) return;
-  double beta = 0.0;
-  if (k > 0) beta = delta / sl.hist[(size_t)(k - 1) * 4 + 0];
-  double mu = 0.0;
-  if (periodic) mu = sum_partials(sl.part_mu, n_xparts) / double(n);
+  double delta, beta, mu;
+  if (!direction_head_finish(sl, h, n_xparts, vec_groups(n), check_neutral, periodic, &k, &delta,
+                             &beta, &mu))
+    return;
+  mu /= double(n);
   const T tb = T(beta), tmu = T(mu), fpi = T(kFourPi);
   double acc = 0.0;
 #pragma unroll
@@ -397,17 +405,17 @@ __global__ __launch_bounds__(kThreads) void k_direction(SlotTable<T> tab, Batch 
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) sl.part_pap[blockIdx.x] = acc;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sl.hist[(size_t)k * 4 + 0] = delta;
-    sl.hist[(size_t)k * 4 + 1] = beta;
-  }
 }
 
 template <typename T>
 void launch_direction(const SlotTable<T>& tab, const Batch& b, long long n, int n_xparts,
                       int periodic, int check_neutral, hipStream_t s) {
-  GPS_LAUNCH((k_direction<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n,
-                     n_xparts, periodic, check_neutral);
+  if (periodic)
+    GPS_LAUNCH((k_direction<T, 1>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n,
+               n_xparts, check_neutral);
+  else
+    GPS_LAUNCH((k_direction<T, 0>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n,
+               n_xparts, check_neutral);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,7 +431,10 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_ion_update(SlotTable<T> tab, Batch b, long long n,
                                                          IonParams ip) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
-  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  // XCD-contiguous chunks: each XCD works on the same 1/8 of the grid as the
+  // x passes, so fields written by one kernel are read from the same L2
+  const long long base =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
   double a0 = 0.0, a3 = 0.0;
   const T fpi = T(kFourPi);
 #pragma unroll 1
@@ -486,7 +497,10 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_zero_ion(SlotTable<T> tab, Batch b,
                                                        long long n) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
-  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  // XCD-contiguous chunks: each XCD works on the same 1/8 of the grid as the
+  // x passes, so fields written by one kernel are read from the same L2
+  const long long base =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
 #pragma unroll
   for (int j = 0; j < kVec; ++j) {
     const long long i = base + (long long)j * kThreads;
@@ -506,7 +520,10 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_energy(SlotTable<T> tab, Batch b,
                                                      const double* __restrict__ rho, long long n) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
-  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  // XCD-contiguous chunks: each XCD works on the same 1/8 of the grid as the
+  // x passes, so fields written by one kernel are read from the same L2
+  const long long base =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < kVec; ++j) {
