@@ -32,6 +32,15 @@ constexpr int round64(int v) { return (v + 63) / 64 * 64; }
 template <typename T>
 __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return cmk(a.x, -a.y); }
 
+// Store of a value that the next kernel reads on other XCDs (the transposes
+// around the z pass): non-temporal, so the line does not stay dirty in this
+// XCD's L2 until the end-of-kernel write-back.
+template <typename T>
+__device__ __forceinline__ void store_stream(cplx<T>* dst, cplx<T> v) {
+  __builtin_nontemporal_store(v.x, &dst->x);
+  __builtin_nontemporal_store(v.y, &dst->y);
+}
+
 // ---------------------------------------------------------------------------
 // strided passes
 // ---------------------------------------------------------------------------
@@ -168,7 +177,7 @@ void k_fstrided(SParams<T> p) {
 #pragma unroll
           for (int k2 = 0; k2 < L2; ++k2) {
             const int kk = q + L1 * k2;
-            if (kk < lout) at_bytes(work, base[t] + (unsigned)kk * es) = y[k2];
+            if (kk < lout) store_stream(&at_bytes(work, base[t] + (unsigned)kk * es), y[k2]);
           }
         }
         continue;
@@ -209,7 +218,10 @@ void k_fstrided(SParams<T> p) {
         for (int nb = 0; nb < L1; ++nb) {
           const int e = q + L2 * nb;
           const bool out = PAD ? (nb < L1 / 2) : (e < lout);
-          if (out) at_bytes(work, base[t] + (unsigned)e * es) = x[nb];
+          if (out) {
+            if constexpr (MODE == ST_CONV) store_stream(&at_bytes(work, base[t] + (unsigned)e * es), x[nb]);
+            else at_bytes(work, base[t] + (unsigned)e * es) = x[nb];
+          }
         }
       }
     }
@@ -229,10 +241,24 @@ template <int L1> constexpr int xthreads() { return round64(kXPairs * L1); }
 // 32-bit byte offset (the buffers of the compile-time lengths are < 4 GiB).
 #define GPS_AT(ptr, idx) at_bytes((ptr), (unsigned)(idx) * (unsigned)sizeof(*(ptr)))
 
-template <typename T>
-__device__ __forceinline__ unsigned xrow_offset(const XParams<T>& p, int row, int Kx) {
-  return (unsigned)(row / p.rows_per_plane) * (unsigned)p.plane_stride +
-         (unsigned)(row % p.rows_per_plane) * (unsigned)Kx;
+// Work-buffer offsets of the NR consecutive rows row0, row0 + 1, ... of a
+// tile (0 for rows past nrows).  row0 is work-group uniform, so the one division runs on the scalar
+// unit and the offsets stay in scalar registers.
+template <int NR, typename T>
+__device__ __forceinline__ void tile_row_offsets(const XParams<T>& p, int row0, int Kx,
+                                                 unsigned* off, bool* ok) {
+  int pl = row0 / p.rows_per_plane;
+  int rr = row0 - pl * p.rows_per_plane;
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    ok[j] = row0 + j < p.nrows;
+    // rows past the end get offset 0, so that unconditional loads stay in bounds
+    off[j] = ok[j] ? (unsigned)pl * (unsigned)p.plane_stride + (unsigned)rr * (unsigned)Kx : 0u;
+    if (++rr == p.rows_per_plane) {
+      rr = 0;
+      ++pl;
+    }
+  }
 }
 
 template <typename T, int L1, int L2, int MODE, bool PAD>
@@ -246,8 +272,7 @@ void k_fxfwd(XParams<T> p) {
   constexpr int Kx = L / 2 + 1;
   constexpr int NIN = 2 * P * Lin;                 // real inputs of the tile
   constexpr int EIN = (NIN + NT - 1) / NT;
-  constexpr int NOUT = P * Kx;                     // complex outputs per row parity
-  constexpr int EOUT = (NOUT + NT - 1) / NT;
+  constexpr int KI = (Kx + NT - 1) / NT;           // output bins per thread and row pair
   __shared__ cplx<T> lds[L * PITCH];
   __shared__ cplx<T> twl[L];
   T* ldsr = reinterpret_cast<T*>(lds);
@@ -363,20 +388,23 @@ void k_fxfwd(XParams<T> p) {
     for (int k2 = 0; k2 < L2; ++k2) lds[(q + L1 * k2) * PITCH + pp] = y[k2];
   }
   __syncthreads();
+  unsigned roff[2 * P];
+  bool rok[2 * P];
+  tile_row_offsets<2 * P>(p, row0, Kx, roff, rok);
 #pragma unroll
-  for (int i = 0; i < EOUT; ++i) {
-    const int e = tid + i * NT;
-    if (e < NOUT) {
-      const int p2 = e / Kx;
-      const int kk = e - p2 * Kx;
-      const int ra = row0 + 2 * p2, rb = ra + 1;
-      const cplx<T> zk = lds[kk * PITCH + p2];
-      const cplx<T> zm = lds[(kk == 0 ? 0 : L - kk) * PITCH + p2];
-      const T half = T(0.5);
-      if (ra < p.nrows)
-        GPS_AT(work, xrow_offset(p, ra, Kx) + kk) = cmk(half * (zk.x + zm.x), half * (zk.y - zm.y));
-      if (rb < p.nrows)
-        GPS_AT(work, xrow_offset(p, rb, Kx) + kk) = cmk(half * (zk.y + zm.y), half * (zm.x - zk.x));
+  for (int p2 = 0; p2 < P; ++p2) {
+#pragma unroll
+    for (int i = 0; i < KI; ++i) {
+      const int kk = tid + i * NT;
+      if (kk < Kx) {
+        const cplx<T> zk = lds[kk * PITCH + p2];
+        const cplx<T> zm = lds[(kk == 0 ? 0 : L - kk) * PITCH + p2];
+        const T half = T(0.5);
+        if (rok[2 * p2])
+          GPS_AT(work, roff[2 * p2] + kk) = cmk(half * (zk.x + zm.x), half * (zk.y - zm.y));
+        if (rok[2 * p2 + 1])
+          GPS_AT(work, roff[2 * p2 + 1] + kk) = cmk(half * (zk.y + zm.y), half * (zm.x - zk.x));
+      }
     }
   }
   if constexpr (MODE == XF_SOLVE) {
@@ -396,8 +424,7 @@ void k_fxinv(XParams<T> p) {
   constexpr int NT = xthreads<L1>();
   constexpr int Lout = PAD ? L / 2 : L;
   constexpr int Kx = L / 2 + 1;
-  constexpr int NIN = P * Kx;
-  constexpr int EIN = (NIN + NT - 1) / NT;
+  constexpr int KI = (Kx + NT - 1) / NT;           // input bins per thread and row pair
   constexpr int NOUT = 2 * P * Lout;
   constexpr int EOUT = (NOUT + NT - 1) / NT;
   __shared__ cplx<T> lds[L * PITCH];
@@ -414,18 +441,20 @@ void k_fxinv(XParams<T> p) {
 #pragma unroll
   for (int i = 0; i < ETW; ++i)
     if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
-  cplx<T> xa[EIN], xb[EIN];
+  unsigned roff[2 * P];
+  bool rok[2 * P];
+  tile_row_offsets<2 * P>(p, row0, Kx, roff, rok);
+  cplx<T> xa[P][KI], xb[P][KI];
 #pragma unroll
-  for (int i = 0; i < EIN; ++i) {
-    const int e = tid + i * NT;
-    const int p2 = e / Kx;
-    const int kk = e - p2 * Kx;
-    const int ra = row0 + 2 * p2, rb = ra + 1;
-    xa[i] = cmk(T(0), T(0));
-    xb[i] = cmk(T(0), T(0));
-    if (e < NIN) {
-      if (ra < p.nrows) xa[i] = GPS_AT(work, xrow_offset(p, ra, Kx) + kk);
-      if (rb < p.nrows) xb[i] = GPS_AT(work, xrow_offset(p, rb, Kx) + kk);
+  for (int p2 = 0; p2 < P; ++p2) {
+#pragma unroll
+    for (int i = 0; i < KI; ++i) {
+      const int kk = tid + i * NT;
+      const int kc = kk < Kx ? kk : Kx - 1;        // clamped: branch-free loads
+      const cplx<T> va = GPS_AT(work, roff[2 * p2] + kc);
+      const cplx<T> vb = GPS_AT(work, roff[2 * p2 + 1] + kc);
+      xa[p2][i] = rok[2 * p2] ? va : cmk(T(0), T(0));
+      xb[p2][i] = rok[2 * p2 + 1] ? vb : cmk(T(0), T(0));
     }
   }
   // epilogue operands are independent of the transform: load them now too
@@ -446,12 +475,12 @@ void k_fxinv(XParams<T> p) {
     if (solve_stopped(sl.st)) return;
   }
 #pragma unroll
-  for (int i = 0; i < EIN; ++i) {
-    const int e = tid + i * NT;
-    if (e < NIN) {
-      const int p2 = e / Kx;
-      const int kk = e - p2 * Kx;
-      cplx<T> a = xa[i], b = xb[i];
+  for (int p2 = 0; p2 < P; ++p2)
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int kk = tid + i * NT;
+    if (kk < Kx) {
+      cplx<T> a = xa[p2][i], b = xb[p2][i];
       if (kk == 0 || 2 * kk == L) {    // self-conjugate bins of a real row
         a.y = T(0);
         b.y = T(0);
