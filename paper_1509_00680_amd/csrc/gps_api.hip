@@ -297,7 +297,7 @@ void ensure_res(gps_plan* pl, bool need_ion) {
     s.part_delta[1] = s.part_delta[0];
     dalloc(&s.part_pap, (size_t)nvg * sizeof(double), &R.bytes);
     dalloc(&s.part_mu, (size_t)nxg * sizeof(double), &R.bytes);
-    dalloc(&s.part_aux, (size_t)2 * nvg * sizeof(double), &R.bytes);
+    dalloc(&s.part_aux, (size_t)kVec * nvg * sizeof(double), &R.bytes);
     dalloc(&s.st, sizeof(SolveState), &R.bytes);
     dalloc(&s.phi, (size_t)n * sizeof(double), &R.bytes);
     if (pl->bc == GPS_BC_PERIODIC) {
@@ -902,7 +902,7 @@ gps_status gps_plan_footprint(int nx, int ny, int nz, int bc, int precision, int
   if (pz) tb += ntab * (sizeof(double) + sizeof(float));                      // Laplacian table
   size_t b = 6 * n * s + (pz ? n * s : 0) + n * sizeof(double);                     // vectors, sq64
   b += wbox * 2 * s;                                                          // work buffer
-  b += (4 * nvg + std::max(nvg, nxg) + nxg + nvg + nxg + 2 * nvg) * sizeof(double);
+  b += (4 * nvg + std::max(nvg, nxg) + nxg + nvg + nxg + (size_t)kVec * nvg) * sizeof(double);
   b += sizeof(SolveState) + n * sizeof(double);                               // state, phi
   if (pz) b += n * sizeof(double) + (s != sizeof(double) ? wbox * 2 * sizeof(double) : 0);
   b += 4 * ((size_t)maxit + 1) * sizeof(double);                              // history

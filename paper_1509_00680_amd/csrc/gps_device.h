@@ -88,9 +88,23 @@ __device__ __forceinline__ V& at_bytes(V* base, unsigned off) {
 
 // Stop flag of a solve, for the passes that run while no kernel writes it
 // (the y, z and x-inverse passes: the flag's writers, the direction kernel and
-// the x-forward head, come earlier in stream order).  A plain load: its value
-// is the same for every wavefront of the launch, so it needs no broadcast, and
-// it waits for nothing but itself.
+// the x-forward head, come earlier in stream order), so its value is the same
+// for every wavefront of the launch.  stop_flag_issue is called right after
+// the pass's operand loads: every lane loads the flag through a vector load
+// (the zero offset comes from an instruction the compiler cannot fold), so it
+// travels with the operands and the wait for them covers it, instead of a
+// scalar load issued after that wait.  stop_flag_set reads lane 0's copy as a
+// scalar.
+__device__ __forceinline__ int stop_flag_issue(const SolveState* st) {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return reinterpret_cast<const int*>(&st->done)[z];
+}
+__device__ __forceinline__ bool stop_flag_set(int v) {
+  return __builtin_amdgcn_readfirstlane(v) != 0;
+}
+
+// Plain scalar read of the stop flag (generic passes).
 __device__ __forceinline__ int solve_stopped(const SolveState* st) { return st->done; }
 
 }  // namespace gps

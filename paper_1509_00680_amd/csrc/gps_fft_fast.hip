@@ -60,11 +60,6 @@ void k_fstrided(SParams<T> p) {
   __shared__ cplx<T> lds[L * PITCH];
   __shared__ cplx<T> twl[L];
   const int tid = threadIdx.x;
-  // twiddles to LDS: their loads are issued first and overlap the tile loads
-  cplx<T> twv[(L + NT - 1) / NT];
-#pragma unroll
-  for (int i = 0; i < (L + NT - 1) / NT; ++i)
-    if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
   cplx<T>* work = p.work;
   const SolveState* st = nullptr;
   if (work == nullptr) {
@@ -72,6 +67,11 @@ void k_fstrided(SParams<T> p) {
     work = sl.work;
     st = sl.st;
   }
+  // twiddles first, then the tile, then the stop flag: all in flight together
+  cplx<T> twv[(L + NT - 1) / NT];
+#pragma unroll
+  for (int i = 0; i < (L + NT - 1) / NT; ++i)
+    if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
   const int b = tid & (B - 1);
   const int q = tid / B;
   const int tile0 = xcd_tile(blockIdx.x, gridDim.x) * NTILE;
@@ -110,24 +110,39 @@ void k_fstrided(SParams<T> p) {
       if (q < L2) {
 #pragma unroll
         for (int n1 = 0; n1 < L1; ++n1) {
+          // branch-free: a clamped element (base 0 for pencils past the end)
+          // is loaded and then selected, so the loads issue back to back
           const int e = L2 * n1 + q;
-          const bool in = PAD ? (n1 < L1 / 2) : (e < lin);
-          xin[t][n1] = (pv[t] && in) ? at_bytes(work, base[t] + (unsigned)e * es)
-                                     : cmk(T(0), T(0));
+          if (PAD && n1 >= L1 / 2) {
+            xin[t][n1] = cmk(T(0), T(0));
+          } else if (PAD) {
+            // no select: a lane past the last pencil (offset 0) transforms
+            // real data and stores nothing
+            xin[t][n1] = at_bytes(work, base[t] + (unsigned)e * es);
+          } else {
+            const int ec = e < lin ? e : lin - 1;
+            const cplx<T> v = at_bytes(work, base[t] + (unsigned)ec * es);
+            xin[t][n1] = (pv[t] && e < lin) ? v : cmk(T(0), T(0));
+          }
         }
       }
       if constexpr (MODE == ST_CONV) {
         // spectrum multipliers of the z pass: prefetched with the tile
-        if (pv[t] && q < L1) {
+        {
+          // branch-free: a lane past the last pencil reads pencil 0's entries,
+          // and a thread with q >= L1 (NT is B * L1 rounded up to a wavefront)
+          // reads those of q = 0; neither is used
           const int Lyh = p.Ly / 2 + 1;
-          const int ky = pen[t] / p.Kx;
-          const int kx = pen[t] - ky * p.Kx;
+          const int pc = pv[t] ? pen[t] : 0;
+          const int qc = q < L1 ? q : 0;
+          const int ky = pc / p.Kx;
+          const int kx = pc - ky * p.Kx;
           const int kyf = min(ky, p.Ly - ky);
           const unsigned row = (unsigned)sizeof(T) * (unsigned)(kyf * p.Kx + kx);
           const unsigned zs = (unsigned)sizeof(T) * (unsigned)(Lyh * p.Kx);
 #pragma unroll
           for (int k2 = 0; k2 < L2; ++k2) {
-            const int kz = q + L1 * k2;
+            const int kz = qc + L1 * k2;
             gm[t][k2] = at_bytes(p.table, row + (unsigned)min(kz, L - kz) * zs);
           }
         }
@@ -137,16 +152,23 @@ void k_fstrided(SParams<T> p) {
 #pragma unroll
         for (int k2 = 0; k2 < L2; ++k2) {
           const int kk = q + L1 * k2;
-          yin[t][k2] = (pv[t] && kk < lin) ? at_bytes(work, base[t] + (unsigned)kk * es)
-                                           : cmk(T(0), T(0));
+          if (PAD) {
+            // full-length input (kk < L): no select, as above
+            yin[t][k2] = at_bytes(work, base[t] + (unsigned)kk * es);
+          } else {
+            const int kc = kk < lin ? kk : lin - 1;     // branch-free, as above
+            const cplx<T> v = at_bytes(work, base[t] + (unsigned)kc * es);
+            yin[t][k2] = (pv[t] && kk < lin) ? v : cmk(T(0), T(0));
+          }
         }
       }
     }
   }
+  const int flag = st ? stop_flag_issue(st) : 0;
 #pragma unroll
   for (int i = 0; i < (L + NT - 1) / NT; ++i)
     if (tid + i * NT < L) twl[tid + i * NT] = twv[i];
-  if (st && solve_stopped(st)) return;
+  if (stop_flag_set(flag)) return;
   __syncthreads();
   const cplx<T>* tw = twl;
 
@@ -472,7 +494,8 @@ void k_fxinv(XParams<T> p) {
         rv[i] = GPS_AT(sl.r, o);
       }
     }
-    if (solve_stopped(sl.st)) return;
+    // stop flag issued after the operand loads, in flight with them
+    if (stop_flag_set(stop_flag_issue(sl.st))) return;
   }
 #pragma unroll
   for (int p2 = 0; p2 < P; ++p2)

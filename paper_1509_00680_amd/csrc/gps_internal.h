@@ -28,6 +28,12 @@ __host__ __device__ inline int vec_groups(long long n) {
   return (int)((n + (long long)kThreads * kVec - 1) / ((long long)kThreads * kVec));
 }
 
+// Work-groups of the q kernel (one point per thread); at most kVec *
+// vec_groups(n), the size of the part_aux array.
+__host__ __device__ inline int qfield_groups(long long n) {
+  return (int)((n + kThreads - 1) / kThreads);
+}
+
 constexpr int kMaxStages = 16;
 constexpr int kMaxLen = 1024;        // longest supported FFT length
 
@@ -81,7 +87,7 @@ template <typename T> struct Slot {
   double *part_delta[2];      // (v, r) partials, by iteration parity
   double *part_pap;           // (p, Ap) partials
   double *part_mu;            // sum r/sqrt(eps) partials (periodic)
-  double *part_aux;           // ionic-update / energy partials (2 per WG)
+  double *part_aux;           // q-kernel (1 per 256 points), ionic-update / energy (2 per WG)
   double *hist;               // per-iteration history: delta, beta, alpha, ||r||^2
   SolveState *st;
   int maxit;

@@ -149,12 +149,13 @@ void launch_reset_state(const SlotTable<T>& tab, const Batch& b, double abs_thr,
 }
 
 // Periodic boundaries with ions: the k = 0 multiplier 4 pi / mean(kappa2/eps)
-// (divided by the transform size) from the partials of the q kernel.
+// (divided by the transform size) from the partials of the q kernel (one per
+// q work-group).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_set_g0(SlotTable<T> tab, Batch b, int nparts,
                                                      double npts, double norm) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.x]];
-  const double sum = sum_partials(sl.part_aux, nparts, 2);
+  const double sum = sum_partials(sl.part_aux, nparts, 1);
   if (threadIdx.x == 0) {
     const double mean = sum / npts;
     sl.st->g0 = mean > 0.0 ? 4.0 * kPi / mean * norm : 0.0;
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_set_g0(SlotTable<T> tab, Batch b, 
 template <typename T>
 void launch_set_g0(const SlotTable<T>& tab, const Batch& b, long long n, double norm,
                    hipStream_t s) {
-  GPS_LAUNCH((k_set_g0<T>), dim3(b.n), dim3(kThreads), 0, s, tab, b, vec_groups(n),
+  GPS_LAUNCH((k_set_g0<T>), dim3(b.n), dim3(kThreads), 0, s, tab, b, qfield_groups(n),
                      double(n), norm);
 }
 
@@ -232,9 +233,10 @@ void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho, con
 // ---------------------------------------------------------------------------
 struct FdWeights { double c[9]; };
 
-// One work-group covers kThreads * kVec consecutive points.  Work-groups are
-// mapped XCD-contiguously, so each XCD's L2 holds one z-slab and its +-M halo
-// planes instead of the whole field.
+// One point per thread (the 6M neighbour loads of a point are many latencies
+// deep, so the latency is hidden by many resident wavefronts rather than by
+// looping); work-groups are mapped XCD-contiguously, so each XCD's L2 holds
+// one z-slab and its +-M halo planes.  One kappa2/eps partial per work-group.
 template <typename T, int M>
 __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, Geom g,
                                                      FdWeights w,
@@ -244,21 +246,16 @@ __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, 
                                                      const double* __restrict__ gamma,
                                                      double eps_bulk) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
-  const long long n = (long long)g.nx * g.ny * g.nz;
-  const long long plane = (long long)g.nx * g.ny;
-  const long long base =
-      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
+  const int n = g.nx * g.ny * g.nz;
+  const int plane = g.nx * g.ny;
+  const int i = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   const double* __restrict__ sq = sl.sq64;
   const double ih2 = 1.0 / (g.h * g.h);
-  const long long sx = 1, sy = g.nx, sz = plane;
   double kacc = 0.0;   // sum kappa2 / eps (periodic k = 0 multiplier)
-#pragma unroll 1
-  for (int j = 0; j < kVec; ++j) {
-    const long long i = base + (long long)j * kThreads;
-    if (i >= n) break;
-    const int x = (int)(i % g.nx);
-    const int y = (int)((i / g.nx) % g.ny);
-    const int z = (int)(i / plane);
+  if (i < n) {
+    const int x = i % g.nx;
+    const int y = (i / g.nx) % g.ny;
+    const int z = i / plane;
     const double sc = sq[i];
     double lap;
     if (lap_sq) {
@@ -267,15 +264,16 @@ __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, 
       double acc = 3.0 * w.c[0] * sc;
       if (x >= M && x < g.nx - M && y >= M && y < g.ny - M && z >= M && z < g.nz - M) {
         // interior: no ghost handling
+        const int sy = g.nx;
 #pragma unroll
         for (int m = 1; m <= M; ++m) {
-          const double sxx = sq[i + m * sx] + sq[i - m * sx];
+          const double sxx = sq[i + m] + sq[i - m];
           const double syy = sq[i + m * sy] + sq[i - m * sy];
-          const double szz = sq[i + m * sz] + sq[i - m * sz];
+          const double szz = sq[i + m * plane] + sq[i - m * plane];
           acc += w.c[m] * (sxx + syy + szz);
         }
       } else {
-        const long long zo = (long long)z * plane, yo = (long long)y * g.nx;
+        const int zo = z * plane, yo = y * g.nx;
 #pragma unroll
         for (int m = 1; m <= M; ++m) {
           int xp = x + m, xm = x - m, yp = y + m, ym = y - m, zp = z + m, zm = z - m;
@@ -286,8 +284,8 @@ __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, 
           if (g.periodic_z) { zp %= g.nz; zm = ((zm % g.nz) + g.nz) % g.nz; }
           else { zp = min(zp, g.nz - 1); zm = max(zm, 0); }
           const double sxx = sq[zo + yo + xp] + sq[zo + yo + xm];
-          const double syy = sq[zo + (long long)yp * g.nx + x] + sq[zo + (long long)ym * g.nx + x];
-          const double szz = sq[(long long)zp * plane + yo + x] + sq[(long long)zm * plane + yo + x];
+          const double syy = sq[zo + yp * g.nx + x] + sq[zo + ym * g.nx + x];
+          const double szz = sq[zp * plane + yo + x] + sq[zm * plane + yo + x];
           acc += w.c[m] * (sxx + syy + szz);
         }
       }
@@ -303,10 +301,7 @@ __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, 
     sl.qk[i] = T(qv);
   }
   kacc = block_sum(kacc);
-  if (threadIdx.x == 0) {
-    sl.part_aux[(size_t)blockIdx.x * 2] = kacc;
-    sl.part_aux[(size_t)blockIdx.x * 2 + 1] = 0.0;
-  }
+  if (threadIdx.x == 0) sl.part_aux[blockIdx.x] = kacc;
 }
 
 static FdWeights fd_weights(int M) {
@@ -331,7 +326,7 @@ void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g, int f
                    const double* lap_sq, double kappa_coef, const double* eps,
                    const double* gamma, double eps_bulk, hipStream_t s) {
   const long long n = (long long)g.nx * g.ny * g.nz;
-  const dim3 grid(vec_groups(n), b.n);
+  const dim3 grid(qfield_groups(n), b.n);
   const FdWeights w = fd_weights(fd_half);
 #define GPS_QF(MM)                                                                        \
   case MM:                                                                                \
