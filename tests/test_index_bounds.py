@@ -7,7 +7,9 @@ conditions and both precisions, and every load and store index is checked
 against its buffer.  Regression guard: the FP64 z pass at lengths 96 and 320
 once read the Green table with the index of a thread past L1 (the thread count
 B * L1 is rounded up to a whole wavefront); the clamp that fixed it is part of
-what is replayed, and the unclamped form is shown to fail."""
+what is replayed, and the unclamped form is shown to fail.  The replay checks
+every thread's tile loads with q clamped to the active range, a superset of
+the loads the kernel issues, and launches of one and two tiles per work-group."""
 import numpy as np
 import pytest
 
@@ -28,17 +30,27 @@ def xcd_tile(bid, G):
 
 
 def strided_violations(T, mode, L, Lin, Lout, npen, per_group, group_stride, elem_stride, wsize,
-                       Kx=None, Ly=None, tabsize=None, clamp_q=True):
+                       Kx=None, Ly=None, tabsize=None, clamp_q=True, ntile=1):
     L1, L2 = FAST[L]
     B = 16 if T == "f" else 8
     pad = ((mode == ST_FWD and 2 * Lin == L) or (mode == ST_CONV and 2 * Lin == L and Lout == Lin)
            or (mode == ST_INV and 2 * Lout == L and Lin == L))
     NT = round64(B * L1)
-    G = (npen + B - 1) // B
+    G = (npen + B * ntile - 1) // (B * ntile)
     bid = np.arange(G)[:, None]
     tid = np.arange(NT)[None, :]
     b, q = tid & (B - 1), tid // B
-    pen = xcd_tile(bid, G) * B + b
+    tile0 = xcd_tile(bid, G) * ntile
+    pens = [(tile0 + t) * B + b for t in range(ntile)]
+    bad = []
+    for pen in pens:
+        bad += _tile(T, mode, L, Lin, Lout, npen, per_group, group_stride, elem_stride, wsize,
+                     Kx, Ly, tabsize, clamp_q, pen, q, L1, L2, pad)
+    return bad
+
+
+def _tile(T, mode, L, Lin, Lout, npen, per_group, group_stride, elem_stride, wsize, Kx, Ly,
+          tabsize, clamp_q, pen, q, L1, L2, pad):
     pv = pen < npen
     grp = pen // per_group
     base = np.where(pv, grp * group_stride + (pen - grp * per_group), 0)
@@ -53,12 +65,13 @@ def strided_violations(T, mode, L, Lin, Lout, npen, per_group, group_stride, ele
 
     every = np.ones(pen.shape, dtype=bool)
     if mode != ST_INV:
+        qa = np.minimum(q, L2 - 1)          # every thread loads (clamped q)
         for n1 in range(L1):
-            e = L2 * n1 + q
+            e = L2 * n1 + qa
             if pad and n1 >= L1 // 2:
                 continue
             ec = e if pad else np.minimum(e, lin - 1)
-            chk(base + ec * elem_stride, (q < L2) & every, "tile load", wsize)
+            chk(base + ec * elem_stride, every, "tile load", wsize)
         if mode == ST_CONV:
             pc = np.where(pv, pen, 0)
             qc = np.where(q < L1, q, 0) if clamp_q else q
@@ -72,10 +85,11 @@ def strided_violations(T, mode, L, Lin, Lout, npen, per_group, group_stride, ele
                 kk = q + L1 * k2
                 chk(base + kk * elem_stride, pv & (q < L1) & (kk < lout), "store", wsize)
     else:
+        qa = np.minimum(q, L1 - 1)
         for k2 in range(L2):
-            kk = q + L1 * k2
+            kk = qa + L1 * k2
             kc = kk if pad else np.minimum(kk, lin - 1)
-            chk(base + kc * elem_stride, (q < L1) & every, "tile load", wsize)
+            chk(base + kc * elem_stride, every, "tile load", wsize)
     if mode != ST_FWD:
         for nb in range(L1):
             e = q + L2 * nb
@@ -116,7 +130,8 @@ def test_strided_passes_stay_in_bounds(bc):
         for tag, T, args, kw in launches(shape, bc):
             if args[1] not in FAST:
                 continue
-            assert not strided_violations(T, *args, **kw), (shape, bc, tag, T)
+            for ntile in (1, 2):
+                assert not strided_violations(T, *args, ntile=ntile, **kw), (shape, bc, tag, T)
             checked += 1
     assert checked > 10
 
