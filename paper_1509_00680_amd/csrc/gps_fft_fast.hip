@@ -25,7 +25,7 @@ namespace gps {
 template <typename T> struct FastTile;
 template <> struct FastTile<float> { static constexpr int B = 16; };
 template <> struct FastTile<double> { static constexpr int B = 8; };
-constexpr int kXPairs = 4;             // row pairs per work-group of the x passes
+constexpr int kXPairs = 3;             // row pairs per work-group of the x passes
 
 constexpr int round64(int v) { return (v + 63) / 64 * 64; }
 
