@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv", "direction")
+PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv")
 
 
 def parse():

@@ -200,13 +200,15 @@ gps_status gps_last_history(const gps_plan *plan, double *out, int max_entries);
  * Errors: GPS_E_INVALID (null plan, unknown kind). */
 typedef enum {
   GPS_K_NONE = 0,
-  GPS_K_XFWD = 1,       /* x pass: phi, r update of the previous iteration, r/sqrt(eps),
-                           pairwise real-to-complex */
+  GPS_K_XFWD = 1,       /* x pass: alpha, phi and r update of the previous iteration,
+                           ||r||^2, r/sqrt(eps), pairwise real-to-complex */
   GPS_K_YFWD = 2,       /* y pass, forward */
-  GPS_K_ZCONV = 3,      /* z pass: forward, times the Green's spectrum, inverse */
-  GPS_K_YINV = 4,       /* y pass, inverse */
-  GPS_K_XINV = 5,       /* x pass: complex-to-real, v = u/sqrt(eps), (v, r), ||r||^2 */
-  GPS_K_DIRECTION = 6   /* stop decision, p, Ap update and (p, Ap) */
+  GPS_K_ZCONV = 3,      /* z pass: forward, times the Green's spectrum (and (v, r) by
+                           Parseval), inverse */
+  GPS_K_YINV = 4,       /* y pass, inverse; its first work-group takes the stop decision
+                           and beta */
+  GPS_K_XINV = 5        /* x pass: complex-to-real, v = u/sqrt(eps), A v (Eq. corr),
+                           p, Ap update and (p, Ap) */
 } gps_kernel_kind;
 gps_status gps_plan_set_timing(gps_plan *plan, int kind);
 

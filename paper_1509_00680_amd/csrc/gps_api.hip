@@ -47,6 +47,21 @@ inline void ck(hipError_t e) {
 
 struct NoMem {};
 
+// Capacities of the per-wavefront partial-sum arrays of the solve passes:
+// x passes at most one partial per row pair (+1), z pass at most one per
+// pencil (+64).
+struct PartCaps {
+  int x, z;
+};
+inline PartCaps part_caps(const Geom& g) {
+  return PartCaps{(g.ny * g.nz + 1) / 2 + 1, g.Ly * g.Kx + 64};
+}
+// A launch configuration whose partials would not fit is a library defect;
+// it is reported as a device error rather than run.
+inline void check_parts(int count, int cap) {
+  if (count < 1 || count > cap) throw DevError{hipErrorInvalidConfiguration};
+}
+
 template <typename P>
 void dalloc(P** p, size_t bytes, size_t* total) {
   *p = nullptr;
@@ -277,13 +292,13 @@ void ensure_res(gps_plan* pl, bool need_ion) {
   const long long n = pl->npts();
   const int nvg = vec_groups(n);
   const Geom& g = pl->g;
-  const int nxg = (g.ny * g.nz + 1) / 2 + 1;   // x-pass groups <= row pairs
+  const int nxg = part_caps(g).x;
+  const int nzg = part_caps(g).z;
   if (!R.ready) {
     Slot<T>& s = R.slot();
     s = Slot<T>{};
     const size_t nb = (size_t)n * sizeof(T);
     dalloc(&s.r, nb, &R.bytes);
-    dalloc(&s.v, nb, &R.bytes);
     dalloc(&s.p, nb, &R.bytes);
     dalloc(&s.ap, nb, &R.bytes);
     dalloc(&s.isq, nb, &R.bytes);
@@ -292,10 +307,9 @@ void ensure_res(gps_plan* pl, bool need_ion) {
     dalloc(&s.sq64, (size_t)n * sizeof(double), &R.bytes);
     dalloc(&s.work, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<T>), &R.bytes);
     dalloc(&s.part_init, (size_t)4 * nvg * sizeof(double), &R.bytes);
-    dalloc(&s.part_rr, (size_t)std::max(nvg, nxg) * sizeof(double), &R.bytes);
-    dalloc(&s.part_delta[0], (size_t)nxg * sizeof(double), &R.bytes);
-    s.part_delta[1] = s.part_delta[0];
-    dalloc(&s.part_pap, (size_t)nvg * sizeof(double), &R.bytes);
+    dalloc(&s.part_rr, (size_t)nxg * sizeof(double), &R.bytes);
+    dalloc(&s.part_delta, (size_t)nzg * sizeof(double), &R.bytes);
+    dalloc(&s.part_pap, (size_t)nxg * sizeof(double), &R.bytes);
     dalloc(&s.part_mu, (size_t)nxg * sizeof(double), &R.bytes);
     dalloc(&s.part_aux, (size_t)kVec * nvg * sizeof(double), &R.bytes);
     dalloc(&s.st, sizeof(SolveState), &R.bytes);
@@ -337,9 +351,9 @@ void free_res(gps_plan* pl) {
   Res<T>& R = pl->res<T>();
   if (R.graph) (void)hipGraphExecDestroy(R.graph);
   Slot<T>& s = R.slot();
-  dfree(s.r); dfree(s.v); dfree(s.p); dfree(s.ap); dfree(s.isq); dfree(s.qk); dfree(s.s);
+  dfree(s.r); dfree(s.p); dfree(s.ap); dfree(s.isq); dfree(s.qk); dfree(s.s);
   dfree(s.ion); dfree(s.sq64); dfree(s.work); dfree(s.part_init); dfree(s.part_rr);
-  dfree(s.part_delta[0]); dfree(s.part_pap); dfree(s.part_mu); dfree(s.part_aux); dfree(s.hist);
+  dfree(s.part_delta); dfree(s.part_pap); dfree(s.part_mu); dfree(s.part_aux); dfree(s.hist);
   dfree(s.st); dfree(s.phi); dfree(R.lap64); dfree(R.work64q);
   if (R.h_state) (void)hipHostFree(R.h_state);
   if (R.h_parts) (void)hipHostFree(R.h_parts);
@@ -431,8 +445,7 @@ double pass_bytes(const gps_plan* pl, int kind, size_t s) {
     case GPS_K_YFWD: return (double)g.nz * g.Kx * g.ny * c + wbox * c;
     case GPS_K_ZCONV: return 2.0 * wbox * c + tab * s;
     case GPS_K_YINV: return wbox * c + (double)g.nz * g.Kx * g.ny * c;
-    case GPS_K_XINV: return rows * g.Kx * c + 3.0 * n * s;
-    case GPS_K_DIRECTION: return (7.0 + periodic) * n * s;
+    case GPS_K_XINV: return rows * g.Kx * c + (7.0 + periodic) * n * s;   // with the direction update
     default: return 0.0;
   }
 }
@@ -450,7 +463,8 @@ void enqueue_iteration(gps_plan* pl, const SlotTable<T>& tab, const Batch& b, in
   xp.tab = tab;
   xp.has_slots = 1;
   xp.batch = b;
-  xp.n_vec_parts = vec_groups(n);
+  xp.n_pap_parts = xpass_parts(xp);
+  check_parts(xp.n_pap_parts, part_caps(g).x);
   xp.periodic_mean = periodic;
   { TimerScope t(pl, s, GPS_K_XFWD, k0); launch_xfwd<T>(XF_SOLVE, xp, s); }
   SParams<T> yf = sparams<T>(pl, 1, g.Ly, g.ny, g.Ly, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
@@ -464,15 +478,22 @@ void enqueue_iteration(gps_plan* pl, const SlotTable<T>& tab, const Batch& b, in
   zc.batch = b;
   zc.table = pl->green<T>();
   zc.k0_from_slot = periodic;
+  zc.Lx = g.Lx;
   { TimerScope t(pl, s, GPS_K_ZCONV, k0); launch_strided<T>(ST_CONV, zc, s); }
   SParams<T> yi = sparams<T>(pl, 1, g.Ly, g.Ly, g.ny, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
                              g.Kx);
   yi.tab = tab;
   yi.batch = b;
+  yi.decide = 1;
+  yi.dec.n_rr = xp.n_pap_parts;
+  yi.dec.n_delta = strided_parts(zc);
+  check_parts(yi.dec.n_delta, part_caps(g).z);
+  yi.dec.n_init = vec_groups(n);
+  yi.dec.check_neutral = check_neutral;
+  yi.dec.periodic = periodic;
+  yi.dec.npts = double(n);
   { TimerScope t(pl, s, GPS_K_YINV, k0); launch_strided<T>(ST_INV, yi, s); }
-  { TimerScope t(pl, s, GPS_K_XINV, k0); launch_xinv<T>(0 /*XI_SOLVE*/, xp, s); }
-  { TimerScope t(pl, s, GPS_K_DIRECTION, k0);
-    launch_direction<T>(tab, b, n, xpass_groups(xp), periodic, check_neutral, s); }
+  { TimerScope t(pl, s, GPS_K_XINV, k0); launch_xinv<T>(XI_SOLVE, xp, s); }
 }
 
 // Spectral Laplacian of sqrt(eps) (periodic q) with the FP64 FFT passes.
@@ -501,7 +522,7 @@ void spectral_laplacian(gps_plan* pl) {
                                        (long long)g.Ly * g.Kx, g.Kx);
   yi.work = work;
   launch_strided<double>(ST_INV, yi, s);
-  launch_xinv<double>(1 /*XI_REAL*/, xp, s);
+  launch_xinv<double>(XI_REAL, xp, s);
 }
 
 // u = G f with the bulk-precision FFT passes (no sqrt(eps) scaling).
@@ -530,7 +551,7 @@ void vacuum_apply(gps_plan* pl, const double* f, double* u) {
                              g.Kx);
   yi.work = work;
   launch_strided<T>(ST_INV, yi, s);
-  launch_xinv<T>(1 /*XI_REAL*/, xp, s);
+  launch_xinv<T>(XI_REAL, xp, s);
   ck(hipGetLastError());
   ck(hipStreamSynchronize(s));
 }
@@ -895,14 +916,15 @@ gps_status gps_plan_footprint(int nx, int ny, int nz, int bc, int precision, int
   const size_t s = precision == GPS_PREC_MIXED ? sizeof(float) : sizeof(double);
   const size_t ntab = (Lz / 2 + 1) * (Ly / 2 + 1) * Kx;
   const size_t nvg = (size_t)vec_groups((long long)n);
-  const size_t nxg = ((size_t)ny * nz + 1) / 2 + 1;
+  const size_t nxg = ((size_t)ny * nz + 1) / 2 + 1;    // as part_caps
   const size_t wbox = (size_t)nz * Ly * Kx;
   size_t tb = 2 * (Lx + Ly + Lz) * (sizeof(double) + sizeof(float));         // twiddles
   tb += ntab * (sizeof(double) + sizeof(float));                              // Green table
   if (pz) tb += ntab * (sizeof(double) + sizeof(float));                      // Laplacian table
-  size_t b = 6 * n * s + (pz ? n * s : 0) + n * sizeof(double);                     // vectors, sq64
+  size_t b = 5 * n * s + (pz ? n * s : 0) + n * sizeof(double);                     // vectors, sq64
   b += wbox * 2 * s;                                                          // work buffer
-  b += (4 * nvg + std::max(nvg, nxg) + nxg + nvg + nxg + (size_t)kVec * nvg) * sizeof(double);
+  const size_t nzg = Ly * Kx + 64;
+  b += (4 * nvg + 3 * nxg + nzg + (size_t)kVec * nvg) * sizeof(double);         // partials
   b += sizeof(SolveState) + n * sizeof(double);                               // state, phi
   if (pz) b += n * sizeof(double) + (s != sizeof(double) ? wbox * 2 * sizeof(double) : 0);
   b += 4 * ((size_t)maxit + 1) * sizeof(double);                              // history
@@ -999,7 +1021,7 @@ gps_status gps_solve_vacuum(gps_plan* pl, const double* f, double* u) {
 }
 
 gps_status gps_plan_set_timing(gps_plan* pl, int kind) {
-  if (!pl || kind < GPS_K_NONE || kind > GPS_K_DIRECTION) return GPS_E_INVALID;
+  if (!pl || kind < GPS_K_NONE || kind > GPS_K_XINV) return GPS_E_INVALID;
   pl->timing_kind = kind;
   pl->timing_ms = 0.0;
   pl->timing_launches = 0;

@@ -45,6 +45,15 @@ __device__ __forceinline__ double block_sum(double v) {
   return r;
 }
 
+// Sum of v over the wavefront, in every lane (fixed butterfly: the result
+// depends only on the inputs).  No barrier: a kernel whose work-groups hold
+// several wavefronts writes one partial per wavefront.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // Deterministic sum of n partials spaced by `stride` doubles: four
 // independent loads in flight per thread, fixed combination order.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n,
@@ -86,10 +95,12 @@ __device__ __forceinline__ V& at_bytes(V* base, unsigned off) {
       typename std::conditional<std::is_const<V>::value, const char, char>::type*>(base) + off);
 }
 
-// Stop flag of a solve, for the passes that run while no kernel writes it
-// (the y, z and x-inverse passes: the flag's writers, the direction kernel and
-// the x-forward head, come earlier in stream order), so its value is the same
-// for every wavefront of the launch.  stop_flag_issue is called right after
+// Stop flag of a solve, for the y, z and x-inverse passes.  Its writers are
+// the x-forward head (loss of definiteness) and work-group 0 of the y-inverse
+// pass (the stop decision), which it reads only at the end: so the flag is
+// the same for every wavefront of a launch, except in the y-inverse pass of
+// the last iteration, where the other work-groups' results are unused either
+// way.  stop_flag_issue is called right after
 // the pass's operand loads: every lane loads the flag through a vector load
 // (the zero offset comes from an instruction the compiler cannot fold), so it
 // travels with the operands and the wait for them covers it, instead of a

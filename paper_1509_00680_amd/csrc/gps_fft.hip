@@ -210,20 +210,20 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(XParams<T> p) {
   if constexpr (MODE == XF_SOLVE) {
     int k;
     XHead hd;
-    xfwd_head_load(sl, p.n_vec_parts, hd);
-    if (!xfwd_head_finish(sl, p.n_vec_parts, hd, &k, &alpha)) return;
+    xfwd_head_load(sl, p.n_pap_parts, hd);
+    if (!xfwd_head_finish(sl, p.n_pap_parts, hd, &k, &alpha)) return;
     upd = k > 0;
     work = sl.work;
   }
-  double mu = 0.0;
+  double mu = 0.0, rr = 0.0;
   for (int e = tid; e < P * Lin; e += kThreads) {
     const int pp = e / Lin;
     const int x = e - pp * Lin;
     const int ra = 2 * (pair0 + pp), rb = ra + 1;
     T a = T(0), b = T(0);
     if constexpr (MODE == XF_SOLVE) {
-      if (ra < p.nrows) a = solve_prologue(sl, (size_t)ra * p.in_row_stride + x, upd, alpha);
-      if (rb < p.nrows) b = solve_prologue(sl, (size_t)rb * p.in_row_stride + x, upd, alpha);
+      if (ra < p.nrows) a = solve_prologue(sl, (size_t)ra * p.in_row_stride + x, upd, alpha, rr);
+      if (rb < p.nrows) b = solve_prologue(sl, (size_t)rb * p.in_row_stride + x, upd, alpha, rr);
       mu += double(a) + double(b);
     } else if constexpr (MODE == XF_REAL) {
       if (ra < p.nrows) a = T(p.in_real[(size_t)ra * p.in_row_stride + x]);
@@ -271,14 +271,14 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(XParams<T> p) {
     }
   }
   if constexpr (MODE == XF_SOLVE) {
+    const double s2 = block_sum(rr);
+    if (tid == 0) sl.part_rr[blockIdx.x] = s2;
     if (p.periodic_mean) {
       const double s = block_sum(mu);
       if (tid == 0) sl.part_mu[blockIdx.x] = s;
     }
   }
 }
-
-enum XinvMode { XI_SOLVE = 0, XI_REAL = 1 };
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void k_xinv(XParams<T> p) {
@@ -289,9 +289,13 @@ __global__ __launch_bounds__(kThreads) void k_xinv(XParams<T> p) {
   const int pair0 = blockIdx.x * P;
   cplx<T>* work = p.work;
   const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
+  DirArgs dir{};
   if constexpr (MODE == XI_SOLVE) {
     if (solve_stopped(sl.st)) return;
     work = sl.work;
+    dir.k = sl.st->k;
+    dir.beta = sl.st->beta;
+    dir.mu = p.periodic_mean ? sl.st->mu : 0.0;
   }
   for (int e = tid; e < P * Kx; e += kThreads) {
     const int pp = e / Kx;
@@ -314,7 +318,8 @@ __global__ __launch_bounds__(kThreads) void k_xinv(XParams<T> p) {
   }
   __syncthreads();
   lds_fft<T, true>(buf, Lx, lgP, p.rp, p.tw);
-  double acc = 0.0, acc2 = 0.0;
+  const bool per = p.periodic_mean != 0;
+  double acc = 0.0;
   for (int e = tid; e < P * Lout; e += kThreads) {
     const int pp = e / Lout;
     const int x = e - pp * Lout;
@@ -322,22 +327,18 @@ __global__ __launch_bounds__(kThreads) void k_xinv(XParams<T> p) {
     const cplx<T> z = buf[(x << lgP) + pp];
     if (ra < p.nrows) {
       const size_t o = (size_t)ra * p.in_row_stride + x;
-      if constexpr (MODE == XI_SOLVE) solve_epilogue(sl, o, z.x, acc, acc2);
+      if constexpr (MODE == XI_SOLVE) solve_epilogue(sl, o, z.x, dir, per, acc);
       else p.out_real[o] = double(z.x);
     }
     if (rb < p.nrows) {
       const size_t o = (size_t)rb * p.in_row_stride + x;
-      if constexpr (MODE == XI_SOLVE) solve_epilogue(sl, o, z.y, acc, acc2);
+      if constexpr (MODE == XI_SOLVE) solve_epilogue(sl, o, z.y, dir, per, acc);
       else p.out_real[o] = double(z.y);
     }
   }
   if constexpr (MODE == XI_SOLVE) {
     const double s1 = block_sum(acc);
-    const double s2 = block_sum(acc2);
-    if (tid == 0) {
-      sl.part_delta[0][blockIdx.x] = s1;
-      sl.part_rr[blockIdx.x] = s2;
-    }
+    if (tid == 0) sl.part_pap[blockIdx.x] = s1;
   }
 }
 
@@ -349,16 +350,25 @@ __global__ __launch_bounds__(kThreads) void k_strided(SParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x;
+  // y inverse of a solve: work-group 0 takes the stop decision, the tiles
+  // start at work-group 1
+  const int dec = MODE == ST_INV ? p.decide : 0;
+  if (MODE == ST_INV && dec && blockIdx.x == 0) {
+    pcg_decide(p.tab.s[p.batch.slot[blockIdx.y]], p.dec);
+    return;
+  }
   cplx<T>* work = p.work;
   const SolveState* st = nullptr;
+  double* part_delta = nullptr;
   if (work == nullptr) {
     const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
     if (solve_stopped(sl.st)) return;
     work = sl.work;
     st = sl.st;
+    part_delta = sl.part_delta;
   }
   const int B = p.B, lgB = p.lgB, L = p.L, Lin = p.Lin;
-  const int pen0 = blockIdx.x * B;
+  const int pen0 = (blockIdx.x - dec) * B;
   for (int e = tid; e < (Lin << lgB); e += kThreads) {
     const int b = e & (B - 1);
     const int t = e >> lgB;
@@ -380,6 +390,7 @@ __global__ __launch_bounds__(kThreads) void k_strided(SParams<T> p) {
   }
   if constexpr (MODE == ST_CONV) {
     const int Lyh = p.Ly / 2 + 1;
+    double dacc = 0.0;              // (v, r) by Parseval, as in the two-level passes
     for (int e = tid; e < (L << lgB); e += kThreads) {
       const int b = e & (B - 1);
       const int t = e >> lgB;
@@ -391,8 +402,14 @@ __global__ __launch_bounds__(kThreads) void k_strided(SParams<T> p) {
         const int kzf = min(t, p.Lz - t);
         T m = p.table[((size_t)kzf * Lyh + kyf) * p.Kx + kx];
         if (p.k0_from_slot && pen == 0 && t == 0) m = T(st->g0);
-        buf[e] = cscale(buf[e], m);
+        const cplx<T> w = buf[e];
+        dacc += double(half_bin_weight(kx, p.Lx)) * double(m * (w.x * w.x + w.y * w.y));
+        buf[e] = cscale(w, m);
       }
+    }
+    if (part_delta) {
+      const double sd = block_sum(dacc);
+      if (tid == 0) part_delta[blockIdx.x] = sd;
     }
     __syncthreads();
     lds_fft<T, true>(buf, L, lgB, p.rp, p.tw);
@@ -418,9 +435,10 @@ template <typename T> static int generic_xpass_groups(const XParams<T>& p) {
   return (npairs + p.P - 1) / p.P;
 }
 
-// Work-groups (= partial sums) of the solve-mode x passes, whichever family runs.
-template <typename T> int xpass_groups(const XParams<T>& p) {
-  if (fast_length(p.g.Lx)) return fast_xpass_groups(p.nrows);
+// Partials of the solve-mode x passes: one per wavefront in the two-level
+// passes, one per work-group in the generic ones.
+template <typename T> int xpass_parts(const XParams<T>& p) {
+  if (fast_length(p.g.Lx)) return fast_xpass_parts(p.g.Lx, p.nrows);
   return generic_xpass_groups(p);
 }
 
@@ -441,17 +459,25 @@ template <typename T> void launch_xinv(int mode, const XParams<T>& p, hipStream_
   else GPS_LAUNCH((k_xinv<T, XI_REAL>), grid, dim3(kThreads), lds, s, p);
 }
 
+template <typename T> int strided_parts(const SParams<T>& p) {
+  if (fast_length(p.L)) return fast_strided_parts<T>(p.L, p.npencils);
+  return (p.npencils + p.B - 1) / p.B;
+}
+
 template <typename T> void launch_strided(int mode, const SParams<T>& p, hipStream_t s) {
   if (fast_length(p.L) && fast_strided<T>(mode, p, s)) return;
-  const dim3 grid((p.npencils + p.B - 1) / p.B, p.work ? 1 : p.batch.n);
+  const int dec = mode == ST_INV && p.decide ? 1 : 0;   // the decision work-group
+  const dim3 grid((p.npencils + p.B - 1) / p.B + dec, p.work ? 1 : p.batch.n);
   const size_t lds = (size_t)p.B * p.L * sizeof(cplx<T>);
   if (mode == ST_FWD) GPS_LAUNCH((k_strided<T, ST_FWD>), grid, dim3(kThreads), lds, s, p);
   else if (mode == ST_INV) GPS_LAUNCH((k_strided<T, ST_INV>), grid, dim3(kThreads), lds, s, p);
   else GPS_LAUNCH((k_strided<T, ST_CONV>), grid, dim3(kThreads), lds, s, p);
 }
 
-template int xpass_groups<float>(const XParams<float>&);
-template int xpass_groups<double>(const XParams<double>&);
+template int strided_parts<float>(const SParams<float>&);
+template int strided_parts<double>(const SParams<double>&);
+template int xpass_parts<float>(const XParams<float>&);
+template int xpass_parts<double>(const XParams<double>&);
 template void launch_xfwd<float>(int, const XParams<float>&, hipStream_t);
 template void launch_xfwd<double>(int, const XParams<double>&, hipStream_t);
 template void launch_xinv<float>(int, const XParams<float>&, hipStream_t);

@@ -60,12 +60,22 @@ void k_fstrided(SParams<T> p) {
   __shared__ cplx<T> lds[L * PITCH];
   __shared__ cplx<T> twl[L];
   const int tid = threadIdx.x;
+  // y inverse of a solve: work-group 0 only takes the stop decision (it runs
+  // beside the transforms instead of after one); the tiles are numbered from
+  // work-group 1 on
+  const int dec = MODE == ST_INV ? p.decide : 0;
+  if (MODE == ST_INV && dec && blockIdx.x == 0) {
+    pcg_decide(p.tab.s[p.batch.slot[blockIdx.y]], p.dec);
+    return;
+  }
   cplx<T>* work = p.work;
   const SolveState* st = nullptr;
+  double* part_delta = nullptr;
   if (work == nullptr) {
     const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
     work = sl.work;
     st = sl.st;
+    part_delta = sl.part_delta;
   }
   // twiddles first, then the tile, then the stop flag: all in flight together
   cplx<T> twv[(L + NT - 1) / NT];
@@ -74,7 +84,9 @@ void k_fstrided(SParams<T> p) {
     if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
   const int b = tid & (B - 1);
   const int q = tid / B;
-  const int tile0 = xcd_tile(blockIdx.x, gridDim.x) * NTILE;
+  // (xcd_tile maps work-group 0 to tile 0, so the shift keeps every XCD's
+  // tiles contiguous)
+  const int tile0 = (xcd_tile(blockIdx.x, gridDim.x) - dec) * NTILE;
   // 32-bit byte offsets: the longest compile-time length is 384, so every
   // buffer these passes index is below 4 GiB
   constexpr unsigned CB = sizeof(cplx<T>);
@@ -173,6 +185,7 @@ void k_fstrided(SParams<T> p) {
   const cplx<T>* tw = twl;
 
   // ---- phase 2: transform the tiles one after the other ----
+  double dacc = 0.0;                            // z pass: this thread's part of (v, r)
 #pragma unroll
   for (int t = 0; t < NTILE; ++t) {
     if (t > 0) __syncthreads();                 // previous tile's LDS reads are done
@@ -205,13 +218,19 @@ void k_fstrided(SParams<T> p) {
         continue;
       } else {
         if (pv[t] && q < L1) {
+          // (v, r) = sum over the full spectrum of m |w^|^2 (Parseval); this
+          // pencil's half-spectrum bin k_x stands for itself and its mirror
+          T ws = T(0);
 #pragma unroll
           for (int k2 = 0; k2 < L2; ++k2) {
             const int kz = q + L1 * k2;
             T m = gm[t][k2];
             if (p.k0_from_slot && pen[t] == 0 && kz == 0) m = T(st->g0);
+            ws += m * (y[k2].x * y[k2].x + y[k2].y * y[k2].y);
             y[k2] = cscale(y[k2], m);
           }
+          const int kx = pen[t] - (pen[t] / p.Kx) * p.Kx;
+          dacc += double(half_bin_weight(kx, p.Lx)) * double(ws);
         }
         __syncthreads();                        // step-2 reads of lds are done
       }
@@ -246,6 +265,12 @@ void k_fstrided(SParams<T> p) {
           }
         }
       }
+    }
+  }
+  if constexpr (MODE == ST_CONV) {
+    if (part_delta) {                           // one partial per wavefront
+      const double sd = wave_sum(dacc);
+      if ((tid & 63) == 0) part_delta[blockIdx.x * (NT / 64) + (tid >> 6)] = sd;
     }
   }
 }
@@ -314,7 +339,7 @@ void k_fxfwd(XParams<T> p) {
   // operands arrive while it decides.  p, Ap and phi are loaded even at k = 0
   // (unused there).
   XHead hd;
-  if constexpr (MODE == XF_SOLVE) xfwd_head_load(sl, p.n_vec_parts, hd);
+  if constexpr (MODE == XF_SOLVE) xfwd_head_load(sl, p.n_pap_parts, hd);
   T rv[EIN], sv[EIN], pv[EIN], av[EIN];
   double fv[EIN];
 #pragma unroll
@@ -342,11 +367,11 @@ void k_fxfwd(XParams<T> p) {
   bool upd = false;
   if constexpr (MODE == XF_SOLVE) {
     int k;
-    if (!xfwd_head_finish(sl, p.n_vec_parts, hd, &k, &alpha)) return;
+    if (!xfwd_head_finish(sl, p.n_pap_parts, hd, &k, &alpha)) return;
     upd = k > 0;
   }
   // phase 2: update, scale, stage the rows in LDS
-  double mu = 0.0;
+  double mu = 0.0, rr = 0.0;
 #pragma unroll
   for (int i = 0; i < EIN; ++i) {
     const int e = tid + i * NT;
@@ -363,6 +388,7 @@ void k_fxfwd(XParams<T> p) {
             a = a - T(alpha) * av[i];
             GPS_AT(sl.r, o) = a;
           }
+          rr += double(a) * double(a);
           a = a * sv[i];
           mu += double(a);
         }
@@ -429,17 +455,24 @@ void k_fxfwd(XParams<T> p) {
       }
     }
   }
-  if constexpr (MODE == XF_SOLVE) {
+  if constexpr (MODE == XF_SOLVE) {             // one partial per wavefront
+    const int pi = tile * (NT / 64) + (tid >> 6);
+    const double s2 = wave_sum(rr);
+    if ((tid & 63) == 0) sl.part_rr[pi] = s2;
     if (p.periodic_mean) {
-      const double s = block_sum(mu);
-      if (tid == 0) sl.part_mu[tile] = s;
+      const double s = wave_sum(mu);
+      if ((tid & 63) == 0) sl.part_mu[pi] = s;
     }
   }
 }
 
-template <typename T, int L1, int L2, int MODE, bool PAD>   // MODE 0: solve epilogue, 1: plain
+// MODE XI_SOLVE / XI_SOLVE_PERIODIC: v = u / sqrt(eps) and the direction update
+// of the PCG iteration (with the periodic mean term); XI_REAL: plain output.
+template <typename T, int L1, int L2, int MODE, bool PAD>
 __global__ __launch_bounds__(xthreads<L1>())
 void k_fxinv(XParams<T> p) {
+  constexpr bool SOLVE = MODE != XI_REAL;
+  constexpr bool PER = MODE == XI_SOLVE_PERIODIC;
   constexpr int P = kXPairs;
   constexpr int L = L1 * L2;
   constexpr int PITCH = P + 1;
@@ -457,7 +490,15 @@ void k_fxinv(XParams<T> p) {
   const int row0 = tile * 2 * P;
   cplx<T>* work = p.work;
   const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
-  if constexpr (MODE == 0) work = sl.work;
+  if constexpr (SOLVE) work = sl.work;
+  // the y-inverse decision of this iteration (plain loads: written by an
+  // earlier kernel, first used in the epilogue)
+  DirArgs dir{};
+  if constexpr (SOLVE) {
+    dir.k = sl.st->k;
+    dir.beta = sl.st->beta;
+    dir.mu = PER ? sl.st->mu : 0.0;
+  }
   constexpr int ETW = (L + NT - 1) / NT;
   cplx<T> twv[ETW];
 #pragma unroll
@@ -480,8 +521,9 @@ void k_fxinv(XParams<T> p) {
     }
   }
   // epilogue operands are independent of the transform: load them now too
-  T sv[MODE == 0 ? EOUT : 1], rv[MODE == 0 ? EOUT : 1];
-  if constexpr (MODE == 0) {
+  constexpr int EO = SOLVE ? EOUT : 1;
+  T sv[EO], rv[EO], qv[EO], pv[EO], av[EO], mv[PER ? EOUT : 1];
+  if constexpr (SOLVE) {
 #pragma unroll
     for (int i = 0; i < EOUT; ++i) {
       const int e = tid + i * NT;
@@ -492,6 +534,10 @@ void k_fxinv(XParams<T> p) {
         const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)xx;
         sv[i] = GPS_AT(sl.isq, o);
         rv[i] = GPS_AT(sl.r, o);
+        qv[i] = GPS_AT(sl.qk, o);
+        pv[i] = GPS_AT(sl.p, o);
+        av[i] = GPS_AT(sl.ap, o);
+        if constexpr (PER) mv[i] = GPS_AT(sl.s, o);
       }
     }
     // stop flag issued after the operand loads, in flight with them
@@ -546,8 +592,8 @@ void k_fxinv(XParams<T> p) {
     for (int nb = 0; nb < L1; ++nb) lds[(q + L2 * nb) * PITCH + pp] = x[nb];
   }
   __syncthreads();
-  if constexpr (MODE == 0) {
-    double acc = 0.0, acc2 = 0.0;
+  if constexpr (SOLVE) {
+    double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < EOUT; ++i) {
       const int e = tid + i * NT;
@@ -557,17 +603,15 @@ void k_fxinv(XParams<T> p) {
       if (e < NOUT && grow < p.nrows) {
         const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)xx;
         const T v = ldsr[2 * (xx * PITCH + (row >> 1)) + (row & 1)] * sv[i];
-        GPS_AT(sl.v, o) = v;
-        acc += double(v) * double(rv[i]);
-        acc2 += double(rv[i]) * double(rv[i]);
+        T pn = pv[i], an = av[i];
+        direction_update(v, rv[i], qv[i], PER ? mv[i] : T(0), pn, an, dir);
+        GPS_AT(sl.p, o) = pn;
+        GPS_AT(sl.ap, o) = an;
+        acc += double(pn) * double(an);
       }
     }
-    const double s1 = block_sum(acc);
-    const double s2 = block_sum(acc2);
-    if (tid == 0) {
-      sl.part_delta[0][tile] = s1;
-      sl.part_rr[tile] = s2;
-    }
+    const double s1 = wave_sum(acc);            // one partial per wavefront
+    if ((tid & 63) == 0) sl.part_pap[tile * (NT / 64) + (tid >> 6)] = s1;
   } else {
 #pragma unroll
     for (int i = 0; i < EOUT; ++i) {
@@ -600,8 +644,35 @@ bool fast_length(int L) {
 
 int fast_xpass_groups(int nrows) { return ((nrows + 1) / 2 + kXPairs - 1) / kXPairs; }
 
+// Partials of the solve-mode passes: one per wavefront.
+int fast_xpass_parts(int L, int nrows) {
+  switch (L) {
+#define GPS_CASE(LL, A, B) case LL: return fast_xpass_groups(nrows) * (xthreads<A>() / 64);
+    GPS_FAST_LENGTHS(GPS_CASE)
+#undef GPS_CASE
+    default: return 0;
+  }
+}
+
 // Tiles per work-group of the strided passes.
 constexpr int kStridedTiles = 1;
+
+template <typename T> int fast_strided_groups(int npencils) {
+  constexpr int W = FastTile<T>::B * kStridedTiles;
+  return (npencils + W - 1) / W;
+}
+
+template <typename T> int fast_strided_parts(int L, int npencils) {
+  switch (L) {
+#define GPS_CASE(LL, A, BB) \
+  case LL: return fast_strided_groups<T>(npencils) * (round64(FastTile<T>::B * A) / 64);
+    GPS_FAST_LENGTHS(GPS_CASE)
+#undef GPS_CASE
+    default: return 0;
+  }
+}
+template int fast_strided_parts<float>(int, int);
+template int fast_strided_parts<double>(int, int);
 
 template <typename T>
 bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
@@ -612,7 +683,8 @@ bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
   const bool pad = (mode == ST_FWD && 2 * p.Lin == p.L) ||
                    (mode == ST_CONV && 2 * p.Lin == p.L && p.Lout == p.Lin) ||
                    (mode == ST_INV && 2 * p.Lout == p.L && p.Lin == p.L);
-  const dim3 grid((p.npencils + B * NTL - 1) / (B * NTL), p.work ? 1 : p.batch.n);
+  const int dec = mode == ST_INV && p.decide ? 1 : 0;   // the decision work-group
+  const dim3 grid(fast_strided_groups<T>(p.npencils) + dec, p.work ? 1 : p.batch.n);
   switch (p.L) {
 #define GPS_CASE(LL, A, BB)                                                                    \
   case LL: {                                                                                   \
@@ -669,12 +741,15 @@ bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s) {
 #define GPS_CASE(LL, A, BB)                                                                      \
   case LL: {                                                                                     \
     const dim3 blk(xthreads<A>());                                                      \
-    if (mode == 0) {                                                                             \
-      if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, 0, true>), grid, blk, 0, s, p);             \
-      else GPS_LAUNCH((k_fxinv<T, A, BB, 0, false>), grid, blk, 0, s, p);                \
+    if (mode == XI_SOLVE && p.periodic_mean) {                                                   \
+      if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE_PERIODIC, true>), grid, blk, 0, s, p);     \
+      else GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE_PERIODIC, false>), grid, blk, 0, s, p);        \
+    } else if (mode == XI_SOLVE) {                                                               \
+      if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE, true>), grid, blk, 0, s, p);              \
+      else GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE, false>), grid, blk, 0, s, p);                 \
     } else {                                                                                     \
-      if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, 1, true>), grid, blk, 0, s, p);             \
-      else GPS_LAUNCH((k_fxinv<T, A, BB, 1, false>), grid, blk, 0, s, p);                \
+      if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, XI_REAL, true>), grid, blk, 0, s, p);               \
+      else GPS_LAUNCH((k_fxinv<T, A, BB, XI_REAL, false>), grid, blk, 0, s, p);                  \
     }                                                                                            \
     return true;                                                                                 \
   }

@@ -53,7 +53,7 @@ struct SolveState {
   int iters;         // iterations completed
   int err;           // input-check flags raised by the init kernel
   int k;             // current iteration (written by the x-forward pass)
-  int k_next;        // next iteration (written by the direction kernel)
+  int k_next;        // next iteration (written by the y-inverse decision)
   double rr0;        // ||r_0||^2
   double thr2;       // stop threshold on ||r||^2
   double rr;         // last ||r||^2
@@ -64,7 +64,9 @@ struct SolveState {
   double abs_thr;    // absolute stop threshold on ||r||
   double rel_thr;    // relative stop threshold on ||r|| / ||r_0||
   double g0;         // periodic k = 0 multiplier of the preconditioner
-  double delta[2];   // delta_k = (v_k, r_k) at index k & 1 (direction kernel)
+  double delta[2];   // delta_k = (v_k, r_k) at index k & 1 (y-inverse decision)
+  double beta;       // beta_k of the current iteration (y-inverse decision)
+  double mu;         // mean of r_k / sqrt(eps) (periodic; y-inverse decision)
 };
 
 // Input-check flags (SolveState::err)
@@ -74,7 +76,7 @@ constexpr int kErrNonFinite = 2;
 // Device-resident pointers of one problem in flight.  T is the bulk type
 // (float in mixed precision, double in plain FP64).
 template <typename T> struct Slot {
-  T *r, *v, *p, *ap;          // PCG vectors
+  T *r, *p, *ap;              // PCG vectors (v_k lives only in registers)
   T *isq;                     // 1/sqrt(eps)
   T *qk;                      // q + kappa2 (fixed operator diagonal)
   T *s;                       // sqrt(eps) (periodic mean term; may be null)
@@ -83,10 +85,10 @@ template <typename T> struct Slot {
   double *sq64;               // sqrt(eps) in FP64 (stencil input)
   cplx<T> *work;              // FFT work buffer  nz * Ly * Kx
   double *part_init;          // 4 partial sums per init work-group
-  double *part_rr;            // ||r||^2 partials
-  double *part_delta[2];      // (v, r) partials, by iteration parity
-  double *part_pap;           // (p, Ap) partials
-  double *part_mu;            // sum r/sqrt(eps) partials (periodic)
+  double *part_rr;            // ||r||^2 partials (x-forward work-groups)
+  double *part_delta;         // (v, r) partials (z-pass work-groups)
+  double *part_pap;           // (p, Ap) partials (x-inverse work-groups)
+  double *part_mu;            // sum r/sqrt(eps) partials (periodic; x-forward work-groups)
   double *part_aux;           // q-kernel (1 per 256 points), ionic-update / energy (2 per WG)
   double *hist;               // per-iteration history: delta, beta, alpha, ||r||^2
   SolveState *st;

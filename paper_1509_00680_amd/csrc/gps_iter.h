@@ -1,11 +1,24 @@
-// Scalar steps of a PCG iteration, evaluated redundantly (and identically) by
-// every work-group of the kernel that needs them, from the FP64 partial sums
-// the previous kernel wrote.  Only work-group 0 writes the solve state.
+// Scalar steps of a PCG iteration (Algorithm PCG with the Eq. corr identity),
+// spread over the five FFT passes of the preconditioner so that an iteration
+// needs no kernel of its own:
 //
-// Iteration k runs:  x-forward pass (applies the update of iteration k-1),
-// y, z, y-inverse passes, x-inverse pass (v_k, partials of (v_k, r_k) and
-// ||r_k||^2), direction kernel (stop decision, beta_k, p_k, Ap_k, partials of
-// (p_k, Ap_k)).
+//   x forward   alpha_{k-1} = delta_{k-1} / (p_{k-1}, A p_{k-1}) (every
+//               work-group, from the x-inverse partials); phi += alpha p,
+//               r -= alpha Ap; w = r / sqrt(eps); partials of ||r_k||^2 and
+//               (periodic) sum w.
+//   y forward
+//   z pass      partials of delta_k = (v_k, r_k), by Parseval on the spectrum
+//               it already holds: (r, v) = (w, G w) = sum_k c(k_x) m(k) |w^(k)|^2
+//               with m the Green's multiplier applied and c the weight of a
+//               half-spectrum bin (1 for k_x = 0 and Nyquist, else 2).
+//   y inverse   one extra work-group: stop decision on ||r_k||^2, delta_k,
+//               beta_k.
+//   x inverse   v_k; A v_k from the Eq. corr identity; p_k = v_k + beta p,
+//               Ap_k = A v_k + beta Ap; partials of (p_k, Ap_k).
+//
+// Every scalar is a fixed-order FP64 sum of per-work-group partials, so a
+// solve's bits do not depend on timing.  Only work-group 0 writes the solve
+// state.
 #pragma once
 
 #include "gps_device.h"
@@ -19,18 +32,18 @@ namespace gps {
 // operands arrive while it reduces and decides.
 
 // Partial sums per thread loaded up front; grids with more partials than
-// kHeadShare * blockDim load the remainder when summing.
-constexpr int kHeadShare = 8;
-
+// N * blockDim load the remainder when summing.
+template <int N>
 struct PartShare {
-  double v[kHeadShare];
+  double v[N];
 };
 
 // Branch-free (a clamped index and a select), so that the loads issue back to
 // back and nothing waits for them before their use.  n >= 1.
-__device__ __forceinline__ void share_load(PartShare& s, const double* __restrict__ p, int n) {
+template <int N>
+__device__ __forceinline__ void share_load(PartShare<N>& s, const double* __restrict__ p, int n) {
 #pragma unroll
-  for (int j = 0; j < kHeadShare; ++j) {
+  for (int j = 0; j < N; ++j) {
     const int i = threadIdx.x + j * blockDim.x;
     const double v = p[min(i, n - 1)];
     s.v[j] = i < n ? v : 0.0;
@@ -39,17 +52,28 @@ __device__ __forceinline__ void share_load(PartShare& s, const double* __restric
 
 // Work-group sum of the n partials (fixed order: every work-group of every
 // launch gets the same bits).
-__device__ __forceinline__ double share_sum(const PartShare& s, const double* __restrict__ p,
+template <int N>
+__device__ __forceinline__ double share_sum(const PartShare<N>& s, const double* __restrict__ p,
                                             int n) {
+  static_assert(N % 4 == 0, "share size");
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-  for (int j = 0; j < kHeadShare; j += 4) {
+  for (int j = 0; j < N; j += 4) {
     a0 += s.v[j];
     a1 += s.v[j + 1];
     a2 += s.v[j + 2];
     a3 += s.v[j + 3];
   }
-  for (int i = threadIdx.x + kHeadShare * blockDim.x; i < n; i += blockDim.x) a0 += p[i];
+  const int step = blockDim.x;
+  int i = threadIdx.x + N * step;
+  for (; i + 3 * step < n; i += 4 * step) {
+    const double b0 = p[i], b1 = p[i + step], b2 = p[i + 2 * step], b3 = p[i + 3 * step];
+    a0 += b0;
+    a1 += b1;
+    a2 += b2;
+    a3 += b3;
+  }
+  for (; i < n; i += step) a0 += p[i];
   return block_sum((a0 + a1) + (a2 + a3));
 }
 
@@ -65,16 +89,19 @@ __device__ __forceinline__ V wg_bcast(V w) {
 }
 
 // ---- x-forward pass: the first kernel of iteration k ------------------------
+// (p, Ap) partials per thread held in registers: one per x-inverse work-group,
+// so a 64-thread x pass over 96^3 (1536 work-groups) needs 24.
+constexpr int kXHeadShare = 24;
+
 struct XHead {
   int done, k;
   double dprev0, dprev1;
-  PartShare pap;
+  PartShare<kXHeadShare> pap;
 };
 
 // State words are loaded by every thread (one request per wavefront) with
-// plain loads, which wait only where used; thread 0's copy is broadcast, so a
-// work-group acts on one value even when the direction kernel's work-group 0
-// writes a word during the same launch.
+// plain loads, which wait only where used; thread 0's copy is broadcast, so
+// every work-group acts on the same value.
 template <typename T>
 __device__ __forceinline__ void xfwd_head_load(const Slot<T>& sl, int n_pap_parts, XHead& h) {
   const SolveState* v = sl.st;
@@ -116,61 +143,46 @@ __device__ __forceinline__ bool xfwd_head_finish(const Slot<T>& sl, int n_pap_pa
   return true;
 }
 
-// ---- direction kernel: the last kernel of iteration k -----------------------
-struct DHead {
-  int done, k, err;
-  double thr2, dprev0, dprev1, abs_thr, rel_thr;
-  PartShare rr, delta, mu;
+// ---- y-inverse pass, decision work-group: the stop decision of iteration k --
+struct DecideArgs {
+  int n_rr;            // ||r||^2 and sum w partials (x-forward work-groups)
+  int n_delta;         // delta partials (z-pass work-groups)
+  int n_init;          // init-kernel work-groups (4 partials each)
+  int check_neutral;   // free / surface boundaries: the net charge must vanish
+  int periodic;
+  double npts;         // grid points (the mean term divides by it)
 };
 
-template <typename T>
-__device__ __forceinline__ void direction_head_load(const Slot<T>& sl, int n_x_parts,
-                                                    int periodic, DHead& h) {
-  const SolveState* v = sl.st;
-  h.done = v->done;
-  h.k = v->k;
-  h.err = v->err;
-  h.thr2 = v->thr2;
-  h.dprev0 = v->delta[0];
-  h.dprev1 = v->delta[1];
-  h.abs_thr = v->abs_thr;
-  h.rel_thr = v->rel_thr;
-  share_load(h.rr, sl.part_rr, n_x_parts);
-  share_load(h.delta, sl.part_delta[0], n_x_parts);
-  if (periodic) share_load(h.mu, sl.part_mu, n_x_parts);
-  else h.mu = PartShare{};
-}
-
 // Stop decision on ||r_k||^2 (and, at k = 0, on the input checks of the init
-// kernel), then delta_k = (v_k, r_k) > 0 and beta_k = delta_k / delta_{k-1}.
-// Returns false (whole work-group) if the solve stops here; otherwise
-// advances the iteration counter.
+// kernel); else delta_k = (v_k, r_k) > 0, beta_k = delta_k / delta_{k-1}.
+// Writes the solve state (done and status, or delta_k, beta_k, the mean term
+// and the next iteration number) for the x-inverse pass.  Run by one
+// work-group of the y-inverse launch, beside the transforms; nothing if the
+// solve has already stopped.
 template <typename T>
-__device__ __forceinline__ bool direction_head_finish(const Slot<T>& sl, const DHead& h,
-                                                      int n_x_parts, int n_vec_parts,
-                                                      int check_neutral, int periodic,
-                                                      int* k_out, double* delta_out,
-                                                      double* beta_out, double* mu_out) {
-  if (wg_bcast(h.done)) return false;
-  const int k = wg_bcast(h.k);
-  *k_out = k;
-  const double rr = share_sum(h.rr, sl.part_rr, n_x_parts);
-  const double delta = share_sum(h.delta, sl.part_delta[0], n_x_parts);
-  *mu_out = periodic ? share_sum(h.mu, sl.part_mu, n_x_parts) : 0.0;
+__device__ void pcg_decide(const Slot<T>& sl, const DecideArgs& a) {
+  SolveState* st = sl.st;
+  if (st->done) return;
+  PartShare<8> srr, sdl, smu;
+  share_load(srr, sl.part_rr, a.n_rr);
+  share_load(sdl, sl.part_delta, a.n_delta);
+  if (a.periodic) share_load(smu, sl.part_mu, a.n_rr);
+  const int k = st->k;
+  const double rr = share_sum(srr, sl.part_rr, a.n_rr);
+  const double delta = share_sum(sdl, sl.part_delta, a.n_delta);
+  const double mu = a.periodic ? share_sum(smu, sl.part_mu, a.n_rr) : 0.0;
   double thr2, rsum = 0.0, rabs = 0.0;
   int status = -1;
   if (k == 0) {
-    // once per solve: the init kernel's partials (a second round)
-    rsum = sum_partials(sl.part_init + 1, n_vec_parts, 4);
-    rabs = sum_partials(sl.part_init + 2, n_vec_parts, 4);
-    const int err = wg_bcast(h.err);
-    const double at = wg_bcast(h.abs_thr), rt = wg_bcast(h.rel_thr);
-    thr2 = fmax(at * at, rt * rt * rr);
+    rsum = sum_partials(sl.part_init + 1, a.n_init, 4);
+    rabs = sum_partials(sl.part_init + 2, a.n_init, 4);
+    const int err = st->err;
+    thr2 = fmax(st->abs_thr * st->abs_thr, st->rel_thr * st->rel_thr * rr);
     if (err & kErrNonFinite) status = GPS_E_NONFINITE;
     else if (err & kErrEpsNonPositive) status = GPS_E_INVALID;
-    else if (check_neutral && fabs(rsum) > 1e-10 * rabs) status = GPS_E_INVALID;
+    else if (a.check_neutral && fabs(rsum) > 1e-10 * rabs) status = GPS_E_INVALID;
   } else {
-    thr2 = wg_bcast(h.thr2);
+    thr2 = st->thr2;
   }
   if (status < 0) {
     if (!isfinite(rr)) status = GPS_E_NONFINITE;
@@ -178,39 +190,68 @@ __device__ __forceinline__ bool direction_head_finish(const Slot<T>& sl, const D
     else if (k >= sl.maxit) status = GPS_E_NOT_CONVERGED;
     else if (!(delta > 0.0)) status = isfinite(delta) ? GPS_E_BREAKDOWN : GPS_E_NONFINITE;
   }
-  double beta = 0.0;
-  if (k > 0) beta = delta / wg_bcast(((k - 1) & 1) ? h.dprev1 : h.dprev0);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  const double beta = k > 0 ? delta / st->delta[(k - 1) & 1] : 0.0;
+  if (threadIdx.x == 0) {
     if (k == 0) {
-      sl.st->rr0 = rr;
-      sl.st->thr2 = thr2;
-      sl.st->rho_sum = rsum;
-      sl.st->rho_abs = rabs;
+      st->rr0 = rr;
+      st->thr2 = thr2;
+      st->rho_sum = rsum;
+      st->rho_abs = rabs;
     } else {
       sl.hist[(size_t)(k - 1) * 4 + 3] = rr;
     }
-    sl.st->iters = k;
-    sl.st->rr = rr;
+    st->iters = k;
+    st->rr = rr;
     if (status >= 0) {
-      sl.st->status = status;
-      sl.st->done = 1;
+      st->status = status;
+      st->done = 1;
     } else {
-      sl.st->delta[k & 1] = delta;
+      st->delta[k & 1] = delta;
+      st->beta = beta;
+      st->mu = mu / a.npts;
       sl.hist[(size_t)k * 4 + 0] = delta;
       sl.hist[(size_t)k * 4 + 1] = beta;
-      sl.st->k_next = k + 1;
+      st->k_next = k + 1;
     }
   }
-  *delta_out = delta;
-  *beta_out = beta;
-  return status < 0;
 }
 
-// x-forward prologue at grid point o: apply the update of iteration k-1
-// (phi += alpha p, r -= alpha Ap) and return the preconditioner input
-// r / sqrt(eps).
+// Weight of half-spectrum bin kx in a sum over the full spectrum of a real
+// field of length Lx along x.
+__device__ __forceinline__ int half_bin_weight(int kx, int Lx) {
+  return (kx == 0 || 2 * kx == Lx) ? 1 : 2;
+}
+
+// ---- x-inverse epilogue: the direction update of iteration k ----------------
+// A v = -(q + kappa2) v - 4 pi (r - sqrt(eps) mean(r / sqrt(eps))) [periodic]
+// p = v + beta p, Ap = A v + beta Ap (beta = 0 at k = 0).
+struct DirArgs {
+  int k;
+  double beta;
+  double mu;           // mean of r / sqrt(eps) (periodic), else 0
+};
+
 template <typename T>
-__device__ __forceinline__ T solve_prologue(const Slot<T>& sl, size_t o, bool upd, double alpha) {
+__device__ __forceinline__ void direction_update(T v, T r, T q, T s, T& p, T& ap,
+                                                 const DirArgs& d) {
+  const T fpi = T(kFourPi);
+  const T av = -q * v - fpi * (r - s * T(d.mu));
+  if (d.k == 0) {
+    p = v;
+    ap = av;
+  } else {
+    const T tb = T(d.beta);
+    p = v + tb * p;
+    ap = av + tb * ap;
+  }
+}
+
+// x-forward prologue at grid point o (generic passes): apply the update of
+// iteration k-1 (phi += alpha p, r -= alpha Ap), accumulate ||r_k||^2 and
+// return the preconditioner input r / sqrt(eps).
+template <typename T>
+__device__ __forceinline__ T solve_prologue(const Slot<T>& sl, size_t o, bool upd, double alpha,
+                                            double& rr) {
   T r = sl.r[o];
   if (upd) {
     const T pv = sl.p[o];
@@ -219,19 +260,21 @@ __device__ __forceinline__ T solve_prologue(const Slot<T>& sl, size_t o, bool up
     r = r - T(alpha) * av;
     sl.r[o] = r;
   }
+  rr += double(r) * double(r);
   return r * sl.isq[o];
 }
 
-// x-inverse epilogue at grid point o: v = u / sqrt(eps); accumulate (v, r)
-// and ||r||^2.
+// x-inverse epilogue at grid point o (generic passes): v = u / sqrt(eps),
+// the direction update, and (p, Ap).
 template <typename T>
-__device__ __forceinline__ void solve_epilogue(const Slot<T>& sl, size_t o, T u, double& vr,
-                                               double& rr) {
+__device__ __forceinline__ void solve_epilogue(const Slot<T>& sl, size_t o, T u,
+                                               const DirArgs& d, bool periodic, double& pap) {
   const T v = u * sl.isq[o];
-  const T r = sl.r[o];
-  sl.v[o] = v;
-  vr += double(v) * double(r);
-  rr += double(r) * double(r);
+  T p = sl.p[o], ap = sl.ap[o];
+  direction_update(v, sl.r[o], sl.qk[o], periodic ? sl.s[o] : T(0), p, ap, d);
+  sl.p[o] = p;
+  sl.ap[o] = ap;
+  pap += double(p) * double(ap);
 }
 
 }  // namespace gps

@@ -4,6 +4,7 @@
 #include <hip/hip_ext.h>
 
 #include "gps_internal.h"
+#include "gps_iter.h"
 
 namespace gps {
 
@@ -56,13 +57,19 @@ template <typename T> struct XParams {
   SlotTable<T> tab;
   int has_slots;
   Batch batch;
-  int n_vec_parts;          // partial sums written by the direction kernel
-  int periodic_mean;        // accumulate sum r/sqrt(eps) (periodic)
+  int n_pap_parts;          // (p, Ap) partials written by the x-inverse pass
+  int periodic_mean;        // periodic: sum r/sqrt(eps) partials and the mean term
 };
+
+// x-inverse modes: the PCG epilogue (plain or with the periodic mean term), or
+// plain real output.
+enum XinvMode { XI_SOLVE = 0, XI_REAL = 1, XI_SOLVE_PERIODIC = 2 };
 
 template <typename T> void launch_xfwd(int mode, const XParams<T>& p, hipStream_t s);
 template <typename T> void launch_xinv(int mode, const XParams<T>& p, hipStream_t s);
-template <typename T> int xpass_groups(const XParams<T>& p);
+// Partial sums written by a solve-mode x pass, whichever family runs (at most
+// the number of row pairs).
+template <typename T> int xpass_parts(const XParams<T>& p);
 
 // Pass along a strided axis: pencils p of length L with elements at
 // base(p) + t * elem_stride, base(p) = (p / per_group) * group_stride + p % per_group.
@@ -80,15 +87,24 @@ template <typename T> struct SParams {
   const T* table;
   int Kx, Ly, Lz;
   int k0_from_slot;         // periodic: the k = 0 multiplier is the solve state's g0
+  int Lx;                   // ST_CONV with slots: x length (weights of the (v, r) partials)
+  int decide;               // ST_INV with slots: work-group 0 takes the stop decision
+  DecideArgs dec;
   cplx<T>* work;            // explicit buffer, or null to use the slots
   SlotTable<T> tab;
   Batch batch;
 };
 template <typename T> void launch_strided(int mode, const SParams<T>& p, hipStream_t s);
+// Partial sums written by a solve-mode z pass, whichever family runs (at most
+// the number of pencils plus 64).
+template <typename T> int strided_parts(const SParams<T>& p);
 
 // Two-level passes for the common lengths (32 ... 384); false if L has none.
 bool fast_length(int L);
 int fast_xpass_groups(int nrows);
+int fast_xpass_parts(int L, int nrows);
+template <typename T> int fast_strided_groups(int npencils);
+template <typename T> int fast_strided_parts(int L, int npencils);
 template <typename T> bool fast_strided(int mode, const SParams<T>& p, hipStream_t s);
 template <typename T> bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s);
 template <typename T> bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s);
@@ -126,9 +142,6 @@ template <typename T> void launch_qfield(const SlotTable<T>& tab, const Batch& b
                                          int fd_half, const double* lap_sq, double kappa_coef,
                                          const double* eps, const double* gamma,
                                          double eps_bulk, hipStream_t s);
-template <typename T> void launch_direction(const SlotTable<T>& tab, const Batch& b, long long n,
-                                            int n_xparts, int periodic, int check_neutral,
-                                            hipStream_t s);
 template <typename T> void launch_ion_update(const SlotTable<T>& tab, const Batch& b, long long n,
                                              const IonParams& ip, int first, hipStream_t s);
 template <typename T> void launch_energy(const SlotTable<T>& tab, const Batch& b, const double* rho,

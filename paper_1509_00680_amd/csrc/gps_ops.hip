@@ -341,79 +341,6 @@ void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g, int f
 }
 
 // ---------------------------------------------------------------------------
-// direction update (Algorithm PCG with Eq. corr), after the stop decision:
-//   beta = delta_k / delta_{k-1}  (0 at k = 0)
-//   A v = -(q + kappa2) v - 4 pi (r - sqrt(eps) mean(r/sqrt(eps)))  [periodic]
-//   p = v + beta p;  Ap = A v + beta Ap;  partial (p, Ap)
-// ---------------------------------------------------------------------------
-template <typename T, int periodic>
-__global__ __launch_bounds__(kThreads) void k_direction(SlotTable<T> tab, Batch b, long long n,
-                                                        int n_xparts, int check_neutral) {
-  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
-  // head inputs first (one round), then the operands, which arrive while the
-  // head reduces and decides
-  DHead h;
-  direction_head_load(sl, n_xparts, periodic, h);
-  // XCD-contiguous chunks: each XCD works on the same 1/8 of the grid as the
-  // x passes, so fields written by one kernel are read from the same L2
-  const long long base =
-      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
-  // branch-free loads (clamped index; results past n are never stored), so
-  // that they issue back to back and nothing waits for them before use
-  T vv[kVec], rv[kVec], qv[kVec], pv[kVec], av[kVec], sv[kVec];
-#pragma unroll
-  for (int j = 0; j < kVec; ++j) {
-    const long long i = base + (long long)j * kThreads;
-    const long long ic = i < n ? i : n - 1;
-    vv[j] = sl.v[ic];
-    rv[j] = sl.r[ic];
-    qv[j] = sl.qk[ic];
-    pv[j] = sl.p[ic];
-    av[j] = sl.ap[ic];
-    sv[j] = periodic ? sl.s[ic] : T(0);
-  }
-  int k;
-  double delta, beta, mu;
-  if (!direction_head_finish(sl, h, n_xparts, vec_groups(n), check_neutral, periodic, &k, &delta,
-                             &beta, &mu))
-    return;
-  mu /= double(n);
-  const T tb = T(beta), tmu = T(mu), fpi = T(kFourPi);
-  double acc = 0.0;
-#pragma unroll
-  for (int j = 0; j < kVec; ++j) {
-    const long long i = base + (long long)j * kThreads;
-    if (i < n) {
-      const T av_ = -qv[j] * vv[j] - fpi * (periodic ? rv[j] - sv[j] * tmu : rv[j]);
-      T pn, apn;
-      if (k == 0) {
-        pn = vv[j];
-        apn = av_;
-      } else {
-        pn = vv[j] + tb * pv[j];
-        apn = av_ + tb * av[j];
-      }
-      sl.p[i] = pn;
-      sl.ap[i] = apn;
-      acc += double(pn) * double(apn);
-    }
-  }
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) sl.part_pap[blockIdx.x] = acc;
-}
-
-template <typename T>
-void launch_direction(const SlotTable<T>& tab, const Batch& b, long long n, int n_xparts,
-                      int periodic, int check_neutral, hipStream_t s) {
-  if (periodic)
-    GPS_LAUNCH((k_direction<T, 1>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n,
-               n_xparts, check_neutral);
-  else
-    GPS_LAUNCH((k_direction<T, 0>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n,
-               n_xparts, check_neutral);
-}
-
-// ---------------------------------------------------------------------------
 // ionic update of Algorithm SCPBimproved (Eqs. rhoions, ionsconcPB/MPB):
 //   new = gamma sum_i Z_i c_i e^{x_i} / D,  x_i = -Z_i phi / kT,
 //   D = 1 (Boltzmann) or 1 + sum_j a_j (e^{x_j} - 1) (steric), evaluated with
@@ -547,8 +474,6 @@ void launch_energy(const SlotTable<T>& tab, const Batch& b, const double* rho, l
                                long long, hipStream_t);                                          \
   template void launch_qfield<T>(const SlotTable<T>&, const Batch&, const Geom&, int, const double*,  \
                                  double, const double*, const double*, double, hipStream_t);     \
-  template void launch_direction<T>(const SlotTable<T>&, const Batch&, long long, int, int, int,      \
-                                    hipStream_t);                                                \
   template void launch_ion_update<T>(const SlotTable<T>&, const Batch&, long long, const IonParams&,  \
                                      int, hipStream_t);                                          \
   template void launch_zero_ion<T>(const SlotTable<T>&, const Batch&, long long, hipStream_t);        \

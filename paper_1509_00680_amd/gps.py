@@ -31,7 +31,7 @@ EXPORTED = ("gps_plan_create", "gps_plan_set_options", "gps_plan_get_options",
             "gps_plan_set_timing", "gps_plan_timing", "gps_status_string",
             "gps_plan_footprint", "gps_plan_release_buffers", "gps_server_create", "gps_server_submit", "gps_server_poll",
             "gps_server_wait", "gps_server_get_stats", "gps_server_destroy")
-KERNEL_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "xinv": 5, "direction": 6}
+KERNEL_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "xinv": 5}
 
 
 class gps_options(ctypes.Structure):

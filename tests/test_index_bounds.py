@@ -30,19 +30,27 @@ def xcd_tile(bid, G):
 
 
 def strided_violations(T, mode, L, Lin, Lout, npen, per_group, group_stride, elem_stride, wsize,
-                       Kx=None, Ly=None, tabsize=None, clamp_q=True, ntile=1):
+                       Kx=None, Ly=None, tabsize=None, clamp_q=True, ntile=1, decide=False):
+    """decide: the solve's y inverse, whose work-group 0 only takes the stop
+    decision; the tiles are numbered from work-group 1 on."""
     L1, L2 = FAST[L]
     B = 16 if T == "f" else 8
     pad = ((mode == ST_FWD and 2 * Lin == L) or (mode == ST_CONV and 2 * Lin == L and Lout == Lin)
            or (mode == ST_INV and 2 * Lout == L and Lin == L))
     NT = round64(B * L1)
-    G = (npen + B * ntile - 1) // (B * ntile)
-    bid = np.arange(G)[:, None]
+    groups = (npen + B * ntile - 1) // (B * ntile)
+    dec = 1 if (decide and mode == ST_INV) else 0
+    G = groups + dec
+    bid = np.arange(dec, G)[:, None]
     tid = np.arange(NT)[None, :]
     b, q = tid & (B - 1), tid // B
-    tile0 = xcd_tile(bid, G) * ntile
-    pens = [(tile0 + t) * B + b for t in range(ntile)]
+    tile = xcd_tile(bid, G) - dec
     bad = []
+    # every tile exactly once
+    if sorted(tile[:, 0].tolist()) != list(range(groups)):
+        bad.append("tile map")
+    tile0 = tile * ntile
+    pens = [(tile0 + t) * B + b for t in range(ntile)]
     for pen in pens:
         bad += _tile(T, mode, L, Lin, Lout, npen, per_group, group_stride, elem_stride, wsize,
                      Kx, Ly, tabsize, clamp_q, pen, q, L1, L2, pad)
@@ -131,9 +139,48 @@ def test_strided_passes_stay_in_bounds(bc):
             if args[1] not in FAST:
                 continue
             for ntile in (1, 2):
-                assert not strided_violations(T, *args, ntile=ntile, **kw), (shape, bc, tag, T)
+                for decide in ((False, True) if tag == "y inverse" else (False,)):
+                    assert not strided_violations(T, *args, ntile=ntile, decide=decide, **kw), \
+                        (shape, bc, tag, T, decide)
             checked += 1
     assert checked > 10
+
+
+def _x_pairs():
+    """Row pairs per work-group of the two-level x passes, read from the source."""
+    import os
+    import re
+    src = os.path.join(os.path.dirname(__file__), "..", "paper_1509_00680_amd", "csrc",
+                       "gps_fft_fast.hip")
+    return int(re.search(r"constexpr int kXPairs = (\d+);", open(src).read()).group(1))
+
+
+X_PAIRS = _x_pairs()
+
+
+def test_partial_sums_fit_their_arrays():
+    """One partial per wavefront: the x passes write tile * W + wave (W waves
+    per work-group) into arrays of (ny nz + 1) / 2 + 1 entries, the z pass
+    writes bid * W + wave into Ly Kx + 64 entries (the capacities of the solve
+    resources)."""
+    for shape in GRIDS:
+        nz, ny, nx = shape
+        for bc in ("free", "surface", "periodic"):
+            px, pz = bc != "free", bc == "periodic"
+            Lx, Ly, Lz = (nx if px else 2 * nx), (ny if px else 2 * ny), (nz if pz else 2 * nz)
+            Kx = Lx // 2 + 1
+            if Lx in FAST:
+                L1 = FAST[Lx][0]
+                nrows = ny * nz
+                groups = ((nrows + 1) // 2 + X_PAIRS - 1) // X_PAIRS
+                W = round64(X_PAIRS * L1) // 64
+                assert groups * W <= (nrows + 1) // 2 + 1, (shape, bc)
+            if Lz in FAST:
+                L1 = FAST[Lz][0]
+                for B in (16, 8):
+                    groups = (Ly * Kx + B - 1) // B
+                    W = round64(B * L1) // 64
+                    assert groups * W <= Ly * Kx + 64, (shape, bc, B)
 
 
 def test_unclamped_table_index_would_fault():
