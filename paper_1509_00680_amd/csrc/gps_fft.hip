@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(XParams<T> p) {
   bool upd = false;
   if constexpr (MODE == XF_SOLVE) {
     int k;
-    XHead hd;
+    XHead<> hd;
     xfwd_head_load(sl, p.n_pap_parts, hd);
     if (!xfwd_head_finish(sl, p.n_pap_parts, hd, &k, &alpha)) return;
     upd = k > 0;

@@ -25,7 +25,7 @@ namespace gps {
 template <typename T> struct FastTile;
 template <> struct FastTile<float> { static constexpr int B = 16; };
 template <> struct FastTile<double> { static constexpr int B = 8; };
-constexpr int kXPairs = 3;             // row pairs per work-group of the x passes
+constexpr int kXPairs = 6;             // row pairs per work-group of the x passes
 
 constexpr int round64(int v) { return (v + 63) / 64 * 64; }
 
@@ -116,6 +116,7 @@ void k_fstrided(SParams<T> p) {
   cplx<T> xin[MODE != ST_INV ? NTILE : 1][L1];
   cplx<T> yin[MODE == ST_INV ? NTILE : 1][L2];
   T gm[MODE == ST_CONV ? NTILE : 1][MODE == ST_CONV ? L2 : 1];
+  T gw[NTILE];                                  // z pass: half-spectrum weight of the pencil
 #pragma unroll
   for (int t = 0; t < NTILE; ++t) {
     if constexpr (MODE != ST_INV) {
@@ -149,6 +150,7 @@ void k_fstrided(SParams<T> p) {
           const int qc = q < L1 ? q : 0;
           const int ky = pc / p.Kx;
           const int kx = pc - ky * p.Kx;
+          gw[t] = T(half_bin_weight(kx, p.Lx));
           const int kyf = min(ky, p.Ly - ky);
           const unsigned row = (unsigned)sizeof(T) * (unsigned)(kyf * p.Kx + kx);
           const unsigned zs = (unsigned)sizeof(T) * (unsigned)(Lyh * p.Kx);
@@ -218,19 +220,20 @@ void k_fstrided(SParams<T> p) {
         continue;
       } else {
         if (pv[t] && q < L1) {
-          // (v, r) = sum over the full spectrum of m |w^|^2 (Parseval); this
-          // pencil's half-spectrum bin k_x stands for itself and its mirror
+          // (v, r) = sum over the full spectrum of m |w^|^2 (Parseval), taken
+          // as Re(conj(w^) m w^); this pencil's half-spectrum bin k_x stands for
+          // itself and its mirror (weight gw)
           T ws = T(0);
 #pragma unroll
           for (int k2 = 0; k2 < L2; ++k2) {
             const int kz = q + L1 * k2;
             T m = gm[t][k2];
             if (p.k0_from_slot && pen[t] == 0 && kz == 0) m = T(st->g0);
-            ws += m * (y[k2].x * y[k2].x + y[k2].y * y[k2].y);
-            y[k2] = cscale(y[k2], m);
+            const cplx<T> w = y[k2];
+            y[k2] = cscale(w, m);
+            ws += y[k2].x * w.x + y[k2].y * w.y;
           }
-          const int kx = pen[t] - (pen[t] / p.Kx) * p.Kx;
-          dacc += double(half_bin_weight(kx, p.Lx)) * double(ws);
+          dacc += double(gw[t] * ws);
         }
         __syncthreads();                        // step-2 reads of lds are done
       }
@@ -283,6 +286,14 @@ void k_fstrided(SParams<T> p) {
 // loop has a fixed trip count and all global loads of a thread are issued
 // before the first one is used.
 template <int L1> constexpr int xthreads() { return round64(kXPairs * L1); }
+
+// Work-group sum for a compile-time block of NT threads: one wavefront needs
+// no barrier.
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v) {
+  if constexpr (NT == 64) return wave_sum(v);
+  else return block_sum(v);
+}
 
 // Element idx of a buffer with a work-group-uniform base, addressed through a
 // 32-bit byte offset (the buffers of the compile-time lengths are < 4 GiB).
@@ -338,7 +349,7 @@ void k_fxfwd(XParams<T> p) {
   // operand load of this thread: the head waits only for its loads, and the
   // operands arrive while it decides.  p, Ap and phi are loaded even at k = 0
   // (unused there).
-  XHead hd;
+  XHead<NT == 64 ? 24 : 8> hd;                     // one (p, Ap) partial per x-inverse group
   if constexpr (MODE == XF_SOLVE) xfwd_head_load(sl, p.n_pap_parts, hd);
   T rv[EIN], sv[EIN], pv[EIN], av[EIN];
   double fv[EIN];
@@ -455,13 +466,12 @@ void k_fxfwd(XParams<T> p) {
       }
     }
   }
-  if constexpr (MODE == XF_SOLVE) {             // one partial per wavefront
-    const int pi = tile * (NT / 64) + (tid >> 6);
-    const double s2 = wave_sum(rr);
-    if ((tid & 63) == 0) sl.part_rr[pi] = s2;
+  if constexpr (MODE == XF_SOLVE) {             // one partial per work-group
+    const double s2 = wg_sum<NT>(rr);
+    if (tid == 0) sl.part_rr[tile] = s2;
     if (p.periodic_mean) {
-      const double s = wave_sum(mu);
-      if ((tid & 63) == 0) sl.part_mu[pi] = s;
+      const double s = wg_sum<NT>(mu);
+      if (tid == 0) sl.part_mu[tile] = s;
     }
   }
 }
@@ -610,8 +620,8 @@ void k_fxinv(XParams<T> p) {
         acc += double(pn) * double(an);
       }
     }
-    const double s1 = wave_sum(acc);            // one partial per wavefront
-    if ((tid & 63) == 0) sl.part_pap[tile * (NT / 64) + (tid >> 6)] = s1;
+    const double s1 = wg_sum<NT>(acc);          // one partial per work-group
+    if (tid == 0) sl.part_pap[tile] = s1;
   } else {
 #pragma unroll
     for (int i = 0; i < EOUT; ++i) {
@@ -644,15 +654,8 @@ bool fast_length(int L) {
 
 int fast_xpass_groups(int nrows) { return ((nrows + 1) / 2 + kXPairs - 1) / kXPairs; }
 
-// Partials of the solve-mode passes: one per wavefront.
-int fast_xpass_parts(int L, int nrows) {
-  switch (L) {
-#define GPS_CASE(LL, A, B) case LL: return fast_xpass_groups(nrows) * (xthreads<A>() / 64);
-    GPS_FAST_LENGTHS(GPS_CASE)
-#undef GPS_CASE
-    default: return 0;
-  }
-}
+// Partials of the solve-mode x passes: one per work-group.
+int fast_xpass_parts(int, int nrows) { return fast_xpass_groups(nrows); }
 
 // Tiles per work-group of the strided passes.
 constexpr int kStridedTiles = 1;

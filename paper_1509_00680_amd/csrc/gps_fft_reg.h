@@ -55,6 +55,19 @@ __device__ __forceinline__ cplx<T> croot(int e) {
   return cmk(T(c), T(INV ? s : -s));
 }
 
+// v * w_N^e for an exponent that is constant after unrolling: the quarter
+// turns (1, -1, -i, +i) become swaps and sign changes instead of a full
+// complex multiplication (whose products with 0 the compiler must keep).
+template <typename T, int N, bool INV>
+__device__ __forceinline__ cplx<T> twiddle(cplx<T> v, int e) {
+  e %= N;
+  if (e == 0) return v;
+  if (2 * e == N) return cmk(-v.x, -v.y);
+  const bool minus_i = (4 * e == N) != INV;         // w = -i (else +i) when a quarter turn
+  if (4 * e == N || 4 * e == 3 * N) return minus_i ? cmk(v.y, -v.x) : cmk(-v.y, v.x);
+  return cmul(v, croot<T, N, INV>(e));
+}
+
 // ---- small DFTs (radix butterflies) ---------------------------------------
 template <int R> struct OddRoots;
 template <> struct OddRoots<3> {
@@ -131,7 +144,7 @@ struct RegFFT<T, INV, N, Ns, R, Rest...> {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         v[r] = x[j + r * (N / R)];
-        if (r > 0 && k > 0) v[r] = cmul(v[r], croot<T, Ns * R, INV>(r * k));
+        if (r > 0 && k > 0) v[r] = twiddle<T, Ns * R, INV>(v[r], r * k);
       }
       rdft<T, INV, R>(v);
       const int base = (j / Ns) * Ns * R + k;

@@ -89,21 +89,20 @@ __device__ __forceinline__ V wg_bcast(V w) {
 }
 
 // ---- x-forward pass: the first kernel of iteration k ------------------------
-// (p, Ap) partials per thread held in registers: one per x-inverse work-group,
-// so a 64-thread x pass over 96^3 (1536 work-groups) needs 24.
-constexpr int kXHeadShare = 24;
-
+// N: (p, Ap) partials per thread held in registers (one partial per x-inverse
+// work-group; more are summed from memory).
+template <int N = 8>
 struct XHead {
   int done, k;
   double dprev0, dprev1;
-  PartShare<kXHeadShare> pap;
+  PartShare<N> pap;
 };
 
 // State words are loaded by every thread (one request per wavefront) with
 // plain loads, which wait only where used; thread 0's copy is broadcast, so
 // every work-group acts on the same value.
-template <typename T>
-__device__ __forceinline__ void xfwd_head_load(const Slot<T>& sl, int n_pap_parts, XHead& h) {
+template <typename T, int N>
+__device__ __forceinline__ void xfwd_head_load(const Slot<T>& sl, int n_pap_parts, XHead<N>& h) {
   const SolveState* v = sl.st;
   h.done = v->done;
   h.k = v->k_next;
@@ -116,9 +115,9 @@ __device__ __forceinline__ void xfwd_head_load(const Slot<T>& sl, int n_pap_part
 // iteration); for k >= 1, alpha_{k-1} = delta_{k-1} / (p_{k-1}, A p_{k-1}).
 // Returns false (whole work-group) if the solve has stopped or (p, Ap) >= 0
 // (loss of definiteness).
-template <typename T>
+template <typename T, int N>
 __device__ __forceinline__ bool xfwd_head_finish(const Slot<T>& sl, int n_pap_parts,
-                                                 const XHead& h, int* k_out,
+                                                 const XHead<N>& h, int* k_out,
                                                  double* alpha_out) {
   if (wg_bcast(h.done)) return false;
   const int k = wg_bcast(h.k);

@@ -51,6 +51,15 @@ def test_gpe_fp64_matches_oracle(bc):
     assert np.abs(got - ref.phi).max() <= 1e-8 * np.abs(ref.phi).max()
     e_ref = pcg.electrostatic_energy(prob.rho, ref.phi, prob.h)
     assert abs(info["energy"] / e_ref - 1.0) < 1e-9
+    # the GPU takes delta_k = (v_k, r_k) in the spectral domain (Parseval over the
+    # half spectrum, with the Green multipliers); the oracle takes it in real space
+    hist = p.history()
+    for k in range(3):
+        d, b, a, rr = hist[k]
+        assert abs(d / ref.history[k]["delta"] - 1) < 1e-9, (k, d, ref.history[k]["delta"])
+        if k > 0:
+            assert abs(b / ref.history[k]["beta"] - 1) < 1e-9
+        assert abs(a / ref.history[k]["alpha"] - 1) < 1e-9
 
 
 def test_sphere_fp64_parity():
