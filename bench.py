@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
+    ap.add_argument("--check-every", type=int, default=8,
+                    help="PCG iterations per replayed graph")
     ap.add_argument("--fp64-steps", type=int, default=5,
                     help="solves of the FP64 one-at-a-time comparator (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -284,7 +286,8 @@ def main():
     rho = torch.from_numpy(prob.rho).cuda()
     eps = torch.from_numpy(prob.eps).cuda()
     phi = torch.empty_like(rho)
-    plan = gps.Plan(prob.shape, prob.h, prob.bc, precision=args.precision)
+    plan = gps.Plan(prob.shape, prob.h, prob.bc, precision=args.precision,
+                    check_every=args.check_every)
 
     for _ in range(args.warmup):
         plan.solve_generalized(rho, eps, phi, args.tol)
@@ -319,7 +322,8 @@ def main():
 
     fp64 = None
     if args.fp64_steps > 0:
-        p64 = gps.Plan(prob.shape, prob.h, prob.bc, precision="fp64")
+        p64 = gps.Plan(prob.shape, prob.h, prob.bc, precision="fp64",
+                       check_every=args.check_every)
         p64.solve_generalized(rho, eps, phi, args.tol)
         w64, l64, it64 = timed_solves(torch, p64, rho, eps, phi, args.tol, args.fp64_steps)
         fp64 = {"solves_per_s": args.fp64_steps / w64,

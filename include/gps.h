@@ -72,8 +72,10 @@ typedef struct {
   int precision;     /* gps_precision, default GPS_PREC_FP64 */
   int fd_order;      /* even order of the central differences of q (2..16), default 16 */
   int maxit;         /* PCG iteration cap, default 1000 */
-  int check_every;   /* PCG iterations per replayed graph (the finest host poll
-                        granularity), default 4 */
+  int check_every;   /* PCG iterations per replayed graph, default 4; between
+                        polls of the device state the host replays this graph and,
+                        for the remainder of the predicted iteration count, a
+                        one-iteration graph */
   void *stream;      /* hipStream_t the solves run on; NULL = null stream */
 } gps_options;
 

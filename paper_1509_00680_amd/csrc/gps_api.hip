@@ -5,7 +5,7 @@
 // FP32 copies, computed on the device at plan time) and, per precision, the
 // buffers of one problem in flight.  A solve enqueues the PCG iterations on
 // the plan's stream; alpha, beta and the stop decision stay on the device,
-// and the host only polls the state every `check_every` iterations.
+// and the host polls the state after a predicted number of iterations.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -120,11 +120,20 @@ template <typename T> struct Res {
   int hist_cap = 0;
   double* lap64 = nullptr;         // periodic spectral Laplacian of sqrt(eps)
   cplx<double>* work64q = nullptr; // FP64 work for the spectral q (mixed + periodic)
-  // graph of `chunk` PCG iterations (kernel arguments are replay-invariant:
-  // the iteration counter lives in the solve state)
+  // graphs of `chunk` PCG iterations and of one iteration (kernel arguments
+  // are replay-invariant: the iteration counter lives in the solve state)
   hipGraphExec_t graph = nullptr;
+  hipGraphExec_t graph1 = nullptr;
   int graph_neutral = -1, graph_timing = -1, graph_chunk = 0;
 };
+
+template <typename T>
+void drop_graphs(Res<T>& R) {
+  if (R.graph) (void)hipGraphExecDestroy(R.graph);
+  if (R.graph1) (void)hipGraphExecDestroy(R.graph1);
+  R.graph = nullptr;
+  R.graph1 = nullptr;
+}
 
 }  // namespace
 
@@ -338,10 +347,8 @@ void ensure_res(gps_plan* pl, bool need_ion) {
     changed = true;
   }
   // the table is captured by value in graphs: rebuild them when it changes
-  if (changed || R.slot().hist_cap != R.hist_cap || R.slot().maxit != pl->opt.maxit) {
-    if (R.graph) (void)hipGraphExecDestroy(R.graph);
-    R.graph = nullptr;
-  }
+  if (changed || R.slot().hist_cap != R.hist_cap || R.slot().maxit != pl->opt.maxit)
+    drop_graphs(R);
   R.slot().hist_cap = R.hist_cap;
   R.slot().maxit = pl->opt.maxit;
 }
@@ -349,7 +356,7 @@ void ensure_res(gps_plan* pl, bool need_ion) {
 template <typename T>
 void free_res(gps_plan* pl) {
   Res<T>& R = pl->res<T>();
-  if (R.graph) (void)hipGraphExecDestroy(R.graph);
+  drop_graphs(R);
   Slot<T>& s = R.slot();
   dfree(s.r); dfree(s.p); dfree(s.ap); dfree(s.isq); dfree(s.qk); dfree(s.s);
   dfree(s.ion); dfree(s.sq64); dfree(s.work); dfree(s.part_init); dfree(s.part_rr);
@@ -561,36 +568,39 @@ void vacuum_apply(gps_plan* pl, const double* f, double* u) {
 template <typename T>
 void build_graph(gps_plan* pl, int check_neutral, int chunk) {
   Res<T>& R = pl->res<T>();
-  if (R.graph && R.graph_neutral == check_neutral && R.graph_timing == pl->timing_kind &&
-      R.graph_chunk == chunk)
+  if (R.graph && R.graph1 && R.graph_neutral == check_neutral &&
+      R.graph_timing == pl->timing_kind && R.graph_chunk == chunk)
     return;
-  if (R.graph) {
-    (void)hipGraphExecDestroy(R.graph);
-    R.graph = nullptr;
-  }
+  drop_graphs(R);
   if (!pl->cap_stream) ck(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
   Batch b{};
   b.n = 1;
   b.slot[0] = 0;
   pl->ev_pending.clear();
   std::lock_guard<std::mutex> lk(g_plan_mu);
-  ck(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-  for (int j = 0; j < chunk; ++j) enqueue_iteration<T>(pl, R.tab, b, check_neutral,
-                                                       pl->cap_stream, j);
-  hipGraph_t graph = nullptr;
-  const hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
-  if (e != hipSuccess) throw DevError{e};
-  const hipError_t e2 = hipGraphInstantiate(&R.graph, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e2 != hipSuccess) throw DevError{e2};
+  auto capture = [&](int iters, hipGraphExec_t* out) {
+    ck(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < iters; ++j)
+      enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->cap_stream, j);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (e != hipSuccess) throw DevError{e};
+    const hipError_t e2 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) throw DevError{e2};
+  };
+  capture(chunk, &R.graph);
+  capture(1, &R.graph1);
   R.graph_neutral = check_neutral;
   R.graph_timing = pl->timing_kind;
   R.graph_chunk = chunk;
 }
 
-// Run PCG iterations until the device-side state says done: replay the
-// iteration graph m times between host polls, m predicted from the recent
-// residual decay so that few replays run past convergence.
+// Run PCG iterations until the device-side state says done.  Between host
+// polls the host enqueues n iterations, n predicted from the recent residual
+// decay: n / chunk replays of the chunk graph and n % chunk of the
+// one-iteration graph, so that a solve runs few iterations past its stop
+// decision (those launches exit at once, but each still costs a dispatch).
 template <typename T>
 SolveState run_pcg(gps_plan* pl, int check_neutral) {
   Res<T>& R = pl->res<T>();
@@ -603,8 +613,8 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
   Batch b{};
   b.n = 1;
   b.slot[0] = 0;
-  int k = 0;            // iterations enqueued
-  int m = 2;            // chunks before the next poll
+  int k = 0;              // iterations enqueued
+  int n = 2 * chunk;      // iterations before the next poll
   double prev_rr = -1.0;
   int prev_it = 0;
   SolveState st{};
@@ -612,14 +622,15 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
     if (timing) {
       pl->ev_pending.clear();
       pl->ev_used = 0;
-      for (int j = 0; j < m * chunk; ++j)
+      for (int j = 0; j < n; ++j)
         enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->stream(), j);
       ck(hipGetLastError());
     } else {
-      for (int r = 0; r < m; ++r) ck(hipGraphLaunch(R.graph, pl->stream()));
+      for (int r = 0; r < n / chunk; ++r) ck(hipGraphLaunch(R.graph, pl->stream()));
+      for (int r = 0; r < n % chunk; ++r) ck(hipGraphLaunch(R.graph1, pl->stream()));
     }
     const int k_base = k;
-    k += m * chunk;
+    k += n;
     st = read_state<T>(pl);
     if (timing) {
       collect_timing(pl, pl->ev_pending, k_base, st.done ? st.iters : k);
@@ -627,12 +638,12 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
     }
     if (st.done || k > pl->opt.maxit + 1) break;
     // predicted iterations left: log-linear extrapolation of ||r||^2
-    m = 2;
+    n = 2 * chunk;
     if (prev_rr > 0.0 && st.rr > 0.0 && st.iters > prev_it && st.rr < prev_rr) {
       const double rate = std::log(st.rr / prev_rr) / double(st.iters - prev_it);
       const double left = std::log(st.thr2 / st.rr) / rate;
-      m = (int)std::ceil(std::max(1.0, left) / chunk);
-      m = std::max(1, std::min(m, 8));
+      n = (int)std::ceil(std::max(1.0, left));
+      n = std::max(1, std::min(n, 8 * chunk));
     }
     prev_rr = st.rr;
     prev_it = st.iters;
@@ -659,18 +670,22 @@ void finish_info(gps_plan* pl, const SolveState& st, const double* rho, double* 
   b.n = 1;
   launch_energy<T>(R.tab, b, rho, n, pl->stream());
   ck(hipGetLastError());
-  const double e = read_sum<T>(pl, R.slot().part_aux, vec_groups(n), 2, 0);
+  // energy partials and the iteration history come back in one host wait
+  const int groups = vec_groups(n);
+  ck(hipMemcpyAsync(R.h_parts, R.slot().part_aux, (size_t)groups * 2 * sizeof(double),
+                    hipMemcpyDeviceToHost, pl->stream()));
+  const int nh = std::min(st.iters, R.hist_cap);
+  pl->hist.assign((size_t)4 * nh, 0.0);
+  if (nh > 0)
+    ck(hipMemcpyAsync(pl->hist.data(), R.slot().hist, (size_t)4 * nh * sizeof(double),
+                      hipMemcpyDeviceToHost, pl->stream()));
+  ck(hipStreamSynchronize(pl->stream()));
+  double e = 0.0;
+  for (int i = 0; i < groups; ++i) e += R.h_parts[(size_t)i * 2];
   pl->info.energy = 0.5 * pl->g.h * pl->g.h * pl->g.h * e;
   pl->info.iterations = total_iters;
   pl->info.rnorm0 = std::sqrt(st.rr0);
   pl->info.rel_residual = st.rr0 > 0 ? std::sqrt(st.rr / st.rr0) : 0.0;
-  const int nh = std::min(st.iters, R.hist_cap);
-  pl->hist.assign((size_t)4 * nh, 0.0);
-  if (nh > 0) {
-    ck(hipMemcpyAsync(pl->hist.data(), R.slot().hist, (size_t)4 * nh * sizeof(double),
-                      hipMemcpyDeviceToHost, pl->stream()));
-    ck(hipStreamSynchronize(pl->stream()));
-  }
   pl->info.history_len = nh;
 }
 
@@ -1028,10 +1043,8 @@ gps_status gps_plan_set_timing(gps_plan* pl, int kind) {
   pl->timing_bytes = 0.0;
   pl->ev_pending.clear();
   // graphs record into pooled events: rebuild them with the new timing
-  if (pl->r32.graph) (void)hipGraphExecDestroy(pl->r32.graph);
-  if (pl->r64.graph) (void)hipGraphExecDestroy(pl->r64.graph);
-  pl->r32.graph = nullptr;
-  pl->r64.graph = nullptr;
+  drop_graphs(pl->r32);
+  drop_graphs(pl->r64);
   pl->ev_used = 0;
   return GPS_OK;
 }
