@@ -224,6 +224,8 @@ SParams<T> sparams(const gps_plan* pl, int axis, int L, int Lin, int Lout, int n
   p.lgB = ilog2(p.B);
   p.npencils = npencils;
   p.per_group = per_group;
+  p.div_group = make_fastdiv((unsigned)per_group);
+  p.div_kx = make_fastdiv((unsigned)pl->g.Kx);
   p.group_stride = group_stride;
   p.elem_stride = elem_stride;
   p.Kx = pl->g.Kx;

@@ -91,19 +91,24 @@ void k_fstrided(SParams<T> p) {
   // buffer these passes index is below 4 GiB
   constexpr unsigned CB = sizeof(cplx<T>);
   const unsigned es = CB * (unsigned)p.elem_stride;
+  // Element e of this thread's pencil sits at base + e * es.  Every element a
+  // thread touches has e = q + L1 k or e = q + L2 k (k compile-time), so its
+  // offset is qb + k * (L1 es) or qb + k * (L2 es): one per-thread product
+  // (es < 2^24 for every compile-time length) and scalar steps.
+  const unsigned s1 = (unsigned)L1 * es, s2 = (unsigned)L2 * es;
   int pen[NTILE];
   bool pv[NTILE];
-  unsigned base[NTILE];
+  unsigned base[NTILE], qb[NTILE];
 #pragma unroll
   for (int t = 0; t < NTILE; ++t) {
     pen[t] = (tile0 + t) * B + b;
     pv[t] = pen[t] < p.npencils;
     base[t] = 0;
     if (pv[t]) {
-      const int grp = pen[t] / p.per_group;
-      base[t] = CB * ((unsigned)grp * (unsigned)p.group_stride +
-                      (unsigned)(pen[t] - grp * p.per_group));
+      const unsigned grp = fast_div((unsigned)pen[t], p.div_group);
+      base[t] = CB * (grp * (unsigned)p.group_stride + ((unsigned)pen[t] - grp * (unsigned)p.per_group));
     }
+    qb[t] = base[t] + __umul24((unsigned)q, es);
   }
   // data extents: PAD bounds the input of the forward and z passes and the
   // output of the inverse and z passes
@@ -131,10 +136,11 @@ void k_fstrided(SParams<T> p) {
           } else if (PAD) {
             // no select: a lane past the last pencil (offset 0) transforms
             // real data and stores nothing
-            xin[t][n1] = at_bytes(work, base[t] + (unsigned)e * es);
+            xin[t][n1] = at_bytes(work, qb[t] + (unsigned)n1 * s2);
           } else {
-            const int ec = e < lin ? e : lin - 1;
-            const cplx<T> v = at_bytes(work, base[t] + (unsigned)ec * es);
+            // clamped to element lin - 1 (branch-free)
+            const unsigned o = e < lin ? qb[t] + (unsigned)n1 * s2 : base[t] + (unsigned)(lin - 1) * es;
+            const cplx<T> v = at_bytes(work, o);
             xin[t][n1] = (pv[t] && e < lin) ? v : cmk(T(0), T(0));
           }
         }
@@ -148,16 +154,22 @@ void k_fstrided(SParams<T> p) {
           const int Lyh = p.Ly / 2 + 1;
           const int pc = pv[t] ? pen[t] : 0;
           const int qc = q < L1 ? q : 0;
-          const int ky = pc / p.Kx;
+          const int ky = (int)fast_div((unsigned)pc, p.div_kx);
           const int kx = pc - ky * p.Kx;
           gw[t] = T(half_bin_weight(kx, p.Lx));
           const int kyf = min(ky, p.Ly - ky);
           const unsigned row = (unsigned)sizeof(T) * (unsigned)(kyf * p.Kx + kx);
           const unsigned zs = (unsigned)sizeof(T) * (unsigned)(Lyh * p.Kx);
+          // folded index min(kz, L - kz) of kz = qc + L1 k2: two arithmetic
+          // progressions in k2 and a select (zs < 2^24)
+          const unsigned up = row + __umul24((unsigned)qc, zs);
+          const unsigned down = row + __umul24((unsigned)(L - qc), zs);
+          const unsigned zstep = (unsigned)L1 * zs;
 #pragma unroll
           for (int k2 = 0; k2 < L2; ++k2) {
-            const int kz = qc + L1 * k2;
-            gm[t][k2] = at_bytes(p.table, row + (unsigned)min(kz, L - kz) * zs);
+            const unsigned o = qc <= L / 2 - L1 * k2 ? up + (unsigned)k2 * zstep
+                                                      : down - (unsigned)k2 * zstep;
+            gm[t][k2] = at_bytes(p.table, o);
           }
         }
       }
@@ -168,10 +180,11 @@ void k_fstrided(SParams<T> p) {
           const int kk = q + L1 * k2;
           if (PAD) {
             // full-length input (kk < L): no select, as above
-            yin[t][k2] = at_bytes(work, base[t] + (unsigned)kk * es);
+            yin[t][k2] = at_bytes(work, qb[t] + (unsigned)k2 * s1);
           } else {
-            const int kc = kk < lin ? kk : lin - 1;     // branch-free, as above
-            const cplx<T> v = at_bytes(work, base[t] + (unsigned)kc * es);
+            // clamped to element lin - 1 (branch-free, as above)
+            const unsigned o = kk < lin ? qb[t] + (unsigned)k2 * s1 : base[t] + (unsigned)(lin - 1) * es;
+            const cplx<T> v = at_bytes(work, o);
             yin[t][k2] = (pv[t] && kk < lin) ? v : cmk(T(0), T(0));
           }
         }
@@ -214,7 +227,7 @@ void k_fstrided(SParams<T> p) {
 #pragma unroll
           for (int k2 = 0; k2 < L2; ++k2) {
             const int kk = q + L1 * k2;
-            if (kk < lout) store_stream(&at_bytes(work, base[t] + (unsigned)kk * es), y[k2]);
+            if (kk < lout) store_stream(&at_bytes(work, qb[t] + (unsigned)k2 * s1), y[k2]);
           }
         }
         continue;
@@ -263,8 +276,8 @@ void k_fstrided(SParams<T> p) {
           const int e = q + L2 * nb;
           const bool out = PAD ? (nb < L1 / 2) : (e < lout);
           if (out) {
-            if constexpr (MODE == ST_CONV) store_stream(&at_bytes(work, base[t] + (unsigned)e * es), x[nb]);
-            else at_bytes(work, base[t] + (unsigned)e * es) = x[nb];
+            if constexpr (MODE == ST_CONV) store_stream(&at_bytes(work, qb[t] + (unsigned)nb * s2), x[nb]);
+            else at_bytes(work, qb[t] + (unsigned)nb * s2) = x[nb];
           }
         }
       }
@@ -294,6 +307,22 @@ __device__ __forceinline__ double wg_sum(double v) {
   if constexpr (NT == 64) return wave_sum(v);
   else return block_sum(v);
 }
+
+// (row, column) of the element e = tid + i NT of a row-major tile with
+// compile-time row length W, advanced in i without a division per element.
+template <int W, int NT>
+struct RowCol {
+  int row, col;
+  __device__ __forceinline__ explicit RowCol(int tid) : row(tid / W), col(tid - (tid / W) * W) {}
+  __device__ __forceinline__ void next() {
+    col += NT % W;
+    row += NT / W;
+    if (col >= W) {
+      col -= W;
+      ++row;
+    }
+  }
+};
 
 // Element idx of a buffer with a work-group-uniform base, addressed through a
 // 32-bit byte offset (the buffers of the compile-time lengths are < 4 GiB).
@@ -351,18 +380,19 @@ void k_fxfwd(XParams<T> p) {
   // (unused there).
   XHead<NT == 64 ? 24 : 8> hd;                     // one (p, Ap) partial per x-inverse group
   if constexpr (MODE == XF_SOLVE) xfwd_head_load(sl, p.n_pap_parts, hd);
+  // rows are contiguous (row stride Lin, checked by the dispatcher), so
+  // element e of the tile is at row0 * Lin + e
+  const unsigned eo = (unsigned)row0 * (unsigned)Lin;
+  const int nin = min(NIN, (p.nrows - row0) * Lin);     // tile elements that exist
   T rv[EIN], sv[EIN], pv[EIN], av[EIN];
   double fv[EIN];
 #pragma unroll
   for (int i = 0; i < EIN; ++i) {
     const int e = tid + i * NT;
-    const int row = e / Lin;
-    const int x = e - row * Lin;
-    const int grow = row0 + row;
     rv[i] = T(0);
     sv[i] = T(0);
-    if (e < NIN && grow < p.nrows) {
-      const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)x;
+    if (e < nin) {
+      const unsigned o = eo + (unsigned)e;
       if constexpr (MODE == XF_SOLVE) {
         rv[i] = GPS_AT(sl.r, o);
         sv[i] = GPS_AT(sl.isq, o);
@@ -383,17 +413,16 @@ void k_fxfwd(XParams<T> p) {
   }
   // phase 2: update, scale, stage the rows in LDS
   double mu = 0.0, rr = 0.0;
+  // LDS float index of (row, x): 2 (x PITCH + row / 2) + row % 2 = 2 PITCH x + row
+  RowCol<Lin, NT> rc(tid);
 #pragma unroll
-  for (int i = 0; i < EIN; ++i) {
+  for (int i = 0; i < EIN; ++i, rc.next()) {
     const int e = tid + i * NT;
-    const int row = e / Lin;
-    const int x = e - row * Lin;
-    const int grow = row0 + row;
     if (e < NIN) {
       T a = rv[i];
       if constexpr (MODE == XF_SOLVE) {
-        if (grow < p.nrows) {
-          const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)x;
+        if (e < nin) {
+          const unsigned o = eo + (unsigned)e;
           if (upd) {
             GPS_AT(sl.phi, o) = fv[i] + alpha * double(pv[i]);
             a = a - T(alpha) * av[i];
@@ -404,7 +433,7 @@ void k_fxfwd(XParams<T> p) {
           mu += double(a);
         }
       }
-      ldsr[2 * (x * PITCH + (row >> 1)) + (row & 1)] = a;
+      ldsr[__umul24(2 * PITCH, (unsigned)rc.col) + rc.row] = a;
     }
   }
   if constexpr (PAD) {
@@ -533,15 +562,15 @@ void k_fxinv(XParams<T> p) {
   // epilogue operands are independent of the transform: load them now too
   constexpr int EO = SOLVE ? EOUT : 1;
   T sv[EO], rv[EO], qv[EO], pv[EO], av[EO], mv[PER ? EOUT : 1];
+  // rows are contiguous (row stride Lout, checked by the dispatcher)
+  const unsigned eo = (unsigned)row0 * (unsigned)Lout;
+  const int nout = min(NOUT, (p.nrows - row0) * Lout);  // tile elements that exist
   if constexpr (SOLVE) {
 #pragma unroll
     for (int i = 0; i < EOUT; ++i) {
       const int e = tid + i * NT;
-      const int row = e / Lout;
-      const int xx = e - row * Lout;
-      const int grow = row0 + row;
-      if (e < NOUT && grow < p.nrows) {
-        const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)xx;
+      if (e < nout) {
+        const unsigned o = eo + (unsigned)e;
         sv[i] = GPS_AT(sl.isq, o);
         rv[i] = GPS_AT(sl.r, o);
         qv[i] = GPS_AT(sl.qk, o);
@@ -604,15 +633,13 @@ void k_fxinv(XParams<T> p) {
   __syncthreads();
   if constexpr (SOLVE) {
     double acc = 0.0;
+    RowCol<Lout, NT> rc(tid);
 #pragma unroll
-    for (int i = 0; i < EOUT; ++i) {
+    for (int i = 0; i < EOUT; ++i, rc.next()) {
       const int e = tid + i * NT;
-      const int row = e / Lout;
-      const int xx = e - row * Lout;
-      const int grow = row0 + row;
-      if (e < NOUT && grow < p.nrows) {
-        const unsigned o = (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)xx;
-        const T v = ldsr[2 * (xx * PITCH + (row >> 1)) + (row & 1)] * sv[i];
+      if (e < nout) {
+        const unsigned o = eo + (unsigned)e;
+        const T v = ldsr[__umul24(2 * PITCH, (unsigned)rc.col) + rc.row] * sv[i];
         T pn = pv[i], an = av[i];
         direction_update(v, rv[i], qv[i], PER ? mv[i] : T(0), pn, an, dir);
         GPS_AT(sl.p, o) = pn;
@@ -623,15 +650,11 @@ void k_fxinv(XParams<T> p) {
     const double s1 = wg_sum<NT>(acc);          // one partial per work-group
     if (tid == 0) sl.part_pap[tile] = s1;
   } else {
+    RowCol<Lout, NT> rc(tid);
 #pragma unroll
-    for (int i = 0; i < EOUT; ++i) {
+    for (int i = 0; i < EOUT; ++i, rc.next()) {
       const int e = tid + i * NT;
-      const int row = e / Lout;
-      const int xx = e - row * Lout;
-      const int grow = row0 + row;
-      if (e < NOUT && grow < p.nrows)
-        GPS_AT(p.out_real, (unsigned)grow * (unsigned)p.in_row_stride + (unsigned)xx) =
-            double(ldsr[2 * (xx * PITCH + (row >> 1)) + (row & 1)]);
+      if (e < nout) GPS_AT(p.out_real, eo + (unsigned)e) = double(ldsr[__umul24(2 * PITCH, (unsigned)rc.col) + rc.row]);
     }
   }
 }
@@ -715,6 +738,7 @@ bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s) {
   if (mode != XF_SOLVE && mode != XF_REAL) return false;
   const bool pad = 2 * p.Lin == p.g.Lx;
   if (!pad && p.Lin != p.g.Lx) return false;
+  if (p.in_row_stride != p.Lin) return false;        // the kernels assume contiguous rows
   const dim3 grid(fast_xpass_groups(p.nrows), p.has_slots ? p.batch.n : 1);
   switch (p.g.Lx) {
 #define GPS_CASE(LL, A, BB)                                                                      \
@@ -739,6 +763,7 @@ template <typename T>
 bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s) {
   const bool pad = 2 * p.Lout == p.g.Lx;
   if (!pad && p.Lout != p.g.Lx) return false;
+  if (p.in_row_stride != p.Lout) return false;       // the kernels assume contiguous rows
   const dim3 grid(fast_xpass_groups(p.nrows), p.has_slots ? p.batch.n : 1);
   switch (p.g.Lx) {
 #define GPS_CASE(LL, A, BB)                                                                      \

@@ -34,6 +34,25 @@ __host__ __device__ inline int qfield_groups(long long n) {
   return (int)((n + kThreads - 1) / kThreads);
 }
 
+// Division of a non-negative n < 2^31 by a divisor d >= 1 fixed at launch:
+// q = (mulhi(n, m) + n) >> s with s = ceil(log2 d) and
+// m = floor(2^32 (2^s - d) / d) + 1 (Granlund and Montgomery's round-up
+// method; mulhi(n, m) <= n, so the sum fits 32 bits).  Replaces the ~15
+// instructions of a runtime integer division in per-thread index math.
+struct FastDiv {
+  unsigned m;
+  int s;
+};
+inline FastDiv make_fastdiv(unsigned d) {
+  int s = 0;
+  while ((1ull << s) < d) ++s;
+  const unsigned long long m = (((1ull << s) - d) << 32) / d + 1;
+  return FastDiv{(unsigned)m, s};
+}
+__device__ __forceinline__ unsigned fast_div(unsigned n, FastDiv f) {
+  return (__umulhi(n, f.m) + n) >> f.s;
+}
+
 constexpr int kMaxStages = 16;
 constexpr int kMaxLen = 1024;        // longest supported FFT length
 

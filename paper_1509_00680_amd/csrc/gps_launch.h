@@ -81,6 +81,8 @@ template <typename T> struct SParams {
   int B, lgB;
   int npencils;
   int per_group;
+  FastDiv div_group;        // per_group and Kx as fast divisors (set by the launchers)
+  FastDiv div_kx;
   long long group_stride;
   long long elem_stride;
   // ST_CONV: multiply by a real, even table folded to (Lz/2+1)(Ly/2+1)Kx

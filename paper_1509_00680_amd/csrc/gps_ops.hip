@@ -233,13 +233,125 @@ void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho, con
 // ---------------------------------------------------------------------------
 struct FdWeights { double c[9]; };
 
-// One point per thread (the 6M neighbour loads of a point are many latencies
-// deep, so the latency is hidden by many resident wavefronts rather than by
-// looping); work-groups are mapped XCD-contiguously, so each XCD's L2 holds
-// one z-slab and its +-M halo planes.  One kappa2/eps partial per work-group.
+// Ghost index on an axis of n points: wrapped (periodic) or edge-replicated.
+__device__ __forceinline__ int ghost_index(int i, int n, int periodic) {
+  if (periodic) {
+    i %= n;
+    return i < 0 ? i + n : i;
+  }
+  return min(max(i, 0), n - 1);
+}
+
+// Stencil form (free and surface boundaries), 2.5D: a work-group owns a
+// kQTX x kQTY column tile and marches along z over kQZC planes.  The x and y
+// neighbours of a plane come from an LDS tile with an M-wide halo (no
+// corners), the z neighbours from a register queue of 2M+1 planes per
+// thread, so a point costs about (2M + kQZC)/kQZC + 1.5 global loads instead
+// of 6M + 1.  The next plane's halo and queue entry are loaded while the
+// current plane is differenced.
+constexpr int kQTX = 32, kQTY = 16, kQZC = 4;
+constexpr int kQThreads = kQTX * kQTY;
+
 template <typename T, int M>
+__global__ __launch_bounds__(kQThreads) void k_qstencil(SlotTable<T> tab, Batch b, Geom g,
+                                                        FdWeights w, int ntx, int nty,
+                                                        double kappa_coef,
+                                                        const double* __restrict__ eps,
+                                                        const double* __restrict__ gamma,
+                                                        double eps_bulk) {
+  constexpr int TW = kQTX + 2 * M;                 // LDS tile width (x) and height (y)
+  constexpr int TH = kQTY + 2 * M;
+  constexpr int NXH = 2 * M * kQTY;                // halo slots left and right of the tile
+  constexpr int NH = NXH + 2 * M * kQTX;           // ... plus above and below
+  constexpr int HS = (NH + kQThreads - 1) / kQThreads;
+  __shared__ double tile[TH * TW];
+  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
+  const double* __restrict__ sq = sl.sq64;
+  const int tid = threadIdx.x;
+  const int tx = tid % kQTX, ty = tid / kQTX;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);   // x fastest, then y, then z chunk
+  const int ntxy = ntx * nty;
+  const int zc = t / ntxy;
+  const int yt = (t - zc * ntxy) / ntx;
+  const int xt = t - zc * ntxy - yt * ntx;
+  const int x0 = xt * kQTX, y0 = yt * kQTY, z0 = zc * kQZC;
+  const int z1 = min(z0 + kQZC, g.nz);
+  const int X = x0 + tx, Y = y0 + ty;
+  const int plane = g.nx * g.ny;
+  const int cxy = ghost_index(Y, g.ny, g.periodic_y) * g.nx + ghost_index(X, g.nx, g.periodic_x);
+  // this thread's halo slots: LDS position and in-plane source offset
+  int hl[HS], ho[HS];
+#pragma unroll
+  for (int s = 0; s < HS; ++s) {
+    const int j = min(tid + s * kQThreads, NH - 1);   // surplus threads repeat the last slot
+    int hx, hy;
+    if (j < NXH) {
+      const int row = j / (2 * M), c = j - (j / (2 * M)) * (2 * M);
+      hx = c < M ? c : c + kQTX;
+      hy = M + row;
+    } else {
+      const int jj = j - NXH;
+      const int row = jj / kQTX, c = jj - (jj / kQTX) * kQTX;
+      hx = M + c;
+      hy = row < M ? row : row + kQTY;
+    }
+    hl[s] = hy * TW + hx;
+    ho[s] = ghost_index(y0 - M + hy, g.ny, g.periodic_y) * g.nx +
+            ghost_index(x0 - M + hx, g.nx, g.periodic_x);
+  }
+  // queue: qv[k] holds plane z - M + k of this thread's column
+  double qv[2 * M + 1];
+#pragma unroll
+  for (int k = 0; k <= 2 * M; ++k)
+    qv[k] = sq[(size_t)ghost_index(z0 - M + k, g.nz, g.periodic_z) * plane + cxy];
+  double hv[HS];
+#pragma unroll
+  for (int s = 0; s < HS; ++s) hv[s] = sq[(size_t)z0 * plane + ho[s]];
+  const double ih2 = 1.0 / (g.h * g.h);
+  const bool out = X < g.nx && Y < g.ny;
+  for (int z = z0; z < z1; ++z) {
+    tile[(M + ty) * TW + M + tx] = qv[M];
+#pragma unroll
+    for (int s = 0; s < HS; ++s) tile[hl[s]] = hv[s];
+    __syncthreads();
+    // next plane's halo and queue entry, in flight while this plane is differenced
+    const int zn = min(z + 1, g.nz - 1);
+    double hn[HS];
+#pragma unroll
+    for (int s = 0; s < HS; ++s) hn[s] = sq[(size_t)zn * plane + ho[s]];
+    const double qn = sq[(size_t)ghost_index(z + 1 + M, g.nz, g.periodic_z) * plane + cxy];
+    double gv = 0.0;
+    if (kappa_coef != 0.0 && out) {
+      const size_t i = (size_t)z * plane + (size_t)Y * g.nx + X;
+      gv = gamma ? gamma[i] : (eps[i] - 1.0) / (eps_bulk - 1.0);
+    }
+    const double* c = &tile[(M + ty) * TW + M + tx];
+    // the rounding order is fixed: the centre product, then one fused
+    // multiply-add per distance m over (x pair + y pair) + z pair
+    double acc = __dmul_rn(3.0 * w.c[0], qv[M]);
+#pragma unroll
+    for (int m = 1; m <= M; ++m)
+      acc = fma(w.c[m], ((c[m] + c[-m]) + (c[m * TW] + c[-m * TW])) + (qv[M + m] + qv[M - m]), acc);
+    if (out) {
+      const double lap = acc * ih2;
+      double q = qv[M] * lap;
+      if (kappa_coef != 0.0) q = __dadd_rn(q, __dmul_rn(kappa_coef, gv));
+      sl.qk[(size_t)z * plane + (size_t)Y * g.nx + X] = T(q);
+    }
+    __syncthreads();                              // tile reads done before the next writes
+#pragma unroll
+    for (int k = 0; k < 2 * M; ++k) qv[k] = qv[k + 1];
+    qv[2 * M] = qn;
+#pragma unroll
+    for (int s = 0; s < HS; ++s) hv[s] = hn[s];
+  }
+}
+
+// Spectral form (periodic): q = sqrt(eps) * lap_sq pointwise, one point per
+// thread.  One kappa2/eps partial per work-group (the periodic k = 0
+// multiplier).
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, Geom g,
-                                                     FdWeights w,
                                                      const double* __restrict__ lap_sq,
                                                      double kappa_coef,
                                                      const double* __restrict__ eps,
@@ -247,51 +359,10 @@ __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, 
                                                      double eps_bulk) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
   const int n = g.nx * g.ny * g.nz;
-  const int plane = g.nx * g.ny;
   const int i = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
-  const double* __restrict__ sq = sl.sq64;
-  const double ih2 = 1.0 / (g.h * g.h);
   double kacc = 0.0;   // sum kappa2 / eps (periodic k = 0 multiplier)
   if (i < n) {
-    const int x = i % g.nx;
-    const int y = (i / g.nx) % g.ny;
-    const int z = i / plane;
-    const double sc = sq[i];
-    double lap;
-    if (lap_sq) {
-      lap = lap_sq[i];
-    } else {
-      double acc = 3.0 * w.c[0] * sc;
-      if (x >= M && x < g.nx - M && y >= M && y < g.ny - M && z >= M && z < g.nz - M) {
-        // interior: no ghost handling
-        const int sy = g.nx;
-#pragma unroll
-        for (int m = 1; m <= M; ++m) {
-          const double sxx = sq[i + m] + sq[i - m];
-          const double syy = sq[i + m * sy] + sq[i - m * sy];
-          const double szz = sq[i + m * plane] + sq[i - m * plane];
-          acc += w.c[m] * (sxx + syy + szz);
-        }
-      } else {
-        const int zo = z * plane, yo = y * g.nx;
-#pragma unroll
-        for (int m = 1; m <= M; ++m) {
-          int xp = x + m, xm = x - m, yp = y + m, ym = y - m, zp = z + m, zm = z - m;
-          if (g.periodic_x) { xp %= g.nx; xm = ((xm % g.nx) + g.nx) % g.nx; }
-          else { xp = min(xp, g.nx - 1); xm = max(xm, 0); }
-          if (g.periodic_y) { yp %= g.ny; ym = ((ym % g.ny) + g.ny) % g.ny; }
-          else { yp = min(yp, g.ny - 1); ym = max(ym, 0); }
-          if (g.periodic_z) { zp %= g.nz; zm = ((zm % g.nz) + g.nz) % g.nz; }
-          else { zp = min(zp, g.nz - 1); zm = max(zm, 0); }
-          const double sxx = sq[zo + yo + xp] + sq[zo + yo + xm];
-          const double syy = sq[zo + yp * g.nx + x] + sq[zo + ym * g.nx + x];
-          const double szz = sq[zp * plane + yo + x] + sq[zm * plane + yo + x];
-          acc += w.c[m] * (sxx + syy + szz);
-        }
-      }
-      lap = acc * ih2;
-    }
-    double qv = sc * lap;
+    double qv = sl.sq64[i] * lap_sq[i];
     if (kappa_coef != 0.0) {
       const double gm = gamma ? gamma[i] : (eps[i] - 1.0) / (eps_bulk - 1.0);
       const double k2 = kappa_coef * gm;
@@ -326,11 +397,18 @@ void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g, int f
                    const double* lap_sq, double kappa_coef, const double* eps,
                    const double* gamma, double eps_bulk, hipStream_t s) {
   const long long n = (long long)g.nx * g.ny * g.nz;
-  const dim3 grid(qfield_groups(n), b.n);
+  if (lap_sq) {
+    GPS_LAUNCH((k_qfield<T>), dim3(qfield_groups(n), b.n), dim3(kThreads), 0, s, tab, b, g,
+               lap_sq, kappa_coef, eps, gamma, eps_bulk);
+    return;
+  }
+  const int ntx = (g.nx + kQTX - 1) / kQTX, nty = (g.ny + kQTY - 1) / kQTY;
+  const int nzc = (g.nz + kQZC - 1) / kQZC;
+  const dim3 grid(ntx * nty * nzc, b.n);
   const FdWeights w = fd_weights(fd_half);
 #define GPS_QF(MM)                                                                        \
   case MM:                                                                                \
-    GPS_LAUNCH((k_qfield<T, MM>), grid, dim3(kThreads), 0, s, tab, b, g, w, lap_sq,       \
+    GPS_LAUNCH((k_qstencil<T, MM>), grid, dim3(kQThreads), 0, s, tab, b, g, w, ntx, nty,  \
                kappa_coef, eps, gamma, eps_bulk);                                         \
     break;
   switch (fd_half) {

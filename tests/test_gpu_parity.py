@@ -62,6 +62,20 @@ def test_gpe_fp64_matches_oracle(bc):
         assert abs(a / ref.history[k]["alpha"] - 1) < 1e-9
 
 
+@pytest.mark.parametrize("bc,order,n", [("free", 2, 20), ("surface", 6, 24), ("free", 12, 18)])
+def test_fd_orders_fp64_match_oracle(bc, order, n):
+    # the q stencil at other orders than 16, on grids that leave partial tiles
+    require_gpu()
+    prob = W.molecule(n, 0.5, seed=9, n_atoms=5, ball=2.0, bc=bc)
+    ref = pcg.pcg_solve(prob.rho, prob.eps, prob.h, bc, tol=1e-10, fd_order=order)
+    p = gps.Plan(prob.shape, prob.h, bc, precision="fp64", fd_order=order)
+    phi = empty(prob.shape)
+    print("fd order", bc, order, n, flush=True)
+    assert p.solve_generalized(dev(prob.rho), dev(prob.eps), phi, 1e-10) == gps.GPS_OK
+    assert abs(p.info()["iterations"] - ref.iterations) <= 1
+    assert np.abs(host(phi) - ref.phi).max() <= 1e-8 * np.abs(ref.phi).max()
+
+
 def test_sphere_fp64_parity():
     # one Gaussian in a spherical erf cavity, free BC, 48^3, h = 0.35, tol 1e-8
     require_gpu()

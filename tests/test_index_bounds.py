@@ -190,3 +190,119 @@ def test_unclamped_table_index_would_fault():
     args = (ST_CONV, Lz, nz, nz, Ly * Kx, Ly * Kx, 0, Ly * Kx, nz * Ly * Kx)
     assert strided_violations("d", *args, Kx=Kx, Ly=Ly, tabsize=tab, clamp_q=False) == ["table"]
     assert not strided_violations("d", *args, Kx=Kx, Ly=Ly, tabsize=tab)
+
+
+def test_fast_division_matches_integer_division():
+    """The strided passes divide pencil indices by per_group and Kx with the
+    round-up multiply-shift of gps_internal.h (make_fastdiv / fast_div):
+    s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1, q = (mulhi(n, m) + n) >> s.
+    Checked against n // d for every divisor the passes use on the test grids
+    and a spread of others, over indices past any grid's pencil count."""
+    rng = np.random.default_rng(0)
+    divisors = set(range(1, 1025)) | {2 ** k for k in range(31)} | {2 ** k - 1 for k in range(1, 31)}
+    divisors |= {int(x) for x in rng.integers(1, 2 ** 31, 2000)}
+    for shape in GRIDS:
+        nz, ny, nx = shape
+        for L in (nx, 2 * nx):
+            Kx = L // 2 + 1
+            divisors |= {Kx, Kx * ny, Kx * 2 * ny}
+    ns = np.concatenate([np.arange(0, 70000, dtype=np.uint64),
+                         rng.integers(0, 2 ** 31, 20000).astype(np.uint64),
+                         np.array([2 ** 31 - 1, 2 ** 24, 2 ** 24 - 1], dtype=np.uint64)])
+    for d in sorted(divisors):
+        s = 0
+        while (1 << s) < d:
+            s += 1
+        m = (((1 << s) - d) << 32) // d + 1
+        assert 0 < m < 2 ** 32 or d == 1 and m == 1
+        hi = (ns * np.uint64(m)) >> np.uint64(32)
+        assert np.all((hi + ns) < 2 ** 32)
+        q = (hi + ns) >> np.uint64(s)
+        assert np.array_equal(q, ns // np.uint64(d)), d
+
+
+# ---- the 2.5D stencil kernel of q (k_qstencil in gps_ops.hip) -------------------------
+QTX, QTY, QZC, QTHREADS = 32, 16, 4, 512
+
+
+def _ghost(i, n, periodic):
+    return np.mod(i, n) if periodic else np.clip(i, 0, n - 1)
+
+
+def qstencil_replay(sq, h, M, per, weights):
+    """Every work-group and thread of k_qstencil, restated on the CPU: tile
+    decomposition, ghosted halo slots, LDS tile, register queue.  Returns q
+    without the kappa term and asserts every access in bounds."""
+    nz, ny, nx = sq.shape
+    px, py, pz = per
+    flat = sq.ravel()
+    plane = nx * ny
+    TW, TH = QTX + 2 * M, QTY + 2 * M
+    NXH = 2 * M * QTY
+    NH = NXH + 2 * M * QTX
+    HS = (NH + QTHREADS - 1) // QTHREADS
+    ntx, nty, nzc = -(-nx // QTX), -(-ny // QTY), -(-nz // QZC)
+    q = np.full(sq.shape, np.nan)
+    tid = np.arange(QTHREADS)
+    tx, ty = tid % QTX, tid // QTX
+    for t in range(ntx * nty * nzc):
+        zc, r = divmod(t, ntx * nty)
+        yt, xt = divmod(r, ntx)
+        x0, y0, z0 = xt * QTX, yt * QTY, zc * QZC
+        z1 = min(z0 + QZC, nz)
+        X, Y = x0 + tx, y0 + ty
+        cxy = _ghost(Y, ny, py) * nx + _ghost(X, nx, px)
+        assert cxy.min() >= 0 and cxy.max() < plane
+        hl, ho = [], []
+        for s in range(HS):
+            j = np.minimum(tid + s * QTHREADS, NH - 1)
+            xh = j < NXH
+            row_x, c_x = j // (2 * M), j % (2 * M)
+            jj = j - NXH
+            row_y, c_y = jj // QTX, jj % QTX
+            hx = np.where(xh, np.where(c_x < M, c_x, c_x + QTX), M + c_y)
+            hy = np.where(xh, M + row_x, np.where(row_y < M, row_y, row_y + QTY))
+            hl.append(hy * TW + hx)
+            ho.append(_ghost(y0 - M + hy, ny, py) * nx + _ghost(x0 - M + hx, nx, px))
+            assert hl[-1].min() >= 0 and hl[-1].max() < TH * TW
+            assert ho[-1].min() >= 0 and ho[-1].max() < plane
+        qv = [flat[_ghost(z0 - M + k, nz, pz) * plane + cxy] for k in range(2 * M + 1)]
+        hv = [flat[z0 * plane + o] for o in ho]
+        out = (X < nx) & (Y < ny)
+        for z in range(z0, z1):
+            tile = np.full(TH * TW, np.nan)
+            tile[(M + ty) * TW + M + tx] = qv[M]
+            for s in range(HS):
+                tile[hl[s]] = hv[s]
+            zn = min(z + 1, nz - 1)
+            hn = [flat[zn * plane + o] for o in ho]
+            qn = flat[_ghost(z + 1 + M, nz, pz) * plane + cxy]
+            c = (M + ty) * TW + M + tx
+            acc = 3.0 * weights[0] * qv[M]
+            for m in range(1, M + 1):
+                for k in (c + m, c - m, c + m * TW, c - m * TW):
+                    assert k.min() >= 0 and k.max() < TH * TW
+                acc = acc + weights[m] * ((tile[c + m] + tile[c - m]) +
+                                          (tile[c + m * TW] + tile[c - m * TW]) +
+                                          (qv[M + m] + qv[M - m]))
+            q[z, Y[out], X[out]] = (qv[M] * acc / (h * h))[out]
+            qv = qv[1:] + [qn]
+            hv = hn
+    assert not np.isnan(q).any()
+    return q
+
+
+@pytest.mark.parametrize("shape,bc,order", [((13, 17, 20), "free", 16), ((13, 17, 20), "surface", 16),
+                                            ((9, 40, 35), "free", 6), ((21, 18, 33), "surface", 2),
+                                            ((5, 6, 7), "free", 16)])
+def test_qstencil_replay_matches_oracle(shape, bc, order):
+    from oracle import stencil
+    rng = np.random.default_rng(3)
+    eps = 1.0 + 77.0 * rng.random(shape)
+    h = 0.3
+    per = (bc != "free", bc != "free", False)
+    M = order // 2
+    w = stencil.fd_second_derivative_weights(M)
+    got = qstencil_replay(np.sqrt(eps), h, M, per, w)
+    ref = stencil.q_field(eps, h, bc, order)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
