@@ -74,8 +74,8 @@ typedef struct {
   int maxit;         /* PCG iteration cap, default 1000 */
   int check_every;   /* PCG iterations per replayed graph, default 4; between
                         polls of the device state the host replays this graph and,
-                        for the remainder of the predicted iteration count, a
-                        one-iteration graph */
+                        for the remainder of the predicted iteration count,
+                        4-iteration and one-iteration graphs */
   void *stream;      /* hipStream_t the solves run on; NULL = null stream */
 } gps_options;
 

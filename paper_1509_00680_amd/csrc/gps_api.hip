@@ -120,19 +120,20 @@ template <typename T> struct Res {
   int hist_cap = 0;
   double* lap64 = nullptr;         // periodic spectral Laplacian of sqrt(eps)
   cplx<double>* work64q = nullptr; // FP64 work for the spectral q (mixed + periodic)
-  // graphs of `chunk` PCG iterations and of one iteration (kernel arguments
-  // are replay-invariant: the iteration counter lives in the solve state)
+  // graphs of `chunk`, 4 and 1 PCG iterations (kernel arguments are
+  // replay-invariant: the iteration counter lives in the solve state)
   hipGraphExec_t graph = nullptr;
+  hipGraphExec_t graph4 = nullptr;
   hipGraphExec_t graph1 = nullptr;
   int graph_neutral = -1, graph_timing = -1, graph_chunk = 0;
 };
 
 template <typename T>
 void drop_graphs(Res<T>& R) {
-  if (R.graph) (void)hipGraphExecDestroy(R.graph);
-  if (R.graph1) (void)hipGraphExecDestroy(R.graph1);
-  R.graph = nullptr;
-  R.graph1 = nullptr;
+  for (hipGraphExec_t* g : {&R.graph, &R.graph4, &R.graph1}) {
+    if (*g) (void)hipGraphExecDestroy(*g);
+    *g = nullptr;
+  }
 }
 
 }  // namespace
@@ -570,7 +571,7 @@ void vacuum_apply(gps_plan* pl, const double* f, double* u) {
 template <typename T>
 void build_graph(gps_plan* pl, int check_neutral, int chunk) {
   Res<T>& R = pl->res<T>();
-  if (R.graph && R.graph1 && R.graph_neutral == check_neutral &&
+  if (R.graph && R.graph4 && R.graph1 && R.graph_neutral == check_neutral &&
       R.graph_timing == pl->timing_kind && R.graph_chunk == chunk)
     return;
   drop_graphs(R);
@@ -592,6 +593,7 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk) {
     if (e2 != hipSuccess) throw DevError{e2};
   };
   capture(chunk, &R.graph);
+  capture(4, &R.graph4);
   capture(1, &R.graph1);
   R.graph_neutral = check_neutral;
   R.graph_timing = pl->timing_kind;
@@ -600,9 +602,9 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk) {
 
 // Run PCG iterations until the device-side state says done.  Between host
 // polls the host enqueues n iterations, n predicted from the recent residual
-// decay: n / chunk replays of the chunk graph and n % chunk of the
-// one-iteration graph, so that a solve runs few iterations past its stop
-// decision (those launches exit at once, but each still costs a dispatch).
+// decay, as replays of the chunk, 4-iteration and 1-iteration graphs, so that
+// a solve runs few iterations past its stop decision (those launches exit at
+// once, but each still costs a dispatch) with few graph launches.
 template <typename T>
 SolveState run_pcg(gps_plan* pl, int check_neutral) {
   Res<T>& R = pl->res<T>();
@@ -628,8 +630,11 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
         enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->stream(), j);
       ck(hipGetLastError());
     } else {
-      for (int r = 0; r < n / chunk; ++r) ck(hipGraphLaunch(R.graph, pl->stream()));
-      for (int r = 0; r < n % chunk; ++r) ck(hipGraphLaunch(R.graph1, pl->stream()));
+      // greedy: chunk graphs, then 4-iteration graphs, then single iterations
+      int left = n;
+      for (; left >= chunk; left -= chunk) ck(hipGraphLaunch(R.graph, pl->stream()));
+      for (; left >= 4; left -= 4) ck(hipGraphLaunch(R.graph4, pl->stream()));
+      for (; left > 0; --left) ck(hipGraphLaunch(R.graph1, pl->stream()));
     }
     const int k_base = k;
     k += n;
