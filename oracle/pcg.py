@@ -86,8 +86,21 @@ def periodic_k0_value(eps, kappa2):
 
 def pcg_solve(rho, eps, h, bc, *, tol=None, abs_threshold=None, kappa2=None,
               solver=None, fd_order=16, maxit=1000, fields=None,
-              surface_k0_offset=None):
-    """Solve -div(eps grad phi) + kappa2 phi = 4 pi rho (A phi = -4 pi rho)."""
+              surface_k0_offset=None, refine_every=None, refine_log=None):
+    """Solve -div(eps grad phi) + kappa2 phi = 4 pi rho (A phi = -4 pi rho).
+
+    refine_every = m (free and surface boundaries): true-residual refinement.
+    Every direction is the preconditioner image of a source,
+        p_k = S^-1 G sigma_k,   sigma_k = S^-1 r_k + beta_k sigma_{k-1},
+    so the iterate keeps the representation sqrt(eps) phi = G s with
+    s = sum_k alpha_k sigma_k.  Every m iterations phi is recomputed as
+    S^-1 G s and the residual from its definition b - A phi, which with
+    A = S L_G S - diag(q + kappa2), L_G G = -4 pi I and b = -4 pi rho is
+        r = -4 pi rho + 4 pi sqrt(eps) s + (q + kappa2) phi ;
+    PCG then restarts from that residual with beta = 0.  On exit phi is
+    recomputed from s.  refine_log (a list) receives, at each refinement,
+    the recursive residual, the recomputed one, the accumulated phi and s.
+    """
     rho = np.asarray(rho, dtype=np.float64)
     shape = rho.shape
     if solver is None:
@@ -112,6 +125,11 @@ def pcg_solve(rho, eps, h, bc, *, tol=None, abs_threshold=None, kappa2=None,
     status = STATUS_NOT_CONVERGED
     k = 0
     rnorm = rnorm0
+    refine = refine_every is not None and refine_every > 0
+    if refine and periodic:
+        raise ValueError("refinement needs an invertible vacuum solver (free or surface)")
+    sig = np.zeros(shape)
+    src = np.zeros(shape)
     while True:
         if not np.isfinite(rnorm):
             status = STATUS_NONFINITE
@@ -130,6 +148,8 @@ def pcg_solve(rho, eps, h, bc, *, tol=None, abs_threshold=None, kappa2=None,
             break
         beta = 0.0 if delta_prev is None else delta / delta_prev
         p = v + beta * p
+        if refine:
+            sig = isq * r + beta * sig
         # operator on v without derivatives, Eq. corr / Eq. corrPB
         if periodic:
             mu = float(np.mean(isq * r))
@@ -144,11 +164,24 @@ def pcg_solve(rho, eps, h, bc, *, tol=None, abs_threshold=None, kappa2=None,
         alpha = delta / pap
         phi = phi + alpha * p
         r = r - alpha * ap
+        if refine:
+            src = src + alpha * sig
         delta_prev = delta
         k += 1
+        if refine and k % refine_every == 0:
+            phi_s = isq * solver.apply(src)
+            r_true = -FOUR_PI * rho + FOUR_PI * s * src + qk * phi_s
+            if refine_log is not None:
+                refine_log.append({"k": k, "r": r, "r_true": r_true, "phi": phi, "src": src})
+            phi, r = phi_s, r_true
+            delta_prev = None                  # restart: beta = 0 next
+            p = np.zeros(shape)
+            ap = np.zeros(shape)
         rnorm = float(np.sqrt(np.sum(r * r)))
         history.append({"delta": delta, "beta": beta, "pAp": pap, "alpha": alpha,
                         "rnorm": rnorm})
+    if refine:
+        phi = isq * solver.apply(src)
     return PCGResult(phi, r, k, status, history, rnorm0)
 
 

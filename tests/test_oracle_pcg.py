@@ -162,3 +162,45 @@ def test_manufactured_solution_second_order():
         errs.append(np.abs(res.phi - phi).max() / np.abs(phi).max())
     assert errs[1] < 2e-2
     assert errs[0] / errs[1] > 3.0
+
+
+# ---- true-residual refinement (sqrt(eps) phi = G s, restart from b - A phi) ----------
+
+@pytest.mark.parametrize("bc", ("free", "surface"))
+@pytest.mark.parametrize("ions", [None, "accessibility"])
+def test_refined_pcg_equals_dense_direct_solve(bc, ions):
+    p = _small_problem(bc)
+    kappa2 = None if ions is None else 0.8 * (p.eps - 1.0) / (W.EPS_WATER - 1.0)
+    phi_d = dense.dense_solve(p.rho, p.eps, p.h, bc, kappa2=kappa2)
+    res = pcg.pcg_solve(p.rho, p.eps, p.h, bc, tol=1e-14, kappa2=kappa2, refine_every=3)
+    assert res.converged
+    assert np.abs(res.phi - phi_d).max() < 1e-12 * np.abs(phi_d).max()
+
+
+@pytest.mark.parametrize("bc", ("free", "surface"))
+def test_refinement_representation_and_true_residual(bc):
+    # At every refinement point, before the restart: the accumulated iterate
+    # equals the source representation S^-1 G s, and the residual recomputed
+    # from its definition equals the recursively updated one (both FP64, so
+    # they differ only by rounding).  A wrong term or sign in either formula
+    # would show up as an O(1) mismatch.
+    p = _small_problem(bc, 12, 0.5)
+    solver = green.VacuumSolver(p.shape, p.h, bc)
+    log = []
+    res = pcg.pcg_solve(p.rho, p.eps, p.h, bc, tol=1e-12, solver=solver, refine_every=4,
+                        refine_log=log)
+    assert res.converged and len(log) >= 2
+    r0 = 4 * math.pi * np.sqrt(np.sum(p.rho ** 2))
+    isq = 1.0 / np.sqrt(p.eps)
+    for e in log:
+        assert np.abs(e["r_true"] - e["r"]).max() < 1e-10 * r0, e["k"]
+        rep = isq * solver.apply(e["src"])
+        assert np.abs(rep - e["phi"]).max() < 1e-10 * np.abs(e["phi"]).max(), e["k"]
+    plain = pcg.pcg_solve(p.rho, p.eps, p.h, bc, tol=1e-12, solver=solver)
+    assert np.abs(res.phi - plain.phi).max() < 1e-9 * np.abs(plain.phi).max()
+
+
+def test_refinement_rejected_for_periodic():
+    p = _small_problem("periodic")
+    with pytest.raises(ValueError):
+        pcg.pcg_solve(p.rho, p.eps, p.h, "periodic", tol=1e-8, refine_every=4)
