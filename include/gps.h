@@ -77,6 +77,14 @@ typedef struct {
                         for the remainder of the predicted iteration count,
                         4-iteration and one-iteration graphs */
   void *stream;      /* hipStream_t the solves run on; NULL = null stream */
+  int refine_every;  /* true-residual refinement every m PCG iterations (0 = off, the
+                        default).  The iterate is kept as sqrt(eps) phi = G s with the
+                        source s in FP64; every m iterations phi and the residual
+                        b - A phi are recomputed in FP64 (one FP64 vacuum solve) and PCG
+                        restarts from them; on exit phi is recomputed from s.  Free and
+                        surface boundaries; applies to gps_solve_generalized and linear
+                        gps_solve_pb (the nonlinear outer loop ignores it).  Costs three
+                        FP64 grid vectors and an FP64 FFT work buffer per plan. */
 } gps_options;
 
 /* Electrolyte of Sec. III (Eqs. rhoions, ionsconcPB, ionsconcMPB, maxconc).
@@ -122,7 +130,8 @@ gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan **
 
 /* Replace the plan's options (NULL fields keep defaults: see gps_options).
  * Errors: GPS_E_INVALID for an odd or out-of-range fd_order, maxit < 1,
- * check_every < 1, unknown precision. */
+ * check_every < 1, unknown precision, refine_every < 0, or refine_every > 0
+ * on a periodic plan. */
 gps_status gps_plan_set_options(gps_plan *plan, const gps_options *opt);
 gps_status gps_plan_get_options(const gps_plan *plan, gps_options *opt);
 
@@ -134,14 +143,15 @@ size_t gps_plan_device_bytes(const gps_plan *plan);
  * *tables, held from gps_plan_create to gps_plan_destroy (twiddles, Green's
  * spectrum); *buffers, the per-solve buffers that one solve in `precision`
  * with iteration cap maxit allocates (nonlinear_pb != 0: a nonlinear
- * Poisson-Boltzmann solve, which adds the ionic-charge field) and
+ * Poisson-Boltzmann solve, which adds the ionic-charge field; refine != 0:
+ * true-residual refinement on, which adds its FP64 buffers) and
  * gps_plan_release_buffers frees; *transient, held only while gps_plan_create
  * builds the Green's spectrum (FP64 padded spectrum for free and surface BC).
  * After one solve gps_plan_device_bytes reports *tables + *buffers.  Any
  * output pointer may be NULL.  Errors: GPS_E_INVALID (n < 2, maxit < 1,
  * unknown bc or precision). */
 gps_status gps_plan_footprint(int nx, int ny, int nz, int bc, int precision, int maxit,
-                              int nonlinear_pb, size_t *tables, size_t *buffers,
+                              int nonlinear_pb, int refine, size_t *tables, size_t *buffers,
                               size_t *transient);
 
 /* Free the plan's per-solve buffers (both precisions) and its captured

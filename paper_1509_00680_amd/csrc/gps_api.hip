@@ -120,12 +120,14 @@ template <typename T> struct Res {
   int hist_cap = 0;
   double* lap64 = nullptr;         // periodic spectral Laplacian of sqrt(eps)
   cplx<double>* work64q = nullptr; // FP64 work for the spectral q (mixed + periodic)
+  double* u64 = nullptr;           // refinement: G s (FP64)
+  cplx<double>* work64r = nullptr; // refinement: FP64 FFT work buffer
   // graphs of `chunk`, 4 and 1 PCG iterations (kernel arguments are
   // replay-invariant: the iteration counter lives in the solve state)
   hipGraphExec_t graph = nullptr;
   hipGraphExec_t graph4 = nullptr;
   hipGraphExec_t graph1 = nullptr;
-  int graph_neutral = -1, graph_timing = -1, graph_chunk = 0;
+  int graph_neutral = -1, graph_timing = -1, graph_chunk = 0, graph_refine = -1;
 };
 
 template <typename T>
@@ -298,7 +300,7 @@ void build_green(gps_plan* pl) {
 // per-precision solve resources
 // ---------------------------------------------------------------------------
 template <typename T>
-void ensure_res(gps_plan* pl, bool need_ion) {
+void ensure_res(gps_plan* pl, bool need_ion, bool need_refine = false) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
   Res<T>& R = pl->res<T>();
   const long long n = pl->npts();
@@ -349,6 +351,16 @@ void ensure_res(gps_plan* pl, bool need_ion) {
     dalloc(&R.slot().ion, (size_t)n * sizeof(T), &R.bytes);
     changed = true;
   }
+  if (need_refine && !R.slot().sig64) {
+    Slot<T>& s = R.slot();
+    const size_t nd = (size_t)n * sizeof(double);
+    dalloc(&s.sig64, nd, &R.bytes);
+    dalloc(&s.src64, nd, &R.bytes);
+    dalloc(&s.qk64, nd, &R.bytes);
+    dalloc(&R.u64, nd, &R.bytes);
+    dalloc(&R.work64r, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<double>), &R.bytes);
+    changed = true;
+  }
   // the table is captured by value in graphs: rebuild them when it changes
   if (changed || R.slot().hist_cap != R.hist_cap || R.slot().maxit != pl->opt.maxit)
     drop_graphs(R);
@@ -365,6 +377,7 @@ void free_res(gps_plan* pl) {
   dfree(s.ion); dfree(s.sq64); dfree(s.work); dfree(s.part_init); dfree(s.part_rr);
   dfree(s.part_delta); dfree(s.part_pap); dfree(s.part_mu); dfree(s.part_aux); dfree(s.hist);
   dfree(s.st); dfree(s.phi); dfree(R.lap64); dfree(R.work64q);
+  dfree(s.sig64); dfree(s.src64); dfree(s.qk64); dfree(R.u64); dfree(R.work64r);
   if (R.h_state) (void)hipHostFree(R.h_state);
   if (R.h_parts) (void)hipHostFree(R.h_parts);
   R = Res<T>{};
@@ -465,7 +478,7 @@ double pass_bytes(const gps_plan* pl, int kind, size_t s) {
 // ---------------------------------------------------------------------------
 template <typename T>
 void enqueue_iteration(gps_plan* pl, const SlotTable<T>& tab, const Batch& b, int check_neutral,
-                       hipStream_t s, int k0) {
+                       hipStream_t s, int k0, int refine) {
   const Geom& g = pl->g;
   const long long n = pl->npts();
   const int periodic = pl->bc == GPS_BC_PERIODIC;
@@ -474,6 +487,7 @@ void enqueue_iteration(gps_plan* pl, const SlotTable<T>& tab, const Batch& b, in
   xp.has_slots = 1;
   xp.batch = b;
   xp.n_pap_parts = xpass_parts(xp);
+  xp.refine = refine;
   check_parts(xp.n_pap_parts, part_caps(g).x);
   xp.periodic_mean = periodic;
   { TimerScope t(pl, s, GPS_K_XFWD, k0); launch_xfwd<T>(XF_SOLVE, xp, s); }
@@ -506,17 +520,16 @@ void enqueue_iteration(gps_plan* pl, const SlotTable<T>& tab, const Batch& b, in
   { TimerScope t(pl, s, GPS_K_XINV, k0); launch_xinv<T>(XI_SOLVE, xp, s); }
 }
 
-// Spectral Laplacian of sqrt(eps) (periodic q) with the FP64 FFT passes.
-template <typename T>
-void spectral_laplacian(gps_plan* pl) {
-  Res<T>& R = pl->res<T>();
+// out = (convolution with the spectrum `table`)(in), all in FP64 with the FP64
+// FFT passes on an explicit work buffer.
+void apply64(gps_plan* pl, const double* in, double* out, cplx<double>* work,
+             const double* table) {
   const Geom& g = pl->g;
   hipStream_t s = pl->stream();
-  cplx<double>* work = R.work64q ? R.work64q : reinterpret_cast<cplx<double>*>(R.slot().work);
   XParams<double> xp = xparams<double>(pl, g.ny * g.nz, g.ny, g.nx, g.nx,
                                        (long long)g.Ly * g.Kx, g.nx);
-  xp.in_real = R.slot().sq64;
-  xp.out_real = R.lap64;
+  xp.in_real = in;
+  xp.out_real = out;
   xp.work = work;
   launch_xfwd<double>(XF_REAL, xp, s);
   SParams<double> yf = sparams<double>(pl, 1, g.Ly, g.ny, g.Ly, g.nz * g.Kx, g.Kx,
@@ -526,13 +539,32 @@ void spectral_laplacian(gps_plan* pl) {
   SParams<double> zc = sparams<double>(pl, 2, g.Lz, g.nz, g.nz, g.Ly * g.Kx, g.Ly * g.Kx, 0,
                                        (long long)g.Ly * g.Kx);
   zc.work = work;
-  zc.table = pl->lap64t;
+  zc.table = table;
   launch_strided<double>(ST_CONV, zc, s);
   SParams<double> yi = sparams<double>(pl, 1, g.Ly, g.Ly, g.ny, g.nz * g.Kx, g.Kx,
                                        (long long)g.Ly * g.Kx, g.Kx);
   yi.work = work;
   launch_strided<double>(ST_INV, yi, s);
   launch_xinv<double>(XI_REAL, xp, s);
+}
+
+// Spectral Laplacian of sqrt(eps) (periodic q) with the FP64 FFT passes.
+template <typename T>
+void spectral_laplacian(gps_plan* pl) {
+  Res<T>& R = pl->res<T>();
+  cplx<double>* work = R.work64q ? R.work64q : reinterpret_cast<cplx<double>*>(R.slot().work);
+  apply64(pl, R.slot().sq64, R.lap64, work, pl->lap64t);
+}
+
+// One true-residual refinement (final: only phi from the source s).
+template <typename T>
+void refine_step(gps_plan* pl, const double* rho, bool final_step) {
+  Res<T>& R = pl->res<T>();
+  apply64(pl, R.slot().src64, R.u64, R.work64r, pl->green64);
+  Batch b{};
+  b.n = 1;
+  launch_refine<T>(R.tab, b, rho, R.u64, pl->npts(), final_step ? 1 : 0, pl->stream());
+  ck(hipGetLastError());
 }
 
 // u = G f with the bulk-precision FFT passes (no sqrt(eps) scaling).
@@ -569,10 +601,10 @@ void vacuum_apply(gps_plan* pl, const double* f, double* u) {
 // Capture `chunk` PCG iterations as one graph (rebuilt when the variant
 // changes: neutrality check, timed pass).
 template <typename T>
-void build_graph(gps_plan* pl, int check_neutral, int chunk) {
+void build_graph(gps_plan* pl, int check_neutral, int chunk, int refine) {
   Res<T>& R = pl->res<T>();
   if (R.graph && R.graph4 && R.graph1 && R.graph_neutral == check_neutral &&
-      R.graph_timing == pl->timing_kind && R.graph_chunk == chunk)
+      R.graph_timing == pl->timing_kind && R.graph_chunk == chunk && R.graph_refine == refine)
     return;
   drop_graphs(R);
   if (!pl->cap_stream) ck(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
@@ -584,7 +616,7 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk) {
   auto capture = [&](int iters, hipGraphExec_t* out) {
     ck(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < iters; ++j)
-      enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->cap_stream, j);
+      enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->cap_stream, j, refine);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
     if (e != hipSuccess) throw DevError{e};
@@ -598,6 +630,7 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk) {
   R.graph_neutral = check_neutral;
   R.graph_timing = pl->timing_kind;
   R.graph_chunk = chunk;
+  R.graph_refine = refine;
 }
 
 // Run PCG iterations until the device-side state says done.  Between host
@@ -606,14 +639,18 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk) {
 // a solve runs few iterations past its stop decision (those launches exit at
 // once, but each still costs a dispatch) with few graph launches.
 template <typename T>
-SolveState run_pcg(gps_plan* pl, int check_neutral) {
+SolveState run_pcg(gps_plan* pl, int check_neutral, const double* refine_rho = nullptr) {
   Res<T>& R = pl->res<T>();
   const int chunk = pl->opt.check_every;
+  // refinement every m iterations (refine_rho: the right-hand side), batches
+  // end at the refinement points
+  const int m = refine_rho ? pl->opt.refine_every : 0;
+  int next_ref = m;
   // Timing needs readable events around single launches; events recorded
   // inside a captured graph cannot be read back, so timed solves launch
   // the same kernels directly on the stream.
   const bool timing = pl->timing_kind != GPS_K_NONE;
-  if (!timing) build_graph<T>(pl, check_neutral, chunk);
+  if (!timing) build_graph<T>(pl, check_neutral, chunk, m > 0);
   Batch b{};
   b.n = 1;
   b.slot[0] = 0;
@@ -623,11 +660,12 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
   int prev_it = 0;
   SolveState st{};
   for (;;) {
+    if (m > 0) n = std::min(n, next_ref - k);
     if (timing) {
       pl->ev_pending.clear();
       pl->ev_used = 0;
       for (int j = 0; j < n; ++j)
-        enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->stream(), j);
+        enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->stream(), j, m > 0);
       ck(hipGetLastError());
     } else {
       // greedy: chunk graphs, then 4-iteration graphs, then single iterations
@@ -644,6 +682,10 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
       pl->timing_bytes = pass_bytes(pl, pl->timing_kind, sizeof(T));
     }
     if (st.done || k > pl->opt.maxit + 1) break;
+    if (m > 0 && k == next_ref) {         // every iteration so far did work
+      refine_step<T>(pl, refine_rho, false);
+      next_ref += m;
+    }
     // predicted iterations left: log-linear extrapolation of ||r||^2
     n = 2 * chunk;
     if (prev_rr > 0.0 && st.rr > 0.0 && st.iters > prev_it && st.rr < prev_rr) {
@@ -655,6 +697,7 @@ SolveState run_pcg(gps_plan* pl, int check_neutral) {
     prev_rr = st.rr;
     prev_it = st.iters;
   }
+  if (m > 0) refine_step<T>(pl, refine_rho, true);   // phi from the source s
   return st;
 }
 
@@ -708,7 +751,9 @@ template <typename T>
 gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double* phi,
                       double tol, const Electrolyte& el) {
   const bool nonlinear = el.present && !el.linear;
-  ensure_res<T>(pl, nonlinear);
+  // true-residual refinement: single PCG solves on invertible vacuum solvers
+  const bool refine = !nonlinear && pl->opt.refine_every > 0 && pl->bc != GPS_BC_PERIODIC;
+  ensure_res<T>(pl, nonlinear, refine);
   Res<T>& R = pl->res<T>();
   hipStream_t s = pl->stream();
   const long long n = pl->npts();
@@ -744,7 +789,7 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
   ck(hipGetLastError());
   std::memset(&pl->info, 0, sizeof(pl->info));
   if (!nonlinear) {
-    const SolveState st = run_pcg<T>(pl, periodic && !el.present);
+    const SolveState st = run_pcg<T>(pl, periodic && !el.present, refine ? rho : nullptr);
     finish_info<T>(pl, st, rho, phi, st.iters);
     pl->info.status = st.status;
     return (gps_status)st.status;
@@ -839,6 +884,7 @@ gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan** 
   pl->opt.maxit = 1000;
   pl->opt.check_every = 4;
   pl->opt.stream = nullptr;
+  pl->opt.refine_every = 0;
   Geom& g = pl->g;
   g.nx = nx;
   g.ny = ny;
@@ -902,6 +948,8 @@ gps_status gps_plan_set_options(gps_plan* pl, const gps_options* o) {
   if (o->precision != GPS_PREC_FP64 && o->precision != GPS_PREC_MIXED) return GPS_E_INVALID;
   if (o->fd_order < 2 || o->fd_order > 16 || (o->fd_order & 1)) return GPS_E_INVALID;
   if (o->maxit < 1 || o->check_every < 1) return GPS_E_INVALID;
+  if (o->refine_every < 0 || (o->refine_every > 0 && pl->bc == GPS_BC_PERIODIC))
+    return GPS_E_INVALID;
   pl->opt = *o;
   return GPS_OK;
 }
@@ -925,7 +973,7 @@ gps_status gps_plan_release_buffers(gps_plan* pl) {
 }
 
 gps_status gps_plan_footprint(int nx, int ny, int nz, int bc, int precision, int maxit,
-                              int nonlinear_pb, size_t* tables, size_t* buffers,
+                              int nonlinear_pb, int refine, size_t* tables, size_t* buffers,
                               size_t* transient) {
   if (nx < 2 || ny < 2 || nz < 2 || maxit < 1) return GPS_E_INVALID;
   if (bc != GPS_BC_FREE && bc != GPS_BC_SURFACE && bc != GPS_BC_PERIODIC) return GPS_E_INVALID;
@@ -951,6 +999,7 @@ gps_status gps_plan_footprint(int nx, int ny, int nz, int bc, int precision, int
   if (pz) b += n * sizeof(double) + (s != sizeof(double) ? wbox * 2 * sizeof(double) : 0);
   b += 4 * ((size_t)maxit + 1) * sizeof(double);                              // history
   if (nonlinear_pb) b += n * s;                                               // ionic charge
+  if (refine && !pz) b += 4 * n * sizeof(double) + wbox * 2 * sizeof(double);    // sigma, s, q, Gs, work
   size_t t = 0;
   if (bc == GPS_BC_FREE) t = Lz * Ly * Kx * 2 * sizeof(double);
   else if (bc == GPS_BC_SURFACE) t = Kx * (Ly / 2 + 1) * Lz * 2 * sizeof(double);

@@ -211,8 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(XParams<T> p) {
     int k;
     XHead<> hd;
     xfwd_head_load(sl, p.n_pap_parts, hd);
-    if (!xfwd_head_finish(sl, p.n_pap_parts, hd, &k, &alpha)) return;
-    upd = k > 0;
+    if (!xfwd_head_finish(sl, p.n_pap_parts, hd, &k, &alpha, &upd)) return;
     work = sl.work;
   }
   double mu = 0.0, rr = 0.0;
@@ -293,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(XParams<T> p) {
   if constexpr (MODE == XI_SOLVE) {
     if (solve_stopped(sl.st)) return;
     work = sl.work;
-    dir.k = sl.st->k;
+    dir.fresh = sl.st->fresh;
     dir.beta = sl.st->beta;
     dir.mu = p.periodic_mean ? sl.st->mu : 0.0;
   }

@@ -351,6 +351,8 @@ __device__ __forceinline__ void tile_row_offsets(const XParams<T>& p, int row0, 
 template <typename T, int L1, int L2, int MODE, bool PAD>
 __global__ __launch_bounds__(xthreads<L1>())
 void k_fxfwd(XParams<T> p) {
+  constexpr bool SOLVE = MODE == XF_SOLVE || MODE == XF_SOLVE_REF;
+  constexpr bool REF = MODE == XF_SOLVE_REF;     // also s += alpha sigma (refinement)
   constexpr int P = kXPairs;
   constexpr int L = L1 * L2;
   constexpr int PITCH = P + 1;
@@ -368,7 +370,7 @@ void k_fxfwd(XParams<T> p) {
   const int row0 = tile * 2 * P;
   cplx<T>* work = p.work;
   const Slot<T> sl = p.tab.s[p.batch.slot[blockIdx.y]];
-  if constexpr (MODE == XF_SOLVE) work = sl.work;
+  if constexpr (SOLVE) work = sl.work;
   constexpr int ETW = (L + NT - 1) / NT;
   cplx<T> twv[ETW];
 #pragma unroll
@@ -379,13 +381,14 @@ void k_fxfwd(XParams<T> p) {
   // operands arrive while it decides.  p, Ap and phi are loaded even at k = 0
   // (unused there).
   XHead<NT == 64 ? 24 : 8> hd;                     // one (p, Ap) partial per x-inverse group
-  if constexpr (MODE == XF_SOLVE) xfwd_head_load(sl, p.n_pap_parts, hd);
+  if constexpr (SOLVE) xfwd_head_load(sl, p.n_pap_parts, hd);
   // rows are contiguous (row stride Lin, checked by the dispatcher), so
   // element e of the tile is at row0 * Lin + e
   const unsigned eo = (unsigned)row0 * (unsigned)Lin;
   const int nin = min(NIN, (p.nrows - row0) * Lin);     // tile elements that exist
   T rv[EIN], sv[EIN], pv[EIN], av[EIN];
   double fv[EIN];
+  double gv[REF ? EIN : 1], cv[REF ? EIN : 1];   // sigma, s
 #pragma unroll
   for (int i = 0; i < EIN; ++i) {
     const int e = tid + i * NT;
@@ -393,12 +396,16 @@ void k_fxfwd(XParams<T> p) {
     sv[i] = T(0);
     if (e < nin) {
       const unsigned o = eo + (unsigned)e;
-      if constexpr (MODE == XF_SOLVE) {
+      if constexpr (SOLVE) {
         rv[i] = GPS_AT(sl.r, o);
         sv[i] = GPS_AT(sl.isq, o);
         pv[i] = GPS_AT(sl.p, o);
         av[i] = GPS_AT(sl.ap, o);
         fv[i] = GPS_AT(sl.phi, o);
+        if constexpr (REF) {
+          gv[i] = GPS_AT(sl.sig64, o);
+          cv[i] = GPS_AT(sl.src64, o);
+        }
       } else {
         rv[i] = T(GPS_AT(p.in_real, o));
       }
@@ -406,10 +413,9 @@ void k_fxfwd(XParams<T> p) {
   }
   double alpha = 0.0;
   bool upd = false;
-  if constexpr (MODE == XF_SOLVE) {
+  if constexpr (SOLVE) {
     int k;
-    if (!xfwd_head_finish(sl, p.n_pap_parts, hd, &k, &alpha)) return;
-    upd = k > 0;
+    if (!xfwd_head_finish(sl, p.n_pap_parts, hd, &k, &alpha, &upd)) return;
   }
   // phase 2: update, scale, stage the rows in LDS
   double mu = 0.0, rr = 0.0;
@@ -420,13 +426,14 @@ void k_fxfwd(XParams<T> p) {
     const int e = tid + i * NT;
     if (e < NIN) {
       T a = rv[i];
-      if constexpr (MODE == XF_SOLVE) {
+      if constexpr (SOLVE) {
         if (e < nin) {
           const unsigned o = eo + (unsigned)e;
           if (upd) {
             GPS_AT(sl.phi, o) = fv[i] + alpha * double(pv[i]);
             a = a - T(alpha) * av[i];
             GPS_AT(sl.r, o) = a;
+            if constexpr (REF) GPS_AT(sl.src64, o) = cv[i] + alpha * gv[i];
           }
           rr += double(a) * double(a);
           a = a * sv[i];
@@ -495,7 +502,7 @@ void k_fxfwd(XParams<T> p) {
       }
     }
   }
-  if constexpr (MODE == XF_SOLVE) {             // one partial per work-group
+  if constexpr (SOLVE) {                        // one partial per work-group
     const double s2 = wg_sum<NT>(rr);
     if (tid == 0) sl.part_rr[tile] = s2;
     if (p.periodic_mean) {
@@ -505,13 +512,15 @@ void k_fxfwd(XParams<T> p) {
   }
 }
 
-// MODE XI_SOLVE / XI_SOLVE_PERIODIC: v = u / sqrt(eps) and the direction update
-// of the PCG iteration (with the periodic mean term); XI_REAL: plain output.
+// MODE XI_SOLVE / XI_SOLVE_PERIODIC / XI_SOLVE_REF: v = u / sqrt(eps) and the
+// direction update of the PCG iteration (with the periodic mean term; with the
+// refinement's sigma = r / sqrt(eps) + beta sigma); XI_REAL: plain output.
 template <typename T, int L1, int L2, int MODE, bool PAD>
 __global__ __launch_bounds__(xthreads<L1>())
 void k_fxinv(XParams<T> p) {
   constexpr bool SOLVE = MODE != XI_REAL;
   constexpr bool PER = MODE == XI_SOLVE_PERIODIC;
+  constexpr bool REF = MODE == XI_SOLVE_REF;
   constexpr int P = kXPairs;
   constexpr int L = L1 * L2;
   constexpr int PITCH = P + 1;
@@ -534,7 +543,7 @@ void k_fxinv(XParams<T> p) {
   // earlier kernel, first used in the epilogue)
   DirArgs dir{};
   if constexpr (SOLVE) {
-    dir.k = sl.st->k;
+    dir.fresh = sl.st->fresh;
     dir.beta = sl.st->beta;
     dir.mu = PER ? sl.st->mu : 0.0;
   }
@@ -562,6 +571,7 @@ void k_fxinv(XParams<T> p) {
   // epilogue operands are independent of the transform: load them now too
   constexpr int EO = SOLVE ? EOUT : 1;
   T sv[EO], rv[EO], qv[EO], pv[EO], av[EO], mv[PER ? EOUT : 1];
+  double gv[REF ? EOUT : 1];                     // sigma
   // rows are contiguous (row stride Lout, checked by the dispatcher)
   const unsigned eo = (unsigned)row0 * (unsigned)Lout;
   const int nout = min(NOUT, (p.nrows - row0) * Lout);  // tile elements that exist
@@ -577,6 +587,7 @@ void k_fxinv(XParams<T> p) {
         pv[i] = GPS_AT(sl.p, o);
         av[i] = GPS_AT(sl.ap, o);
         if constexpr (PER) mv[i] = GPS_AT(sl.s, o);
+        if constexpr (REF) gv[i] = GPS_AT(sl.sig64, o);
       }
     }
     // stop flag issued after the operand loads, in flight with them
@@ -641,6 +652,10 @@ void k_fxinv(XParams<T> p) {
         const unsigned o = eo + (unsigned)e;
         const T v = ldsr[__umul24(2 * PITCH, (unsigned)rc.col) + rc.row] * sv[i];
         T pn = pv[i], an = av[i];
+        if constexpr (REF) {
+          const double w = double(rv[i] * sv[i]);   // the preconditioner input of this iteration
+          GPS_AT(sl.sig64, o) = dir.fresh ? w : w + dir.beta * gv[i];
+        }
         direction_update(v, rv[i], qv[i], PER ? mv[i] : T(0), pn, an, dir);
         GPS_AT(sl.p, o) = pn;
         GPS_AT(sl.ap, o) = an;
@@ -744,7 +759,10 @@ bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s) {
 #define GPS_CASE(LL, A, BB)                                                                      \
   case LL: {                                                                                     \
     const dim3 blk(xthreads<A>());                                                      \
-    if (mode == XF_SOLVE) {                                                                      \
+    if (mode == XF_SOLVE && p.refine) {                                                          \
+      if (pad) GPS_LAUNCH((k_fxfwd<T, A, BB, XF_SOLVE_REF, true>), grid, blk, 0, s, p);          \
+      else GPS_LAUNCH((k_fxfwd<T, A, BB, XF_SOLVE_REF, false>), grid, blk, 0, s, p);             \
+    } else if (mode == XF_SOLVE) {                                                               \
       if (pad) GPS_LAUNCH((k_fxfwd<T, A, BB, XF_SOLVE, true>), grid, blk, 0, s, p);      \
       else GPS_LAUNCH((k_fxfwd<T, A, BB, XF_SOLVE, false>), grid, blk, 0, s, p);         \
     } else {                                                                                     \
@@ -772,6 +790,9 @@ bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s) {
     if (mode == XI_SOLVE && p.periodic_mean) {                                                   \
       if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE_PERIODIC, true>), grid, blk, 0, s, p);     \
       else GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE_PERIODIC, false>), grid, blk, 0, s, p);        \
+    } else if (mode == XI_SOLVE && p.refine) {                                                   \
+      if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE_REF, true>), grid, blk, 0, s, p);          \
+      else GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE_REF, false>), grid, blk, 0, s, p);             \
     } else if (mode == XI_SOLVE) {                                                               \
       if (pad) GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE, true>), grid, blk, 0, s, p);              \
       else GPS_LAUNCH((k_fxinv<T, A, BB, XI_SOLVE, false>), grid, blk, 0, s, p);                 \

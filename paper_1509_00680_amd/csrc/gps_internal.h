@@ -86,6 +86,9 @@ struct SolveState {
   double delta[2];   // delta_k = (v_k, r_k) at index k & 1 (y-inverse decision)
   double beta;       // beta_k of the current iteration (y-inverse decision)
   double mu;         // mean of r_k / sqrt(eps) (periodic; y-inverse decision)
+  int restart;       // set by a refinement: the next iteration applies no update and
+                     // starts a new direction (cleared by the y-inverse decision)
+  int fresh;         // this iteration starts a direction: p = v (y-inverse decision)
 };
 
 // Input-check flags (SolveState::err)
@@ -101,6 +104,8 @@ template <typename T> struct Slot {
   T *s;                       // sqrt(eps) (periodic mean term; may be null)
   T *ion, *ion_prev;          // ionic charge (nonlinear PB only)
   double *phi;                // solution accumulator (FP64)
+  double *sig64, *src64;      // refinement: source of p and of phi (FP64; null when off)
+  double *qk64;               // refinement: q + kappa2 in FP64 (null when off)
   double *sq64;               // sqrt(eps) in FP64 (stencil input)
   cplx<T> *work;              // FFT work buffer  nz * Ly * Kx
   double *part_init;          // 4 partial sums per init work-group

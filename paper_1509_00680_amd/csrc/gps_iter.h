@@ -93,7 +93,7 @@ __device__ __forceinline__ V wg_bcast(V w) {
 // work-group; more are summed from memory).
 template <int N = 8>
 struct XHead {
-  int done, k;
+  int done, k, restart;
   double dprev0, dprev1;
   PartShare<N> pap;
 };
@@ -106,25 +106,30 @@ __device__ __forceinline__ void xfwd_head_load(const Slot<T>& sl, int n_pap_part
   const SolveState* v = sl.st;
   h.done = v->done;
   h.k = v->k_next;
+  h.restart = v->restart;
   h.dprev0 = v->delta[0];
   h.dprev1 = v->delta[1];
   share_load(h.pap, sl.part_pap, n_pap_parts);
 }
 
 // Takes the iteration number k (and publishes it for the other kernels of the
-// iteration); for k >= 1, alpha_{k-1} = delta_{k-1} / (p_{k-1}, A p_{k-1}).
-// Returns false (whole work-group) if the solve has stopped or (p, Ap) >= 0
-// (loss of definiteness).
+// iteration); for k >= 1, alpha_{k-1} = delta_{k-1} / (p_{k-1}, A p_{k-1}),
+// unless a refinement has just replaced phi and r (then there is no update).
+// *upd_out: whether the update of iteration k-1 is applied.  Returns false
+// (whole work-group) if the solve has stopped or (p, Ap) >= 0 (loss of
+// definiteness).
 template <typename T, int N>
 __device__ __forceinline__ bool xfwd_head_finish(const Slot<T>& sl, int n_pap_parts,
                                                  const XHead<N>& h, int* k_out,
-                                                 double* alpha_out) {
+                                                 double* alpha_out, bool* upd_out) {
   if (wg_bcast(h.done)) return false;
   const int k = wg_bcast(h.k);
   if (blockIdx.x == 0 && threadIdx.x == 0) sl.st->k = k;
   *k_out = k;
   double alpha = 0.0;
-  if (k > 0) {
+  const bool upd = k > 0 && !wg_bcast(h.restart);
+  *upd_out = upd;
+  if (upd) {
     const double pap = share_sum(h.pap, sl.part_pap, n_pap_parts);
     if (!(pap < 0.0)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -189,7 +194,10 @@ __device__ void pcg_decide(const Slot<T>& sl, const DecideArgs& a) {
     else if (k >= sl.maxit) status = GPS_E_NOT_CONVERGED;
     else if (!(delta > 0.0)) status = isfinite(delta) ? GPS_E_BREAKDOWN : GPS_E_NONFINITE;
   }
-  const double beta = k > 0 ? delta / st->delta[(k - 1) & 1] : 0.0;
+  // a new direction at k = 0 and after a refinement
+  const int fresh = (k == 0 || st->restart) ? 1 : 0;
+  const double beta = fresh ? 0.0 : delta / st->delta[(k - 1) & 1];
+  __syncthreads();                       // every thread has read restart
   if (threadIdx.x == 0) {
     if (k == 0) {
       st->rr0 = rr;
@@ -207,6 +215,8 @@ __device__ void pcg_decide(const Slot<T>& sl, const DecideArgs& a) {
     } else {
       st->delta[k & 1] = delta;
       st->beta = beta;
+      st->fresh = fresh;
+      st->restart = 0;
       st->mu = mu / a.npts;
       sl.hist[(size_t)k * 4 + 0] = delta;
       sl.hist[(size_t)k * 4 + 1] = beta;
@@ -225,7 +235,7 @@ __device__ __forceinline__ int half_bin_weight(int kx, int Lx) {
 // A v = -(q + kappa2) v - 4 pi (r - sqrt(eps) mean(r / sqrt(eps))) [periodic]
 // p = v + beta p, Ap = A v + beta Ap (beta = 0 at k = 0).
 struct DirArgs {
-  int k;
+  int fresh;           // p = v (first iteration, or the first after a refinement)
   double beta;
   double mu;           // mean of r / sqrt(eps) (periodic), else 0
 };
@@ -235,7 +245,7 @@ __device__ __forceinline__ void direction_update(T v, T r, T q, T s, T& p, T& ap
                                                  const DirArgs& d) {
   const T fpi = T(kFourPi);
   const T av = -q * v - fpi * (r - s * T(d.mu));
-  if (d.k == 0) {
+  if (d.fresh) {
     p = v;
     ap = av;
   } else {
@@ -246,8 +256,9 @@ __device__ __forceinline__ void direction_update(T v, T r, T q, T s, T& p, T& ap
 }
 
 // x-forward prologue at grid point o (generic passes): apply the update of
-// iteration k-1 (phi += alpha p, r -= alpha Ap), accumulate ||r_k||^2 and
-// return the preconditioner input r / sqrt(eps).
+// iteration k-1 (phi += alpha p, r -= alpha Ap, and with refinement
+// s += alpha sigma), accumulate ||r_k||^2 and return the preconditioner input
+// r / sqrt(eps).
 template <typename T>
 __device__ __forceinline__ T solve_prologue(const Slot<T>& sl, size_t o, bool upd, double alpha,
                                             double& rr) {
@@ -258,6 +269,7 @@ __device__ __forceinline__ T solve_prologue(const Slot<T>& sl, size_t o, bool up
     sl.phi[o] += alpha * double(pv);
     r = r - T(alpha) * av;
     sl.r[o] = r;
+    if (sl.src64) sl.src64[o] += alpha * sl.sig64[o];
   }
   rr += double(r) * double(r);
   return r * sl.isq[o];
@@ -270,7 +282,12 @@ __device__ __forceinline__ void solve_epilogue(const Slot<T>& sl, size_t o, T u,
                                                const DirArgs& d, bool periodic, double& pap) {
   const T v = u * sl.isq[o];
   T p = sl.p[o], ap = sl.ap[o];
-  direction_update(v, sl.r[o], sl.qk[o], periodic ? sl.s[o] : T(0), p, ap, d);
+  const T r = sl.r[o];
+  if (sl.sig64) {                        // refinement: sigma = r / sqrt(eps) + beta sigma
+    const double w = double(r * sl.isq[o]);
+    sl.sig64[o] = d.fresh ? w : w + d.beta * sl.sig64[o];
+  }
+  direction_update(v, r, sl.qk[o], periodic ? sl.s[o] : T(0), p, ap, d);
   sl.p[o] = p;
   sl.ap[o] = ap;
   pap += double(p) * double(ap);

@@ -38,6 +38,9 @@ LaunchEvents& launch_events();
 // Row `row` of the input is in[row * in_row_stride + x], x < Lin; the output
 // row goes to work[(row / rows_per_plane) * plane_stride + (row % rows_per_plane) * Kx + k].
 enum XfwdMode { XF_SOLVE = 0, XF_REAL = 1, XF_GEN_FREE = 2 };
+// (the two-level x passes have refinement variants XF_SOLVE_REF / XI_SOLVE_REF,
+// chosen by XParams::refine; the generic ones test the slot's buffers)
+constexpr int XF_SOLVE_REF = 3;
 template <typename T> struct XParams {
   Geom g;
   RadixPlan rp;
@@ -59,11 +62,13 @@ template <typename T> struct XParams {
   Batch batch;
   int n_pap_parts;          // (p, Ap) partials written by the x-inverse pass
   int periodic_mean;        // periodic: sum r/sqrt(eps) partials and the mean term
+  int refine;               // track the FP64 sources sigma and s (true-residual refinement)
 };
 
 // x-inverse modes: the PCG epilogue (plain or with the periodic mean term), or
 // plain real output.
 enum XinvMode { XI_SOLVE = 0, XI_REAL = 1, XI_SOLVE_PERIODIC = 2 };
+constexpr int XI_SOLVE_REF = 3;
 
 template <typename T> void launch_xfwd(int mode, const XParams<T>& p, hipStream_t s);
 template <typename T> void launch_xinv(int mode, const XParams<T>& p, hipStream_t s);
@@ -150,5 +155,8 @@ template <typename T> void launch_energy(const SlotTable<T>& tab, const Batch& b
                                          long long n, hipStream_t s);
 template <typename T> void launch_zero_ion(const SlotTable<T>& tab, const Batch& b, long long n,
                                            hipStream_t s);
+template <typename T> void launch_refine(const SlotTable<T>& tab, const Batch& b, const double* rho,
+                                         const double* u, long long n, int final_step,
+                                         hipStream_t s);
 
 }  // namespace gps

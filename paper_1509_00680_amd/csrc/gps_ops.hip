@@ -198,6 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotTable<T> tab, Batch b,
       const T r0 = T(-kFourPi * rv);
       sl.r[i] = r0;
       sl.phi[i] = 0.0;
+      if (sl.src64) sl.src64[i] = 0.0;
       a0 += double(r0) * double(r0);
       a1 += rv;
       a2 += fabs(rv);
@@ -336,7 +337,9 @@ __global__ __launch_bounds__(kQThreads) void k_qstencil(SlotTable<T> tab, Batch 
       const double lap = acc * ih2;
       double q = qv[M] * lap;
       if (kappa_coef != 0.0) q = __dadd_rn(q, __dmul_rn(kappa_coef, gv));
-      sl.qk[(size_t)z * plane + (size_t)Y * g.nx + X] = T(q);
+      const size_t o = (size_t)z * plane + (size_t)Y * g.nx + X;
+      sl.qk[o] = T(q);
+      if (sl.qk64) sl.qk64[o] = q;
     }
     __syncthreads();                              // tile reads done before the next writes
 #pragma unroll
@@ -370,6 +373,7 @@ __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, 
       kacc += k2 / eps[i];
     }
     sl.qk[i] = T(qv);
+    if (sl.qk64) sl.qk64[i] = qv;
   }
   kacc = block_sum(kacc);
   if (threadIdx.x == 0) sl.part_aux[blockIdx.x] = kacc;
@@ -543,6 +547,44 @@ void launch_energy(const SlotTable<T>& tab, const Batch& b, const double* rho, l
   GPS_LAUNCH((k_energy<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, rho, n);
 }
 
+// ---------------------------------------------------------------------------
+// true-residual refinement, in FP64 (free and surface boundaries).  The
+// search directions are preconditioner images of sources, p = S^-1 G sigma,
+// so the iterate is sqrt(eps) phi = G s with s accumulated by the x passes.
+// Given u = G s:  phi = u / sqrt(eps) and, with A = S L_G S - diag(q + kappa2)
+// and L_G G = -4 pi I,  r = b - A phi = -4 pi rho + 4 pi sqrt(eps) s + (q + kappa2) phi.
+// The next iteration restarts PCG from this residual (no update, beta = 0).
+// final: only phi (the iterate returned on exit).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_refine(SlotTable<T> tab, Batch b,
+                                                     const double* __restrict__ rho,
+                                                     const double* __restrict__ u, long long n,
+                                                     int final_step) {
+  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
+  const long long base =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) {
+      const double sq = sl.sq64[i];
+      const double ph = u[i] / sq;
+      sl.phi[i] = ph;
+      if (!final_step)
+        sl.r[i] = T(-kFourPi * rho[i] + kFourPi * sq * sl.src64[i] + sl.qk64[i] * ph);
+    }
+  }
+  if (!final_step && blockIdx.x == 0 && threadIdx.x == 0) sl.st->restart = 1;
+}
+
+template <typename T>
+void launch_refine(const SlotTable<T>& tab, const Batch& b, const double* rho, const double* u,
+                   long long n, int final_step, hipStream_t s) {
+  GPS_LAUNCH((k_refine<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, rho, u, n,
+             final_step);
+}
+
 #define GPS_INST(T)                                                                              \
   template void launch_reset_state<T>(const SlotTable<T>&, const Batch&, double, double,            \
                                       hipStream_t);                                              \
@@ -556,7 +598,9 @@ void launch_energy(const SlotTable<T>& tab, const Batch& b, const double* rho, l
                                      int, hipStream_t);                                          \
   template void launch_zero_ion<T>(const SlotTable<T>&, const Batch&, long long, hipStream_t);        \
   template void launch_energy<T>(const SlotTable<T>&, const Batch&, const double*, long long,         \
-                                 hipStream_t);
+                                 hipStream_t);                                                   \
+  template void launch_refine<T>(const SlotTable<T>&, const Batch&, const double*, const double*,    \
+                                 long long, int, hipStream_t);
 GPS_INST(float)
 GPS_INST(double)
 #undef GPS_INST

@@ -338,7 +338,7 @@ gps_status gps_server_submit(gps_server* S, const gps_request* q, long long* tic
     R->req.ions = &R->ions;
   }
   const int nonlinear = R->has_ions && !R->ions.linear;
-  if (gps_plan_footprint(q->nx, q->ny, q->nz, q->bc, S->opt.precision, S->opt.maxit, nonlinear,
+  if (gps_plan_footprint(q->nx, q->ny, q->nz, q->bc, S->opt.precision, S->opt.maxit, nonlinear, 0,
                          &R->tables, &R->buffers, &R->transient) != GPS_OK) {
     delete R;
     return GPS_E_INVALID;

@@ -37,7 +37,7 @@ KERNEL_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "xinv": 5}
 class gps_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("fd_order", ctypes.c_int),
                 ("maxit", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("refine_every", ctypes.c_int)]
 
 
 class gps_ions(ctypes.Structure):
@@ -137,7 +137,7 @@ def load(path=LIB_PATH):
     lib.gps_status_string.argtypes = [I]
     lib.gps_status_string.restype = ctypes.c_char_p
     SZ = ctypes.POINTER(ctypes.c_size_t)
-    lib.gps_plan_footprint.argtypes = [I, I, I, I, I, I, I, SZ, SZ, SZ]
+    lib.gps_plan_footprint.argtypes = [I, I, I, I, I, I, I, I, SZ, SZ, SZ]
     lib.gps_plan_release_buffers.argtypes = [P]
     lib.gps_plan_release_buffers.restype = I
     lib.gps_plan_footprint.restype = I
@@ -207,7 +207,7 @@ class Plan:
     """A libgps plan for one grid, spacing and boundary condition."""
 
     def __init__(self, shape, h, bc, precision="fp64", fd_order=16, maxit=1000,
-                 check_every=8, stream=None):
+                 check_every=8, stream=None, refine_every=0):
         nz, ny, nx = shape
         self.shape = (nz, ny, nx)
         self.h = float(h)
@@ -216,15 +216,15 @@ class Plan:
         if st != GPS_OK:
             raise GPSError(st, "gps_plan_create(%d,%d,%d,%g,%s)" % (nx, ny, nz, h, bc))
         self.handle = handle
-        self.set_options(precision, fd_order, maxit, check_every, stream)
+        self.set_options(precision, fd_order, maxit, check_every, stream, refine_every)
 
     def set_options(self, precision="fp64", fd_order=16, maxit=1000, check_every=8,
-                    stream=None):
+                    stream=None, refine_every=0):
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
         o = gps_options(PRECISIONS[precision], int(fd_order), int(maxit), int(check_every),
-                        ctypes.c_void_p(stream))
+                        ctypes.c_void_p(stream), int(refine_every))
         st = load().gps_plan_set_options(self.handle, ctypes.byref(o))
         if st != GPS_OK:
             raise GPSError(st, "gps_plan_set_options")
@@ -290,13 +290,13 @@ class Plan:
             pass
 
 
-def plan_footprint(shape, bc, precision="mixed", maxit=1000, nonlinear_pb=False):
+def plan_footprint(shape, bc, precision="mixed", maxit=1000, nonlinear_pb=False, refine=False):
     """(tables, buffers, transient) device bytes of a plan (gps_plan_footprint)."""
     nz, ny, nx = shape
     tb, b, t = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     st = load().gps_plan_footprint(int(nx), int(ny), int(nz), BC_CODES[bc], PRECISIONS[precision],
-                                   int(maxit), int(bool(nonlinear_pb)), ctypes.byref(tb),
-                                   ctypes.byref(b), ctypes.byref(t))
+                                   int(maxit), int(bool(nonlinear_pb)), int(bool(refine)),
+                                   ctypes.byref(tb), ctypes.byref(b), ctypes.byref(t))
     if st != GPS_OK:
         raise GPSError(st, "gps_plan_footprint")
     return tb.value, b.value, t.value

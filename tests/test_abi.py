@@ -74,6 +74,10 @@ def test_footprint_host_side(lib):
     assert b > 96 * 192 * 97 * 8 + 6 * 4 * n
     tbp, bp, tp = gps.plan_footprint((32, 32, 32), "periodic", "mixed")
     assert tp == 0 and bp > 0 and tbp > 0
+    # refinement: sigma, s, q and G s in FP64 and an FP64 work buffer; never periodic
+    _, br, _ = gps.plan_footprint((96, 96, 96), "free", "mixed", refine=True)
+    assert br - b == 4 * 8 * n + 96 * 192 * 97 * 16
+    assert gps.plan_footprint((32, 32, 32), "periodic", "mixed", refine=True)[1] == bp
     with pytest.raises(gps.GPSError):
         gps.plan_footprint((1, 8, 8), "free")
 

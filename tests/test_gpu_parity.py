@@ -173,3 +173,37 @@ def test_boltzmann_overflow_reported():
     p = plan(prob.shape, prob.h, "free", "fp64")
     st = p.solve_pb(dev(prob.rho), dev(prob.eps), prob.ions, empty(prob.shape), 1e-9)
     assert st == gps.GPS_E_NONFINITE
+
+
+@pytest.mark.parametrize("bc", ["free", "surface"])
+def test_refinement_reaches_fp64_accuracy_in_mixed(bc):
+    # mixed precision with the FP64 true-residual refinement converges to the
+    # FP64 solution: at tol 1e-9 it agrees with the oracle far below the ~1e-7
+    # level where FP32 PCG alone stalls
+    require_gpu()
+    prob = W.molecule(32, 0.45, seed=7, n_atoms=10, ball=3.0, bc=bc)
+    ref = pcg.pcg_solve(prob.rho, prob.eps, prob.h, bc, tol=1e-12)
+    p = gps.Plan(prob.shape, prob.h, bc, precision="mixed", refine_every=12)
+    phi = empty(prob.shape)
+    print("refine mixed", bc, flush=True)
+    st = p.solve_generalized(dev(prob.rho), dev(prob.eps), phi, 1e-9)
+    assert st == gps.GPS_OK, gps.STATUS[st]
+    err = np.abs(host(phi) - ref.phi).max() / np.abs(ref.phi).max()
+    print("  iterations %d  rel err %.3e" % (p.info()["iterations"], err))
+    assert err <= 1e-8
+    e_ref = pcg.electrostatic_energy(prob.rho, ref.phi, prob.h)
+    assert abs(p.info()["energy"] / e_ref - 1.0) <= 1e-9
+
+
+def test_refinement_in_fp64_and_periodic_rejected():
+    require_gpu()
+    prob = W.molecule(24, 0.5, seed=3, n_atoms=6, ball=2.0, bc="free")
+    ref = pcg.pcg_solve(prob.rho, prob.eps, prob.h, "free", tol=1e-11)
+    p = gps.Plan(prob.shape, prob.h, "free", precision="fp64", refine_every=7)
+    phi = empty(prob.shape)
+    print("refine fp64", flush=True)
+    assert p.solve_generalized(dev(prob.rho), dev(prob.eps), phi, 1e-11) == gps.GPS_OK
+    assert np.abs(host(phi) - ref.phi).max() <= 1e-9 * np.abs(ref.phi).max()
+    per = gps.Plan((16, 16, 16), 0.5, "periodic", precision="mixed")
+    with pytest.raises(gps.GPSError):
+        per.set_options("mixed", refine_every=8)
