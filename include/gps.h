@@ -85,6 +85,14 @@ typedef struct {
                         surface boundaries; applies to gps_solve_generalized and linear
                         gps_solve_pb (the nonlinear outer loop ignores it).  Costs three
                         FP64 grid vectors and an FP64 FFT work buffer per plan. */
+  int warm_start;    /* 1: start each solve from the previous solve's iterate on this plan
+                        (kept as its FP64 source s, so the starting residual b - A phi is
+                        exact in FP64) when that solve tracked it (any solve with
+                        warm_start or refine_every set, that ended with GPS_OK or
+                        GPS_E_NOT_CONVERGED); the caller guarantees that eps, fd_order and
+                        the electrolyte are those of that solve.  The relative tolerance
+                        stays relative to ||4 pi rho||.  Same scope and buffers as
+                        refine_every.  Default 0. */
 } gps_options;
 
 /* Electrolyte of Sec. III (Eqs. rhoions, ionsconcPB, ionsconcMPB, maxconc).
@@ -130,8 +138,8 @@ gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan **
 
 /* Replace the plan's options (NULL fields keep defaults: see gps_options).
  * Errors: GPS_E_INVALID for an odd or out-of-range fd_order, maxit < 1,
- * check_every < 1, unknown precision, refine_every < 0, or refine_every > 0
- * on a periodic plan. */
+ * check_every < 1, unknown precision, refine_every < 0, or refine_every > 0 or
+ * warm_start on a periodic plan. */
 gps_status gps_plan_set_options(gps_plan *plan, const gps_options *opt);
 gps_status gps_plan_get_options(const gps_plan *plan, gps_options *opt);
 
@@ -144,7 +152,7 @@ size_t gps_plan_device_bytes(const gps_plan *plan);
  * spectrum); *buffers, the per-solve buffers that one solve in `precision`
  * with iteration cap maxit allocates (nonlinear_pb != 0: a nonlinear
  * Poisson-Boltzmann solve, which adds the ionic-charge field; refine != 0:
- * true-residual refinement on, which adds its FP64 buffers) and
+ * true-residual refinement or warm start on, which adds their FP64 buffers) and
  * gps_plan_release_buffers frees; *transient, held only while gps_plan_create
  * builds the Green's spectrum (FP64 padded spectrum for free and surface BC).
  * After one solve gps_plan_device_bytes reports *tables + *buffers.  Any

@@ -121,6 +121,7 @@ template <typename T> struct Res {
   double* lap64 = nullptr;         // periodic spectral Laplacian of sqrt(eps)
   cplx<double>* work64q = nullptr; // FP64 work for the spectral q (mixed + periodic)
   double* u64 = nullptr;           // refinement: G s (FP64)
+  bool have_src = false;           // src64 holds the source of the last solve's iterate
   cplx<double>* work64r = nullptr; // refinement: FP64 FFT work buffer
   // graphs of `chunk`, 4 and 1 PCG iterations (kernel arguments are
   // replay-invariant: the iteration counter lives in the solve state)
@@ -639,18 +640,20 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk, int refine) {
 // a solve runs few iterations past its stop decision (those launches exit at
 // once, but each still costs a dispatch) with few graph launches.
 template <typename T>
-SolveState run_pcg(gps_plan* pl, int check_neutral, const double* refine_rho = nullptr) {
+SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nullptr) {
   Res<T>& R = pl->res<T>();
   const int chunk = pl->opt.check_every;
-  // refinement every m iterations (refine_rho: the right-hand side), batches
-  // end at the refinement points
-  const int m = refine_rho ? pl->opt.refine_every : 0;
+  // track_rho (the right-hand side): the x passes keep the FP64 source s of
+  // the iterate, phi is recomputed from it on exit, and with refine_every = m
+  // the residual is recomputed every m iterations (batches end there)
+  const int track = track_rho != nullptr;
+  const int m = track ? pl->opt.refine_every : 0;
   int next_ref = m;
   // Timing needs readable events around single launches; events recorded
   // inside a captured graph cannot be read back, so timed solves launch
   // the same kernels directly on the stream.
   const bool timing = pl->timing_kind != GPS_K_NONE;
-  if (!timing) build_graph<T>(pl, check_neutral, chunk, m > 0);
+  if (!timing) build_graph<T>(pl, check_neutral, chunk, track);
   Batch b{};
   b.n = 1;
   b.slot[0] = 0;
@@ -665,7 +668,7 @@ SolveState run_pcg(gps_plan* pl, int check_neutral, const double* refine_rho = n
       pl->ev_pending.clear();
       pl->ev_used = 0;
       for (int j = 0; j < n; ++j)
-        enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->stream(), j, m > 0);
+        enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->stream(), j, track);
       ck(hipGetLastError());
     } else {
       // greedy: chunk graphs, then 4-iteration graphs, then single iterations
@@ -683,7 +686,7 @@ SolveState run_pcg(gps_plan* pl, int check_neutral, const double* refine_rho = n
     }
     if (st.done || k > pl->opt.maxit + 1) break;
     if (m > 0 && k == next_ref) {         // every iteration so far did work
-      refine_step<T>(pl, refine_rho, false);
+      refine_step<T>(pl, track_rho, false);
       next_ref += m;
     }
     // predicted iterations left: log-linear extrapolation of ||r||^2
@@ -697,16 +700,16 @@ SolveState run_pcg(gps_plan* pl, int check_neutral, const double* refine_rho = n
     prev_rr = st.rr;
     prev_it = st.iters;
   }
-  if (m > 0) refine_step<T>(pl, refine_rho, true);   // phi from the source s
+  if (track) refine_step<T>(pl, track_rho, true);   // phi from the source s
   return st;
 }
 
 template <typename T>
-void reset_state(gps_plan* pl, double abs_thr, double rel_thr) {
+void reset_state(gps_plan* pl, double abs_thr, double rel_thr, int rel_from_b = 0) {
   Res<T>& R = pl->res<T>();
   Batch b{};
   b.n = 1;
-  launch_reset_state<T>(R.tab, b, abs_thr, rel_thr, pl->stream());
+  launch_reset_state<T>(R.tab, b, abs_thr, rel_thr, rel_from_b, pl->stream());
 }
 
 template <typename T>
@@ -751,10 +754,15 @@ template <typename T>
 gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double* phi,
                       double tol, const Electrolyte& el) {
   const bool nonlinear = el.present && !el.linear;
-  // true-residual refinement: single PCG solves on invertible vacuum solvers
-  const bool refine = !nonlinear && pl->opt.refine_every > 0 && pl->bc != GPS_BC_PERIODIC;
-  ensure_res<T>(pl, nonlinear, refine);
+  // source tracking (refinement, warm start): single PCG solves on invertible
+  // vacuum solvers
+  const bool track = !nonlinear && pl->bc != GPS_BC_PERIODIC &&
+                     (pl->opt.refine_every > 0 || pl->opt.warm_start);
+  ensure_res<T>(pl, nonlinear, track);
   Res<T>& R = pl->res<T>();
+  // warm start from the resident source of the previous tracked solve
+  const bool warm = track && pl->opt.warm_start && R.have_src;
+  R.have_src = false;
   hipStream_t s = pl->stream();
   const long long n = pl->npts();
   const int periodic = pl->bc == GPS_BC_PERIODIC;
@@ -765,14 +773,14 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
   double rho_norm = 0.0;
   if (nonlinear) {
     // ||rho|| is needed before the first reset: one reduction on the host
-    launch_init<T>(R.tab, b, rho, eps, n, s);
+    launch_init<T>(R.tab, b, rho, eps, n, 0, s);
     ck(hipGetLastError());
     rho_norm = std::sqrt(read_sum<T>(pl, sl.part_init, vec_groups(n), 4, 3));
     reset_state<T>(pl, kFourPi * tol * rho_norm, 1e-2);
   } else {
-    reset_state<T>(pl, 0.0, tol);
+    reset_state<T>(pl, 0.0, tol, warm ? 1 : 0);
   }
-  launch_init<T>(R.tab, b, rho, eps, n, s);
+  launch_init<T>(R.tab, b, rho, eps, n, warm ? 1 : 0, s);
   if (nonlinear) launch_zero_ion<T>(R.tab, b, n, s);
   const double kcoef = (el.present && el.linear) ? el.kappa_coef : 0.0;
   const double* lap = nullptr;
@@ -789,7 +797,10 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
   ck(hipGetLastError());
   std::memset(&pl->info, 0, sizeof(pl->info));
   if (!nonlinear) {
-    const SolveState st = run_pcg<T>(pl, periodic && !el.present, refine ? rho : nullptr);
+    // warm start: phi_0 = S^-1 G s and r_0 = b - A phi_0 from the kept source
+    if (warm) refine_step<T>(pl, rho, false);
+    const SolveState st = run_pcg<T>(pl, periodic && !el.present, track ? rho : nullptr);
+    R.have_src = track && (st.status == GPS_OK || st.status == GPS_E_NOT_CONVERGED);
     finish_info<T>(pl, st, rho, phi, st.iters);
     pl->info.status = st.status;
     return (gps_status)st.status;
@@ -885,6 +896,7 @@ gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan** 
   pl->opt.check_every = 4;
   pl->opt.stream = nullptr;
   pl->opt.refine_every = 0;
+  pl->opt.warm_start = 0;
   Geom& g = pl->g;
   g.nx = nx;
   g.ny = ny;
@@ -948,7 +960,8 @@ gps_status gps_plan_set_options(gps_plan* pl, const gps_options* o) {
   if (o->precision != GPS_PREC_FP64 && o->precision != GPS_PREC_MIXED) return GPS_E_INVALID;
   if (o->fd_order < 2 || o->fd_order > 16 || (o->fd_order & 1)) return GPS_E_INVALID;
   if (o->maxit < 1 || o->check_every < 1) return GPS_E_INVALID;
-  if (o->refine_every < 0 || (o->refine_every > 0 && pl->bc == GPS_BC_PERIODIC))
+  if (o->refine_every < 0 ||
+      ((o->refine_every > 0 || o->warm_start) && pl->bc == GPS_BC_PERIODIC))
     return GPS_E_INVALID;
   pl->opt = *o;
   return GPS_OK;

@@ -89,6 +89,7 @@ struct SolveState {
   int restart;       // set by a refinement: the next iteration applies no update and
                      // starts a new direction (cleared by the y-inverse decision)
   int fresh;         // this iteration starts a direction: p = v (y-inverse decision)
+  int rel_from_b;    // warm start: the relative threshold is taken on ||4 pi rho||, not ||r_0||
 };
 
 // Input-check flags (SolveState::err)

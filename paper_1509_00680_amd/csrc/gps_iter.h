@@ -177,11 +177,14 @@ __device__ void pcg_decide(const Slot<T>& sl, const DecideArgs& a) {
   const double mu = a.periodic ? share_sum(smu, sl.part_mu, a.n_rr) : 0.0;
   double thr2, rsum = 0.0, rabs = 0.0;
   int status = -1;
+  double rr0 = rr;
   if (k == 0) {
     rsum = sum_partials(sl.part_init + 1, a.n_init, 4);
     rabs = sum_partials(sl.part_init + 2, a.n_init, 4);
+    // warm start: relative to ||4 pi rho|| (the init kernel's ||r||^2 of phi = 0)
+    if (st->rel_from_b) rr0 = sum_partials(sl.part_init + 0, a.n_init, 4);
     const int err = st->err;
-    thr2 = fmax(st->abs_thr * st->abs_thr, st->rel_thr * st->rel_thr * rr);
+    thr2 = fmax(st->abs_thr * st->abs_thr, st->rel_thr * st->rel_thr * rr0);
     if (err & kErrNonFinite) status = GPS_E_NONFINITE;
     else if (err & kErrEpsNonPositive) status = GPS_E_INVALID;
     else if (a.check_neutral && fabs(rsum) > 1e-10 * rabs) status = GPS_E_INVALID;
@@ -200,7 +203,7 @@ __device__ void pcg_decide(const Slot<T>& sl, const DecideArgs& a) {
   __syncthreads();                       // every thread has read restart
   if (threadIdx.x == 0) {
     if (k == 0) {
-      st->rr0 = rr;
+      st->rr0 = rr0;
       st->thr2 = thr2;
       st->rho_sum = rsum;
       st->rho_abs = rabs;

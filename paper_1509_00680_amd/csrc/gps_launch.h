@@ -140,11 +140,13 @@ struct IonParams {
 };
 
 template <typename T> void launch_reset_state(const SlotTable<T>& tab, const Batch& b,
-                                              double abs_thr, double rel_thr, hipStream_t s);
+                                              double abs_thr, double rel_thr, int rel_from_b,
+                                              hipStream_t s);
 template <typename T> void launch_set_g0(const SlotTable<T>& tab, const Batch& b, long long n,
                                          double norm, hipStream_t s);
 template <typename T> void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho,
-                                       const double* eps, long long n, hipStream_t s);
+                                       const double* eps, long long n, int keep_src,
+                                       hipStream_t s);
 template <typename T> void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g,
                                          int fd_half, const double* lap_sq, double kappa_coef,
                                          const double* eps, const double* gamma,

@@ -132,20 +132,22 @@ void launch_periodic_table(const Geom& g, int laplacian, double* t64, float* t32
 // solve-state reset (a kernel rather than a memset, so it may sit in a graph)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_reset_state(SlotTable<T> tab, Batch b, double abs_thr, double rel_thr) {
+__global__ void k_reset_state(SlotTable<T> tab, Batch b, double abs_thr, double rel_thr,
+                              int rel_from_b) {
   if (threadIdx.x == 0) {
     SolveState* st = tab.s[b.slot[blockIdx.x]].st;
     SolveState z{};
     z.abs_thr = abs_thr;
     z.rel_thr = rel_thr;
+    z.rel_from_b = rel_from_b;
     *st = z;
   }
 }
 
 template <typename T>
 void launch_reset_state(const SlotTable<T>& tab, const Batch& b, double abs_thr, double rel_thr,
-                        hipStream_t s) {
-  GPS_LAUNCH((k_reset_state<T>), dim3(b.n), dim3(64), 0, s, tab, b, abs_thr, rel_thr);
+                        int rel_from_b, hipStream_t s) {
+  GPS_LAUNCH((k_reset_state<T>), dim3(b.n), dim3(64), 0, s, tab, b, abs_thr, rel_thr, rel_from_b);
 }
 
 // Periodic boundaries with ions: the k = 0 multiplier 4 pi / mean(kappa2/eps)
@@ -176,7 +178,8 @@ void launch_set_g0(const SlotTable<T>& tab, const Batch& b, long long n, double 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_init(SlotTable<T> tab, Batch b,
                                                    const double* __restrict__ rho,
-                                                   const double* __restrict__ eps, long long n) {
+                                                   const double* __restrict__ eps, long long n,
+                                                   int keep_src) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
   // XCD-contiguous chunks: each XCD works on the same 1/8 of the grid as the
   // x passes, so fields written by one kernel are read from the same L2
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotTable<T> tab, Batch b,
       const T r0 = T(-kFourPi * rv);
       sl.r[i] = r0;
       sl.phi[i] = 0.0;
-      if (sl.src64) sl.src64[i] = 0.0;
+      if (sl.src64 && !keep_src) sl.src64[i] = 0.0;   // (kept: warm start from s)
       a0 += double(r0) * double(r0);
       a1 += rv;
       a2 += fabs(rv);
@@ -221,9 +224,9 @@ __global__ __launch_bounds__(kThreads) void k_init(SlotTable<T> tab, Batch b,
 
 template <typename T>
 void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho, const double* eps,
-                 long long n, hipStream_t s) {
+                 long long n, int keep_src, hipStream_t s) {
   GPS_LAUNCH((k_init<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, rho,
-                     eps, n);
+                     eps, n, keep_src);
 }
 
 // ---------------------------------------------------------------------------
@@ -586,12 +589,12 @@ void launch_refine(const SlotTable<T>& tab, const Batch& b, const double* rho, c
 }
 
 #define GPS_INST(T)                                                                              \
-  template void launch_reset_state<T>(const SlotTable<T>&, const Batch&, double, double,            \
+  template void launch_reset_state<T>(const SlotTable<T>&, const Batch&, double, double, int,       \
                                       hipStream_t);                                              \
   template void launch_set_g0<T>(const SlotTable<T>&, const Batch&, long long, double,            \
                                  hipStream_t);                                                   \
   template void launch_init<T>(const SlotTable<T>&, const Batch&, const double*, const double*,       \
-                               long long, hipStream_t);                                          \
+                               long long, int, hipStream_t);                                          \
   template void launch_qfield<T>(const SlotTable<T>&, const Batch&, const Geom&, int, const double*,  \
                                  double, const double*, const double*, double, hipStream_t);     \
   template void launch_ion_update<T>(const SlotTable<T>&, const Batch&, long long, const IonParams&,  \

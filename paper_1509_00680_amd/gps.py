@@ -37,7 +37,8 @@ KERNEL_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "xinv": 5}
 class gps_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("fd_order", ctypes.c_int),
                 ("maxit", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("refine_every", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("refine_every", ctypes.c_int),
+                ("warm_start", ctypes.c_int)]
 
 
 class gps_ions(ctypes.Structure):
@@ -207,7 +208,7 @@ class Plan:
     """A libgps plan for one grid, spacing and boundary condition."""
 
     def __init__(self, shape, h, bc, precision="fp64", fd_order=16, maxit=1000,
-                 check_every=8, stream=None, refine_every=0):
+                 check_every=8, stream=None, refine_every=0, warm_start=False):
         nz, ny, nx = shape
         self.shape = (nz, ny, nx)
         self.h = float(h)
@@ -216,15 +217,16 @@ class Plan:
         if st != GPS_OK:
             raise GPSError(st, "gps_plan_create(%d,%d,%d,%g,%s)" % (nx, ny, nz, h, bc))
         self.handle = handle
-        self.set_options(precision, fd_order, maxit, check_every, stream, refine_every)
+        self.set_options(precision, fd_order, maxit, check_every, stream, refine_every,
+                         warm_start)
 
     def set_options(self, precision="fp64", fd_order=16, maxit=1000, check_every=8,
-                    stream=None, refine_every=0):
+                    stream=None, refine_every=0, warm_start=False):
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
         o = gps_options(PRECISIONS[precision], int(fd_order), int(maxit), int(check_every),
-                        ctypes.c_void_p(stream), int(refine_every))
+                        ctypes.c_void_p(stream), int(refine_every), int(bool(warm_start)))
         st = load().gps_plan_set_options(self.handle, ctypes.byref(o))
         if st != GPS_OK:
             raise GPSError(st, "gps_plan_set_options")

@@ -207,3 +207,41 @@ def test_refinement_in_fp64_and_periodic_rejected():
     per = gps.Plan((16, 16, 16), 0.5, "periodic", precision="mixed")
     with pytest.raises(gps.GPSError):
         per.set_options("mixed", refine_every=8)
+    with pytest.raises(gps.GPSError):
+        per.set_options("mixed", warm_start=True)
+
+
+@pytest.mark.parametrize("bc", ["free", "surface"])
+def test_warm_start_repeated_solves(bc):
+    # Repeated solves with one dielectric (the paper's use inside an SCF loop):
+    # the next solve starts from the kept source of the previous iterate.  The
+    # same rho again needs (almost) no iterations and returns the same phi; a
+    # perturbed rho converges in fewer iterations than cold, to the oracle's
+    # answer.
+    require_gpu()
+    prob = W.molecule(32, 0.45, seed=7, n_atoms=10, ball=3.0, bc=bc)
+    d = W.molecule(32, 0.45, seed=8, n_atoms=10, ball=3.0, bc=bc).rho
+    rho2 = prob.rho + 0.02 * d
+    ref2 = pcg.pcg_solve(rho2, prob.eps, prob.h, bc, tol=1e-11)
+    warm = gps.Plan(prob.shape, prob.h, bc, precision="mixed", warm_start=True)
+    cold = gps.Plan(prob.shape, prob.h, bc, precision="mixed")
+    eps = dev(prob.eps)
+    phi1, phi1b, phi2, phi2c = (empty(prob.shape) for _ in range(4))
+    print("warm start", bc, flush=True)
+    assert warm.solve_generalized(dev(prob.rho), eps, phi1, 1e-6) == gps.GPS_OK
+    n1 = warm.info()["iterations"]
+    assert warm.solve_generalized(dev(prob.rho), eps, phi1b, 1e-6) == gps.GPS_OK
+    n1b = warm.info()["iterations"]
+    # the first solve stopped on its recursive FP32 residual; recomputed in FP64
+    # its true residual sits near the threshold, so a few iterations may remain
+    assert n1b <= max(6, n1 // 8), (n1, n1b)
+    assert np.abs(host(phi1b) - host(phi1)).max() <= 1e-5
+    assert warm.solve_generalized(dev(rho2), eps, phi2, 1e-6) == gps.GPS_OK
+    n2 = warm.info()["iterations"]
+    assert cold.solve_generalized(dev(rho2), eps, phi2c, 1e-6) == gps.GPS_OK
+    n2c = cold.info()["iterations"]
+    print("  iterations: first %d, same rho %d, perturbed %d (cold %d)" % (n1, n1b, n2, n2c))
+    assert n2 < n2c
+    assert np.abs(host(phi2) - ref2.phi).max() <= 1e-5
+    e_ref = pcg.electrostatic_energy(rho2, ref2.phi, prob.h)
+    assert abs(warm.info()["energy"] / e_ref - 1.0) <= 1e-6
