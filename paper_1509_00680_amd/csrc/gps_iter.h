@@ -77,17 +77,6 @@ __device__ __forceinline__ double share_sum(const PartShare<N>& s, const double*
   return block_sum((a0 + a1) + (a2 + a3));
 }
 
-// Work-group broadcast of thread 0's value (loaded earlier by thread 0).
-template <typename V>
-__device__ __forceinline__ V wg_bcast(V w) {
-  __shared__ V f;
-  if (threadIdx.x == 0) f = w;
-  __syncthreads();
-  const V r = f;
-  __syncthreads();
-  return r;
-}
-
 // ---- x-forward pass: the first kernel of iteration k ------------------------
 // N: (p, Ap) partials per thread held in registers (one partial per x-inverse
 // work-group; more are summed from memory).
@@ -122,12 +111,23 @@ template <typename T, int N>
 __device__ __forceinline__ bool xfwd_head_finish(const Slot<T>& sl, int n_pap_parts,
                                                  const XHead<N>& h, int* k_out,
                                                  double* alpha_out, bool* upd_out) {
-  if (wg_bcast(h.done)) return false;
-  const int k = wg_bcast(h.k);
+  // thread 0's state words, broadcast once: every wavefront of the work-group
+  // acts on the same values (work-group 0 may set done during the launch)
+  struct Words {
+    int done, k, restart;
+    double dprev0, dprev1;
+  };
+  __shared__ Words wb;
+  if (threadIdx.x == 0) wb = Words{h.done, h.k, h.restart, h.dprev0, h.dprev1};
+  __syncthreads();
+  const Words w = wb;
+  __syncthreads();
+  if (w.done) return false;
+  const int k = w.k;
   if (blockIdx.x == 0 && threadIdx.x == 0) sl.st->k = k;
   *k_out = k;
   double alpha = 0.0;
-  const bool upd = k > 0 && !wg_bcast(h.restart);
+  const bool upd = k > 0 && !w.restart;
   *upd_out = upd;
   if (upd) {
     const double pap = share_sum(h.pap, sl.part_pap, n_pap_parts);
@@ -139,7 +139,7 @@ __device__ __forceinline__ bool xfwd_head_finish(const Slot<T>& sl, int n_pap_pa
       }
       return false;
     }
-    const double dprev = wg_bcast(((k - 1) & 1) ? h.dprev1 : h.dprev0);
+    const double dprev = ((k - 1) & 1) ? w.dprev1 : w.dprev0;
     alpha = dprev / pap;
     if (blockIdx.x == 0 && threadIdx.x == 0) sl.hist[(size_t)(k - 1) * 4 + 2] = alpha;
   }
