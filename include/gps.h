@@ -72,10 +72,10 @@ typedef struct {
   int precision;     /* gps_precision, default GPS_PREC_FP64 */
   int fd_order;      /* even order of the central differences of q (2..16), default 16 */
   int maxit;         /* PCG iteration cap, default 1000 */
-  int check_every;   /* PCG iterations per replayed graph, default 4; between
-                        polls of the device state the host replays this graph and,
-                        for the remainder of the predicted iteration count,
-                        4-iteration and one-iteration graphs */
+  int check_every;   /* base length (PCG iterations) of the replayed graphs, default 4;
+                        between polls of the device state the host replays graphs of
+                        4, 2 and 1 times this length and of 4, 2 and 1 iterations to
+                        cover the predicted iteration count */
   void *stream;      /* hipStream_t the solves run on; NULL = null stream */
   int refine_every;  /* true-residual refinement every m PCG iterations (0 = off, the
                         default).  The iterate is kept as sqrt(eps) phi = G s with the

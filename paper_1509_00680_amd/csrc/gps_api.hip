@@ -123,19 +123,20 @@ template <typename T> struct Res {
   double* u64 = nullptr;           // refinement: G s (FP64)
   bool have_src = false;           // src64 holds the source of the last solve's iterate
   cplx<double>* work64r = nullptr; // refinement: FP64 FFT work buffer
-  // graphs of `chunk`, 4 and 1 PCG iterations (kernel arguments are
-  // replay-invariant: the iteration counter lives in the solve state)
-  hipGraphExec_t graph = nullptr;
-  hipGraphExec_t graph4 = nullptr;
-  hipGraphExec_t graph1 = nullptr;
+  // graphs of 4, 2 and 1 times `chunk` and of 4, 2 and 1 PCG iterations,
+  // longest first (kernel arguments are replay-invariant: the iteration
+  // counter lives in the solve state)
+  static constexpr int kGraphs = 6;
+  hipGraphExec_t graphs[kGraphs] = {};
+  int graph_iters[kGraphs] = {};
   int graph_neutral = -1, graph_timing = -1, graph_chunk = 0, graph_refine = -1;
 };
 
 template <typename T>
 void drop_graphs(Res<T>& R) {
-  for (hipGraphExec_t* g : {&R.graph, &R.graph4, &R.graph1}) {
-    if (*g) (void)hipGraphExecDestroy(*g);
-    *g = nullptr;
+  for (hipGraphExec_t& g : R.graphs) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
   }
 }
 
@@ -604,7 +605,7 @@ void vacuum_apply(gps_plan* pl, const double* f, double* u) {
 template <typename T>
 void build_graph(gps_plan* pl, int check_neutral, int chunk, int refine) {
   Res<T>& R = pl->res<T>();
-  if (R.graph && R.graph4 && R.graph1 && R.graph_neutral == check_neutral &&
+  if (R.graphs[0] && R.graph_neutral == check_neutral &&
       R.graph_timing == pl->timing_kind && R.graph_chunk == chunk && R.graph_refine == refine)
     return;
   drop_graphs(R);
@@ -625,9 +626,11 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk, int refine) {
     (void)hipGraphDestroy(graph);
     if (e2 != hipSuccess) throw DevError{e2};
   };
-  capture(chunk, &R.graph);
-  capture(4, &R.graph4);
-  capture(1, &R.graph1);
+  const int sizes[Res<T>::kGraphs] = {4 * chunk, 2 * chunk, chunk, 4, 2, 1};
+  for (int i = 0; i < Res<T>::kGraphs; ++i) {
+    R.graph_iters[i] = sizes[i];
+    capture(sizes[i], &R.graphs[i]);
+  }
   R.graph_neutral = check_neutral;
   R.graph_timing = pl->timing_kind;
   R.graph_chunk = chunk;
@@ -636,9 +639,10 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk, int refine) {
 
 // Run PCG iterations until the device-side state says done.  Between host
 // polls the host enqueues n iterations, n predicted from the recent residual
-// decay, as replays of the chunk, 4-iteration and 1-iteration graphs, so that
-// a solve runs few iterations past its stop decision (those launches exit at
-// once, but each still costs a dispatch) with few graph launches.
+// decay, as replays of graphs of 4, 2, 1 chunks and 4, 2, 1 iterations, so
+// that a solve runs few iterations past its stop decision (those launches
+// exit at once, but each still costs a dispatch) with few graph launches
+// (each costs about as much idle GPU time as an early-exit iteration).
 template <typename T>
 SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nullptr) {
   Res<T>& R = pl->res<T>();
@@ -671,11 +675,11 @@ SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nu
         enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->stream(), j, track);
       ck(hipGetLastError());
     } else {
-      // greedy: chunk graphs, then 4-iteration graphs, then single iterations
+      // greedy over the graph lengths, longest first: few graph launches
       int left = n;
-      for (; left >= chunk; left -= chunk) ck(hipGraphLaunch(R.graph, pl->stream()));
-      for (; left >= 4; left -= 4) ck(hipGraphLaunch(R.graph4, pl->stream()));
-      for (; left > 0; --left) ck(hipGraphLaunch(R.graph1, pl->stream()));
+      for (int i = 0; i < Res<T>::kGraphs; ++i)
+        for (; left >= R.graph_iters[i]; left -= R.graph_iters[i])
+          ck(hipGraphLaunch(R.graphs[i], pl->stream()));
     }
     const int k_base = k;
     k += n;
