@@ -19,6 +19,9 @@ Modules
   pb       -- ionic charge (Eqs. ionsconcPB, ionsconcMPB, maxconc) and the
               self-consistent loops of Algorithms SCPB and SCPBimproved.
   dense    -- dense direct solve of the same discrete problem (tiny grids).
+  cavity   -- rigid cavity of Eq. RigCav with its analytic q (Sec. IV.A), and
+              the polarization charge of Eqs. rhoiter / remap / rhopol with
+              order-2M first differences.
 
 Every floating-point quantity is IEEE binary64.  Grid fields are numpy arrays
 of shape (nz, ny, nx), x fastest, cell-centred: point (i, j, k) sits at
