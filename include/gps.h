@@ -198,6 +198,46 @@ gps_status gps_solve_pb(gps_plan *plan, const double *rho, const double *eps,
  * Errors: GPS_E_INVALID (null pointer), GPS_E_NOMEM, GPS_E_DEVICE. */
 gps_status gps_solve_vacuum(gps_plan *plan, const double *f, double *u);
 
+/* As gps_solve_generalized, with the correction vector q of Eq. corr
+ * (q = sqrt(eps) lap sqrt(eps), in bohr^-2) given by the caller instead of the
+ * plan's finite-difference one: for instance the analytic q of
+ * gps_rigid_cavity (Sec. IV.A: every field that depends on eps follows
+ * analytically from the cavity).  q: device double[nz][ny][nx], read only,
+ * rounded to the bulk precision like the computed q.  Free and surface
+ * boundaries only: with periodic boundaries the operator annihilates constants
+ * only for the q of the plan's spectral Laplacian.  Errors: as
+ * gps_solve_generalized, plus GPS_E_INVALID for a null q or a periodic plan. */
+gps_status gps_solve_generalized_q(gps_plan *plan, const double *rho, const double *eps,
+                                   const double *q, double *phi, double tol);
+
+/* Rigid cavity of Eq. RigCav (Sec. IV.A) on the plan's grid:
+ *   eps(r) = (eps0 - 1) prod_i h(d_i, Delta; |r - R_i|) + 1,
+ * h the erf switch of Eq. hfunc, and, when q is not NULL, its correction
+ * vector q = sqrt(eps) lap sqrt(eps) evaluated analytically (product rule over
+ * the atoms; at a grid point on an atom centre that atom's cusp contributes
+ * h''(0) to the Laplacian and nothing to the gradient).  Separations along
+ * periodic axes of the plan are minimum-image ones in the cell of n h.
+ * atoms: DEVICE array of natoms x 4 doubles (X, Y, Z, d_i) in bohr, in the
+ * grid's coordinates (the grid is centred on the origin); eps and q: device
+ * double[nz][ny][nx], written.  FP64.  Runs on the plan's stream and returns
+ * when it has finished.  Errors: GPS_E_INVALID (null plan, atoms or eps,
+ * natoms < 1, Delta <= 0, eps0 < 1, a non-finite value, a radius <= 0),
+ * GPS_E_DEVICE. */
+gps_status gps_rigid_cavity(gps_plan *plan, int natoms, const double *atoms, double delta,
+                            double eps0, double *eps, double *q);
+
+/* Polarization charge of the dielectric for a potential phi (Eqs. rhoiter,
+ * remap; Eq. rhopol with the sign that Eq. remap implies):
+ *   rho_pol = (1/4 pi) grad ln eps . grad phi - (1 - 1/eps) rho,
+ * so that lap phi = -4 pi (rho + rho_pol).  Gradients are central
+ * differences of the plan's fd_order, with edge-replicated ghosts on free axes
+ * and wrapped ones on periodic axes.  rho, eps, phi: device, read; rho_pol:
+ * device, written; all double[nz][ny][nx].  FP64.  Runs on the plan's stream
+ * and returns when it has finished.  Errors: GPS_E_INVALID (null pointer),
+ * GPS_E_DEVICE. */
+gps_status gps_polarization_charge(gps_plan *plan, const double *rho, const double *eps,
+                                   const double *phi, double *rho_pol);
+
 /* Information about the last solve of this plan. */
 gps_status gps_last_info(const gps_plan *plan, gps_info *out);
 

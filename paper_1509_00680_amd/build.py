@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgps.so")
-SOURCES = ["gps_fft.hip", "gps_fft_fast.hip", "gps_ops.hip", "gps_api.hip", "gps_server.hip"]
+SOURCES = ["gps_fft.hip", "gps_fft_fast.hip", "gps_ops.hip", "gps_cavity.hip", "gps_api.hip",
+           "gps_server.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

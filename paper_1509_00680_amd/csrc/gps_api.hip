@@ -756,7 +756,7 @@ struct Electrolyte {
 
 template <typename T>
 gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double* phi,
-                      double tol, const Electrolyte& el) {
+                      double tol, const Electrolyte& el, const double* q_user) {
   const bool nonlinear = el.present && !el.linear;
   // source tracking (refinement, warm start): single PCG solves on invertible
   // vacuum solvers
@@ -787,13 +787,17 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
   launch_init<T>(R.tab, b, rho, eps, n, warm ? 1 : 0, s);
   if (nonlinear) launch_zero_ion<T>(R.tab, b, n, s);
   const double kcoef = (el.present && el.linear) ? el.kappa_coef : 0.0;
-  const double* lap = nullptr;
-  if (periodic) {
-    spectral_laplacian<T>(pl);
-    lap = R.lap64;
+  if (q_user) {
+    launch_qcopy<T>(R.tab, b, n, q_user, s);
+  } else {
+    const double* lap = nullptr;
+    if (periodic) {
+      spectral_laplacian<T>(pl);
+      lap = R.lap64;
+    }
+    launch_qfield<T>(R.tab, b, pl->g, pl->opt.fd_order / 2, lap, kcoef, eps, el.ip.gamma,
+                     el.ip.eps_bulk, s);
   }
-  launch_qfield<T>(R.tab, b, pl->g, pl->opt.fd_order / 2, lap, kcoef, eps, el.ip.gamma,
-                   el.ip.eps_bulk, s);
   if (periodic && kcoef != 0.0) {
     const Geom& g = pl->g;
     launch_set_g0<T>(R.tab, b, n, 1.0 / ((double)g.Lx * g.Ly * g.Lz), s);
@@ -1034,11 +1038,12 @@ void gps_plan_destroy(gps_plan* pl) {
 }
 
 static gps_status run_guarded(gps_plan* pl, bool mixed, const double* rho, const double* eps,
-                              double* phi, double tol, const Electrolyte& el) {
+                              double* phi, double tol, const Electrolyte& el,
+                              const double* q_user = nullptr) {
   pl->info.device_error = 0;
   try {
-    if (mixed) return solve_impl<float>(pl, rho, eps, phi, tol, el);
-    return solve_impl<double>(pl, rho, eps, phi, tol, el);
+    if (mixed) return solve_impl<float>(pl, rho, eps, phi, tol, el, q_user);
+    return solve_impl<double>(pl, rho, eps, phi, tol, el, q_user);
   } catch (const NoMem&) {
     return GPS_E_NOMEM;
   } catch (const DevError& d) {
@@ -1053,6 +1058,56 @@ gps_status gps_solve_generalized(gps_plan* pl, const double* rho, const double* 
   if (!pl || !rho || !eps || !phi || !(tol > 0.0) || !std::isfinite(tol)) return GPS_E_INVALID;
   Electrolyte el;
   return run_guarded(pl, pl->opt.precision == GPS_PREC_MIXED, rho, eps, phi, tol, el);
+}
+
+gps_status gps_solve_generalized_q(gps_plan* pl, const double* rho, const double* eps,
+                                   const double* q, double* phi, double tol) {
+  if (!pl || !rho || !eps || !q || !phi || !(tol > 0.0) || !std::isfinite(tol))
+    return GPS_E_INVALID;
+  if (pl->bc == GPS_BC_PERIODIC) return GPS_E_INVALID;
+  Electrolyte el;
+  return run_guarded(pl, pl->opt.precision == GPS_PREC_MIXED, rho, eps, phi, tol, el, q);
+}
+
+gps_status gps_rigid_cavity(gps_plan* pl, int natoms, const double* atoms, double delta,
+                            double eps0, double* eps, double* q) {
+  if (!pl || natoms < 1 || !atoms || !eps || !(delta > 0.0) || !std::isfinite(delta) ||
+      !(eps0 >= 1.0) || !std::isfinite(eps0))
+    return GPS_E_INVALID;
+  try {
+    // the atom table is checked on the host (finite centres, radii > 0)
+    std::vector<double> h((size_t)natoms * 4);
+    ck(hipMemcpyAsync(h.data(), atoms, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                      pl->stream()));
+    ck(hipStreamSynchronize(pl->stream()));
+    for (int a = 0; a < natoms; ++a) {
+      const double* at = &h[(size_t)a * 4];
+      if (!std::isfinite(at[0]) || !std::isfinite(at[1]) || !std::isfinite(at[2]) ||
+          !(at[3] > 0.0) || !std::isfinite(at[3]))
+        return GPS_E_INVALID;
+    }
+    launch_rigid_cavity(pl->g, atoms, natoms, delta, eps0, eps, q, pl->stream());
+    ck(hipGetLastError());
+    ck(hipStreamSynchronize(pl->stream()));
+  } catch (const DevError& d) {
+    pl->info.device_error = (int)d.e;
+    return GPS_E_DEVICE;
+  }
+  return GPS_OK;
+}
+
+gps_status gps_polarization_charge(gps_plan* pl, const double* rho, const double* eps,
+                                   const double* phi, double* rho_pol) {
+  if (!pl || !rho || !eps || !phi || !rho_pol) return GPS_E_INVALID;
+  try {
+    launch_polarization(pl->g, pl->opt.fd_order / 2, rho, eps, phi, rho_pol, pl->stream());
+    ck(hipGetLastError());
+    ck(hipStreamSynchronize(pl->stream()));
+  } catch (const DevError& d) {
+    pl->info.device_error = (int)d.e;
+    return GPS_E_DEVICE;
+  }
+  return GPS_OK;
 }
 
 gps_status gps_solve_pb(gps_plan* pl, const double* rho, const double* eps, const gps_ions* ions,

@@ -1,0 +1,241 @@
+// Cavity builder and diagnostics around the PCG solve:
+//  * the rigid cavity of Eq. RigCav (Sec. IV.A) with its analytic correction
+//    vector q = sqrt(eps) lap sqrt(eps) (Eq. corr);
+//  * the polarization charge of Eqs. rhoiter and remap,
+//    rho_pol = (1/4 pi) grad ln eps . grad phi - (1 - 1/eps) rho,
+//    with order-2M central first differences (the sign of the second term is
+//    the one Eq. remap implies; Eq. rhopol prints a plus).
+#include "gps_device.h"
+#include "gps_launch.h"
+
+namespace gps {
+
+// ---------------------------------------------------------------------------
+// Rigid cavity.  With a = eps0 - 1, h_i = erfc(-t_i)/2, t_i = (r_i - d_i)/Delta
+// (Eq. hfunc) and H = prod_i h_i:  eps = a H + 1 and
+//   q = (a/2) lap H - a^2 |grad H|^2 / (4 eps).
+// The derivatives of H go through the logarithmic derivatives
+//   u_i = h_i'/h_i = 2 / (Delta sqrt(pi) erfcx(-t_i)),
+// which stay finite where h_i underflows (deep inside an atom):
+//   grad H = H G,  G = sum_i u_i (r - R_i)/r_i,
+//   lap H  = H (|G|^2 + sum_i [u_i (2/r_i - 2 t_i/Delta) - u_i^2]).
+// At r_i = 0 (a grid point on an atom centre) the radial switch has a cusp;
+// its gradient is taken as 0 and its Laplacian as h_i''(0): the atom adds
+// -2 t_i u_i/Delta only.  Periodic axes use minimum-image separations.
+// One grid point per thread; the atom table is read with uniform loads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_rigid_cavity(Geom g,
+                                                           const double* __restrict__ atoms,
+                                                           int natoms, double delta, double eps0,
+                                                           double* __restrict__ eps,
+                                                           double* __restrict__ q) {
+  const int n = g.nx * g.ny * g.nz;
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int plane = g.nx * g.ny;
+  const int iz = i / plane;
+  const int iy = (i - iz * plane) / g.nx;
+  const int ix = i - iz * plane - iy * g.nx;
+  const double x = (ix - 0.5 * (g.nx - 1)) * g.h;
+  const double y = (iy - 0.5 * (g.ny - 1)) * g.h;
+  const double z = (iz - 0.5 * (g.nz - 1)) * g.h;
+  const double lx = g.nx * g.h, ly = g.ny * g.h, lz = g.nz * g.h;
+  const double idelta = 1.0 / delta;
+  const double cu = 2.0 / (delta * 1.7724538509055160273);   // 2 / (Delta sqrt(pi))
+  double H = 1.0, gx = 0.0, gy = 0.0, gz = 0.0, w = 0.0;
+  for (int a = 0; a < natoms; ++a) {
+    const double* at = atoms + 4 * a;
+    double dx = x - at[0], dy = y - at[1], dz = z - at[2];
+    if (g.periodic_x) dx -= lx * rint(dx / lx);
+    if (g.periodic_y) dy -= ly * rint(dy / ly);
+    if (g.periodic_z) dz -= lz * rint(dz / lz);
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double t = (r - at[3]) * idelta;
+    H *= 0.5 * erfc(-t);
+    const double u = cu / erfcx(-t);
+    w -= 2.0 * t * u * idelta;
+    if (r > 0.0) {
+      const double ur = u / r;
+      gx += ur * dx;
+      gy += ur * dy;
+      gz += ur * dz;
+      w += 2.0 * ur - u * u;
+    }
+  }
+  const double a = eps0 - 1.0;
+  const double aH = a * H;
+  const double e = aH + 1.0;
+  eps[i] = e;
+  if (q) {
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    q[i] = 0.5 * aH * (g2 + w) - aH * aH * g2 / (4.0 * e);
+  }
+}
+
+void launch_rigid_cavity(const Geom& g, const double* atoms, int natoms, double delta,
+                         double eps0, double* eps, double* q, hipStream_t s) {
+  const long long n = (long long)g.nx * g.ny * g.nz;
+  GPS_LAUNCH(k_rigid_cavity, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+             s, g, atoms, natoms, delta, eps0, eps, q);
+}
+
+// ---------------------------------------------------------------------------
+// Polarization charge.  First differences of order 2M:
+//   f'(x) ~ (1/h) sum_{m=1..M} c_m (f(x + m h) - f(x - m h)),
+//   c_m = (-1)^(m+1) (M!)^2 / (m (M - m)! (M + m)!),
+// with the ghosts of the q stencil (edge-replicated on free axes, wrapped on
+// periodic ones).  2.5D like the q stencil: a kPTX x kPTY column tile marches
+// along z over kPZC planes; x and y neighbours of ln eps and phi come from
+// two LDS tiles with an M-wide halo, z neighbours from two register queues of
+// 2M+1 planes, and the next plane's loads are in flight while the current
+// one is differenced.  ln eps is taken as each value is loaded.
+// ---------------------------------------------------------------------------
+struct FdFirst { double c[9]; };
+
+constexpr int kPTX = 32, kPTY = 16, kPZC = 4;
+constexpr int kPThreads = kPTX * kPTY;
+
+template <int M>
+__global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, int ntx, int nty,
+                                                            const double* __restrict__ rho,
+                                                            const double* __restrict__ eps,
+                                                            const double* __restrict__ phi,
+                                                            double* __restrict__ out) {
+  constexpr int TW = kPTX + 2 * M;
+  constexpr int TH = kPTY + 2 * M;
+  constexpr int NXH = 2 * M * kPTY;                // halo slots left and right of the tile
+  constexpr int NH = NXH + 2 * M * kPTX;           // ... plus above and below
+  constexpr int HS = (NH + kPThreads - 1) / kPThreads;
+  __shared__ double te[TH * TW];
+  __shared__ double tp[TH * TW];
+  const int tid = threadIdx.x;
+  const int tx = tid % kPTX, ty = tid / kPTX;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);   // x fastest, then y, then z chunk
+  const int ntxy = ntx * nty;
+  const int zc = t / ntxy;
+  const int yt = (t - zc * ntxy) / ntx;
+  const int xt = t - zc * ntxy - yt * ntx;
+  const int x0 = xt * kPTX, y0 = yt * kPTY, z0 = zc * kPZC;
+  const int z1 = min(z0 + kPZC, g.nz);
+  const int X = x0 + tx, Y = y0 + ty;
+  const int plane = g.nx * g.ny;
+  const int cxy = ghost_index(Y, g.ny, g.periodic_y) * g.nx + ghost_index(X, g.nx, g.periodic_x);
+  int hl[HS], ho[HS];
+#pragma unroll
+  for (int s = 0; s < HS; ++s) {
+    const int j = min(tid + s * kPThreads, NH - 1);   // surplus threads repeat the last slot
+    int hx, hy;
+    if (j < NXH) {
+      const int row = j / (2 * M), c = j - (j / (2 * M)) * (2 * M);
+      hx = c < M ? c : c + kPTX;
+      hy = M + row;
+    } else {
+      const int jj = j - NXH;
+      const int row = jj / kPTX, c = jj - (jj / kPTX) * kPTX;
+      hx = M + c;
+      hy = row < M ? row : row + kPTY;
+    }
+    hl[s] = hy * TW + hx;
+    ho[s] = ghost_index(y0 - M + hy, g.ny, g.periodic_y) * g.nx +
+            ghost_index(x0 - M + hx, g.nx, g.periodic_x);
+  }
+  double qe[2 * M + 1], qp[2 * M + 1];             // planes z - M .. z + M of this column
+#pragma unroll
+  for (int k = 0; k <= 2 * M; ++k) {
+    const size_t o = (size_t)ghost_index(z0 - M + k, g.nz, g.periodic_z) * plane + cxy;
+    qe[k] = log(eps[o]);
+    qp[k] = phi[o];
+  }
+  double he[HS], hp[HS];
+#pragma unroll
+  for (int s = 0; s < HS; ++s) {
+    he[s] = log(eps[(size_t)z0 * plane + ho[s]]);
+    hp[s] = phi[(size_t)z0 * plane + ho[s]];
+  }
+  const double scale = 1.0 / (4.0 * kPi * g.h * g.h);
+  const bool inside = X < g.nx && Y < g.ny;
+  for (int z = z0; z < z1; ++z) {
+    te[(M + ty) * TW + M + tx] = qe[M];
+    tp[(M + ty) * TW + M + tx] = qp[M];
+#pragma unroll
+    for (int s = 0; s < HS; ++s) {
+      te[hl[s]] = he[s];
+      tp[hl[s]] = hp[s];
+    }
+    __syncthreads();
+    const int zn = min(z + 1, g.nz - 1);
+    double hne[HS], hnp[HS];
+#pragma unroll
+    for (int s = 0; s < HS; ++s) {
+      hne[s] = eps[(size_t)zn * plane + ho[s]];
+      hnp[s] = phi[(size_t)zn * plane + ho[s]];
+    }
+    const size_t on = (size_t)ghost_index(z + 1 + M, g.nz, g.periodic_z) * plane + cxy;
+    const double qne = eps[on], qnp = phi[on];
+    double rv = 0.0, ev = 1.0;
+    const size_t o = (size_t)z * plane + (size_t)Y * g.nx + X;
+    if (inside) {
+      rv = rho[o];
+      ev = eps[o];
+    }
+    const double* ce = &te[(M + ty) * TW + M + tx];
+    const double* cp = &tp[(M + ty) * TW + M + tx];
+    double exd = 0.0, eyd = 0.0, ezd = 0.0, pxd = 0.0, pyd = 0.0, pzd = 0.0;
+#pragma unroll
+    for (int m = 1; m <= M; ++m) {
+      exd = fma(w.c[m], ce[m] - ce[-m], exd);
+      eyd = fma(w.c[m], ce[m * TW] - ce[-m * TW], eyd);
+      ezd = fma(w.c[m], qe[M + m] - qe[M - m], ezd);
+      pxd = fma(w.c[m], cp[m] - cp[-m], pxd);
+      pyd = fma(w.c[m], cp[m * TW] - cp[-m * TW], pyd);
+      pzd = fma(w.c[m], qp[M + m] - qp[M - m], pzd);
+    }
+    if (inside) out[o] = (exd * pxd + eyd * pyd + ezd * pzd) * scale - (1.0 - 1.0 / ev) * rv;
+    __syncthreads();                              // tile reads done before the next writes
+#pragma unroll
+    for (int k = 0; k < 2 * M; ++k) {
+      qe[k] = qe[k + 1];
+      qp[k] = qp[k + 1];
+    }
+    qe[2 * M] = log(qne);
+    qp[2 * M] = qnp;
+#pragma unroll
+    for (int s = 0; s < HS; ++s) {
+      he[s] = log(hne[s]);
+      hp[s] = hnp[s];
+    }
+  }
+}
+
+static FdFirst fd_first_weights(int M) {
+  FdFirst w{};
+  double fM = 1.0;
+  for (int i = 2; i <= M; ++i) fM *= i;
+  for (int m = 1; m <= M; ++m) {
+    double fa = 1.0, fb = 1.0;
+    for (int i = 2; i <= M - m; ++i) fa *= i;
+    for (int i = 2; i <= M + m; ++i) fb *= i;
+    w.c[m] = (m % 2 == 1 ? 1.0 : -1.0) * fM * fM / (double(m) * fa * fb);
+  }
+  return w;
+}
+
+void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
+                         const double* phi, double* out, hipStream_t s) {
+  const int ntx = (g.nx + kPTX - 1) / kPTX, nty = (g.ny + kPTY - 1) / kPTY;
+  const int nzc = (g.nz + kPZC - 1) / kPZC;
+  const dim3 grid(ntx * nty * nzc);
+  const FdFirst w = fd_first_weights(fd_half);
+#define GPS_PF(MM)                                                                        \
+  case MM:                                                                                \
+    GPS_LAUNCH((k_polarization<MM>), grid, dim3(kPThreads), 0, s, g, w, ntx, nty, rho,    \
+               eps, phi, out);                                                            \
+    break;
+  switch (fd_half) {
+    GPS_PF(1) GPS_PF(2) GPS_PF(3) GPS_PF(4) GPS_PF(5) GPS_PF(6) GPS_PF(7) GPS_PF(8)
+    default: break;
+  }
+#undef GPS_PF
+}
+
+}  // namespace gps

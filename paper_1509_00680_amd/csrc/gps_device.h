@@ -86,6 +86,15 @@ __device__ __forceinline__ int xcd_tile(int bid, int G) {
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// Ghost index on an axis of n points: wrapped (periodic) or edge-replicated.
+__device__ __forceinline__ int ghost_index(int i, int n, int periodic) {
+  if (periodic) {
+    i %= n;
+    return i < 0 ? i + n : i;
+  }
+  return min(max(i, 0), n - 1);
+}
+
 // Element at a 32-bit byte offset from a work-group-uniform base pointer.
 // The address is then the scalar base plus a 32-bit vector offset, with no
 // 64-bit vector arithmetic.  Callers guarantee offsets below 4 GiB.

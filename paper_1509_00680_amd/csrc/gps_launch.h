@@ -151,6 +151,8 @@ template <typename T> void launch_qfield(const SlotTable<T>& tab, const Batch& b
                                          int fd_half, const double* lap_sq, double kappa_coef,
                                          const double* eps, const double* gamma,
                                          double eps_bulk, hipStream_t s);
+template <typename T> void launch_qcopy(const SlotTable<T>& tab, const Batch& b, long long n,
+                                        const double* q, hipStream_t s);
 template <typename T> void launch_ion_update(const SlotTable<T>& tab, const Batch& b, long long n,
                                              const IonParams& ip, int first, hipStream_t s);
 template <typename T> void launch_energy(const SlotTable<T>& tab, const Batch& b, const double* rho,
@@ -160,5 +162,11 @@ template <typename T> void launch_zero_ion(const SlotTable<T>& tab, const Batch&
 template <typename T> void launch_refine(const SlotTable<T>& tab, const Batch& b, const double* rho,
                                          const double* u, long long n, int final_step,
                                          hipStream_t s);
+
+// Cavity builder and diagnostics (gps_cavity.hip)
+void launch_rigid_cavity(const Geom& g, const double* atoms, int natoms, double delta,
+                         double eps0, double* eps, double* q, hipStream_t s);
+void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
+                         const double* phi, double* out, hipStream_t s);
 
 }  // namespace gps

@@ -237,15 +237,6 @@ void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho, con
 // ---------------------------------------------------------------------------
 struct FdWeights { double c[9]; };
 
-// Ghost index on an axis of n points: wrapped (periodic) or edge-replicated.
-__device__ __forceinline__ int ghost_index(int i, int n, int periodic) {
-  if (periodic) {
-    i %= n;
-    return i < 0 ? i + n : i;
-  }
-  return min(max(i, 0), n - 1);
-}
-
 // Stencil form (free and surface boundaries), 2.5D: a work-group owns a
 // kQTX x kQTY column tile and marches along z over kQZC planes.  The x and y
 // neighbours of a plane come from an LDS tile with an M-wide halo (no
@@ -380,6 +371,31 @@ __global__ __launch_bounds__(kThreads) void k_qfield(SlotTable<T> tab, Batch b, 
   }
   kacc = block_sum(kacc);
   if (threadIdx.x == 0) sl.part_aux[blockIdx.x] = kacc;
+}
+
+// Caller-supplied q (for instance the analytic q of a rigid cavity):
+// q + kappa2 is q itself (no electrolyte on this path).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_qcopy(SlotTable<T> tab, Batch b, long long n,
+                                                    const double* __restrict__ q) {
+  const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
+  const long long base =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * kThreads * kVec + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) {
+      const double v = q[i];
+      sl.qk[i] = T(v);
+      if (sl.qk64) sl.qk64[i] = v;
+    }
+  }
+}
+
+template <typename T>
+void launch_qcopy(const SlotTable<T>& tab, const Batch& b, long long n, const double* q,
+                  hipStream_t s) {
+  GPS_LAUNCH((k_qcopy<T>), dim3(vec_groups(n), b.n), dim3(kThreads), 0, s, tab, b, n, q);
 }
 
 static FdWeights fd_weights(int M) {
@@ -597,6 +613,8 @@ void launch_refine(const SlotTable<T>& tab, const Batch& b, const double* rho, c
                                long long, int, hipStream_t);                                          \
   template void launch_qfield<T>(const SlotTable<T>&, const Batch&, const Geom&, int, const double*,  \
                                  double, const double*, const double*, double, hipStream_t);     \
+  template void launch_qcopy<T>(const SlotTable<T>&, const Batch&, long long, const double*,        \
+                                hipStream_t);                                                    \
   template void launch_ion_update<T>(const SlotTable<T>&, const Batch&, long long, const IonParams&,  \
                                      int, hipStream_t);                                          \
   template void launch_zero_ion<T>(const SlotTable<T>&, const Batch&, long long, hipStream_t);        \

@@ -27,7 +27,8 @@ GPS_PENDING = 8
 # every symbol include/gps.h declares
 EXPORTED = ("gps_plan_create", "gps_plan_set_options", "gps_plan_get_options",
             "gps_plan_device_bytes", "gps_plan_destroy", "gps_solve_generalized",
-            "gps_solve_pb", "gps_solve_vacuum", "gps_last_info", "gps_last_history",
+            "gps_solve_pb", "gps_solve_vacuum", "gps_solve_generalized_q", "gps_rigid_cavity",
+            "gps_polarization_charge", "gps_last_info", "gps_last_history",
             "gps_plan_set_timing", "gps_plan_timing", "gps_status_string",
             "gps_plan_footprint", "gps_plan_release_buffers", "gps_server_create", "gps_server_submit", "gps_server_poll",
             "gps_server_wait", "gps_server_get_stats", "gps_server_destroy")
@@ -126,6 +127,12 @@ def load(path=LIB_PATH):
     lib.gps_solve_pb.restype = I
     lib.gps_solve_vacuum.argtypes = [P, P, P]
     lib.gps_solve_vacuum.restype = I
+    lib.gps_solve_generalized_q.argtypes = [P, P, P, P, P, D]
+    lib.gps_solve_generalized_q.restype = I
+    lib.gps_rigid_cavity.argtypes = [P, I, P, D, D, P, P]
+    lib.gps_rigid_cavity.restype = I
+    lib.gps_polarization_charge.argtypes = [P, P, P, P, P]
+    lib.gps_polarization_charge.restype = I
     lib.gps_last_info.argtypes = [P, ctypes.POINTER(gps_info)]
     lib.gps_last_info.restype = I
     lib.gps_last_history.argtypes = [P, ctypes.POINTER(D), I]
@@ -251,6 +258,31 @@ class Plan:
         s = ions_struct(ions, gamma)
         return load().gps_solve_pb(self.handle, _ptr(rho), _ptr(eps), ctypes.byref(s),
                                    _ptr(phi), float(tol))
+
+    def solve_generalized_q(self, rho, eps, q, phi, tol):
+        """gps_solve_generalized_q: PCG with a caller-supplied q (Eq. corr)."""
+        for t in (rho, eps, q, phi):
+            _check_field(t, self.shape)
+        return load().gps_solve_generalized_q(self.handle, _ptr(rho), _ptr(eps), _ptr(q),
+                                              _ptr(phi), float(tol))
+
+    def rigid_cavity(self, atoms, delta, eps0, eps, q=None):
+        """gps_rigid_cavity: atoms is a device float64 tensor of shape (natoms, 4)."""
+        import torch
+        if atoms.dtype != torch.float64 or atoms.dim() != 2 or atoms.shape[1] != 4:
+            raise ValueError("atoms must be a float64 tensor of shape (natoms, 4)")
+        _check_field(eps, self.shape)
+        if q is not None:
+            _check_field(q, self.shape)
+        return load().gps_rigid_cavity(self.handle, int(atoms.shape[0]), _ptr(atoms),
+                                       float(delta), float(eps0), _ptr(eps), _ptr(q))
+
+    def polarization_charge(self, rho, eps, phi, rho_pol):
+        """gps_polarization_charge (Eqs. rhoiter, remap, rhopol)."""
+        for t in (rho, eps, phi, rho_pol):
+            _check_field(t, self.shape)
+        return load().gps_polarization_charge(self.handle, _ptr(rho), _ptr(eps), _ptr(phi),
+                                              _ptr(rho_pol))
 
     def solve_vacuum(self, f, u):
         for t in (f, u):

@@ -198,6 +198,21 @@ def molecule(n=96, h=0.3, seed=2, n_atoms=24, ball=6.0, net_charge=0.0, tol=1e-6
                    meta={"seed": seed, "n_atoms": n_atoms, "net_charge": net_charge})
 
 
+def rigid_solute(n=48, h=0.35, seed=6, n_atoms=6, ball=2.0, radii=(2.2, 2.8), delta=0.4,
+                 eps0=EPS_WATER, net_charge=0.0, bc=BC_FREE, shape=None):
+    """Inputs of a rigid-cavity solve (Eq. RigCav): the atom table
+    (natoms x 4: X, Y, Z, cavity radius d_i), Delta, eps0 and the solute's
+    Gaussian charge.  The cavity itself is left to the solver."""
+    rng = np.random.default_rng(seed)
+    centres, sig, q = random_solute(rng, n_atoms, ball, net_charge)
+    d = rng.uniform(radii[0], radii[1], n_atoms)
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    rho = gaussian_sum(shape, h, centres, sig, q, bc=bc, discrete_norm=bc != BC_FREE)
+    atoms = np.concatenate([np.asarray(centres), d[:, None]], axis=1)
+    return {"shape": shape, "h": h, "bc": bc, "rho": rho, "atoms": atoms, "delta": delta,
+            "eps0": eps0, "name": "rigid%d_s%d" % (shape[0], seed)}
+
+
 def charged_solute_mpb(n=160, h=0.3, seed=4, n_atoms=48, ball=6.0, net_charge=4.0,
                        molar=1.0, eta=0.15, tol=1e-6, steric=True, outer_maxit=200):
     """Nonlinear PB: charged solute, 1:1 electrolyte, accessibility from eps.

@@ -1,0 +1,170 @@
+"""GPU parity of the cavity builder and diagnostics (through the C ABI):
+the rigid cavity of Eq. RigCav with its analytic q, PCG with that q
+(gps_solve_generalized_q), and the polarization charge of Eqs. rhoiter /
+remap / rhopol.  All FP64.  Tolerances: eps within 1e-13 eps0 and q within
+1e-10 max|q| of the oracle (the kernel uses logarithmic derivatives and
+erfcx, the oracle the product rule and erf); rho_pol within 1e-11 of its
+maximum; solves as the other parity tests (FP64 1e-8 max|phi|, mixed
+1e-5 Ha/e)."""
+import numpy as np
+import pytest
+
+from oracle import cavity, pcg
+from paper_1509_00680_amd import workloads as W
+from paper_1509_00680_amd import gps
+from gpu_util import dev, host, empty, plan, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_cavity(p, atoms, delta, eps0, with_q=True):
+    shape = p.shape
+    e, q = empty(shape), (empty(shape) if with_q else None)
+    st = p.rigid_cavity(dev(atoms), delta, eps0, e, q)
+    assert st == gps.GPS_OK, gps.STATUS[st]
+    return host(e), (host(q) if with_q else None)
+
+
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic"])
+def test_rigid_cavity_matches_oracle(bc):
+    require_gpu()
+    shape, h = (30, 35, 27), 0.3                 # ragged: partial work-groups
+    rng = np.random.default_rng(21)
+    atoms = np.concatenate([rng.uniform(-3.5, 3.5, (5, 3)), rng.uniform(1.6, 2.4, (5, 1))], axis=1)
+    atoms[0, :3] = [(3 - 13) * h, 0.0, -0.5 * h]      # exactly on a grid point: the r = 0 reading
+    atoms[1, 0] = 27 * h / 2 - 0.1                    # near a face: minimum image on periodic x
+    ref_e, ref_q = cavity.rigid_cavity(shape, h, atoms, 0.45, 78.36, bc=bc)
+    p = plan(shape, h, bc, "fp64")
+    print("rigid cavity", bc, flush=True)
+    e, q = _gpu_cavity(p, atoms, 0.45, 78.36)
+    assert np.abs(e - ref_e).max() <= 1e-13 * 78.36
+    assert np.abs(q - ref_q).max() <= 1e-10 * np.abs(ref_q).max()
+    e2, _ = _gpu_cavity(p, atoms, 0.45, 78.36, with_q=False)
+    assert np.array_equal(e2, e)
+
+
+def test_rigid_cavity_full_size_sampled():
+    # 24 atoms on 96^3 (the molecule workload's grid): 4096 sampled points
+    require_gpu()
+    n, h = 96, 0.3
+    rng = np.random.default_rng(2)
+    centres, _, _ = W.random_solute(rng, 24, 6.0)
+    atoms = np.concatenate([centres, rng.uniform(2.2, 3.0, (24, 1))], axis=1)
+    p = plan((n, n, n), h, "free", "fp64")
+    print("rigid cavity 96^3", flush=True)
+    e, q = _gpu_cavity(p, atoms, 0.5, 78.36)
+    idx = rng.integers(0, n, size=(4096, 3))
+    ax = (np.arange(n) - (n - 1) / 2.0) * h
+    ref_e, ref_q = cavity.rigid_cavity_points(ax[idx[:, 2]], ax[idx[:, 1]], ax[idx[:, 0]],
+                                              atoms, 0.5, 78.36)
+    got_e, got_q = e[idx[:, 0], idx[:, 1], idx[:, 2]], q[idx[:, 0], idx[:, 1], idx[:, 2]]
+    assert np.abs(got_e - ref_e).max() <= 1e-13 * 78.36
+    assert np.abs(got_q - ref_q).max() <= 1e-10 * np.abs(q).max()
+    assert e.min() >= 1.0 and e.max() <= 78.36
+
+
+@pytest.mark.parametrize("bc", ["free", "surface"])
+def test_solve_with_analytic_q_fp64(bc):
+    require_gpu()
+    w = W.rigid_solute(n=24, h=0.45, seed=8, n_atoms=5, ball=2.0, radii=(2.0, 2.6), bc=bc)
+    shape, h = w["shape"], w["h"]
+    eps, q = cavity.rigid_cavity(shape, h, w["atoms"], w["delta"], w["eps0"], bc=bc)
+    s = np.sqrt(eps)
+    ref = pcg.pcg_solve(w["rho"], eps, h, bc, tol=1e-10, fields=(s, 1.0 / s, q))
+    assert ref.converged
+    p = plan(shape, h, bc, "fp64")
+    print("analytic q fp64", bc, flush=True)
+    e_d, q_d = empty(shape), empty(shape)
+    assert p.rigid_cavity(dev(w["atoms"]), w["delta"], w["eps0"], e_d, q_d) == gps.GPS_OK
+    phi = empty(shape)
+    st = p.solve_generalized_q(dev(w["rho"]), e_d, q_d, phi, 1e-10)
+    assert st == gps.GPS_OK, gps.STATUS[st]
+    assert abs(p.info()["iterations"] - ref.iterations) <= 1
+    assert np.abs(host(phi) - ref.phi).max() <= 1e-8 * np.abs(ref.phi).max()
+    # the finite-difference q gives a different (nearby) discrete problem
+    phi_fd = empty(shape)
+    assert p.solve_generalized(dev(w["rho"]), e_d, phi_fd, 1e-10) == gps.GPS_OK
+    assert np.abs(host(phi_fd) - host(phi)).max() > 1e-6 * np.abs(ref.phi).max()
+
+
+def test_solve_with_analytic_q_mixed_and_refined():
+    require_gpu()
+    w = W.rigid_solute(n=48, h=0.35, seed=3, n_atoms=8, ball=2.5)
+    shape, h = w["shape"], w["h"]
+    eps, q = cavity.rigid_cavity(shape, h, w["atoms"], w["delta"], w["eps0"])
+    s = np.sqrt(eps)
+    ref = pcg.pcg_solve(w["rho"], eps, h, "free", tol=1e-10, fields=(s, 1.0 / s, q))
+    e_ref = pcg.electrostatic_energy(w["rho"], ref.phi, h)
+    for refine in (0, 20):
+        p = plan(shape, h, "free", "mixed", refine_every=refine)
+        print("analytic q mixed refine", refine, flush=True)
+        e_d, q_d = empty(shape), empty(shape)
+        assert p.rigid_cavity(dev(w["atoms"]), w["delta"], w["eps0"], e_d, q_d) == gps.GPS_OK
+        phi = empty(shape)
+        tol = 1e-6 if refine == 0 else 1e-9
+        assert p.solve_generalized_q(dev(w["rho"]), e_d, q_d, phi, tol) == gps.GPS_OK
+        err = np.abs(host(phi) - ref.phi).max()
+        assert err <= (1e-5 if refine == 0 else 1e-8 * np.abs(ref.phi).max()), err
+        assert abs(p.info()["energy"] / e_ref - 1.0) < 1e-6
+
+
+def test_solve_q_rejects_periodic_and_nulls():
+    require_gpu()
+    shape = (8, 8, 8)
+    p = plan(shape, 0.5, "periodic", "fp64")
+    f = dev(np.ones(shape))
+    phi = empty(shape)
+    assert p.solve_generalized_q(dev(np.zeros(shape)), f, f, phi, 1e-6) == gps.GPS_E_INVALID
+    lib = gps.load()
+    q = plan(shape, 0.5, "free", "fp64")
+    assert lib.gps_solve_generalized_q(q.handle, None, None, None, None, 1e-6) == gps.GPS_E_INVALID
+
+
+def test_rigid_cavity_rejects_bad_arguments():
+    require_gpu()
+    shape = (8, 8, 8)
+    p = plan(shape, 0.5, "free", "fp64")
+    e = empty(shape)
+    good = np.array([[0.0, 0.0, 0.0, 1.5]])
+    assert p.rigid_cavity(dev(good), 0.0, 78.36, e) == gps.GPS_E_INVALID
+    assert p.rigid_cavity(dev(good), 0.4, 0.5, e) == gps.GPS_E_INVALID
+    assert p.rigid_cavity(dev(np.array([[0.0, 0.0, 0.0, -1.0]])), 0.4, 78.36, e) == gps.GPS_E_INVALID
+    assert p.rigid_cavity(dev(np.array([[np.nan, 0.0, 0.0, 1.0]])), 0.4, 78.36, e) == gps.GPS_E_INVALID
+    lib = gps.load()
+    assert lib.gps_rigid_cavity(p.handle, 0, None, 0.4, 78.36, None, None) == gps.GPS_E_INVALID
+    assert lib.gps_polarization_charge(p.handle, None, None, None, None) == gps.GPS_E_INVALID
+
+
+@pytest.mark.parametrize("bc,order,shape", [("free", 16, (12, 18, 40)), ("surface", 16, (20, 27, 35)),
+                                            ("periodic", 6, (9, 40, 35)), ("free", 2, (6, 5, 7))])
+def test_polarization_charge_matches_oracle(bc, order, shape):
+    require_gpu()
+    rng = np.random.default_rng(17)
+    eps = 1.0 + 77.0 * rng.random(shape)
+    phi = rng.normal(size=shape)
+    rho = rng.normal(size=shape)
+    h = 0.3
+    ref = cavity.polarization_charge(rho, eps, phi, h, bc, order)
+    p = plan(shape, h, bc, "fp64", fd_order=order)
+    out = empty(shape)
+    print("polarization", bc, order, shape, flush=True)
+    assert p.polarization_charge(dev(rho), dev(eps), dev(phi), out) == gps.GPS_OK
+    assert np.abs(host(out) - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_polarization_charge_gauss_law_on_gpu_solution():
+    # a unit charge in a spherical cavity: the solvent's bound charge totals
+    # -(1 - 1/eps0) Q; phi from the GPU solve, rho_pol from the GPU
+    require_gpu()
+    prob = W.single_sphere(n=64, h=0.18, sigma=0.6, q=1.0, d0=2.5, delta=0.6)
+    p = plan(prob.shape, prob.h, "free", "fp64")
+    phi = empty(prob.shape)
+    print("gauss law", flush=True)
+    rho_d, eps_d = dev(prob.rho), dev(prob.eps)
+    assert p.solve_generalized(rho_d, eps_d, phi, 1e-9) == gps.GPS_OK
+    out = empty(prob.shape)
+    assert p.polarization_charge(rho_d, eps_d, phi, out) == gps.GPS_OK
+    total = float(host(out).sum()) * prob.h ** 3
+    q = float(prob.rho.sum()) * prob.h ** 3
+    expect = -(1.0 - 1.0 / W.EPS_WATER) * q
+    assert abs(total - expect) < 2e-3 * abs(expect), (total, expect)

@@ -10,6 +10,8 @@ B * L1 is rounded up to a whole wavefront); the clamp that fixed it is part of
 what is replayed, and the unclamped form is shown to fail.  The replay checks
 every thread's tile loads with q clamped to the active range, a superset of
 the loads the kernel issues, and launches of one and two tiles per work-group."""
+import os
+
 import numpy as np
 import pytest
 
@@ -305,4 +307,109 @@ def test_qstencil_replay_matches_oracle(shape, bc, order):
     w = stencil.fd_second_derivative_weights(M)
     got = qstencil_replay(np.sqrt(eps), h, M, per, w)
     ref = stencil.q_field(eps, h, bc, order)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def _source_constants(name, keys):
+    import re
+    text = open(os.path.join(os.path.dirname(__file__), "..", "paper_1509_00680_amd", "csrc",
+                             name)).read()
+    out = {}
+    for k in keys:
+        m = re.search(r"\b%s = (\d+)" % k, text)
+        assert m, k
+        out[k] = int(m.group(1))
+    return out
+
+
+def polarization_replay(rho, eps, phi, h, M, per, w):
+    """Every work-group and thread of k_polarization, restated on the CPU
+    (tiles, ghosted halo slots, the two LDS tiles and register queues);
+    asserts every access in bounds and returns rho_pol."""
+    c = _source_constants("gps_cavity.hip", ["kPTX", "kPTY", "kPZC"])
+    PTX, PTY, PZC = c["kPTX"], c["kPTY"], c["kPZC"]
+    PTHREADS = PTX * PTY
+    nz, ny, nx = eps.shape
+    px, py, pz = per
+    fe, fp = np.log(eps).ravel(), phi.ravel()
+    plane = nx * ny
+    TW, TH = PTX + 2 * M, PTY + 2 * M
+    NXH = 2 * M * PTY
+    NH = NXH + 2 * M * PTX
+    HS = (NH + PTHREADS - 1) // PTHREADS
+    ntx, nty, nzc = -(-nx // PTX), -(-ny // PTY), -(-nz // PZC)
+    out = np.full(eps.shape, np.nan)
+    tid = np.arange(PTHREADS)
+    tx, ty = tid % PTX, tid // PTX
+    for t in range(ntx * nty * nzc):
+        zc, r = divmod(t, ntx * nty)
+        yt, xt = divmod(r, ntx)
+        x0, y0, z0 = xt * PTX, yt * PTY, zc * PZC
+        z1 = min(z0 + PZC, nz)
+        X, Y = x0 + tx, y0 + ty
+        cxy = _ghost(Y, ny, py) * nx + _ghost(X, nx, px)
+        assert cxy.min() >= 0 and cxy.max() < plane
+        hl, ho = [], []
+        for s in range(HS):
+            j = np.minimum(tid + s * PTHREADS, NH - 1)
+            xh = j < NXH
+            row_x, c_x = j // (2 * M), j % (2 * M)
+            jj = j - NXH
+            row_y, c_y = jj // PTX, jj % PTX
+            hx = np.where(xh, np.where(c_x < M, c_x, c_x + PTX), M + c_y)
+            hy = np.where(xh, M + row_x, np.where(row_y < M, row_y, row_y + PTY))
+            hl.append(hy * TW + hx)
+            ho.append(_ghost(y0 - M + hy, ny, py) * nx + _ghost(x0 - M + hx, nx, px))
+            assert hl[-1].min() >= 0 and hl[-1].max() < TH * TW
+            assert ho[-1].min() >= 0 and ho[-1].max() < plane
+        qidx = [_ghost(z0 - M + k, nz, pz) * plane + cxy for k in range(2 * M + 1)]
+        qe, qp = [fe[i] for i in qidx], [fp[i] for i in qidx]
+        he, hp = [fe[z0 * plane + o] for o in ho], [fp[z0 * plane + o] for o in ho]
+        inside = (X < nx) & (Y < ny)
+        for z in range(z0, z1):
+            te, tp = np.full(TH * TW, np.nan), np.full(TH * TW, np.nan)
+            te[(M + ty) * TW + M + tx] = qe[M]
+            tp[(M + ty) * TW + M + tx] = qp[M]
+            for s in range(HS):
+                te[hl[s]] = he[s]
+                tp[hl[s]] = hp[s]
+            zn = min(z + 1, nz - 1)
+            hne, hnp = [fe[zn * plane + o] for o in ho], [fp[zn * plane + o] for o in ho]
+            on = _ghost(z + 1 + M, nz, pz) * plane + cxy
+            ctr = (M + ty) * TW + M + tx
+            d = np.zeros((6, PTHREADS))
+            for m in range(1, M + 1):
+                for k in (ctr + m, ctr - m, ctr + m * TW, ctr - m * TW):
+                    assert k.min() >= 0 and k.max() < TH * TW
+                d[0] += w[m - 1] * (te[ctr + m] - te[ctr - m])
+                d[1] += w[m - 1] * (te[ctr + m * TW] - te[ctr - m * TW])
+                d[2] += w[m - 1] * (qe[M + m] - qe[M - m])
+                d[3] += w[m - 1] * (tp[ctr + m] - tp[ctr - m])
+                d[4] += w[m - 1] * (tp[ctr + m * TW] - tp[ctr - m * TW])
+                d[5] += w[m - 1] * (qp[M + m] - qp[M - m])
+            o = z * plane + Y * nx + X
+            val = (d[0] * d[3] + d[1] * d[4] + d[2] * d[5]) / (4 * np.pi * h * h)
+            oi = o[inside]
+            ev = eps.ravel()[oi]
+            out.ravel()[oi] = val[inside] - (1 - 1 / ev) * rho.ravel()[oi]
+            qe, qp = qe[1:] + [fe[on]], qp[1:] + [fp[on]]
+            he, hp = hne, hnp
+    assert not np.isnan(out).any()
+    return out
+
+
+@pytest.mark.parametrize("shape,bc,order", [((13, 17, 20), "free", 16), ((13, 17, 40), "surface", 16),
+                                            ((9, 40, 35), "periodic", 6), ((6, 5, 7), "free", 2)])
+def test_polarization_replay_matches_oracle(shape, bc, order):
+    from oracle import cavity
+    rng = np.random.default_rng(5)
+    eps = 1.0 + 77.0 * rng.random(shape)
+    phi = rng.normal(size=shape)
+    rho = rng.normal(size=shape)
+    h = 0.3
+    per = {"free": (False, False, False), "surface": (True, True, False),
+           "periodic": (True, True, True)}[bc]
+    M = order // 2
+    got = polarization_replay(rho, eps, phi, h, M, per, cavity.fd_first_derivative_weights(M))
+    ref = cavity.polarization_charge(rho, eps, phi, h, bc, order)
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
