@@ -52,7 +52,7 @@ def parse():
                     help="skip the per-pass kernel times (extra eager solves)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum wall time of the oracle sample (whole solves)")
-    ap.add_argument("--workload", default="molecule", choices=("molecule", "serving"),
+    ap.add_argument("--workload", default="molecule", choices=("molecule", "serving", "rigid"),
                     help="molecule: one 96^3 solve per step (default); serving: a request "
                          "stream through the serving loop")
     ap.add_argument("--requests", type=int, default=512, help="serving: stream length")
@@ -265,6 +265,73 @@ def serving_bench(args, torch, gps, W):
     }
 
 
+def rigid_bench(args, torch, gps, W):
+    """Rigid-cavity pipeline on one plan (Sec. IV.A): per step, the cavity and
+    its analytic q (gps_rigid_cavity), the PCG solve with that q
+    (gps_solve_generalized_q) and the polarization charge
+    (gps_polarization_charge).  24 atoms of radius 2.2-3.0 bohr, Delta 0.5,
+    on the molecule workload's grid."""
+    w = W.rigid_solute(n=args.n, h=args.h, seed=args.seed, n_atoms=24, ball=6.0,
+                       radii=(2.2, 3.0), delta=0.5)
+    shape = w["shape"]
+    rho = torch.from_numpy(w["rho"]).cuda()
+    atoms = torch.from_numpy(np.ascontiguousarray(w["atoms"])).cuda()
+    eps, q, phi, pol = (torch.empty_like(rho) for _ in range(4))
+    plan = gps.Plan(shape, w["h"], w["bc"], precision=args.precision,
+                    check_every=args.check_every)
+
+    def step(times=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        if plan.rigid_cavity(atoms, w["delta"], w["eps0"], eps, q) != 0:
+            raise RuntimeError("gps_rigid_cavity failed")
+        ev[1].record()
+        st = plan.solve_generalized_q(rho, eps, q, phi, args.tol)
+        if st != 0:
+            raise RuntimeError("solve failed with status %d" % st)
+        ev[2].record()
+        if plan.polarization_charge(rho, eps, phi, pol) != 0:
+            raise RuntimeError("gps_polarization_charge failed")
+        ev[3].record()
+        if times is not None:
+            torch.cuda.synchronize()
+            times.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = []
+    for _ in range(args.steps):
+        step(times)
+    tm = np.mean(np.array(times), axis=0)
+    info = plan.info()
+    npts = int(np.prod(shape))
+    pol_bytes = 32.0 * npts          # eps, phi, rho read, rho_pol written (FP64)
+    total_pol = float(pol.sum().item()) * w["h"] ** 3
+    qsum = float(np.sum(w["rho"])) * w["h"] ** 3
+    return {
+        "metric": "rigid-cavity pipeline steps/s (cavity + analytic q, PCG at 1e-6, "
+                  "polarization charge)",
+        "value": args.steps / wall, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": w["name"] + "_rigid_free", "grid": list(shape), "h": w["h"],
+                   "n_atoms": 24, "delta": w["delta"], "tol": args.tol,
+                   "precision": args.precision},
+        "iters_per_solve": info["iterations"],
+        "event_ms": {"rigid_cavity": tm[0], "solve": tm[1], "polarization": tm[2]},
+        "polarization_gbs_event": pol_bytes / (tm[2] * 1e-3) / 1e9,
+        "atom_points_per_s_event": 24.0 * npts / (tm[0] * 1e-3),
+        "polarization_total": total_pol, "solute_charge": qsum,
+    }
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -280,6 +347,9 @@ def main():
     from paper_1509_00680_amd import gps, workloads as W
     if args.workload == "serving":
         print(json.dumps(serving_bench(args, torch, gps, W)))
+        return
+    if args.workload == "rigid":
+        print(json.dumps(rigid_bench(args, torch, gps, W)))
         return
 
     prob = W.molecule(args.n, args.h, seed=args.seed)

@@ -22,20 +22,28 @@ namespace gps {
 // At r_i = 0 (a grid point on an atom centre) the radial switch has a cusp;
 // its gradient is taken as 0 and its Laplacian as h_i''(0): the atom adds
 // -2 t_i u_i/Delta only.  Periodic axes use minimum-image separations.
-// One grid point per thread; the atom table is read with uniform loads.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_rigid_cavity(Geom g,
+// An atom with t_i > kFarT contributes nothing: there erfc(-t_i)/2 rounds to
+// 1 in binary64 and u_i Delta < 3e-19, so its terms in G and in the sum are
+// below 1e-17 / Delta^2, far below the rounding of max|q| ~ (eps0 - 1)/Delta^2.  A work-group covers an 8 x 8 x 4 block of grid
+// points (a wavefront an 8 x 8 patch of one plane), so the lanes of a
+// wavefront are near the same atoms and skip the same ones.
+constexpr double kFarT = 6.5;
+constexpr int kCBX = 8, kCBY = 8, kCBZ = kThreads / (kCBX * kCBY);
+
+__global__ __launch_bounds__(kThreads) void k_rigid_cavity(Geom g, int nbx, int nby,
                                                            const double* __restrict__ atoms,
                                                            int natoms, double delta, double eps0,
                                                            double* __restrict__ eps,
                                                            double* __restrict__ q) {
-  const int n = g.nx * g.ny * g.nz;
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const int plane = g.nx * g.ny;
-  const int iz = i / plane;
-  const int iy = (i - iz * plane) / g.nx;
-  const int ix = i - iz * plane - iy * g.nx;
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  const int bz = b / (nbx * nby);
+  const int by = (b - bz * nbx * nby) / nbx;
+  const int bx = b - bz * nbx * nby - by * nbx;
+  const int ix = bx * kCBX + tid % kCBX;
+  const int iy = by * kCBY + (tid / kCBX) % kCBY;
+  const int iz = bz * kCBZ + tid / (kCBX * kCBY);
+  if (ix >= g.nx || iy >= g.ny || iz >= g.nz) return;
   const double x = (ix - 0.5 * (g.nx - 1)) * g.h;
   const double y = (iy - 0.5 * (g.ny - 1)) * g.h;
   const double z = (iz - 0.5 * (g.nz - 1)) * g.h;
@@ -51,6 +59,7 @@ __global__ __launch_bounds__(kThreads) void k_rigid_cavity(Geom g,
     if (g.periodic_z) dz -= lz * rint(dz / lz);
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     const double t = (r - at[3]) * idelta;
+    if (t > kFarT) continue;
     H *= 0.5 * erfc(-t);
     const double u = cu / erfcx(-t);
     w -= 2.0 * t * u * idelta;
@@ -62,6 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_rigid_cavity(Geom g,
       w += 2.0 * ur - u * u;
     }
   }
+  const size_t i = ((size_t)iz * g.ny + iy) * g.nx + ix;
   const double a = eps0 - 1.0;
   const double aH = a * H;
   const double e = aH + 1.0;
@@ -74,9 +84,10 @@ __global__ __launch_bounds__(kThreads) void k_rigid_cavity(Geom g,
 
 void launch_rigid_cavity(const Geom& g, const double* atoms, int natoms, double delta,
                          double eps0, double* eps, double* q, hipStream_t s) {
-  const long long n = (long long)g.nx * g.ny * g.nz;
-  GPS_LAUNCH(k_rigid_cavity, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-             s, g, atoms, natoms, delta, eps0, eps, q);
+  const int nbx = (g.nx + kCBX - 1) / kCBX, nby = (g.ny + kCBY - 1) / kCBY;
+  const int nbz = (g.nz + kCBZ - 1) / kCBZ;
+  GPS_LAUNCH(k_rigid_cavity, dim3((unsigned)(nbx * nby * nbz)), dim3(kThreads), 0, s, g, nbx,
+             nby, atoms, natoms, delta, eps0, eps, q);
 }
 
 // ---------------------------------------------------------------------------
