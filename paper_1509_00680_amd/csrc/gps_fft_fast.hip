@@ -81,7 +81,7 @@ void k_fstrided(SParams<T> p) {
   cplx<T> twv[(L + NT - 1) / NT];
 #pragma unroll
   for (int i = 0; i < (L + NT - 1) / NT; ++i)
-    if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
+    twv[i] = p.tw[min(tid + i * NT, L - 1)];    // clamped: no branch around the load
   const int b = tid & (B - 1);
   const int q = tid / B;
   // (xcd_tile maps work-group 0 to tile 0, so the shift keeps every XCD's
@@ -349,7 +349,7 @@ __device__ __forceinline__ void tile_row_offsets(const XParams<T>& p, int row0, 
 }
 
 template <typename T, int L1, int L2, int MODE, bool PAD>
-__global__ __launch_bounds__(xthreads<L1>())
+__global__ __launch_bounds__(xthreads<L1>()) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_fxfwd(XParams<T> p) {
   constexpr bool SOLVE = MODE == XF_SOLVE || MODE == XF_SOLVE_REF;
   constexpr bool REF = MODE == XF_SOLVE_REF;     // also s += alpha sigma (refinement)
@@ -375,11 +375,13 @@ void k_fxfwd(XParams<T> p) {
   cplx<T> twv[ETW];
 #pragma unroll
   for (int i = 0; i < ETW; ++i)
-    if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
-  // the head's own loads (state words, (p, Ap) partials) go first, then every
-  // operand load of this thread: the head waits only for its loads, and the
-  // operands arrive while it decides.  p, Ap and phi are loaded even at k = 0
-  // (unused there).
+    twv[i] = p.tw[min(tid + i * NT, L - 1)];    // clamped: no branch around the load
+  // the head's own loads (state words, (p, Ap) partials) go first, then the
+  // operands of the r update and of the transform (r, 1/sqrt(eps), Ap), then
+  // those of the phi (and s) update (p, phi), which are used only after the
+  // transform: the head waits only for its loads, the transform only for the
+  // first group, and the second group arrives while the transform runs.
+  // Operands are loaded even at k = 0 (unused there).
   XHead<NT == 64 ? 24 : 8> hd;                     // one (p, Ap) partial per x-inverse group
   if constexpr (SOLVE) xfwd_head_load(sl, p.n_pap_parts, hd);
   // rows are contiguous (row stride Lin, checked by the dispatcher), so
@@ -389,25 +391,35 @@ void k_fxfwd(XParams<T> p) {
   T rv[EIN], sv[EIN], pv[EIN], av[EIN];
   double fv[EIN];
   double gv[REF ? EIN : 1], cv[REF ? EIN : 1];   // sigma, s
+  // Loads are unconditional: elements past the tile's end load its first
+  // element (unused).  Without branches around the loads the compiler counts
+  // them exactly and waits for each group alone.
 #pragma unroll
   for (int i = 0; i < EIN; ++i) {
     const int e = tid + i * NT;
-    rv[i] = T(0);
-    sv[i] = T(0);
-    if (e < nin) {
-      const unsigned o = eo + (unsigned)e;
-      if constexpr (SOLVE) {
-        rv[i] = GPS_AT(sl.r, o);
-        sv[i] = GPS_AT(sl.isq, o);
-        pv[i] = GPS_AT(sl.p, o);
-        av[i] = GPS_AT(sl.ap, o);
-        fv[i] = GPS_AT(sl.phi, o);
-        if constexpr (REF) {
-          gv[i] = GPS_AT(sl.sig64, o);
-          cv[i] = GPS_AT(sl.src64, o);
-        }
-      } else {
-        rv[i] = T(GPS_AT(p.in_real, o));
+    const bool in = e < nin;
+    const unsigned o = eo + (unsigned)(in ? e : 0);
+    if constexpr (SOLVE) {
+      const T r0 = GPS_AT(sl.r, o), s0 = GPS_AT(sl.isq, o);
+      av[i] = GPS_AT(sl.ap, o);
+      rv[i] = in ? r0 : T(0);
+      sv[i] = in ? s0 : T(0);
+    } else {
+      const T r0 = T(GPS_AT(p.in_real, o));
+      rv[i] = in ? r0 : T(0);
+      sv[i] = T(0);
+    }
+  }
+  if constexpr (SOLVE) {
+#pragma unroll
+    for (int i = 0; i < EIN; ++i) {
+      const int e = tid + i * NT;
+      const unsigned o = eo + (unsigned)(e < nin ? e : 0);
+      pv[i] = GPS_AT(sl.p, o);
+      fv[i] = GPS_AT(sl.phi, o);
+      if constexpr (REF) {
+        gv[i] = GPS_AT(sl.sig64, o);
+        cv[i] = GPS_AT(sl.src64, o);
       }
     }
   }
@@ -430,10 +442,8 @@ void k_fxfwd(XParams<T> p) {
         if (e < nin) {
           const unsigned o = eo + (unsigned)e;
           if (upd) {
-            GPS_AT(sl.phi, o) = fv[i] + alpha * double(pv[i]);
             a = a - T(alpha) * av[i];
             GPS_AT(sl.r, o) = a;
-            if constexpr (REF) GPS_AT(sl.src64, o) = cv[i] + alpha * gv[i];
           }
           rr += double(a) * double(a);
           a = a * sv[i];
@@ -502,6 +512,21 @@ void k_fxfwd(XParams<T> p) {
       }
     }
   }
+  if constexpr (SOLVE) {
+    // phi += alpha p (and s += alpha sigma) of the previous iteration, after
+    // the transform so that its operands' latency hides behind it
+    if (upd) {
+#pragma unroll
+      for (int i = 0; i < EIN; ++i) {
+        const int e = tid + i * NT;
+        if (e < nin) {
+          const unsigned o = eo + (unsigned)e;
+          GPS_AT(sl.phi, o) = fv[i] + alpha * double(pv[i]);
+          if constexpr (REF) GPS_AT(sl.src64, o) = cv[i] + alpha * gv[i];
+        }
+      }
+    }
+  }
   if constexpr (SOLVE) {                        // one partial per work-group
     const double s2 = wg_sum<NT>(rr);
     if (tid == 0) sl.part_rr[tile] = s2;
@@ -516,7 +541,7 @@ void k_fxfwd(XParams<T> p) {
 // direction update of the PCG iteration (with the periodic mean term; with the
 // refinement's sigma = r / sqrt(eps) + beta sigma); XI_REAL: plain output.
 template <typename T, int L1, int L2, int MODE, bool PAD>
-__global__ __launch_bounds__(xthreads<L1>())
+__global__ __launch_bounds__(xthreads<L1>()) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_fxinv(XParams<T> p) {
   constexpr bool SOLVE = MODE != XI_REAL;
   constexpr bool PER = MODE == XI_SOLVE_PERIODIC;
@@ -551,7 +576,7 @@ void k_fxinv(XParams<T> p) {
   cplx<T> twv[ETW];
 #pragma unroll
   for (int i = 0; i < ETW; ++i)
-    if (tid + i * NT < L) twv[i] = p.tw[tid + i * NT];
+    twv[i] = p.tw[min(tid + i * NT, L - 1)];    // clamped: no branch around the load
   unsigned roff[2 * P];
   bool rok[2 * P];
   tile_row_offsets<2 * P>(p, row0, Kx, roff, rok);
@@ -568,6 +593,10 @@ void k_fxinv(XParams<T> p) {
       xb[p2][i] = rok[2 * p2 + 1] ? vb : cmk(T(0), T(0));
     }
   }
+  // the stop flag right after the rows: the transform waits for both, and the
+  // epilogue operands below stay in flight while it runs
+  int stop = 0;
+  if constexpr (SOLVE) stop = stop_flag_issue(sl.st);
   // epilogue operands are independent of the transform: load them now too
   constexpr int EO = SOLVE ? EOUT : 1;
   T sv[EO], rv[EO], qv[EO], pv[EO], av[EO], mv[PER ? EOUT : 1];
@@ -576,22 +605,22 @@ void k_fxinv(XParams<T> p) {
   const unsigned eo = (unsigned)row0 * (unsigned)Lout;
   const int nout = min(NOUT, (p.nrows - row0) * Lout);  // tile elements that exist
   if constexpr (SOLVE) {
+    // unconditional loads (elements past the tile's end load its first
+    // element, unused): no branches, so the transform waits for the row loads
+    // alone
 #pragma unroll
     for (int i = 0; i < EOUT; ++i) {
       const int e = tid + i * NT;
-      if (e < nout) {
-        const unsigned o = eo + (unsigned)e;
-        sv[i] = GPS_AT(sl.isq, o);
-        rv[i] = GPS_AT(sl.r, o);
-        qv[i] = GPS_AT(sl.qk, o);
-        pv[i] = GPS_AT(sl.p, o);
-        av[i] = GPS_AT(sl.ap, o);
-        if constexpr (PER) mv[i] = GPS_AT(sl.s, o);
-        if constexpr (REF) gv[i] = GPS_AT(sl.sig64, o);
-      }
+      const unsigned o = eo + (unsigned)(e < nout ? e : 0);
+      sv[i] = GPS_AT(sl.isq, o);
+      rv[i] = GPS_AT(sl.r, o);
+      qv[i] = GPS_AT(sl.qk, o);
+      pv[i] = GPS_AT(sl.p, o);
+      av[i] = GPS_AT(sl.ap, o);
+      if constexpr (PER) mv[i] = GPS_AT(sl.s, o);
+      if constexpr (REF) gv[i] = GPS_AT(sl.sig64, o);
     }
-    // stop flag issued after the operand loads, in flight with them
-    if (stop_flag_set(stop_flag_issue(sl.st))) return;
+    if (stop_flag_set(stop)) return;
   }
 #pragma unroll
   for (int p2 = 0; p2 < P; ++p2)
