@@ -19,6 +19,8 @@ Modules
   pb       -- ionic charge (Eqs. ionsconcPB, ionsconcMPB, maxconc) and the
               self-consistent loops of Algorithms SCPB and SCPBimproved.
   dense    -- dense direct solve of the same discrete problem (tiny grids).
+  wire     -- the wire-BC kernel (periodic z, isolated x and y): cell-averaged
+              2 K0(|kz| rho) per z mode (Sec. II.C lists the wire BC).
   cavity   -- rigid cavity of Eq. RigCav with its analytic q (Sec. IV.A), and
               the polarization charge of Eqs. rhoiter / remap / rhopol with
               order-2M first differences.
@@ -34,5 +36,6 @@ closed forms, brute force or limits, except where a docstring says
 
 BC_FREE = "free"
 BC_SURFACE = "surface"      # periodic in x and y, free in z
+BC_WIRE = "wire"            # periodic in z, free in x and y
 BC_PERIODIC = "periodic"
-BCS = (BC_FREE, BC_SURFACE, BC_PERIODIC)
+BCS = (BC_FREE, BC_SURFACE, BC_PERIODIC, BC_WIRE)

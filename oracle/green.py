@@ -11,6 +11,9 @@ kernel on a cell-centred grid:
             I(m) = integral over the unit cube centred at m of 1/|u| d^3u ,
             evaluated through zero padding to (2nz, 2ny, 2nx) (Hockney).
   periodic  u = F^-1[ 4 pi / |k|^2  F f ],  zero at k = 0.
+  wire      z spectral (periodic); in x, y, for each kz, the cell average of
+            2 K0(|kz| rho) (kz != 0) or -2 ln(rho/Rw) (kz = 0), zero-padded to
+            (2ny, 2nx) (oracle/wire.py).
   surface   x, y spectral (periodic); along z, for each in-plane wavevector
             k_par the cell average of the 1D Green's function
             g(k_par, z) = (2 pi / k_par) exp(-k_par |z|)     (k_par > 0),
@@ -35,7 +38,7 @@ All functions work in binary64.  Array shape convention: (nz, ny, nx).
 import numpy as np
 from scipy import fft as sfft
 
-from . import BC_FREE, BC_SURFACE, BC_PERIODIC
+from . import BC_FREE, BC_SURFACE, BC_PERIODIC, BC_WIRE
 
 # Cells with max_a |m_a| <= NEAR_CUTOFF use the exact cube integral; the
 # others use the multipole expansion of the cube average.  At the cutoff the
@@ -172,7 +175,7 @@ class VacuumSolver:
     """u = G_bc f on a (nz, ny, nx) cell-centred grid of spacing h."""
 
     def __init__(self, shape, h, bc, surface_k0_offset=None, workers=None):
-        if bc not in (BC_FREE, BC_SURFACE, BC_PERIODIC):
+        if bc not in (BC_FREE, BC_SURFACE, BC_PERIODIC, BC_WIRE):
             raise ValueError("unknown boundary condition %r" % (bc,))
         self.shape = tuple(int(s) for s in shape)
         self.h = float(h)
@@ -183,6 +186,10 @@ class VacuumSolver:
             self.fft_shape = (2 * nz, 2 * ny, 2 * nx)
             kern = free_kernel_table(self.shape, h)
             self.spectrum = h ** 3 * sfft.rfftn(kern, workers=workers).real
+        elif bc == BC_WIRE:
+            from . import wire
+            self.fft_shape = (nz, 2 * ny, 2 * nx)
+            self.spectrum = wire.wire_spectrum(self.shape, h)
         elif bc == BC_PERIODIC:
             self.fft_shape = (nz, ny, nx)
             kz = wavenumbers(nz, h)[:, None, None]
@@ -294,4 +301,7 @@ def dense_green(shape, h, bc, surface_k0_offset=None):
         return dense_green_periodic(shape, h)
     if bc == BC_SURFACE:
         return dense_green_surface(shape, h, surface_k0_offset)
+    if bc == BC_WIRE:
+        from .wire import dense_green_wire
+        return dense_green_wire(shape, h)
     raise ValueError(bc)

@@ -20,7 +20,7 @@ from math import factorial
 import numpy as np
 from scipy import fft as sfft
 
-from . import BC_FREE, BC_SURFACE, BC_PERIODIC
+from . import BC_FREE, BC_SURFACE, BC_PERIODIC, BC_WIRE
 from .green import wavenumbers, rwavenumbers
 
 
@@ -59,6 +59,8 @@ def periodic_axes(bc):
         return ()
     if bc == BC_SURFACE:
         return (1, 2)
+    if bc == BC_WIRE:
+        return (0,)
     if bc == BC_PERIODIC:
         return (0, 1, 2)
     raise ValueError(bc)

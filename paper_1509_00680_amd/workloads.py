@@ -37,7 +37,7 @@ MOLAR_BOHR3 = AVOGADRO * 1e3 * BOHR_M ** 3        # 1 mol/L in bohr^-3
 RHO_MAX_SCCS = 5e-3                                # Sec. IV.C
 RHO_MIN_SCCS = 1e-4
 
-BC_FREE, BC_SURFACE, BC_PERIODIC = "free", "surface", "periodic"
+BC_FREE, BC_SURFACE, BC_PERIODIC, BC_WIRE = "free", "surface", "periodic", "wire"
 
 
 # --------------------------------------------------------------------------
@@ -56,7 +56,7 @@ def grid_coords(shape, h):
 def periodic_flags(bc):
     """(x, y, z) periodicity of a boundary condition."""
     return {BC_FREE: (False, False, False), BC_SURFACE: (True, True, False),
-            BC_PERIODIC: (True, True, True)}[bc]
+            BC_PERIODIC: (True, True, True), BC_WIRE: (False, False, True)}[bc]
 
 
 def _min_image(d, length, periodic):

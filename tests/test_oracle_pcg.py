@@ -10,7 +10,7 @@ from scipy.special import erf, erfc
 from oracle import green, pcg, dense, pb
 from paper_1509_00680_amd import workloads as W
 
-BCS = ("free", "surface", "periodic")
+BCS = ("free", "surface", "periodic", "wire")
 
 
 def _small_problem(bc, n=8, h=0.6, seed=1):
