@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
+    ap.add_argument("--bc", default="free", choices=("free", "surface", "periodic", "wire"),
+                    help="molecule workload: boundary conditions")
     ap.add_argument("--check-every", type=int, default=8,
                     help="PCG iterations per replayed graph")
     ap.add_argument("--fp64-steps", type=int, default=5,
@@ -352,7 +354,7 @@ def main():
         print(json.dumps(rigid_bench(args, torch, gps, W)))
         return
 
-    prob = W.molecule(args.n, args.h, seed=args.seed)
+    prob = W.molecule(args.n, args.h, seed=args.seed, bc=args.bc)
     rho = torch.from_numpy(prob.rho).cuda()
     eps = torch.from_numpy(prob.eps).cuda()
     phi = torch.empty_like(rho)
@@ -414,7 +416,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "molecule%d_sccs_free" % args.n, "grid": list(prob.shape),
+        "config": {"workload": "molecule%d_sccs_%s" % (args.n, args.bc), "grid": list(prob.shape),
                    "h": prob.h, "bc": prob.bc, "n_charges": 24, "seed": args.seed,
                    "tol": args.tol, "precision": args.precision
                    + (" (fp32 bulk, fp64 dots/solution)" if args.precision == "mixed" else "")},
@@ -426,7 +428,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("traffic_zpass_molecule96_free_mixed.json")
-                     if (args.n, args.precision) == (96, "mixed") else None,
+                     if (args.n, args.precision, args.bc) == (96, "mixed", "free") else None,
                      "kernel": "z pass (forward FFT, Green's spectrum, inverse FFT)",
                      "avg_us": avg_ms * 1e3, "bytes_per_launch": tz["bytes_per_launch"],
                      "launches": tz["launches"]},

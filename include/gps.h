@@ -46,8 +46,15 @@ extern "C" {
  *   FREE      isolated system, zero-padded (Hockney) convolution with the
  *             cell-averaged 1/|r| kernel;
  *   SURFACE   periodic along x and y, isolated along z;
- *   PERIODIC  periodic along x, y and z (rho must be neutral for Poisson). */
-typedef enum { GPS_BC_FREE = 0, GPS_BC_SURFACE = 1, GPS_BC_PERIODIC = 2 } gps_bc;
+ *   PERIODIC  periodic along x, y and z (rho must be neutral for Poisson);
+ *   WIRE      periodic along z, isolated along x and y: per z mode kz the
+ *             cell-averaged in-plane kernel 2 K0(|kz| rho) (kz != 0) or
+ *             -2 ln(rho / Rw) (kz = 0, Rw = 2 h sqrt(nx^2 + ny^2), a constant
+ *             shift that keeps the operator positive definite; it adds a
+ *             constant times the charge per unit length to phi), zero-padded
+ *             in x and y. */
+typedef enum { GPS_BC_FREE = 0, GPS_BC_SURFACE = 1, GPS_BC_PERIODIC = 2,
+               GPS_BC_WIRE = 3 } gps_bc;
 
 /* Arithmetic of the bulk work (FFT passes and PCG vectors).  Inner products,
  * the solution accumulator, the Green's-function tables and the stencil are
@@ -132,7 +139,7 @@ typedef struct {
  * condition bc.  Computes the Green's-function spectrum on the device (FP64)
  * and allocates the work buffers.  Errors: GPS_E_INVALID (n < 2, h <= 0 or
  * not finite, unknown bc, out == NULL), GPS_E_UNSUPPORTED (an FFT length
- * -- 2n on free axes, n on periodic axes -- with a prime factor > 7 or
+ * -- 2n on isolated axes, n on periodic axes -- with a prime factor > 7 or
  * longer than 1024), GPS_E_NOMEM, GPS_E_DEVICE.  *out is NULL on error. */
 gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan **out);
 

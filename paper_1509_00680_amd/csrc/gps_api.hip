@@ -242,6 +242,33 @@ SParams<T> sparams(const gps_plan* pl, int axis, int L, int Lin, int Lout, int n
 // ---------------------------------------------------------------------------
 // plan-time Green's-function spectrum (FP64 on the device)
 // ---------------------------------------------------------------------------
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton's method on the
+// Legendre recurrence), for the wire kernel's cell averages.
+GLRule gauss_legendre() {
+  GLRule r{};
+  const int n = kGLPoints;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double pn = 0.0, dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      pn = p1;
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = pn / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    r.t[i] = x;
+    r.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return r;
+}
+
 void build_green(gps_plan* pl) {
   const Geom& g = pl->g;
   hipStream_t s = pl->cap_stream;
@@ -272,6 +299,31 @@ void build_green(gps_plan* pl) {
     ck(hipGetLastError());
     ck(hipStreamSynchronize(s));
     dfree(full);
+  } else if (pl->bc == GPS_BC_WIRE) {
+    // per z mode, the cell-averaged in-plane kernel on the (2ny, 2nx) padded
+    // plane -> 2D FFT (FP64) -> fold and scale by h^2/N
+    const size_t nfull = (size_t)g.Lz * g.Ly * g.Kx;
+    size_t tmp_bytes = 0;
+    cplx<double>* full = nullptr;
+    double* kt = nullptr;
+    dalloc(&full, nfull * sizeof(cplx<double>), &tmp_bytes);
+    dalloc(&kt, (size_t)g.Lz * g.Ly * g.Lx * sizeof(double), &tmp_bytes);
+    const double rw = 2.0 * g.h * std::sqrt((double)g.nx * g.nx + (double)g.ny * g.ny);
+    launch_wire_gen(kt, g, rw, gauss_legendre(), s);
+    XParams<double> xp = xparams<double>(pl, g.Ly * g.Lz, g.Ly, g.Lx, g.Lx,
+                                         (long long)g.Ly * g.Kx, g.Lx);
+    xp.in_real = kt;
+    xp.work = full;
+    launch_xfwd<double>(XF_REAL, xp, s);
+    SParams<double> yp = sparams<double>(pl, 1, g.Ly, g.Ly, g.Ly, g.Lz * g.Kx, g.Kx,
+                                         (long long)g.Ly * g.Kx, g.Kx);
+    yp.work = full;
+    launch_strided<double>(ST_FWD, yp, s);
+    launch_compress_table(full, g.Kx, g.Ly, g.Lz, g.h * g.h * norm, pl->green64, pl->green32, s);
+    ck(hipGetLastError());
+    ck(hipStreamSynchronize(s));
+    dfree(full);
+    dfree(kt);
   } else if (pl->bc == GPS_BC_SURFACE) {
     const int Lyh = g.Ly / 2 + 1;
     const size_t nc = (size_t)g.Kx * Lyh;
@@ -894,7 +946,8 @@ gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan** 
   if (!out) return GPS_E_INVALID;
   *out = nullptr;
   if (nx < 2 || ny < 2 || nz < 2 || !(h > 0.0) || !std::isfinite(h)) return GPS_E_INVALID;
-  if (bc != GPS_BC_FREE && bc != GPS_BC_SURFACE && bc != GPS_BC_PERIODIC) return GPS_E_INVALID;
+  if (bc != GPS_BC_FREE && bc != GPS_BC_SURFACE && bc != GPS_BC_PERIODIC && bc != GPS_BC_WIRE)
+    return GPS_E_INVALID;
   gps_plan* pl = new (std::nothrow) gps_plan();
   if (!pl) return GPS_E_NOMEM;
   pl->bc = bc;
@@ -910,9 +963,9 @@ gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan** 
   g.ny = ny;
   g.nz = nz;
   g.h = h;
-  g.periodic_x = bc != GPS_BC_FREE;
-  g.periodic_y = bc != GPS_BC_FREE;
-  g.periodic_z = bc == GPS_BC_PERIODIC;
+  g.periodic_x = bc == GPS_BC_SURFACE || bc == GPS_BC_PERIODIC;
+  g.periodic_y = g.periodic_x;
+  g.periodic_z = bc == GPS_BC_PERIODIC || bc == GPS_BC_WIRE;
   g.Lx = g.periodic_x ? nx : 2 * nx;
   g.Ly = g.periodic_y ? ny : 2 * ny;
   g.Lz = g.periodic_z ? nz : 2 * nz;
@@ -997,12 +1050,15 @@ gps_status gps_plan_footprint(int nx, int ny, int nz, int bc, int precision, int
                               int nonlinear_pb, int refine, size_t* tables, size_t* buffers,
                               size_t* transient) {
   if (nx < 2 || ny < 2 || nz < 2 || maxit < 1) return GPS_E_INVALID;
-  if (bc != GPS_BC_FREE && bc != GPS_BC_SURFACE && bc != GPS_BC_PERIODIC) return GPS_E_INVALID;
+  if (bc != GPS_BC_FREE && bc != GPS_BC_SURFACE && bc != GPS_BC_PERIODIC && bc != GPS_BC_WIRE)
+    return GPS_E_INVALID;
   if (precision != GPS_PREC_FP64 && precision != GPS_PREC_MIXED) return GPS_E_INVALID;
   // the same sizes as gps_plan_create, build_green and ensure_res
-  const bool px = bc != GPS_BC_FREE, pz = bc == GPS_BC_PERIODIC;
+  const bool px = bc == GPS_BC_SURFACE || bc == GPS_BC_PERIODIC;   // x and y periodic
+  const bool pz = bc == GPS_BC_PERIODIC;                           // fully periodic
+  const bool zper = pz || bc == GPS_BC_WIRE;                      // z periodic
   const size_t Lx = px ? nx : 2 * (size_t)nx, Ly = px ? ny : 2 * (size_t)ny;
-  const size_t Lz = pz ? nz : 2 * (size_t)nz, Kx = Lx / 2 + 1;
+  const size_t Lz = zper ? nz : 2 * (size_t)nz, Kx = Lx / 2 + 1;
   const size_t n = (size_t)nx * ny * nz;
   const size_t s = precision == GPS_PREC_MIXED ? sizeof(float) : sizeof(double);
   const size_t ntab = (Lz / 2 + 1) * (Ly / 2 + 1) * Kx;
@@ -1023,6 +1079,7 @@ gps_status gps_plan_footprint(int nx, int ny, int nz, int bc, int precision, int
   if (refine && !pz) b += 4 * n * sizeof(double) + wbox * 2 * sizeof(double);    // sigma, s, q, Gs, work
   size_t t = 0;
   if (bc == GPS_BC_FREE) t = Lz * Ly * Kx * 2 * sizeof(double);
+  else if (bc == GPS_BC_WIRE) t = Lz * Ly * (Kx * 2 + Lx) * sizeof(double);
   else if (bc == GPS_BC_SURFACE) t = Kx * (Ly / 2 + 1) * Lz * 2 * sizeof(double);
   if (tables) *tables = tb;
   if (buffers) *buffers = b;

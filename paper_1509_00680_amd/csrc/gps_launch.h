@@ -124,6 +124,11 @@ void launch_surface_gen(cplx<double>* buf, int Kx, int Lyh, int Lz, int nx, int 
 void launch_surface_compress(const cplx<double>* buf, int Kx, int Lyh, int Lz, double scale,
                              double* t64, float* t32, hipStream_t s);
 void launch_periodic_table(const Geom& g, int laplacian, double* t64, float* t32, hipStream_t s);
+// Gauss-Legendre rule on [-1, 1] (nodes, weights) for the wire kernel's cell averages.
+constexpr int kGLPoints = 10;
+struct GLRule { double t[kGLPoints], w[kGLPoints]; };
+void launch_wire_gen(double* out, const Geom& g, double rw, const GLRule& gl, hipStream_t s);
+
 
 // ---- per-solve vector kernels -------------------------------------------------
 struct IonParams {

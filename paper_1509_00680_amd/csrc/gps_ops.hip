@@ -76,6 +76,119 @@ void launch_surface_gen(cplx<double>* buf, int Kx, int Lyh, int Lz, int nx, int 
                      k0_offset);
 }
 
+// Wire boundaries (periodic z, isolated x and y): for each z mode kz the
+// in-plane Green's function of (-lap_xy + kz^2) u = 4 pi f,
+//   g(rho) = 2 K0(|kz| rho)  (kz != 0),   g(rho) = -2 ln(rho / Rw)  (kz = 0),
+// averaged over the h x h cell of each offset of the (2ny, 2nx) padded plane.
+// Off-origin cells: 10 x 10 Gauss-Legendre points.  The origin cell: polar
+// coordinates on its eight triangles, (8/h^2) int_0^{pi/4} dt int_0^{R(t)}
+// g(rho) rho drho with R(t) = h/(2 cos t); with I0 and the series of K0 the
+// rho integral is exact term by term, the t integral takes the same 10
+// Gauss-Legendre points.  out[iz][iy][ix] (real, Lz x Ly x Lx).
+
+// K0(x), x > 0.  x <= 2: K0 = -(ln(x/2) + gamma) I0(x) + sum_j t^j H_j/(j!)^2,
+// t = x^2/4, H_j the harmonic numbers.  x > 2: the integral
+// K0(x) = e^{-x} int_0^inf exp(-x (cosh s - 1)) ds by the trapezoidal rule
+// with step tau = min(0.2, 0.7/sqrt(x)) (the integrand is analytic in a
+// strip, so the error falls like exp(-2 pi d / tau); these steps keep it below
+// ~1e-16 relative), summed until x (cosh s - 1) > 40.
+__device__ double wire_k0(double x) {
+  constexpr double kGamma = 0.57721566490153286061;
+  if (x <= 2.0) {
+    const double t = 0.25 * x * x;
+    double term = 1.0, i0 = 1.0, tail = 0.0, hj = 0.0;
+    for (int j = 1; j < 30; ++j) {
+      term *= t / ((double)j * j);
+      hj += 1.0 / j;
+      i0 += term;
+      tail += term * hj;
+      if (term < 1e-18) break;
+    }
+    return -(log(0.5 * x) + kGamma) * i0 + tail;
+  }
+  if (x > 740.0) return 0.0;
+  const double tau = fmin(0.2, 0.7 / sqrt(x));
+  double sum = 0.5;
+  for (int j = 1; j < 400; ++j) {
+    const double e = x * (cosh(j * tau) - 1.0);
+    if (e > 40.0) break;
+    sum += exp(-e);
+  }
+  return exp(-x) * tau * sum;
+}
+
+__device__ double wire_g(double rho, double k, double rw) {
+  return k == 0.0 ? -2.0 * log(rho / rw) : 2.0 * wire_k0(k * rho);
+}
+
+__device__ double wire_origin(double k, double h, double rw, const GLRule& gl) {
+  constexpr double kGamma = 0.57721566490153286061;
+  double acc = 0.0;
+  for (int a = 0; a < kGLPoints; ++a) {
+    const double th = (gl.t[a] + 1.0) * (kPi / 8.0);
+    const double R = h / (2.0 * cos(th));
+    const double lR = log(R);
+    double inner;
+    if (k == 0.0) {
+      inner = R * R * (log(rw) - lR + 0.5);
+    } else {
+      inner = 0.0;
+      double coef = 1.0, hj = 0.0, Rp = R * R;
+      const double base = -kGamma - log(0.5 * k);
+      for (int j = 0; j < 24; ++j) {
+        if (j > 0) {
+          hj += 1.0 / j;
+          coef *= 0.25 * k * k / ((double)j * j);
+          Rp *= R * R;
+        }
+        const double p = 2.0 * j + 2.0;
+        inner += 2.0 * coef * Rp / p * (hj + base - lR + 1.0 / p);
+      }
+    }
+    acc += gl.w[a] * (kPi / 8.0) * inner;
+  }
+  return 8.0 / (h * h) * acc;
+}
+
+__global__ void k_wire_gen(double* __restrict__ out, int Lx, int Ly, int Lz, int nx, int ny,
+                           double h, double rw, GLRule gl) {
+  const long long n = (long long)Lx * Ly * Lz;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % Lx);
+    const int iy = (int)((i / Lx) % Ly);
+    const int iz = (int)(i / ((long long)Lx * Ly));
+    const int mx = ix <= nx ? ix : Lx - ix;
+    const int my = iy <= ny ? iy : Ly - iy;
+    const int mz = iz <= Lz - iz ? iz : Lz - iz;
+    const double k = 2.0 * kPi * mz / (Lz * h);
+    double v;
+    if (mx == 0 && my == 0) {
+      v = wire_origin(k, h, rw, gl);
+    } else {
+      double acc = 0.0;
+      for (int a = 0; a < kGLPoints; ++a) {
+        const double x = (mx + 0.5 * gl.t[a]) * h;
+        double row = 0.0;
+        for (int b = 0; b < kGLPoints; ++b) {
+          const double y = (my + 0.5 * gl.t[b]) * h;
+          row += gl.w[b] * wire_g(sqrt(x * x + y * y), k, rw);
+        }
+        acc += gl.w[a] * row;
+      }
+      v = 0.25 * acc;
+    }
+    out[i] = v;
+  }
+}
+
+void launch_wire_gen(double* out, const Geom& g, double rw, const GLRule& gl, hipStream_t s) {
+  const long long n = (long long)g.Lx * g.Ly * g.Lz;
+  const int grid = (int)std::min<long long>((n + kThreads - 1) / kThreads, 65535);
+  GPS_LAUNCH(k_wire_gen, dim3(grid), dim3(kThreads), 0, s, out, g.Lx, g.Ly, g.Lz, g.nx, g.ny,
+             g.h, rw, gl);
+}
+
 // t[kz][ky][kx] = scale * Re buf[kz][ky * Kx + kx], kz <= Lz/2
 __global__ void k_surface_compress(const cplx<double>* __restrict__ buf, int Kx, int Lyh, int Lz,
                                    double scale, double* __restrict__ t64,

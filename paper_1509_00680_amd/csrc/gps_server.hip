@@ -312,7 +312,8 @@ gps_status gps_server_create(const gps_server_options* opt, gps_server** out) {
 gps_status gps_server_submit(gps_server* S, const gps_request* q, long long* ticket) {
   if (!S || !q || !ticket) return GPS_E_INVALID;
   if (q->nx < 2 || q->ny < 2 || q->nz < 2 || !(q->h > 0.0) || !(q->tol > 0.0)) return GPS_E_INVALID;
-  if (q->bc != GPS_BC_FREE && q->bc != GPS_BC_SURFACE && q->bc != GPS_BC_PERIODIC)
+  if (q->bc != GPS_BC_FREE && q->bc != GPS_BC_SURFACE && q->bc != GPS_BC_PERIODIC &&
+      q->bc != GPS_BC_WIRE)
     return GPS_E_INVALID;
   if (!q->rho || !q->eps || !q->phi) return GPS_E_INVALID;
   Request* R = new (std::nothrow) Request();

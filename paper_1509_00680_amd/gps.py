@@ -12,8 +12,9 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgps.so")
 
-GPS_BC_FREE, GPS_BC_SURFACE, GPS_BC_PERIODIC = 0, 1, 2
-BC_CODES = {"free": GPS_BC_FREE, "surface": GPS_BC_SURFACE, "periodic": GPS_BC_PERIODIC}
+GPS_BC_FREE, GPS_BC_SURFACE, GPS_BC_PERIODIC, GPS_BC_WIRE = 0, 1, 2, 3
+BC_CODES = {"free": GPS_BC_FREE, "surface": GPS_BC_SURFACE, "periodic": GPS_BC_PERIODIC,
+            "wire": GPS_BC_WIRE}
 GPS_PREC_FP64, GPS_PREC_MIXED = 0, 1
 PRECISIONS = {"fp64": GPS_PREC_FP64, "mixed": GPS_PREC_MIXED}
 

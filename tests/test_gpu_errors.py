@@ -15,7 +15,7 @@ def _prob():
 
 def test_invalid_plan_arguments():
     require_gpu()
-    for args in [(1, 8, 8, 0.5, 0), (8, 8, 8, 0.0, 0), (8, 8, 8, 0.5, 3), (8, 8, 8, float("nan"), 0)]:
+    for args in [(1, 8, 8, 0.5, 0), (8, 8, 8, 0.0, 0), (8, 8, 8, 0.5, 4), (8, 8, 8, float("nan"), 0)]:
         st, h = gps.gps_plan_create(*args)
         assert st == gps.GPS_E_INVALID and not h.value
 

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 SHAPES = [(12, 10, 14), (9, 7, 5), (16, 16, 16)]
 
 
-@pytest.mark.parametrize("bc", ["free", "surface", "periodic"])
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_vacuum_solver_matches_oracle(bc, shape, precision):
@@ -35,7 +35,7 @@ def test_vacuum_solver_matches_oracle(bc, shape, precision):
     assert np.abs(got - expect).max() <= tol * np.abs(expect).max()
 
 
-@pytest.mark.parametrize("bc", ["free", "surface", "periodic"])
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
 def test_gpe_fp64_matches_oracle(bc):
     require_gpu()
     prob = W.molecule(20, 0.5, seed=5, n_atoms=6, ball=2.0, bc=bc)
@@ -99,7 +99,7 @@ def test_sphere_fp64_parity():
         assert a < 0 and d > 0
 
 
-@pytest.mark.parametrize("bc", ["free", "surface", "periodic"])
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
 def test_gpe_mixed_matches_oracle(bc):
     require_gpu()
     prob = W.molecule(32, 0.45, seed=7, n_atoms=10, ball=3.0, bc=bc)
@@ -117,7 +117,7 @@ def test_gpe_mixed_matches_oracle(bc):
     assert abs(p.info()["energy"] / e_ref - 1.0) <= 1e-6
 
 
-@pytest.mark.parametrize("bc", ["free", "surface", "periodic"])
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_linear_pb_matches_oracle(bc, precision):
     require_gpu()
@@ -175,7 +175,7 @@ def test_boltzmann_overflow_reported():
     assert st == gps.GPS_E_NONFINITE
 
 
-@pytest.mark.parametrize("bc", ["free", "surface"])
+@pytest.mark.parametrize("bc", ["free", "surface", "wire"])
 def test_refinement_reaches_fp64_accuracy_in_mixed(bc):
     # mixed precision with the FP64 true-residual refinement converges to the
     # FP64 solution: at tol 1e-9 it agrees with the oracle far below the ~1e-7

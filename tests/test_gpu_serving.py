@@ -38,7 +38,7 @@ def _solve_alone(prob, rho, eps, precision="mixed"):
     return st, phi, info
 
 
-@pytest.mark.parametrize("bc", ["free", "surface", "periodic"])
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_footprint_matches_plan_bytes(bc, precision):
     require_gpu()

@@ -111,7 +111,7 @@ def _tile(T, mode, L, Lin, Lout, npen, per_group, group_stride, elem_stride, wsi
 def launches(shape, bc):
     """(tag, T, args, kwargs) of the strided launches for a grid."""
     nz, ny, nx = shape
-    px, pz = bc != "free", bc == "periodic"
+    px, pz = bc in ("surface", "periodic"), bc in ("periodic", "wire")
     Lx, Ly, Lz = (nx if px else 2 * nx), (ny if px else 2 * ny), (nz if pz else 2 * nz)
     Kx = Lx // 2 + 1
     tab = (Lz // 2 + 1) * (Ly // 2 + 1) * Kx
@@ -125,6 +125,8 @@ def launches(shape, bc):
         Wf = Lz * Ly * Kx
         yield "plan y", "d", (ST_FWD, Ly, Ly, Ly, Lz * Kx, Kx, Ly * Kx, Kx, Wf), {}
         yield "plan z", "d", (ST_FWD, Lz, Lz, Lz // 2 + 1, Ly * Kx, Ly * Kx, 0, Ly * Kx, Wf), {}
+    if bc == "wire":
+        yield "plan y", "d", (ST_FWD, Ly, Ly, Ly, Lz * Kx, Kx, Ly * Kx, Kx, Lz * Ly * Kx), {}
     if bc == "surface":
         nc = Kx * (Ly // 2 + 1)
         yield "plan z", "d", (ST_FWD, Lz, Lz, Lz // 2 + 1, nc, nc, 0, nc, nc * Lz), {}
@@ -133,7 +135,7 @@ def launches(shape, bc):
 GRIDS = [(n, n, n) for n in (16, 24, 32, 48, 64, 96, 128, 160)] + [(192, 128, 128), (14, 10, 12)]
 
 
-@pytest.mark.parametrize("bc", ["free", "surface", "periodic"])
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
 def test_strided_passes_stay_in_bounds(bc):
     checked = 0
     for shape in GRIDS:
@@ -167,8 +169,8 @@ def test_partial_sums_fit_their_arrays():
     the solve resources)."""
     for shape in GRIDS:
         nz, ny, nx = shape
-        for bc in ("free", "surface", "periodic"):
-            px, pz = bc != "free", bc == "periodic"
+        for bc in ("free", "surface", "periodic", "wire"):
+            px, pz = bc in ("surface", "periodic"), bc in ("periodic", "wire")
             Lx, Ly, Lz = (nx if px else 2 * nx), (ny if px else 2 * ny), (nz if pz else 2 * nz)
             Kx = Lx // 2 + 1
             if Lx in FAST:
