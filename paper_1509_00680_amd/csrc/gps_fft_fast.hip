@@ -349,7 +349,7 @@ __device__ __forceinline__ void tile_row_offsets(const XParams<T>& p, int row0, 
 }
 
 template <typename T, int L1, int L2, int MODE, bool PAD>
-__global__ __launch_bounds__(xthreads<L1>()) __attribute__((amdgpu_waves_per_eu(1, 2)))
+__global__ __launch_bounds__(xthreads<L1>())
 void k_fxfwd(XParams<T> p) {
   constexpr bool SOLVE = MODE == XF_SOLVE || MODE == XF_SOLVE_REF;
   constexpr bool REF = MODE == XF_SOLVE_REF;     // also s += alpha sigma (refinement)
@@ -541,7 +541,7 @@ void k_fxfwd(XParams<T> p) {
 // direction update of the PCG iteration (with the periodic mean term; with the
 // refinement's sigma = r / sqrt(eps) + beta sigma); XI_REAL: plain output.
 template <typename T, int L1, int L2, int MODE, bool PAD>
-__global__ __launch_bounds__(xthreads<L1>()) __attribute__((amdgpu_waves_per_eu(1, 2)))
+__global__ __launch_bounds__(xthreads<L1>())
 void k_fxinv(XParams<T> p) {
   constexpr bool SOLVE = MODE != XI_REAL;
   constexpr bool PER = MODE == XI_SOLVE_PERIODIC;
