@@ -19,6 +19,8 @@ Modules
   pb       -- ionic charge (Eqs. ionsconcPB, ionsconcMPB, maxconc) and the
               self-consistent loops of Algorithms SCPB and SCPBimproved.
   dense    -- dense direct solve of the same discrete problem (tiny grids).
+  sc       -- Algorithm SC and the PSD minimization (Sec. II.A), with their
+              dense operator for tiny grids.
   wire     -- the wire-BC kernel (periodic z, isolated x and y): cell-averaged
               2 K0(|kz| rho) per z mode (Sec. II.C lists the wire BC).
   cavity   -- rigid cavity of Eq. RigCav with its analytic q (Sec. IV.A), and
