@@ -902,6 +902,116 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
   return result;
 }
 
+// Algorithm SC and the PSD minimization (Sec. II.A), driven from the host:
+// per step one vacuum solve (the plan's passes, bulk precision) of f = r/eps,
+// the operator A v = -4 pi r + eps grad ln eps . grad v with (A v, r/eps^2)
+// and (A v, A v/eps^2), and the update phi += alpha v, r -= alpha A v (FP64).
+// PSD takes the step that minimizes ||r/eps||_2; SC is the same recurrence
+// with the fixed steps -1/(4 pi) (first) and -eta/(4 pi), and its residual
+// ||rho_iter_{k+1} - rho_iter_k|| equals (eta/4 pi) ||r/eps|| at the current
+// iterate.
+struct ScBuffers {
+  double *r = nullptr, *v = nullptr, *av = nullptr, *f = nullptr, *part = nullptr;
+  ~ScBuffers() {
+    dfree(r);
+    dfree(v);
+    dfree(av);
+    dfree(f);
+    dfree(part);
+  }
+};
+
+template <typename T>
+gps_status sc_impl(gps_plan* pl, const double* rho, const double* eps, double* phi, double tol,
+                   int method, double eta) {
+  const long long n = pl->npts();
+  const Geom& g = pl->g;
+  hipStream_t s = pl->stream();
+  ScBuffers b;
+  size_t bytes = 0;
+  dalloc(&b.r, (size_t)n * sizeof(double), &bytes);
+  dalloc(&b.v, (size_t)n * sizeof(double), &bytes);
+  dalloc(&b.av, (size_t)n * sizeof(double), &bytes);
+  dalloc(&b.f, (size_t)n * sizeof(double), &bytes);
+  const int gv = vec_groups(n), gp = polarization_groups(g);
+  dalloc(&b.part, (size_t)2 * std::max(gv, gp) * sizeof(double), &bytes);
+  std::vector<double> hp((size_t)2 * std::max(gv, gp));
+  auto sums = [&](int groups, double* a0, double* a1) {
+    ck(hipMemcpyAsync(hp.data(), b.part, (size_t)2 * groups * sizeof(double),
+                      hipMemcpyDeviceToHost, s));
+    ck(hipStreamSynchronize(s));
+    double x = 0.0, y = 0.0;
+    for (int i = 0; i < groups; ++i) {
+      x += hp[(size_t)2 * i];
+      y += hp[(size_t)2 * i + 1];
+    }
+    *a0 = x;
+    *a1 = y;
+  };
+  launch_sc_step(0, n, 0.0, rho, eps, phi, b.r, nullptr, nullptr, b.f, b.part, s);
+  ck(hipGetLastError());
+  double rr0 = 0.0, ff = 0.0;
+  sums(gv, &rr0, &ff);
+  std::memset(&pl->info, 0, sizeof(pl->info));
+  pl->hist.clear();
+  if (!std::isfinite(rr0) || !std::isfinite(ff)) return GPS_E_NONFINITE;
+  const double thr_psd = tol * std::sqrt(ff);                 // tol ||4 pi rho/eps||
+  const double thr_sc = tol * std::sqrt(rr0) / kFourPi;      // tol ||rho||
+  gps_status status = GPS_E_NOT_CONVERGED;
+  int iters = 0;
+  double rr = rr0;
+  if (rr0 == 0.0) status = GPS_OK;
+  const int max_steps = method == GPS_METHOD_SC ? pl->opt.maxit + 1 : pl->opt.maxit;
+  for (int step = 0; status == GPS_E_NOT_CONVERGED && step < max_steps; ++step) {
+    vacuum_apply<T>(pl, b.f, b.v);
+    launch_sc_operator(g, pl->opt.fd_order / 2, b.r, eps, b.v, b.av, b.part, s);
+    ck(hipGetLastError());
+    double vr = 0.0, vav = 0.0;
+    sums(gp, &vr, &vav);
+    double alpha;
+    if (method == GPS_METHOD_SC) {
+      alpha = (step == 0 ? -1.0 : -eta) / kFourPi;
+    } else {
+      if (!std::isfinite(vr) || !std::isfinite(vav)) {
+        status = GPS_E_NONFINITE;
+        break;
+      }
+      if (!(vav > 0.0)) {
+        status = GPS_E_BREAKDOWN;
+        break;
+      }
+      alpha = vr / vav;
+    }
+    const double ff_before = ff;
+    launch_sc_step(1, n, alpha, rho, eps, phi, b.r, b.v, b.av, b.f, b.part, s);
+    ck(hipGetLastError());
+    sums(gv, &rr, &ff);
+    if (!std::isfinite(rr) || !std::isfinite(ff)) {
+      status = GPS_E_NONFINITE;
+      break;
+    }
+    if (method == GPS_METHOD_SC) {
+      if (step >= 1) {
+        iters = step;
+        if (eta / kFourPi * std::sqrt(ff_before) <= thr_sc) status = GPS_OK;
+      }
+    } else {
+      iters = step + 1;
+      if (std::sqrt(ff) <= thr_psd) status = GPS_OK;
+    }
+  }
+  launch_sc_step(2, n, 0.0, rho, eps, phi, b.r, b.v, b.av, b.f, b.part, s);
+  ck(hipGetLastError());
+  double e = 0.0, unused = 0.0;
+  sums(gv, &e, &unused);
+  pl->info.status = status;
+  pl->info.iterations = iters;
+  pl->info.rnorm0 = std::sqrt(rr0);
+  pl->info.rel_residual = rr0 > 0.0 ? std::sqrt(rr / rr0) : 0.0;
+  pl->info.energy = 0.5 * g.h * g.h * g.h * e;
+  return status;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1124,6 +1234,25 @@ gps_status gps_solve_generalized_q(gps_plan* pl, const double* rho, const double
   if (pl->bc == GPS_BC_PERIODIC) return GPS_E_INVALID;
   Electrolyte el;
   return run_guarded(pl, pl->opt.precision == GPS_PREC_MIXED, rho, eps, phi, tol, el, q);
+}
+
+gps_status gps_solve_sc(gps_plan* pl, const double* rho, const double* eps, double* phi,
+                        double tol, int method, double eta) {
+  if (!pl || !rho || !eps || !phi || !(tol > 0.0) || !std::isfinite(tol)) return GPS_E_INVALID;
+  if (method != GPS_METHOD_SC && method != GPS_METHOD_PSD) return GPS_E_INVALID;
+  if (method == GPS_METHOD_SC && !(eta > 0.0 && eta <= 1.0)) return GPS_E_INVALID;
+  if (pl->bc == GPS_BC_PERIODIC) return GPS_E_INVALID;
+  pl->info.device_error = 0;
+  try {
+    if (pl->opt.precision == GPS_PREC_MIXED) return sc_impl<float>(pl, rho, eps, phi, tol, method, eta);
+    return sc_impl<double>(pl, rho, eps, phi, tol, method, eta);
+  } catch (const NoMem&) {
+    return GPS_E_NOMEM;
+  } catch (const DevError& d) {
+    pl->info.device_error = (int)d.e;
+    pl->info.status = GPS_E_DEVICE;
+    return GPS_E_DEVICE;
+  }
 }
 
 gps_status gps_rigid_cavity(gps_plan* pl, int natoms, const double* atoms, double delta,

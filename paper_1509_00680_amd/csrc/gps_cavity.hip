@@ -1,10 +1,12 @@
-// Cavity builder and diagnostics around the PCG solve:
+// Cavity builder, diagnostics and the comparison iterations around the PCG solve:
 //  * the rigid cavity of Eq. RigCav (Sec. IV.A) with its analytic correction
 //    vector q = sqrt(eps) lap sqrt(eps) (Eq. corr);
 //  * the polarization charge of Eqs. rhoiter and remap,
 //    rho_pol = (1/4 pi) grad ln eps . grad phi - (1 - 1/eps) rho,
 //    with order-2M central first differences (the sign of the second term is
-//    the one Eq. remap implies; Eq. rhopol prints a plus).
+//    the one Eq. remap implies; Eq. rhopol prints a plus);
+//  * the operator and pointwise steps of Algorithm SC and the PSD minimization
+//    (Sec. II.A, Eq. PrePSD).
 #include "gps_device.h"
 #include "gps_launch.h"
 
@@ -106,12 +108,18 @@ struct FdFirst { double c[9]; };
 constexpr int kPTX = 32, kPTY = 16, kPZC = 4;
 constexpr int kPThreads = kPTX * kPTY;
 
-template <int M>
+// AV = false: out = rho_pol from (rho, eps, phi).  AV = true (PSD / SC
+// operator, Eq. PrePSD with grad eps = eps grad ln eps): with rho -> r and
+// phi -> v, out = A v = -4 pi r + eps grad ln eps . grad v, and two FP64
+// partials per work-group, (A v, r/eps^2) and (A v, A v/eps^2) (the step that
+// minimizes ||r/eps||_2), into part[2 b], part[2 b + 1].
+template <int M, bool AV>
 __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, int ntx, int nty,
                                                             const double* __restrict__ rho,
                                                             const double* __restrict__ eps,
                                                             const double* __restrict__ phi,
-                                                            double* __restrict__ out) {
+                                                            double* __restrict__ out,
+                                                            double* __restrict__ part) {
   constexpr int TW = kPTX + 2 * M;
   constexpr int TH = kPTY + 2 * M;
   constexpr int NXH = 2 * M * kPTY;                // halo slots left and right of the tile
@@ -163,8 +171,9 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
     he[s] = log(eps[(size_t)z0 * plane + ho[s]]);
     hp[s] = phi[(size_t)z0 * plane + ho[s]];
   }
-  const double scale = 1.0 / (4.0 * kPi * g.h * g.h);
+  const double scale = AV ? 1.0 / (g.h * g.h) : 1.0 / (4.0 * kPi * g.h * g.h);
   const bool inside = X < g.nx && Y < g.ny;
+  double vr = 0.0, vav = 0.0;
   for (int z = z0; z < z1; ++z) {
     te[(M + ty) * TW + M + tx] = qe[M];
     tp[(M + ty) * TW + M + tx] = qp[M];
@@ -201,7 +210,18 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
       pyd = fma(w.c[m], cp[m * TW] - cp[-m * TW], pyd);
       pzd = fma(w.c[m], qp[M + m] - qp[M - m], pzd);
     }
-    if (inside) out[o] = (exd * pxd + eyd * pyd + ezd * pzd) * scale - (1.0 - 1.0 / ev) * rv;
+    if (inside) {
+      const double dot = (exd * pxd + eyd * pyd + ezd * pzd) * scale;
+      if constexpr (AV) {
+        const double av = -4.0 * kPi * rv + ev * dot;
+        out[o] = av;
+        const double aw = av / (ev * ev);
+        vr += aw * rv;
+        vav += aw * av;
+      } else {
+        out[o] = dot - (1.0 - 1.0 / ev) * rv;
+      }
+    }
     __syncthreads();                              // tile reads done before the next writes
 #pragma unroll
     for (int k = 0; k < 2 * M; ++k) {
@@ -214,6 +234,14 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
     for (int s = 0; s < HS; ++s) {
       he[s] = log(hne[s]);
       hp[s] = hnp[s];
+    }
+  }
+  if constexpr (AV) {
+    vr = block_sum(vr);
+    vav = block_sum(vav);
+    if (tid == 0) {
+      part[2 * blockIdx.x] = vr;
+      part[2 * blockIdx.x + 1] = vav;
     }
   }
 }
@@ -231,22 +259,93 @@ static FdFirst fd_first_weights(int M) {
   return w;
 }
 
-void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
-                         const double* phi, double* out, hipStream_t s) {
+int polarization_groups(const Geom& g) {
+  return ((g.nx + kPTX - 1) / kPTX) * ((g.ny + kPTY - 1) / kPTY) * ((g.nz + kPZC - 1) / kPZC);
+}
+
+template <bool AV>
+static void launch_graddot(const Geom& g, int fd_half, const double* rho, const double* eps,
+                           const double* phi, double* out, double* part, hipStream_t s) {
   const int ntx = (g.nx + kPTX - 1) / kPTX, nty = (g.ny + kPTY - 1) / kPTY;
-  const int nzc = (g.nz + kPZC - 1) / kPZC;
-  const dim3 grid(ntx * nty * nzc);
+  const dim3 grid(polarization_groups(g));
   const FdFirst w = fd_first_weights(fd_half);
 #define GPS_PF(MM)                                                                        \
   case MM:                                                                                \
-    GPS_LAUNCH((k_polarization<MM>), grid, dim3(kPThreads), 0, s, g, w, ntx, nty, rho,    \
-               eps, phi, out);                                                            \
+    GPS_LAUNCH((k_polarization<MM, AV>), grid, dim3(kPThreads), 0, s, g, w, ntx, nty,     \
+               rho, eps, phi, out, part);                                                 \
     break;
   switch (fd_half) {
     GPS_PF(1) GPS_PF(2) GPS_PF(3) GPS_PF(4) GPS_PF(5) GPS_PF(6) GPS_PF(7) GPS_PF(8)
     default: break;
   }
 #undef GPS_PF
+}
+
+void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
+                         const double* phi, double* out, hipStream_t s) {
+  launch_graddot<false>(g, fd_half, rho, eps, phi, out, nullptr, s);
+}
+
+void launch_sc_operator(const Geom& g, int fd_half, const double* r, const double* eps,
+                        const double* v, double* av, double* part, hipStream_t s) {
+  launch_graddot<true>(g, fd_half, r, eps, v, av, part, s);
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise steps of Algorithm SC / PSD (FP64), two partials per work-group.
+// init:   r = -4 pi rho, f = r/eps, phi = 0;       partials ||r||^2, ||r/eps||^2
+// update: phi += alpha v, r -= alpha A v, f = r/eps; partials ||r||^2, ||r/eps||^2
+// energy: partials sum rho phi, 0
+// ---------------------------------------------------------------------------
+constexpr int kScInit = 0, kScUpdate = 1, kScEnergy = 2;
+
+__global__ __launch_bounds__(kThreads) void k_sc_step(int mode, long long n, double alpha,
+                                                      const double* __restrict__ rho,
+                                                      const double* __restrict__ eps,
+                                                      double* __restrict__ phi,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ av,
+                                                      double* __restrict__ f,
+                                                      double* __restrict__ part) {
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) {
+      if (mode == kScEnergy) {
+        a0 += rho[i] * phi[i];
+        continue;
+      }
+      double ri;
+      if (mode == kScInit) {
+        ri = -4.0 * kPi * rho[i];
+        phi[i] = 0.0;
+      } else {
+        phi[i] += alpha * v[i];
+        ri = r[i] - alpha * av[i];
+      }
+      r[i] = ri;
+      const double fi = ri / eps[i];
+      f[i] = fi;
+      a0 += ri * ri;
+      a1 += fi * fi;
+    }
+  }
+  a0 = block_sum(a0);
+  a1 = block_sum(a1);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a0;
+    part[2 * blockIdx.x + 1] = a1;
+  }
+}
+
+void launch_sc_step(int mode, long long n, double alpha, const double* rho, const double* eps,
+                    double* phi, double* r, const double* v, const double* av, double* f,
+                    double* part, hipStream_t s) {
+  GPS_LAUNCH(k_sc_step, dim3(vec_groups(n)), dim3(kThreads), 0, s, mode, n, alpha, rho, eps,
+             phi, r, v, av, f, part);
 }
 
 }  // namespace gps

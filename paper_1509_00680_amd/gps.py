@@ -28,7 +28,8 @@ GPS_PENDING = 8
 # every symbol include/gps.h declares
 EXPORTED = ("gps_plan_create", "gps_plan_set_options", "gps_plan_get_options",
             "gps_plan_device_bytes", "gps_plan_destroy", "gps_solve_generalized",
-            "gps_solve_pb", "gps_solve_vacuum", "gps_solve_generalized_q", "gps_rigid_cavity",
+            "gps_solve_pb", "gps_solve_vacuum", "gps_solve_generalized_q", "gps_solve_sc",
+            "gps_rigid_cavity",
             "gps_polarization_charge", "gps_last_info", "gps_last_history",
             "gps_plan_set_timing", "gps_plan_timing", "gps_status_string",
             "gps_plan_footprint", "gps_plan_release_buffers", "gps_server_create", "gps_server_submit", "gps_server_poll",
@@ -130,6 +131,8 @@ def load(path=LIB_PATH):
     lib.gps_solve_vacuum.restype = I
     lib.gps_solve_generalized_q.argtypes = [P, P, P, P, P, D]
     lib.gps_solve_generalized_q.restype = I
+    lib.gps_solve_sc.argtypes = [P, P, P, P, D, I, D]
+    lib.gps_solve_sc.restype = I
     lib.gps_rigid_cavity.argtypes = [P, I, P, D, D, P, P]
     lib.gps_rigid_cavity.restype = I
     lib.gps_polarization_charge.argtypes = [P, P, P, P, P]
@@ -266,6 +269,14 @@ class Plan:
             _check_field(t, self.shape)
         return load().gps_solve_generalized_q(self.handle, _ptr(rho), _ptr(eps), _ptr(q),
                                               _ptr(phi), float(tol))
+
+    def solve_sc(self, rho, eps, phi, tol, method="sc", eta=0.6):
+        """gps_solve_sc: Algorithm SC (method "sc", mixing eta) or PSD ("psd")."""
+        for t in (rho, eps, phi):
+            _check_field(t, self.shape)
+        code = {"sc": 0, "psd": 1}[method]
+        return load().gps_solve_sc(self.handle, _ptr(rho), _ptr(eps), _ptr(phi), float(tol),
+                                   code, float(eta))
 
     def rigid_cavity(self, atoms, delta, eps0, eps, q=None):
         """gps_rigid_cavity: atoms is a device float64 tensor of shape (natoms, 4)."""
