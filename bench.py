@@ -54,7 +54,8 @@ def parse():
                     help="skip the per-pass kernel times (extra eager solves)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum wall time of the oracle sample (whole solves)")
-    ap.add_argument("--workload", default="molecule", choices=("molecule", "serving", "rigid"),
+    ap.add_argument("--workload", default="molecule",
+                    choices=("molecule", "serving", "rigid", "sc"),
                     help="molecule: one 96^3 solve per step (default); serving: a request "
                          "stream through the serving loop")
     ap.add_argument("--requests", type=int, default=512, help="serving: stream length")
@@ -334,6 +335,46 @@ def rigid_bench(args, torch, gps, W):
     }
 
 
+def sc_bench(args, torch, gps, W):
+    """Algorithm SC (mixing 0.6) and PSD on the molecule workload, against
+    Algorithm PCG on the same plan (Sec. II.A vs II.B): iterations, solves/s
+    and time per iteration at the same tolerance (SC and PSD measure their
+    own residuals, ||rho_iter_{k+1} - rho_iter_k|| / ||rho|| and ||r/eps||)."""
+    prob = W.molecule(args.n, args.h, seed=args.seed, bc=args.bc)
+    rho = torch.from_numpy(prob.rho).cuda()
+    eps = torch.from_numpy(prob.eps).cuda()
+    phi = torch.empty_like(rho)
+    plan = gps.Plan(prob.shape, prob.h, prob.bc, precision=args.precision, maxit=5000,
+                    check_every=args.check_every)
+    out = {}
+    for name, run in (("pcg", lambda: plan.solve_generalized(rho, eps, phi, args.tol)),
+                      ("sc", lambda: plan.solve_sc(rho, eps, phi, args.tol, "sc", 0.6)),
+                      ("psd", lambda: plan.solve_sc(rho, eps, phi, args.tol, "psd"))):
+        run()
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // (1 if name == "pcg" else 4))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = run()
+            if st != 0:
+                raise RuntimeError("%s failed with status %d" % (name, st))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        it = plan.info()["iterations"]
+        out[name] = {"solves_per_s": 1.0 / dt, "iterations": it, "ms_per_solve": dt * 1e3,
+                     "us_per_iteration": dt * 1e6 / max(1, it), "energy": plan.info()["energy"]}
+    return {
+        "metric": "SC and PSD against PCG: solves/s at the same tolerance",
+        "value": out["sc"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": out["sc"]["ms_per_solve"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "molecule%d_sccs_%s" % (args.n, args.bc), "tol": args.tol,
+                   "precision": args.precision, "eta": 0.6},
+        "methods": out,
+    }
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -352,6 +393,9 @@ def main():
         return
     if args.workload == "rigid":
         print(json.dumps(rigid_bench(args, torch, gps, W)))
+        return
+    if args.workload == "sc":
+        print(json.dumps(sc_bench(args, torch, gps, W)))
         return
 
     prob = W.molecule(args.n, args.h, seed=args.seed, bc=args.bc)
