@@ -58,6 +58,9 @@ def parse():
                     choices=("molecule", "serving", "rigid", "sc"),
                     help="molecule: one 96^3 solve per step (default); serving: a request "
                          "stream through the serving loop")
+    ap.add_argument("--problem", default="molecule", choices=("molecule", "manufactured"),
+                    help="sc workload: the molecule, or the Gaussian test of Sec. II.C "
+                         "(box 10, sigma 0.5, d0 1.7, Delta 0.3) with its analytic potential")
     ap.add_argument("--requests", type=int, default=512, help="serving: stream length")
     ap.add_argument("--max-active", type=int, default=4, help="serving: concurrent solves")
     ap.add_argument("--budget-frac", type=float, default=0.75,
@@ -340,37 +343,44 @@ def sc_bench(args, torch, gps, W):
     Algorithm PCG on the same plan (Sec. II.A vs II.B): iterations, solves/s
     and time per iteration at the same tolerance (SC and PSD measure their
     own residuals, ||rho_iter_{k+1} - rho_iter_k|| / ||rho|| and ||r/eps||)."""
-    prob = W.molecule(args.n, args.h, seed=args.seed, bc=args.bc)
+    exact = None
+    if args.problem == "manufactured":
+        prob, exact = W.manufactured_gaussian(args.n, box=10.0, sigma=0.5, d0=1.7, delta=0.3)
+        name = "manufactured%d" % args.n
+    else:
+        prob = W.molecule(args.n, args.h, seed=args.seed, bc=args.bc)
+        name = "molecule%d_sccs_%s" % (args.n, args.bc)
     rho = torch.from_numpy(prob.rho).cuda()
     eps = torch.from_numpy(prob.eps).cuda()
     phi = torch.empty_like(rho)
     plan = gps.Plan(prob.shape, prob.h, prob.bc, precision=args.precision, maxit=5000,
                     check_every=args.check_every)
     out = {}
-    for name, run in (("pcg", lambda: plan.solve_generalized(rho, eps, phi, args.tol)),
+    for meth, run in (("pcg", lambda: plan.solve_generalized(rho, eps, phi, args.tol)),
                       ("sc", lambda: plan.solve_sc(rho, eps, phi, args.tol, "sc", 0.6)),
                       ("psd", lambda: plan.solve_sc(rho, eps, phi, args.tol, "psd"))):
         run()
         torch.cuda.synchronize()
-        reps = max(1, args.steps // (1 if name == "pcg" else 4))
+        reps = max(1, args.steps // (1 if meth == "pcg" else 4))
         t0 = time.perf_counter()
         for _ in range(reps):
             st = run()
             if st != 0:
-                raise RuntimeError("%s failed with status %d" % (name, st))
+                raise RuntimeError("%s failed with status %d" % (meth, st))
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         it = plan.info()["iterations"]
-        out[name] = {"solves_per_s": 1.0 / dt, "iterations": it, "ms_per_solve": dt * 1e3,
+        out[meth] = {"solves_per_s": 1.0 / dt, "iterations": it, "ms_per_solve": dt * 1e3,
                      "us_per_iteration": dt * 1e6 / max(1, it), "energy": plan.info()["energy"]}
+        if exact is not None:
+            out[meth]["max_error_vs_analytic"] = float(np.abs(phi.cpu().numpy() - exact).max())
     return {
         "metric": "SC and PSD against PCG: solves/s at the same tolerance",
         "value": out["sc"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": out["sc"]["ms_per_solve"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": "molecule%d_sccs_%s" % (args.n, args.bc), "tol": args.tol,
-                   "precision": args.precision, "eta": 0.6},
+        "config": {"workload": name, "tol": args.tol, "precision": args.precision, "eta": 0.6},
         "methods": out,
     }
 
