@@ -73,3 +73,27 @@ def test_sc_arguments_checked():
     # zero charge: nothing to do
     assert pf.solve_sc(rho, eps, phi, 1e-6) == gps.GPS_OK
     assert pf.info()["iterations"] == 0 and not host(phi).any()
+
+
+def test_paper_gaussian_test_pcg_faster_than_sc():
+    # the Gaussian test of Sec. II.C (box 10, sigma 0.5, d0 1.7, Delta 0.3):
+    # PCG reaches 1e-10 in about ten iterations, SC (eta 0.6) and PSD need
+    # about twice as many; all three approach the analytic potential to the
+    # kernel's discretization error
+    require_gpu()
+    prob, exact = W.manufactured_gaussian(64, box=10.0, sigma=0.5, d0=1.7, delta=0.3)
+    pl = plan(prob.shape, prob.h, "free", "fp64", maxit=500)
+    rho, eps, phi = dev(prob.rho), dev(prob.eps), empty(prob.shape)
+    print("paper gaussian test", flush=True)
+    assert pl.solve_generalized(rho, eps, phi, 1e-10) == gps.GPS_OK
+    it_pcg = pl.info()["iterations"]
+    err_pcg = np.abs(host(phi) - exact).max()
+    assert pl.solve_sc(rho, eps, phi, 1e-10, method="sc", eta=0.6) == gps.GPS_OK
+    it_sc = pl.info()["iterations"]
+    err_sc = np.abs(host(phi) - exact).max()
+    assert pl.solve_sc(rho, eps, phi, 1e-10, method="psd") == gps.GPS_OK
+    it_psd = pl.info()["iterations"]
+    print("  iterations pcg %d sc %d psd %d" % (it_pcg, it_sc, it_psd))
+    assert it_pcg <= 15 and it_sc >= 1.5 * it_pcg and it_psd >= 1.5 * it_pcg
+    # second-order kernel: 1.2e-2 of max|phi| at h = 10/64
+    assert err_pcg < 3e-2 * np.abs(exact).max() and err_sc < 3e-2 * np.abs(exact).max()
