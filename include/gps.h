@@ -265,9 +265,11 @@ gps_status gps_rigid_cavity(gps_plan *plan, int natoms, const double *atoms, dou
  * so that lap phi = -4 pi (rho + rho_pol).  Gradients are central
  * differences of the plan's fd_order, with edge-replicated ghosts on free axes
  * and wrapped ones on periodic axes.  rho, eps, phi: device, read; rho_pol:
- * device, written; all double[nz][ny][nx].  FP64.  Runs on the plan's stream
- * and returns when it has finished.  Errors: GPS_E_INVALID (null pointer),
- * GPS_E_DEVICE. */
+ * device, written; all double[nz][ny][nx].  FP64.  The first call allocates
+ * a scratch field (ln eps, nx*ny*nz doubles) that the plan keeps until
+ * gps_plan_release_buffers or gps_plan_destroy (counted by
+ * gps_plan_device_bytes).  Runs on the plan's stream and returns when it has
+ * finished.  Errors: GPS_E_INVALID (null pointer), GPS_E_NOMEM, GPS_E_DEVICE. */
 gps_status gps_polarization_charge(gps_plan *plan, const double *rho, const double *eps,
                                    const double *phi, double *rho_pol);
 

@@ -163,6 +163,8 @@ struct gps_plan {
   double* green64 = nullptr;
   float* green32 = nullptr;
   double* lap64t = nullptr;     // spectral Laplacian table (periodic)
+  double* pol_lne = nullptr;    // ln eps scratch of gps_polarization_charge (n doubles)
+  size_t pol_bytes = 0;
   float* lap32t = nullptr;
   Res<float> r32;
   Res<double> r64;
@@ -912,7 +914,9 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
 // iterate.
 struct ScBuffers {
   double *r = nullptr, *v = nullptr, *av = nullptr, *f = nullptr, *part = nullptr;
+  double* lne = nullptr;
   ~ScBuffers() {
+    dfree(lne);
     dfree(r);
     dfree(v);
     dfree(av);
@@ -933,6 +937,8 @@ gps_status sc_impl(gps_plan* pl, const double* rho, const double* eps, double* p
   dalloc(&b.v, (size_t)n * sizeof(double), &bytes);
   dalloc(&b.av, (size_t)n * sizeof(double), &bytes);
   dalloc(&b.f, (size_t)n * sizeof(double), &bytes);
+  dalloc(&b.lne, (size_t)n * sizeof(double), &bytes);
+  launch_log_field(n, eps, b.lne, s);
   const int gv = vec_groups(n), gp = polarization_groups(g);
   dalloc(&b.part, (size_t)2 * std::max(gv, gp) * sizeof(double), &bytes);
   std::vector<double> hp((size_t)2 * std::max(gv, gp));
@@ -964,7 +970,7 @@ gps_status sc_impl(gps_plan* pl, const double* rho, const double* eps, double* p
   const int max_steps = method == GPS_METHOD_SC ? pl->opt.maxit + 1 : pl->opt.maxit;
   for (int step = 0; status == GPS_E_NOT_CONVERGED && step < max_steps; ++step) {
     vacuum_apply<T>(pl, b.f, b.v);
-    launch_sc_operator(g, pl->opt.fd_order / 2, b.r, eps, b.v, b.av, b.part, s);
+    launch_sc_operator(g, pl->opt.fd_order / 2, b.r, eps, b.lne, b.v, b.av, b.part, s);
     ck(hipGetLastError());
     double vr = 0.0, vav = 0.0;
     sums(gp, &vr, &vav);
@@ -1050,6 +1056,8 @@ static void plan_release(gps_plan* pl) {
   dfree(pl->green32);
   dfree(pl->lap64t);
   dfree(pl->lap32t);
+  dfree(pl->pol_lne);
+  pl->pol_bytes = 0;
 }
 
 gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan** out) {
@@ -1145,7 +1153,7 @@ gps_status gps_plan_get_options(const gps_plan* pl, gps_options* o) {
 }
 
 size_t gps_plan_device_bytes(const gps_plan* pl) {
-  return pl ? pl->bytes + pl->r32.bytes + pl->r64.bytes : 0;
+  return pl ? pl->bytes + pl->r32.bytes + pl->r64.bytes + pl->pol_bytes : 0;
 }
 
 gps_status gps_plan_release_buffers(gps_plan* pl) {
@@ -1153,6 +1161,8 @@ gps_status gps_plan_release_buffers(gps_plan* pl) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
   free_res<float>(pl);
   free_res<double>(pl);
+  dfree(pl->pol_lne);
+  pl->pol_bytes = 0;
   return GPS_OK;
 }
 
@@ -1286,9 +1296,17 @@ gps_status gps_polarization_charge(gps_plan* pl, const double* rho, const double
                                    const double* phi, double* rho_pol) {
   if (!pl || !rho || !eps || !phi || !rho_pol) return GPS_E_INVALID;
   try {
-    launch_polarization(pl->g, pl->opt.fd_order / 2, rho, eps, phi, rho_pol, pl->stream());
+    if (!pl->pol_lne) {
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      dalloc(&pl->pol_lne, (size_t)pl->npts() * sizeof(double), &pl->pol_bytes);
+    }
+    launch_log_field(pl->npts(), eps, pl->pol_lne, pl->stream());
+    launch_polarization(pl->g, pl->opt.fd_order / 2, rho, eps, pl->pol_lne, phi, rho_pol,
+                        pl->stream());
     ck(hipGetLastError());
     ck(hipStreamSynchronize(pl->stream()));
+  } catch (const NoMem&) {
+    return GPS_E_NOMEM;
   } catch (const DevError& d) {
     pl->info.device_error = (int)d.e;
     return GPS_E_DEVICE;

@@ -101,11 +101,12 @@ void launch_rigid_cavity(const Geom& g, const double* atoms, int natoms, double 
 // along z over kPZC planes; x and y neighbours of ln eps and phi come from
 // two LDS tiles with an M-wide halo, z neighbours from two register queues of
 // 2M+1 planes, and the next plane's loads are in flight while the current
-// one is differenced.  ln eps is taken as each value is loaded.
+// one is differenced.  ln eps comes precomputed (k_log_field), and eps itself
+// is read only at the tile's own points.
 // ---------------------------------------------------------------------------
 struct FdFirst { double c[9]; };
 
-constexpr int kPTX = 32, kPTY = 16, kPZC = 4;
+constexpr int kPTX = 32, kPTY = 8, kPZC = 8;
 constexpr int kPThreads = kPTX * kPTY;
 
 // AV = false: out = rho_pol from (rho, eps, phi).  AV = true (PSD / SC
@@ -117,6 +118,7 @@ template <int M, bool AV>
 __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, int ntx, int nty,
                                                             const double* __restrict__ rho,
                                                             const double* __restrict__ eps,
+                                                            const double* __restrict__ lne,
                                                             const double* __restrict__ phi,
                                                             double* __restrict__ out,
                                                             double* __restrict__ part) {
@@ -162,13 +164,13 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
 #pragma unroll
   for (int k = 0; k <= 2 * M; ++k) {
     const size_t o = (size_t)ghost_index(z0 - M + k, g.nz, g.periodic_z) * plane + cxy;
-    qe[k] = log(eps[o]);
+    qe[k] = lne[o];
     qp[k] = phi[o];
   }
   double he[HS], hp[HS];
 #pragma unroll
   for (int s = 0; s < HS; ++s) {
-    he[s] = log(eps[(size_t)z0 * plane + ho[s]]);
+    he[s] = lne[(size_t)z0 * plane + ho[s]];
     hp[s] = phi[(size_t)z0 * plane + ho[s]];
   }
   const double scale = AV ? 1.0 / (g.h * g.h) : 1.0 / (4.0 * kPi * g.h * g.h);
@@ -187,11 +189,11 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
     double hne[HS], hnp[HS];
 #pragma unroll
     for (int s = 0; s < HS; ++s) {
-      hne[s] = eps[(size_t)zn * plane + ho[s]];
+      hne[s] = lne[(size_t)zn * plane + ho[s]];
       hnp[s] = phi[(size_t)zn * plane + ho[s]];
     }
     const size_t on = (size_t)ghost_index(z + 1 + M, g.nz, g.periodic_z) * plane + cxy;
-    const double qne = eps[on], qnp = phi[on];
+    const double qne = lne[on], qnp = phi[on];
     double rv = 0.0, ev = 1.0;
     const size_t o = (size_t)z * plane + (size_t)Y * g.nx + X;
     if (inside) {
@@ -228,11 +230,11 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
       qe[k] = qe[k + 1];
       qp[k] = qp[k + 1];
     }
-    qe[2 * M] = log(qne);
+    qe[2 * M] = qne;
     qp[2 * M] = qnp;
 #pragma unroll
     for (int s = 0; s < HS; ++s) {
-      he[s] = log(hne[s]);
+      he[s] = hne[s];
       hp[s] = hnp[s];
     }
   }
@@ -263,16 +265,29 @@ int polarization_groups(const Geom& g) {
   return ((g.nx + kPTX - 1) / kPTX) * ((g.ny + kPTY - 1) / kPTY) * ((g.nz + kPZC - 1) / kPZC);
 }
 
+// lne = ln eps, pointwise
+__global__ __launch_bounds__(kThreads) void k_log_field(long long n, const double* __restrict__ eps,
+                                                        double* __restrict__ lne) {
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) lne[i] = log(eps[i]);
+}
+
+void launch_log_field(long long n, const double* eps, double* lne, hipStream_t s) {
+  GPS_LAUNCH(k_log_field, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+             n, eps, lne);
+}
+
 template <bool AV>
 static void launch_graddot(const Geom& g, int fd_half, const double* rho, const double* eps,
-                           const double* phi, double* out, double* part, hipStream_t s) {
+                           const double* lne, const double* phi, double* out, double* part,
+                           hipStream_t s) {
   const int ntx = (g.nx + kPTX - 1) / kPTX, nty = (g.ny + kPTY - 1) / kPTY;
   const dim3 grid(polarization_groups(g));
   const FdFirst w = fd_first_weights(fd_half);
 #define GPS_PF(MM)                                                                        \
   case MM:                                                                                \
     GPS_LAUNCH((k_polarization<MM, AV>), grid, dim3(kPThreads), 0, s, g, w, ntx, nty,     \
-               rho, eps, phi, out, part);                                                 \
+               rho, eps, lne, phi, out, part);                                            \
     break;
   switch (fd_half) {
     GPS_PF(1) GPS_PF(2) GPS_PF(3) GPS_PF(4) GPS_PF(5) GPS_PF(6) GPS_PF(7) GPS_PF(8)
@@ -282,13 +297,14 @@ static void launch_graddot(const Geom& g, int fd_half, const double* rho, const 
 }
 
 void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
-                         const double* phi, double* out, hipStream_t s) {
-  launch_graddot<false>(g, fd_half, rho, eps, phi, out, nullptr, s);
+                         const double* lne, const double* phi, double* out, hipStream_t s) {
+  launch_graddot<false>(g, fd_half, rho, eps, lne, phi, out, nullptr, s);
 }
 
 void launch_sc_operator(const Geom& g, int fd_half, const double* r, const double* eps,
-                        const double* v, double* av, double* part, hipStream_t s) {
-  launch_graddot<true>(g, fd_half, r, eps, v, av, part, s);
+                        const double* lne, const double* v, double* av, double* part,
+                        hipStream_t s) {
+  launch_graddot<true>(g, fd_half, r, eps, lne, v, av, part, s);
 }
 
 // ---------------------------------------------------------------------------
