@@ -391,8 +391,9 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported "
-              "(requests shard one plan per GPU, see DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU; --gpus %d is not supported "
+              "(one GPU per process; requests would shard one plan per GPU)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
