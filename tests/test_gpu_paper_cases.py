@@ -1,0 +1,40 @@
+"""The paper's analytic test of the Poisson-Boltzmann solver (Sec. III): a
+normalized Gaussian potential in an erf cavity, with rho derived from the
+nonlinear operator for a 0.1 M 1:1 electrolyte with steric ions (p = 0.74,
+R = 3 Angstrom); Algorithm SCPBimproved converges in a handful of outer
+steps (the paper: about five) to the analytic potential within the kernel's
+discretization error, and agrees with the oracle."""
+import numpy as np
+import pytest
+
+from oracle import pb
+from paper_1509_00680_amd import workloads as W
+from paper_1509_00680_amd import gps
+from gpu_util import dev, host, empty, plan, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_paper_mpb_gaussian_test():
+    require_gpu()
+    prob, phi_exact = W.manufactured_gaussian(64, box=10.0, sigma=0.5, d0=1.7, delta=0.3)
+    ions = W.electrolyte_1to1(0.1 * W.MOLAR_BOHR3, c_max=W.steric_cmax(0.74, 3.0), eta=1.0,
+                              outer_maxit=30)
+    oi = pb.Electrolyte(ions["Z"], ions["c_bulk"], ions["kT"], c_max=ions["c_max"],
+                        eps_bulk=W.EPS_WATER)
+    # rho of the nonlinear operator: div(eps grad phi) = -4 pi (rho + rho_ions[phi])
+    rho = prob.rho - pb.ionic_charge(phi_exact, oi, oi.accessibility(prob.eps))
+    ref = pb.scpb_improved(rho, prob.eps, prob.h, "free", oi, 1e-10, eta=1.0, outer_maxit=30)
+    assert ref.status == "ok"
+    p = plan(prob.shape, prob.h, "free", "fp64")
+    phi = empty(prob.shape)
+    print("paper mpb test", flush=True)
+    st = p.solve_pb(dev(rho), dev(prob.eps), ions, phi, 1e-10)
+    assert st == gps.GPS_OK, gps.STATUS[st]
+    info = p.info()
+    print("  outer steps %d (oracle %d)" % (info["outer_iterations"], ref.outer))
+    assert info["outer_iterations"] <= 8 and abs(info["outer_iterations"] - ref.outer) <= 1
+    got = host(phi)
+    assert np.abs(got - ref.phi).max() <= 1e-8 * np.abs(ref.phi).max()
+    # second-order kernel: 1.2e-2 of max|phi| at h = 10/64
+    assert np.abs(got - phi_exact).max() <= 3e-2 * np.abs(phi_exact).max()
