@@ -3,7 +3,8 @@ normalized Gaussian potential in an erf cavity, with rho derived from the
 nonlinear operator for a 0.1 M 1:1 electrolyte with steric ions (p = 0.74,
 R = 3 Angstrom); Algorithm SCPBimproved converges in a handful of outer
 steps (the paper: about five) to the analytic potential within the kernel's
-discretization error, and agrees with the oracle."""
+discretization error, and agrees with the oracle; in the linear regime PCG
+takes about ten iterations."""
 import numpy as np
 import pytest
 
@@ -37,4 +38,25 @@ def test_paper_mpb_gaussian_test():
     got = host(phi)
     assert np.abs(got - ref.phi).max() <= 1e-8 * np.abs(ref.phi).max()
     # second-order kernel: 1.2e-2 of max|phi| at h = 10/64
+    assert np.abs(got - phi_exact).max() <= 3e-2 * np.abs(phi_exact).max()
+
+
+def test_paper_linear_pb_gaussian_test():
+    # linear regime (Eq. corrPB): rho = (-div(eps grad phi) + kappa2 phi) / (4 pi);
+    # PCG reaches 1e-10 in about ten iterations (the paper's Fig. for linear PB)
+    require_gpu()
+    prob, phi_exact = W.manufactured_gaussian(64, box=10.0, sigma=0.5, d0=1.7, delta=0.3)
+    ions = W.electrolyte_1to1(0.1 * W.MOLAR_BOHR3, linear=True)
+    oi = pb.Electrolyte(ions["Z"], ions["c_bulk"], ions["kT"], eps_bulk=W.EPS_WATER)
+    rho = prob.rho + oi.kappa2(prob.eps) * phi_exact / (4 * np.pi)
+    ref = pb.solve_linear_pb(rho, prob.eps, prob.h, "free", oi, 1e-10)
+    p = plan(prob.shape, prob.h, "free", "fp64")
+    phi = empty(prob.shape)
+    print("paper linear pb test", flush=True)
+    assert p.solve_pb(dev(rho), dev(prob.eps), ions, phi, 1e-10) == gps.GPS_OK
+    it = p.info()["iterations"]
+    print("  iterations %d (oracle %d)" % (it, ref.iterations))
+    assert it <= 15 and abs(it - ref.iterations) <= 1
+    got = host(phi)
+    assert np.abs(got - ref.phi).max() <= 1e-8 * np.abs(ref.phi).max()
     assert np.abs(got - phi_exact).max() <= 3e-2 * np.abs(phi_exact).max()
