@@ -60,3 +60,23 @@ def test_paper_linear_pb_gaussian_test():
     got = host(phi)
     assert np.abs(got - ref.phi).max() <= 1e-8 * np.abs(ref.phi).max()
     assert np.abs(got - phi_exact).max() <= 3e-2 * np.abs(phi_exact).max()
+
+
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
+def test_paper_gaussian_test_every_bc(bc):
+    # the Gaussian GPe test under each boundary condition: PCG's iteration
+    # count barely depends on it (the paper's remark), GPU equal to the oracle
+    require_gpu()
+    from oracle import pcg
+    prob, phi_exact = W.manufactured_gaussian(48, box=10.0, sigma=0.5, d0=1.7, delta=0.3, bc=bc)
+    rho = prob.rho - (prob.rho.mean() if bc == "periodic" else 0.0)
+    ref = pcg.pcg_solve(rho, prob.eps, prob.h, bc, tol=1e-10)
+    p = plan(prob.shape, prob.h, bc, "fp64")
+    phi = empty(prob.shape)
+    print("paper gaussian", bc, flush=True)
+    assert p.solve_generalized(dev(rho), dev(prob.eps), phi, 1e-10) == gps.GPS_OK
+    it = p.info()["iterations"]
+    print("  iterations %d (oracle %d)" % (it, ref.iterations))
+    # 14 (free), 17 (surface) at 48^3
+    assert it <= 20 and abs(it - ref.iterations) <= 1
+    assert np.abs(host(phi) - ref.phi).max() <= 1e-8 * np.abs(ref.phi).max()
