@@ -128,9 +128,11 @@ def timed_solves(torch, plan, rho, eps, phi, tol, steps):
     return time.perf_counter() - t0, lat, iters
 
 
-def cpu_baseline(prob, tol, min_seconds):
+def cpu_baseline(prob, tol, min_seconds, gpu_phi=None, gpu_energy=None):
     """The oracle as it stands: whole FP64 solves of the same workload, repeated
-    until at least `min_seconds` have passed."""
+    until at least `min_seconds` have passed.  With gpu_phi (a host array of the
+    GPU's solution at the same tolerance), also the GPU result's max |dphi| and
+    relative energy error against the oracle's last solution."""
     from oracle import green, pcg
     workers = min(16, os.cpu_count() or 1)
     solver = green.VacuumSolver(prob.shape, prob.h, prob.bc, workers=workers)
@@ -143,10 +145,17 @@ def cpu_baseline(prob, tol, min_seconds):
         dt = time.perf_counter() - t0
         if dt >= min_seconds:
             break
-    return {"value": solves / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
-            "sample": "%d full FP64 solves of the same workload (%d iterations each, %.1f s, "
-                      "scipy.fft workers=%d)" % (solves, res.iterations, dt, workers),
-            "mgridpts_iter_per_s": prob.npoints * iters / dt / 1e6}
+    out = {"value": solves / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
+           "sample": "%d full FP64 solves of the same workload (%d iterations each, %.1f s, "
+                     "scipy.fft workers=%d)" % (solves, res.iterations, dt, workers),
+           "mgridpts_iter_per_s": prob.npoints * iters / dt / 1e6}
+    if gpu_phi is not None:
+        e_ref = pcg.electrostatic_energy(prob.rho, res.phi, prob.h)
+        out["gpu_result_vs_oracle"] = {
+            "max_abs_dphi": float(np.abs(gpu_phi - res.phi).max()),
+            "rel_energy_err": abs(gpu_energy / e_ref - 1.0),
+            "oracle_iterations": res.iterations}
+    return out
 
 
 def run_stream(torch, gps, srv, reqs, arrivals, phis):
@@ -428,6 +437,7 @@ def main():
     plan.set_timing(None)
 
     info = plan.info()
+    phi_gpu = phi.cpu().numpy()             # the last timed solve's potential
     mean_iters = float(np.mean(iters))
     solves_per_s = args.steps / wall
     lat_ms = np.array(lat) * 1e3
@@ -455,7 +465,9 @@ def main():
         w64, l64, it64 = timed_solves(torch, p64, rho, eps, phi, args.tol, args.fp64_steps)
         fp64 = {"solves_per_s": args.fp64_steps / w64,
                 "p99_ms": float(np.percentile(np.array(l64) * 1e3, 99)),
-                "iters_per_solve": float(np.mean(it64))}
+                "iters_per_solve": float(np.mean(it64)),
+                "max_abs_dphi_vs_this": float(np.abs(phi.cpu().numpy() - phi_gpu).max()),
+                "rel_energy_diff_vs_this": abs(info["energy"] / p64.info()["energy"] - 1.0)}
         p64.close()
 
     out = {
@@ -492,7 +504,8 @@ def main():
     if pass_ms:
         out["passes"] = pass_ms
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.tol, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(prob, args.tol, args.cpu_seconds,
+                                           gpu_phi=phi_gpu, gpu_energy=info["energy"])
     print(json.dumps(out))
 
 
