@@ -210,8 +210,8 @@ gps_status gps_solve_vacuum(gps_plan *plan, const double *f, double *u);
  * plan's finite-difference one: for instance the analytic q of
  * gps_rigid_cavity (Sec. IV.A: every field that depends on eps follows
  * analytically from the cavity).  q: device double[nz][ny][nx], read only,
- * rounded to the bulk precision like the computed q.  Free and surface
- * boundaries only: with periodic boundaries the operator annihilates constants
+ * rounded to the bulk precision like the computed q.  Free, surface and wire
+ * boundaries: with periodic boundaries the operator annihilates constants
  * only for the q of the plan's spectral Laplacian.  Errors: as
  * gps_solve_generalized, plus GPS_E_INVALID for a null q or a periodic plan. */
 gps_status gps_solve_generalized_q(gps_plan *plan, const double *rho, const double *eps,

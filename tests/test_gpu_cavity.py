@@ -25,7 +25,7 @@ def _gpu_cavity(p, atoms, delta, eps0, with_q=True):
     return host(e), (host(q) if with_q else None)
 
 
-@pytest.mark.parametrize("bc", ["free", "surface", "periodic"])
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
 def test_rigid_cavity_matches_oracle(bc):
     require_gpu()
     shape, h = (30, 35, 27), 0.3                 # ragged: partial work-groups
@@ -63,7 +63,7 @@ def test_rigid_cavity_full_size_sampled():
     assert e.min() >= 1.0 and e.max() <= 78.36
 
 
-@pytest.mark.parametrize("bc", ["free", "surface"])
+@pytest.mark.parametrize("bc", ["free", "surface", "wire"])
 def test_solve_with_analytic_q_fp64(bc):
     require_gpu()
     w = W.rigid_solute(n=24, h=0.45, seed=8, n_atoms=5, ball=2.0, radii=(2.0, 2.6), bc=bc)
@@ -136,7 +136,8 @@ def test_rigid_cavity_rejects_bad_arguments():
 
 
 @pytest.mark.parametrize("bc,order,shape", [("free", 16, (12, 18, 40)), ("surface", 16, (20, 27, 35)),
-                                            ("periodic", 6, (9, 40, 35)), ("free", 2, (6, 5, 7))])
+                                            ("periodic", 6, (9, 40, 35)), ("free", 2, (6, 5, 7)),
+                                            ("wire", 12, (18, 20, 24))])
 def test_polarization_charge_matches_oracle(bc, order, shape):
     require_gpu()
     rng = np.random.default_rng(17)

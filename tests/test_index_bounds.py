@@ -401,7 +401,8 @@ def polarization_replay(rho, eps, phi, h, M, per, w):
 
 
 @pytest.mark.parametrize("shape,bc,order", [((13, 17, 20), "free", 16), ((13, 17, 40), "surface", 16),
-                                            ((9, 40, 35), "periodic", 6), ((6, 5, 7), "free", 2)])
+                                            ((9, 40, 35), "periodic", 6), ((6, 5, 7), "free", 2),
+                                            ((18, 20, 24), "wire", 12)])
 def test_polarization_replay_matches_oracle(shape, bc, order):
     from oracle import cavity
     rng = np.random.default_rng(5)
@@ -410,7 +411,7 @@ def test_polarization_replay_matches_oracle(shape, bc, order):
     rho = rng.normal(size=shape)
     h = 0.3
     per = {"free": (False, False, False), "surface": (True, True, False),
-           "periodic": (True, True, True)}[bc]
+           "periodic": (True, True, True), "wire": (False, False, True)}[bc]
     M = order // 2
     got = polarization_replay(rho, eps, phi, h, M, per, cavity.fd_first_derivative_weights(M))
     ref = cavity.polarization_charge(rho, eps, phi, h, bc, order)
