@@ -1,21 +1,28 @@
 #!/usr/bin/env python3
-"""Throughput of the generalized-Poisson PCG solver on one MI355X.
+"""Throughput of the generalized Poisson / Poisson-Boltzmann solver on one MI355X.
 
-Workload (default): molecule-like solute in a density-dependent (sccs)
-cavity, free boundaries, 96^3 grid, h = 0.3 bohr, 24 Gaussian charges
-(sigma in U[0.6, 1.2], q in U[-1, 1] shifted to net 0, centres in a 6-bohr
-ball, seed 2), mixed precision (FP32 FFT passes and vectors, FP64 inner
-products and solution), stop at ||r||/||r_0|| <= 1e-6.
+Workload (default, `--workload charged_solute`): nonlinear Poisson-Boltzmann
+for a charged solute, free boundaries, 160^3 grid, h = 0.3 bohr (FFT lengths
+320), 48 Gaussian charges (sigma in U[0.6, 1.2], q in U[-1, 1] shifted to a
+net +4, centres in a 6-bohr ball, seed 4) in a density-dependent (sccs)
+cavity, 1 M 1:1 electrolyte with steric ions (p = 0.74, R = 3 A) excluded
+where eps < eps0, Algorithm SCPBimproved with mixing 0.15, outer tolerance
+1e-6, inner PCG iterations to the absolute residual the algorithm sets;
+mixed precision (FP32 FFT passes and vectors, FP64 inner products and
+solution).
 
 One step = one complete solve on inputs already resident in HBM: the
-per-request fields (sqrt(eps), q), the PCG iterations to the stop decision
-and the energy.  The plan (Green's spectrum, buffers) is built once before
-the timed region.
+per-request fields (sqrt(eps), q), every outer step with its inner PCG
+iterations and ionic update, and the energy.  The plan (Green's spectrum,
+buffers, captured graphs) is built before the timed region.
 
-Prints ONE JSON line: solves/s as `value`, plus Mgridpts*iter/s, p50/p99
-latency, the FP64 one-at-a-time comparator, the roofline of the dominant
-pass (timed live with HIP events on the solve stream) and the oracle timed
-on the host cores.
+Prints ONE JSON line: solves/s as `value`, Mgridpts*iter/s over all inner
+iterations, p50/p99 latency, the FP64 one-at-a-time comparator, the roofline
+of the dominant pass (timed live with HIP events on the solve stream), the
+oracle's accuracy check at 1e-10 and its timing on the host cores, plus the
+molecule 96^3 line and the serving stream's latencies as extra keys.
+Other workloads: molecule (96^3 generalized Poisson), slab (128x128x192
+surface, linear PB), serving, rigid, sc.
 """
 import argparse
 import json
@@ -36,28 +43,33 @@ PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed solves (default: 10 for charged_solute, 20 otherwise)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=96)
+    ap.add_argument("--workload", default="charged_solute",
+                    choices=("charged_solute", "molecule", "slab", "serving", "rigid", "sc"),
+                    help="charged_solute: nonlinear PB at 160^3 (default); molecule: "
+                         "generalized Poisson at 96^3; slab: linear PB, surface BC, "
+                         "128x128x192; serving: a request stream through the serving loop")
+    ap.add_argument("--n", type=int, default=None, help="grid points per axis (cubic workloads)")
     ap.add_argument("--h", type=float, default=0.3)
-    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--bc", default="free", choices=("free", "surface", "periodic", "wire"),
                     help="molecule workload: boundary conditions")
     ap.add_argument("--check-every", type=int, default=8,
                     help="PCG iterations per replayed graph")
-    ap.add_argument("--fp64-steps", type=int, default=5,
-                    help="solves of the FP64 one-at-a-time comparator (0: skip)")
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="solves of the FP64 one-at-a-time comparator (0: skip; default 2 "
+                         "for charged_solute, 5 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-times", action="store_true",
                     help="skip the per-pass kernel times (extra eager solves)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="charged_solute: skip the molecule and serving extra keys")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="minimum wall time of the oracle sample (whole solves)")
-    ap.add_argument("--workload", default="molecule",
-                    choices=("molecule", "serving", "rigid", "sc"),
-                    help="molecule: one 96^3 solve per step (default); serving: a request "
-                         "stream through the serving loop")
+                    help="minimum wall time of the oracle sample (molecule, slab)")
     ap.add_argument("--problem", default="molecule", choices=("molecule", "manufactured"),
                     help="sc workload: the molecule, or the Gaussian test of Sec. II.C "
                          "(box 10, sigma 0.5, d0 1.7, Delta 0.3) with its analytic potential")
@@ -71,7 +83,23 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (10 times) and exit: the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 10 if args.workload == "charged_solute" else 20
+    if args.fp64_steps is None:
+        args.fp64_steps = 2 if args.workload == "charged_solute" else 5
+    return args
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def copy_calibration(mib):
@@ -112,49 +140,90 @@ def measured_traffic(name):
     return rec["traffic_bytes_per_launch"]
 
 
-def timed_solves(torch, plan, rho, eps, phi, tol, steps):
+def timed_solves(torch, plan, solve, steps):
+    """Runs `solve` (one complete solve on `plan`) `steps` times; returns the
+    wall time, per-solve latencies and the plan's info after each solve."""
     lat = []
-    iters = []
+    infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         s0 = time.perf_counter()
-        st = plan.solve_generalized(rho, eps, phi, tol)
+        st = solve(plan)
         lat.append(time.perf_counter() - s0)
         if st != 0:
             raise RuntimeError("solve failed with status %d" % st)
-        iters.append(plan.info()["iterations"])
+        infos.append(plan.info())
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, lat, iters
+    return time.perf_counter() - t0, lat, infos
 
 
-def cpu_baseline(prob, tol, min_seconds, gpu_phi=None, gpu_energy=None):
-    """The oracle as it stands: whole FP64 solves of the same workload, repeated
-    until at least `min_seconds` have passed.  With gpu_phi (a host array of the
-    GPU's solution at the same tolerance), also the GPU result's max |dphi| and
-    relative energy error against the oracle's last solution."""
-    from oracle import green, pcg
-    workers = min(16, os.cpu_count() or 1)
+def oracle_accuracy(prob, gpu_phi, gpu_energy, workers, nonlinear_ions=None):
+    """The GPU result against the oracle solved to 1e-10 (FP64, scipy.fft with
+    `workers` threads).  Linear problems: the oracle's own solve of the same
+    problem.  Nonlinear PB (nonlinear_ions, an oracle Electrolyte): a
+    fixed-point check -- the oracle's generalized Poisson solve with the fixed
+    source rho + rho^ions[phi_gpu]; at the self-consistent solution it returns
+    phi_gpu itself.  Returns the figures and the oracle's timing."""
+    from oracle import green, pb, pcg
+    solver = green.VacuumSolver(prob.shape, prob.h, prob.bc, workers=workers)
+    rho = prob.rho
+    t0 = time.perf_counter()
+    if nonlinear_ions is not None:
+        rho = prob.rho + pb.ionic_charge(gpu_phi, nonlinear_ions,
+                                         nonlinear_ions.accessibility(prob.eps))
+        res = pcg.pcg_solve(rho, prob.eps, prob.h, prob.bc, tol=1e-10, solver=solver,
+                            maxit=2000)
+    elif prob.kind == "pb_linear":
+        ions = _oracle_electrolyte(prob.ions)
+        res = pb.solve_linear_pb(prob.rho, prob.eps, prob.h, prob.bc, ions, 1e-10,
+                                 solver=solver)
+    else:
+        res = pcg.pcg_solve(rho, prob.eps, prob.h, prob.bc, tol=1e-10, solver=solver)
+    dt = time.perf_counter() - t0
+    e_ref = pcg.electrostatic_energy(prob.rho, res.phi, prob.h)
+    return {"max_abs_dphi": float(np.abs(gpu_phi - res.phi).max()),
+            "rel_energy_err": abs(gpu_energy / e_ref - 1.0),
+            "oracle_tol": 1e-10, "oracle_iterations": res.iterations,
+            "oracle_converged": bool(res.converged),
+            "check": "fixed point: oracle PCG with the source rho + rho_ions[phi_gpu]"
+            if nonlinear_ions is not None else "oracle solve of the same problem"}, \
+        dt, res.iterations
+
+
+def _oracle_electrolyte(d):
+    from oracle import pb
+    return pb.Electrolyte(d["Z"], d["c_bulk"], d["kT"], c_max=d.get("c_max"),
+                          eps_bulk=d.get("eps_bulk", 78.36))
+
+
+def cpu_baseline(prob, tol, min_seconds, workers, gpu_phi=None, gpu_energy=None):
+    """The oracle as it stands: whole FP64 solves of the same workload at the
+    bench tolerance, repeated until at least `min_seconds` have passed; then,
+    with gpu_phi, the GPU result against the oracle solved to 1e-10."""
+    from oracle import green, pb, pcg
     solver = green.VacuumSolver(prob.shape, prob.h, prob.bc, workers=workers)
     solves, iters = 0, 0
     t0 = time.perf_counter()
     while True:
-        res = pcg.pcg_solve(prob.rho, prob.eps, prob.h, prob.bc, tol=tol, solver=solver)
+        if prob.kind == "pb_linear":
+            res = pb.solve_linear_pb(prob.rho, prob.eps, prob.h, prob.bc,
+                                     _oracle_electrolyte(prob.ions), tol, solver=solver)
+        else:
+            res = pcg.pcg_solve(prob.rho, prob.eps, prob.h, prob.bc, tol=tol, solver=solver)
         solves += 1
         iters += res.iterations
         dt = time.perf_counter() - t0
         if dt >= min_seconds:
             break
     out = {"value": solves / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
-           "sample": "%d full FP64 solves of the same workload (%d iterations each, %.1f s, "
-                     "scipy.fft workers=%d)" % (solves, res.iterations, dt, workers),
+           "cpu_model": cpu_model(),
+           "sample": "%d full FP64 solves of the same workload at tol %g (%d iterations "
+                     "each, %.1f s, scipy.fft workers=%d)" % (solves, tol, res.iterations, dt,
+                                                            workers),
            "mgridpts_iter_per_s": prob.npoints * iters / dt / 1e6}
     if gpu_phi is not None:
-        e_ref = pcg.electrostatic_energy(prob.rho, res.phi, prob.h)
-        out["gpu_result_vs_oracle"] = {
-            "max_abs_dphi": float(np.abs(gpu_phi - res.phi).max()),
-            "rel_energy_err": abs(gpu_energy / e_ref - 1.0),
-            "oracle_iterations": res.iterations}
+        out["gpu_result_vs_oracle"] = oracle_accuracy(prob, gpu_phi, gpu_energy, workers)[0]
     return out
 
 
@@ -227,10 +296,13 @@ def serving_bench(args, torch, gps, W):
                 "mgridpts_iter_per_s": sum(n * r["iterations"] for n, r in zip(npts, results))
                 / wall / 1e6, "iterations": iters, "failed": len(bad), "stats": srv.stats()}
 
-    warm = min(64, len(reqs))
+    # capacity: the whole stream closed-loop (every request submitted at once),
+    # after one closed-loop pass that creates the plans and graphs; the open-loop
+    # arrival rate is a fraction of it, so the server is not overloaded
+    nreq = len(reqs)
     srv = gps.Server(budget_bytes=budget, max_active=args.max_active, precision="mixed")
-    closed_loop(srv, warm, phis)                       # plans, graphs
-    capacity = closed_loop(srv, warm, phis)
+    closed_loop(srv, nreq, phis)
+    capacity = closed_loop(srv, nreq, phis)
     rate = args.load * capacity
     arrivals = np.cumsum(gaps / rate)
     res_mixed = run_stream(torch, gps, srv, reqs, arrivals, phis)
@@ -238,8 +310,8 @@ def serving_bench(args, torch, gps, W):
     srv.close()
 
     srv64 = gps.Server(budget_bytes=0, max_active=1, precision="fp64")
-    closed_loop(srv64, warm, phis64)
-    cap64 = closed_loop(srv64, warm, phis64)
+    closed_loop(srv64, nreq, phis64)
+    cap64 = closed_loop(srv64, nreq, phis64)
     res64 = run_stream(torch, gps, srv64, reqs, arrivals, phis64)
     fp64 = summarize(res64, srv64)
     srv64.close()
@@ -258,7 +330,7 @@ def serving_bench(args, torch, gps, W):
     return {
         "metric": "serving solves/s at 1e-6 rel. residual; p50/p99 latency (arrival to result)",
         "value": mixed["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
-        "steps": len(reqs), "warmup": 2 * warm, "ms_per_step": 1e3 / mixed["solves_per_s"],
+        "steps": len(reqs), "warmup": 2 * nreq, "ms_per_step": 1e3 / mixed["solves_per_s"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "serving_stream_%d" % len(reqs), "grids": list(W.SERVING_GRIDS),
@@ -268,12 +340,14 @@ def serving_bench(args, torch, gps, W):
                    "arrival_rate_per_s": rate, "closed_loop_capacity_per_s": capacity,
                    "precision": "mixed (fp32 bulk, fp64 dots/solution)"},
         "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"],
+        "utilization": {"offered_load": rate / capacity,
+                        "served_over_arrival_rate": mixed["solves_per_s"] / rate},
         "mgridpts_iter_per_s": mixed["mgridpts_iter_per_s"],
         "failed": mixed["failed"], "server": mixed["stats"],
         "fp64_one_at_a_time": dict({k: fp64[k] for k in ("solves_per_s", "p50_ms", "p99_ms",
                                                           "closed_loop_solves_per_s", "failed")},
                                    budget_bytes="unlimited", max_active=1,
-                                   arrival_rate_per_s=rate),
+                                   arrival_rate_per_s=rate, offered_load=rate / cap64),
         "max_abs_dphi_vs_fp64": dphi,
         "max_rel_energy_diff_vs_fp64": max(abs(a["energy"] / b["energy"] - 1.0)
                                            for a, b in zip(res_mixed, res64) if b["energy"]),
@@ -367,7 +441,8 @@ def sc_bench(args, torch, gps, W):
     out = {}
     for meth, run in (("pcg", lambda: plan.solve_generalized(rho, eps, phi, args.tol)),
                       ("sc", lambda: plan.solve_sc(rho, eps, phi, args.tol, "sc", 0.6)),
-                      ("psd", lambda: plan.solve_sc(rho, eps, phi, args.tol, "psd"))):
+                      ("psd_weighted",
+                       lambda: plan.solve_sc(rho, eps, phi, args.tol, "psd_weighted"))):
         run()
         torch.cuda.synchronize()
         reps = max(1, args.steps // (1 if meth == "pcg" else 4))
@@ -383,6 +458,13 @@ def sc_bench(args, torch, gps, W):
                      "us_per_iteration": dt * 1e6 / max(1, it), "energy": plan.info()["energy"]}
         if exact is not None:
             out[meth]["max_error_vs_analytic"] = float(np.abs(phi.cpu().numpy() - exact).max())
+    # PSD with Algorithm PCG's own step (beta = 0): reported with its status,
+    # since it does not contract on this discretization
+    p200 = gps.Plan(prob.shape, prob.h, prob.bc, precision=args.precision, maxit=200)
+    st = p200.solve_sc(rho, eps, phi, args.tol, "psd")
+    out["psd"] = {"status": gps.STATUS[st], "iterations": p200.info()["iterations"],
+                  "rel_residual": p200.info()["rel_residual"]}
+    p200.close()
     return {
         "metric": "SC and PSD against PCG: solves/s at the same tolerance",
         "value": out["sc"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
@@ -392,6 +474,123 @@ def sc_bench(args, torch, gps, W):
         "config": {"workload": name, "tol": args.tol, "precision": args.precision, "eta": 0.6},
         "methods": out,
     }
+
+
+def solve_fn(prob):
+    """A closure running one complete solve of `prob` on a plan (generalized
+    Poisson, or Poisson-Boltzmann when the problem has an electrolyte)."""
+    def solve(plan, rho, eps, phi, tol):
+        if prob.ions is None:
+            return plan.solve_generalized(rho, eps, phi, tol)
+        return plan.solve_pb(rho, eps, prob.ions, phi, tol)
+    return solve
+
+
+def pcg_line(args, torch, gps, W, prob, name, steps, warmup, cpu=True, pass_times=True):
+    """The bench line of one PCG / PB workload: solves/s, Mgridpts*iter/s over
+    all PCG iterations, latency, roofline of the z pass, per-pass times, the
+    FP64 one-at-a-time comparator, the oracle's accuracy check and timing."""
+    rho = torch.from_numpy(prob.rho).cuda()
+    eps = torch.from_numpy(prob.eps).cuda()
+    phi = torch.empty_like(rho)
+    run = solve_fn(prob)
+    nonlinear = prob.kind == "pb_nonlinear"
+    plan = gps.Plan(prob.shape, prob.h, prob.bc, precision=args.precision,
+                    check_every=args.check_every)
+
+    def solve(pl):
+        return run(pl, rho, eps, phi, args.tol)
+
+    for _ in range(warmup):
+        solve(plan)
+    # timed region (iterations replayed as HIP graphs)
+    wall, lat, infos = timed_solves(torch, plan, solve, steps)
+    iters = [i["iterations"] for i in infos]
+    info = infos[-1]
+    phi_gpu = phi.cpu().numpy()             # the last timed solve's potential
+    # dominant pass: every launch bracketed by HIP events on the solve stream
+    # (kernels launched one by one while timed)
+    plan.set_timing("zconv")
+    timed_solves(torch, plan, solve, 1 if nonlinear else max(3, steps // 4))
+    tz = plan.timing()
+    plan.set_timing(None)
+    avg_ms = tz["total_ms"] / max(1, tz["launches"])
+    achieved = tz["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+
+    pass_ms = {}
+    if pass_times:
+        for k in PASSES:
+            plan.set_timing(k)
+            timed_solves(torch, plan, solve, 1 if nonlinear else 2)
+            t = plan.timing()
+            us = 1e3 * t["total_ms"] / max(1, t["launches"])
+            pass_ms[k] = {"avg_us": us, "bytes_per_launch": t["bytes_per_launch"],
+                          "gbs": t["bytes_per_launch"] / (us * 1e-6) / 1e9 if us > 0 else 0.0}
+        plan.set_timing(None)
+    plan.close()
+
+    fp64 = None
+    if args.fp64_steps > 0 and args.precision != "fp64":
+        p64 = gps.Plan(prob.shape, prob.h, prob.bc, precision="fp64",
+                       check_every=args.check_every)
+        solve(p64)
+        w64, l64, i64 = timed_solves(torch, p64, solve, args.fp64_steps)
+        fp64 = {"solves_per_s": args.fp64_steps / w64,
+                "p99_ms": float(np.percentile(np.array(l64) * 1e3, 99)),
+                "iters_per_solve": float(np.mean([i["iterations"] for i in i64])),
+                "max_abs_dphi_vs_this": float(np.abs(phi.cpu().numpy() - phi_gpu).max()),
+                "rel_energy_diff_vs_this": abs(info["energy"] / i64[-1]["energy"] - 1.0)}
+        if nonlinear:
+            fp64["outer_per_solve"] = float(np.mean([i["outer_iterations"] for i in i64]))
+        p64.close()
+
+    lat_ms = np.array(lat) * 1e3
+    traffic_file = "traffic_zpass_%s_%s.json" % (name, args.precision)
+    out = {
+        "value": steps / wall,
+        "unit": "solves/s",
+        "ms_per_step": wall / steps * 1e3,
+        "mgridpts_iter_per_s": prob.npoints * sum(iters) / wall / 1e6,
+        "iters_per_solve": float(np.mean(iters)),
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "energy": info["energy"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(traffic_file),
+                     "kernel": "z pass (forward FFT, Green's spectrum, inverse FFT)",
+                     "avg_us": avg_ms * 1e3, "bytes_per_launch": tz["bytes_per_launch"],
+                     "launches": tz["launches"]},
+        "fp64_one_at_a_time": fp64,
+    }
+    if nonlinear:
+        out["outer_per_solve"] = float(np.mean([i["outer_iterations"] for i in infos]))
+        out["outer_residual"] = info["outer_residual"]
+    if pass_ms:
+        out["passes"] = pass_ms
+    if cpu and not args.no_cpu_baseline:
+        workers = min(16, os.cpu_count() or 1)
+        if nonlinear:
+            # the oracle's sample is the accuracy check itself: one FP64 PCG solve
+            # at 160^3 to 1e-10, timed per iteration and scaled to whole nonlinear
+            # solves with the FP64 path's inner iteration count
+            acc, dt, it = oracle_accuracy(prob, phi_gpu, info["energy"], workers,
+                                          nonlinear_ions=_oracle_electrolyte(prob.ions))
+            per_solve = fp64["iters_per_solve"] if fp64 else float(np.mean(iters))
+            rate = it / dt
+            out["cpu_baseline"] = {
+                "value": rate / per_solve, "unit": "solves/s", "cores": workers,
+                "kind": "oracle", "cpu_model": cpu_model(),
+                "sample": "one FP64 oracle PCG solve of the %s generalized Poisson problem "
+                          "with the source rho + rho_ions[phi_gpu], to 1e-10 (%d iterations, "
+                          "%.1f s, scipy.fft workers=%d); solves/s = iterations/s over the "
+                          "%.0f inner iterations of one FP64 nonlinear solve"
+                          % ("x".join(map(str, prob.shape)), it, dt, workers, per_solve),
+                "mgridpts_iter_per_s": prob.npoints * rate / 1e6,
+                "gpu_result_vs_oracle": acc}
+        else:
+            out["cpu_baseline"] = cpu_baseline(prob, args.tol, args.cpu_seconds, workers,
+                                               gpu_phi=phi_gpu, gpu_energy=info["energy"])
+    return out
 
 
 def main():
@@ -412,100 +611,68 @@ def main():
         print(json.dumps(serving_bench(args, torch, gps, W)))
         return
     if args.workload == "rigid":
+        args.n = args.n or 96
+        args.seed = 2 if args.seed is None else args.seed
         print(json.dumps(rigid_bench(args, torch, gps, W)))
         return
     if args.workload == "sc":
+        args.n = args.n or 96
+        args.seed = 2 if args.seed is None else args.seed
         print(json.dumps(sc_bench(args, torch, gps, W)))
         return
 
-    prob = W.molecule(args.n, args.h, seed=args.seed, bc=args.bc)
-    rho = torch.from_numpy(prob.rho).cuda()
-    eps = torch.from_numpy(prob.eps).cuda()
-    phi = torch.empty_like(rho)
-    plan = gps.Plan(prob.shape, prob.h, prob.bc, precision=args.precision,
-                    check_every=args.check_every)
-
-    for _ in range(args.warmup):
-        plan.solve_generalized(rho, eps, phi, args.tol)
-    # timed region (iterations replayed as HIP graphs)
-    wall, lat, iters = timed_solves(torch, plan, rho, eps, phi, args.tol, args.steps)
-    # dominant pass: every launch bracketed by HIP events on the solve stream
-    # (kernels launched one by one while timed)
-    plan.set_timing("zconv")
-    timed_solves(torch, plan, rho, eps, phi, args.tol, max(3, args.steps // 4))
-    tz = plan.timing()
-    plan.set_timing(None)
-
-    info = plan.info()
-    phi_gpu = phi.cpu().numpy()             # the last timed solve's potential
-    mean_iters = float(np.mean(iters))
-    solves_per_s = args.steps / wall
-    lat_ms = np.array(lat) * 1e3
-
-    avg_ms = tz["total_ms"] / max(1, tz["launches"])
-    achieved = tz["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-
-    pass_ms = {}
-    if not args.no_pass_times:
-        for k in PASSES:
-            plan.set_timing(k)
-            timed_solves(torch, plan, rho, eps, phi, args.tol, 2)
-            t = plan.timing()
-            pass_ms[k] = {"avg_us": 1e3 * t["total_ms"] / max(1, t["launches"]),
-                          "gbs": t["bytes_per_launch"] / (t["total_ms"] / max(1, t["launches"])
-                                                          * 1e-3) / 1e9
-                          if t["total_ms"] > 0 else 0.0}
-        plan.set_timing(None)
-
-    fp64 = None
-    if args.fp64_steps > 0:
-        p64 = gps.Plan(prob.shape, prob.h, prob.bc, precision="fp64",
-                       check_every=args.check_every)
-        p64.solve_generalized(rho, eps, phi, args.tol)
-        w64, l64, it64 = timed_solves(torch, p64, rho, eps, phi, args.tol, args.fp64_steps)
-        fp64 = {"solves_per_s": args.fp64_steps / w64,
-                "p99_ms": float(np.percentile(np.array(l64) * 1e3, 99)),
-                "iters_per_solve": float(np.mean(it64)),
-                "max_abs_dphi_vs_this": float(np.abs(phi.cpu().numpy() - phi_gpu).max()),
-                "rel_energy_diff_vs_this": abs(info["energy"] / p64.info()["energy"] - 1.0)}
-        p64.close()
-
-    out = {
-        "metric": "PCG solves/s and Mgridpts·iter/s at 1e-6 rel. residual; p50/p99 latency",
-        "value": solves_per_s,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if args.precision == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {"workload": "molecule%d_sccs_%s" % (args.n, args.bc), "grid": list(prob.shape),
-                   "h": prob.h, "bc": prob.bc, "n_charges": 24, "seed": args.seed,
-                   "tol": args.tol, "precision": args.precision
-                   + (" (fp32 bulk, fp64 dots/solution)" if args.precision == "mixed" else "")},
-        "mgridpts_iter_per_s": prob.npoints * sum(iters) / wall / 1e6,
-        "iters_per_solve": mean_iters,
-        "p50_ms": float(np.percentile(lat_ms, 50)),
-        "p99_ms": float(np.percentile(lat_ms, 99)),
-        "energy": info["energy"],
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("traffic_zpass_molecule96_free_mixed.json")
-                     if (args.n, args.precision, args.bc) == (96, "mixed", "free") else None,
-                     "kernel": "z pass (forward FFT, Green's spectrum, inverse FFT)",
-                     "avg_us": avg_ms * 1e3, "bytes_per_launch": tz["bytes_per_launch"],
-                     "launches": tz["launches"]},
-        "fp64_one_at_a_time": fp64,
-    }
-    if pass_ms:
-        out["passes"] = pass_ms
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.tol, args.cpu_seconds,
-                                           gpu_phi=phi_gpu, gpu_energy=info["energy"])
+    if args.workload == "charged_solute":
+        n = args.n or 160
+        seed = 4 if args.seed is None else args.seed
+        prob = W.charged_solute_mpb(n=n, h=args.h, seed=seed, tol=args.tol)
+        name = "charged_solute%d_mpb_free" % n
+        config = {"workload": name, "grid": list(prob.shape), "h": prob.h, "bc": "free",
+                  "n_charges": 48, "net_charge": 4.0, "seed": seed,
+                  "electrolyte": "1:1, 1 M, steric (p 0.74, R 3 A), gamma = (eps-1)/(eps0-1)",
+                  "algorithm": "SCPBimproved, eta %g" % prob.ions["eta"],
+                  "tol": args.tol}
+        metric = ("PCG solves/s and Mgridpts\u00b7iter/s at 1e-6 rel. residual; p50/p99 "
+                  "latency")
+    elif args.workload == "slab":
+        prob = W.slab(tol=args.tol)
+        name = "slab128x128x192_surface"
+        config = {"workload": name, "grid": list(prob.shape), "h": prob.h, "bc": "surface",
+                  "n_charges": 64, "seed": 3, "electrolyte": "linear PB, Debye length 10 bohr",
+                  "tol": args.tol}
+        metric = "PCG solves/s and Mgridpts\u00b7iter/s at 1e-6 rel. residual; p50/p99 latency"
+    else:
+        n = args.n or 96
+        seed = 2 if args.seed is None else args.seed
+        prob = W.molecule(n, args.h, seed=seed, bc=args.bc, tol=args.tol)
+        name = "molecule%d_sccs_%s" % (n, args.bc)
+        config = {"workload": name, "grid": list(prob.shape), "h": prob.h, "bc": prob.bc,
+                  "n_charges": 24, "seed": seed, "tol": args.tol}
+        metric = "PCG solves/s and Mgridpts\u00b7iter/s at 1e-6 rel. residual; p50/p99 latency"
+    config["precision"] = args.precision + (" (fp32 bulk, fp64 dots/solution)"
+                                            if args.precision == "mixed" else "")
+    line = pcg_line(args, torch, gps, W, prob, name, args.steps, args.warmup,
+                    pass_times=not args.no_pass_times)
+    out = {"metric": json.loads('"%s"' % metric), "value": line.pop("value"),
+           "unit": line.pop("unit"), "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": line.pop("ms_per_step"), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
+           "config": config}
+    out.update(line)
+    if args.workload == "charged_solute" and not args.no_extras:
+        # the molecule 96^3 line and the serving stream, as extra keys
+        mol = W.molecule(96, 0.3, seed=2, tol=args.tol)
+        m = pcg_line(args, torch, gps, W, mol, "molecule96_sccs_free", 20, 3, cpu=False,
+                     pass_times=False)
+        out["molecule96_sccs_free"] = {k: m[k] for k in (
+            "value", "unit", "mgridpts_iter_per_s", "iters_per_solve", "p50_ms", "p99_ms",
+            "fp64_one_at_a_time")}
+        out["molecule96_sccs_free"]["roofline_frac"] = m["roofline"]["frac"]
+        sv = serving_bench(args, torch, gps, W)
+        out["serving_stream512"] = {k: sv[k] for k in (
+            "value", "unit", "p50_ms", "p99_ms", "utilization", "fp64_one_at_a_time",
+            "max_abs_dphi_vs_fp64")}
+        out["serving_stream512"]["arrival_rate_per_s"] = sv["config"]["arrival_rate_per_s"]
     print(json.dumps(out))
 
 

@@ -222,16 +222,25 @@ gps_status gps_solve_generalized_q(gps_plan *plan, const double *rho, const doub
  * compared), on the same discrete operator
  *   A phi = eps L_G phi + eps (grad_h ln eps) . grad_h phi,  L_G = -4 pi G^-1,
  * with central differences of the plan's fd_order for the gradients (ghosts
- * as for q).  PSD: Algorithm PCG with beta = 0 and the preconditioner of
- * Eq. PrePSD (eps lap v = -4 pi r, v = G(r/eps)); A v = -4 pi r + eps grad ln
- * eps . grad v; the step alpha = (A v, r/eps^2)/(A v, A v/eps^2), which
- * minimizes ||r/eps||_2 (A and P are not symmetric in this form, and the
- * step (v, r)/(v, A v) stalls); stops at ||r/eps||_2 <= tol ||4 pi rho/eps||_2;
- * GPS_E_BREAKDOWN if A v = 0.  SC (Eqs. remap, rhoiter, linear mixing
- * eta in (0, 1]): the same recurrence with the fixed steps -1/(4 pi) (first,
- * the unmixed phi_0 = G(rho/eps)) and -eta/(4 pi), which reproduces
- * Algorithm SC's iterates; stops when ||rho_iter_{k+1} - rho_iter_k||_2 <=
- * tol ||rho||_2 (gps_info.iterations counts SC iterations after phi_0).
+ * as for q).  PSD is Algorithm PCG with beta = 0 and the preconditioner of
+ * Eq. PrePSD (eps lap v = -4 pi r, v = G(r/eps)), with A v = -4 pi r +
+ * eps grad ln eps . grad v.  Its step, per method:
+ *   GPS_METHOD_PSD           Algorithm PCG's alpha = (v, r)/(v, A v); stops at
+ *                            ||r||_2 <= tol ||4 pi rho||_2; GPS_E_BREAKDOWN if
+ *                            (v, A v) = 0.  A and P are not symmetric in this
+ *                            form and this step does not contract on the
+ *                            paper's Gaussian test or on molecules (the
+ *                            relative residual stays near 1): such solves end
+ *                            with GPS_E_NOT_CONVERGED at maxit.
+ *   GPS_METHOD_PSD_WEIGHTED  alpha = (A v, r/eps^2)/(A v, A v/eps^2), the step
+ *                            that minimizes ||r/eps||_2 along A v; stops at
+ *                            ||r/eps||_2 <= tol ||4 pi rho/eps||_2;
+ *                            GPS_E_BREAKDOWN if A v = 0.
+ * SC (Eqs. remap, rhoiter, linear mixing eta in (0, 1]): the same recurrence
+ * with the fixed steps -1/(4 pi) (first, the unmixed phi_0 = G(rho/eps)) and
+ * -eta/(4 pi), which reproduces Algorithm SC's iterates; stops when
+ * ||rho_iter_{k+1} - rho_iter_k||_2 <= tol ||rho||_2 (gps_info.iterations counts
+ * SC iterations after phi_0).  eta is ignored by the PSD methods.
  * At most maxit iterations.  The vacuum solves run in the plan's bulk
  * precision, everything else in FP64; the host takes alpha and the stop
  * decision after each step.  rho, eps: device, read; phi: device, written.
@@ -239,7 +248,8 @@ gps_status gps_solve_generalized_q(gps_plan *plan, const double *rho, const doub
  * tol <= 0, unknown method, eta outside (0, 1] for SC, a periodic plan),
  * GPS_E_NOT_CONVERGED, GPS_E_BREAKDOWN, GPS_E_NONFINITE, GPS_E_NOMEM,
  * GPS_E_DEVICE. */
-typedef enum { GPS_METHOD_SC = 0, GPS_METHOD_PSD = 1 } gps_sc_method;
+typedef enum { GPS_METHOD_SC = 0, GPS_METHOD_PSD = 1,
+               GPS_METHOD_PSD_WEIGHTED = 2 } gps_sc_method;
 gps_status gps_solve_sc(gps_plan *plan, const double *rho, const double *eps, double *phi,
                         double tol, int method, double eta);
 

@@ -906,12 +906,14 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
 
 // Algorithm SC and the PSD minimization (Sec. II.A), driven from the host:
 // per step one vacuum solve (the plan's passes, bulk precision) of f = r/eps,
-// the operator A v = -4 pi r + eps grad ln eps . grad v with (A v, r/eps^2)
-// and (A v, A v/eps^2), and the update phi += alpha v, r -= alpha A v (FP64).
-// PSD takes the step that minimizes ||r/eps||_2; SC is the same recurrence
-// with the fixed steps -1/(4 pi) (first) and -eta/(4 pi), and its residual
-// ||rho_iter_{k+1} - rho_iter_k|| equals (eta/4 pi) ||r/eps|| at the current
-// iterate.
+// the operator A v = -4 pi r + eps grad ln eps . grad v with the two inner
+// products of the step, and the update phi += alpha v, r -= alpha A v (FP64).
+// PSD takes Algorithm PCG's step with beta = 0, (v, r)/(v, A v), and stops on
+// ||r||_2; its weighted variant takes the step that minimizes ||r/eps||_2,
+// (A v, r/eps^2)/(A v, A v/eps^2), and stops on ||r/eps||_2.  SC is the same
+// recurrence with the fixed steps -1/(4 pi) (first) and -eta/(4 pi), and its
+// residual ||rho_iter_{k+1} - rho_iter_k|| equals (eta/4 pi) ||r/eps|| at the
+// current iterate.
 struct ScBuffers {
   double *r = nullptr, *v = nullptr, *av = nullptr, *f = nullptr, *part = nullptr;
   double* lne = nullptr;
@@ -961,8 +963,10 @@ gps_status sc_impl(gps_plan* pl, const double* rho, const double* eps, double* p
   std::memset(&pl->info, 0, sizeof(pl->info));
   pl->hist.clear();
   if (!std::isfinite(rr0) || !std::isfinite(ff)) return GPS_E_NONFINITE;
-  const double thr_psd = tol * std::sqrt(ff);                 // tol ||4 pi rho/eps||
+  const double thr_w = tol * std::sqrt(ff);                   // tol ||4 pi rho/eps||
+  const double thr_r = tol * std::sqrt(rr0);                  // tol ||4 pi rho||
   const double thr_sc = tol * std::sqrt(rr0) / kFourPi;      // tol ||rho||
+  const int paper_step = method == GPS_METHOD_PSD;
   gps_status status = GPS_E_NOT_CONVERGED;
   int iters = 0;
   double rr = rr0;
@@ -970,7 +974,8 @@ gps_status sc_impl(gps_plan* pl, const double* rho, const double* eps, double* p
   const int max_steps = method == GPS_METHOD_SC ? pl->opt.maxit + 1 : pl->opt.maxit;
   for (int step = 0; status == GPS_E_NOT_CONVERGED && step < max_steps; ++step) {
     vacuum_apply<T>(pl, b.f, b.v);
-    launch_sc_operator(g, pl->opt.fd_order / 2, b.r, eps, b.lne, b.v, b.av, b.part, s);
+    launch_sc_operator(g, pl->opt.fd_order / 2, paper_step, b.r, eps, b.lne, b.v, b.av,
+                       b.part, s);
     ck(hipGetLastError());
     double vr = 0.0, vav = 0.0;
     sums(gp, &vr, &vav);
@@ -982,7 +987,7 @@ gps_status sc_impl(gps_plan* pl, const double* rho, const double* eps, double* p
         status = GPS_E_NONFINITE;
         break;
       }
-      if (!(vav > 0.0)) {
+      if (paper_step ? vav == 0.0 : !(vav > 0.0)) {
         status = GPS_E_BREAKDOWN;
         break;
       }
@@ -1003,7 +1008,7 @@ gps_status sc_impl(gps_plan* pl, const double* rho, const double* eps, double* p
       }
     } else {
       iters = step + 1;
-      if (std::sqrt(ff) <= thr_psd) status = GPS_OK;
+      if (paper_step ? std::sqrt(rr) <= thr_r : std::sqrt(ff) <= thr_w) status = GPS_OK;
     }
   }
   launch_sc_step(2, n, 0.0, rho, eps, phi, b.r, b.v, b.av, b.f, b.part, s);
@@ -1249,7 +1254,8 @@ gps_status gps_solve_generalized_q(gps_plan* pl, const double* rho, const double
 gps_status gps_solve_sc(gps_plan* pl, const double* rho, const double* eps, double* phi,
                         double tol, int method, double eta) {
   if (!pl || !rho || !eps || !phi || !(tol > 0.0) || !std::isfinite(tol)) return GPS_E_INVALID;
-  if (method != GPS_METHOD_SC && method != GPS_METHOD_PSD) return GPS_E_INVALID;
+  if (method != GPS_METHOD_SC && method != GPS_METHOD_PSD && method != GPS_METHOD_PSD_WEIGHTED)
+    return GPS_E_INVALID;
   if (method == GPS_METHOD_SC && !(eta > 0.0 && eta <= 1.0)) return GPS_E_INVALID;
   if (pl->bc == GPS_BC_PERIODIC) return GPS_E_INVALID;
   pl->info.device_error = 0;

@@ -112,10 +112,12 @@ constexpr int kPThreads = kPTX * kPTY;
 // AV = false: out = rho_pol from (rho, eps, phi).  AV = true (PSD / SC
 // operator, Eq. PrePSD with grad eps = eps grad ln eps): with rho -> r and
 // phi -> v, out = A v = -4 pi r + eps grad ln eps . grad v, and two FP64
-// partials per work-group, (A v, r/eps^2) and (A v, A v/eps^2) (the step that
-// minimizes ||r/eps||_2), into part[2 b], part[2 b + 1].
+// partials per work-group into part[2 b], part[2 b + 1]: (v, r) and (v, A v)
+// (paper != 0: Algorithm PCG's step with beta = 0), else (A v, r/eps^2) and
+// (A v, A v/eps^2) (the step that minimizes ||r/eps||_2).
 template <int M, bool AV>
 __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, int ntx, int nty,
+                                                            int paper,
                                                             const double* __restrict__ rho,
                                                             const double* __restrict__ eps,
                                                             const double* __restrict__ lne,
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
       if constexpr (AV) {
         const double av = -4.0 * kPi * rv + ev * dot;
         out[o] = av;
-        const double aw = av / (ev * ev);
+        const double aw = paper ? cp[0] : av / (ev * ev);
         vr += aw * rv;
         vav += aw * av;
       } else {
@@ -278,16 +280,16 @@ void launch_log_field(long long n, const double* eps, double* lne, hipStream_t s
 }
 
 template <bool AV>
-static void launch_graddot(const Geom& g, int fd_half, const double* rho, const double* eps,
-                           const double* lne, const double* phi, double* out, double* part,
-                           hipStream_t s) {
+static void launch_graddot(const Geom& g, int fd_half, int paper, const double* rho,
+                           const double* eps, const double* lne, const double* phi, double* out,
+                           double* part, hipStream_t s) {
   const int ntx = (g.nx + kPTX - 1) / kPTX, nty = (g.ny + kPTY - 1) / kPTY;
   const dim3 grid(polarization_groups(g));
   const FdFirst w = fd_first_weights(fd_half);
 #define GPS_PF(MM)                                                                        \
   case MM:                                                                                \
     GPS_LAUNCH((k_polarization<MM, AV>), grid, dim3(kPThreads), 0, s, g, w, ntx, nty,     \
-               rho, eps, lne, phi, out, part);                                            \
+               paper, rho, eps, lne, phi, out, part);                                     \
     break;
   switch (fd_half) {
     GPS_PF(1) GPS_PF(2) GPS_PF(3) GPS_PF(4) GPS_PF(5) GPS_PF(6) GPS_PF(7) GPS_PF(8)
@@ -298,13 +300,13 @@ static void launch_graddot(const Geom& g, int fd_half, const double* rho, const 
 
 void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
                          const double* lne, const double* phi, double* out, hipStream_t s) {
-  launch_graddot<false>(g, fd_half, rho, eps, lne, phi, out, nullptr, s);
+  launch_graddot<false>(g, fd_half, 0, rho, eps, lne, phi, out, nullptr, s);
 }
 
-void launch_sc_operator(const Geom& g, int fd_half, const double* r, const double* eps,
-                        const double* lne, const double* v, double* av, double* part,
-                        hipStream_t s) {
-  launch_graddot<true>(g, fd_half, r, eps, lne, v, av, part, s);
+void launch_sc_operator(const Geom& g, int fd_half, int paper_step, const double* r,
+                        const double* eps, const double* lne, const double* v, double* av,
+                        double* part, hipStream_t s) {
+  launch_graddot<true>(g, fd_half, paper_step, r, eps, lne, v, av, part, s);
 }
 
 // ---------------------------------------------------------------------------

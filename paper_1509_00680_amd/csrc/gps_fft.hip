@@ -402,7 +402,8 @@ __global__ __launch_bounds__(kThreads) void k_strided(SParams<T> p) {
         T m = p.table[((size_t)kzf * Lyh + kyf) * p.Kx + kx];
         if (p.k0_from_slot && pen == 0 && t == 0) m = T(st->g0);
         const cplx<T> w = buf[e];
-        dacc += double(half_bin_weight(kx, p.Lx)) * double(m * (w.x * w.x + w.y * w.y));
+        dacc += double(half_bin_weight(kx, p.Lx)) * double(m) *
+                (double(w.x) * double(w.x) + double(w.y) * double(w.y));
         buf[e] = cscale(w, m);
       }
     }

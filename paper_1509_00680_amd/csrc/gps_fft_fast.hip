@@ -236,7 +236,8 @@ void k_fstrided(SParams<T> p) {
           // (v, r) = sum over the full spectrum of m |w^|^2 (Parseval), taken
           // as Re(conj(w^) m w^); this pencil's half-spectrum bin k_x stands for
           // itself and its mirror (weight gw)
-          T ws = T(0);
+          // (products of the bulk type, summed in FP64 like every inner product)
+          double ws = 0.0;
 #pragma unroll
           for (int k2 = 0; k2 < L2; ++k2) {
             const int kz = q + L1 * k2;
@@ -244,9 +245,9 @@ void k_fstrided(SParams<T> p) {
             if (p.k0_from_slot && pen[t] == 0 && kz == 0) m = T(st->g0);
             const cplx<T> w = y[k2];
             y[k2] = cscale(w, m);
-            ws += y[k2].x * w.x + y[k2].y * w.y;
+            ws += double(y[k2].x) * double(w.x) + double(y[k2].y) * double(w.y);
           }
-          dacc += double(gw[t] * ws);
+          dacc += double(gw[t]) * ws;
         }
         __syncthreads();                        // step-2 reads of lds are done
       }

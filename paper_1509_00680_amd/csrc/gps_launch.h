@@ -175,9 +175,9 @@ void launch_log_field(long long n, const double* eps, double* lne, hipStream_t s
 void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
                          const double* lne, const double* phi, double* out, hipStream_t s);
 int polarization_groups(const Geom& g);
-void launch_sc_operator(const Geom& g, int fd_half, const double* r, const double* eps,
-                        const double* lne, const double* v, double* av, double* part,
-                        hipStream_t s);
+void launch_sc_operator(const Geom& g, int fd_half, int paper_step, const double* r,
+                        const double* eps, const double* lne, const double* v, double* av,
+                        double* part, hipStream_t s);
 void launch_sc_step(int mode, long long n, double alpha, const double* rho, const double* eps,
                     double* phi, double* r, const double* v, const double* av, double* f,
                     double* part, hipStream_t s);

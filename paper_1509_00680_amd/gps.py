@@ -271,10 +271,11 @@ class Plan:
                                               _ptr(phi), float(tol))
 
     def solve_sc(self, rho, eps, phi, tol, method="sc", eta=0.6):
-        """gps_solve_sc: Algorithm SC (method "sc", mixing eta) or PSD ("psd")."""
+        """gps_solve_sc: Algorithm SC (method "sc", mixing eta), PSD with Algorithm
+        PCG's step ("psd") or PSD with the step minimizing ||r/eps|| ("psd_weighted")."""
         for t in (rho, eps, phi):
             _check_field(t, self.shape)
-        code = {"sc": 0, "psd": 1}[method]
+        code = {"sc": 0, "psd": 1, "psd_weighted": 2}[method]
         return load().gps_solve_sc(self.handle, _ptr(rho), _ptr(eps), _ptr(phi), float(tol),
                                    code, float(eta))
 

@@ -4,11 +4,16 @@ graphs).
 
   molecule 96^3 (sccs cavity, free BC)     element-wise against the FP64 oracle
   slab 128x128x192 (surface BC, linear PB) element-wise against the FP64 oracle
-  charged solute 160^3 (nonlinear PB, MPB) the converged potential satisfies the
-      discrete equation, checked with the oracle's own vacuum solver and
-      stencil (the oracle's full nonlinear solve takes tens of minutes here);
-      element-wise parity with the same recipe on a 48^3 grid of the same
-      box.
+  charged solute 160^3 (nonlinear PB, MPB) element-wise by a fixed-point
+      check: the oracle's generalized Poisson solve to 1e-10 with the fixed
+      source rho + rho^ions[phi_gpu] returns phi_gpu at the self-consistent
+      solution (the oracle's full nonlinear solve takes tens of minutes
+      here); also the discrete equation's residual with the oracle's own
+      vacuum solver and stencil, and element-wise parity of the whole
+      nonlinear solve with the same recipe on a 48^3 grid of the same box.
+  vacuum solver at full size: free 160^3 (FFT length 320), surface
+      128x128x192 (lengths 128 and 384) and free 128x128x192 (256 and 384),
+      both precisions, element-wise against the oracle's convolution.
 
 Mixed precision is held to |dphi|max <= 1e-5 Ha/e and a relative energy error
 of 1e-6 against the oracle solved to 1e-10."""
@@ -90,6 +95,7 @@ def _ls_residual(phi, prob, oi, solver, q):
     return float(np.linalg.norm(res) / np.linalg.norm(psi))
 
 
+@pytest.mark.timeout(1200)
 def test_charged_solute_mpb160_full_size():
     require_gpu()
     prob = W.charged_solute_mpb()                         # 160^3, h 0.3, net +4, 1 M, MPB
@@ -108,9 +114,51 @@ def test_charged_solute_mpb160_full_size():
     q = stencil.q_field(prob.eps, prob.h, "free")
     r = _ls_residual(got, prob, oi, solver, q)
     r_off = _ls_residual(got * (1.0 + 1e-3), prob, oi, solver, q)
-    print("  equation residual %.3e (phi scaled by 1+1e-3: %.3e)" % (r, r_off))
+    print("  equation residual %.3e (phi scaled by 1+1e-3: %.3e)" % (r, r_off), flush=True)
     assert r <= 2e-5
     assert r_off >= 10 * r
+    # fixed point, element by element: with the ionic charge of phi_gpu as a
+    # fixed source, the oracle's generalized Poisson solve (FP64, 1e-10)
+    # returns phi_gpu
+    rho_tot = prob.rho + pb.ionic_charge(got, oi, oi.accessibility(prob.eps))
+    ref = pcg.pcg_solve(rho_tot, prob.eps, prob.h, "free", tol=1e-10, solver=solver,
+                        maxit=2000)
+    assert ref.converged
+    d = np.abs(got - ref.phi).max()
+    de = abs(info["energy"] / pcg.electrostatic_energy(prob.rho, ref.phi, prob.h) - 1.0)
+    print("  fixed point: oracle %d iterations, max|dphi| %.3e, rel dE %.3e"
+          % (ref.iterations, d, de))
+    assert d <= 1e-5 and de <= 1e-6
+
+
+FULL_VACUUM = [("free", (160, 160, 160)), ("surface", (192, 128, 128)),
+               ("free", (192, 128, 128))]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("bc,shape", FULL_VACUUM)
+def test_vacuum_solver_full_size(bc, shape):
+    # the FFT lengths of the full-size workloads (320; 128 and 384; 256 and 384)
+    # element-wise against the oracle's convolution, both precisions
+    require_gpu()
+    h = 0.3
+    rng = np.random.default_rng(11)
+    inputs = [rng.normal(size=shape)]
+    prob = W.charged_solute_mpb() if shape == (160, 160, 160) else W.slab()
+    inputs.append(prob.rho)
+    solver = green.VacuumSolver(shape, h, bc, workers=WORKERS)
+    expects = [solver.apply(f) for f in inputs]
+    for precision in ("fp64", "mixed"):
+        p = plan(shape, h, bc, precision)
+        u = empty(shape)
+        tol = 1e-12 if precision == "fp64" else 3e-6
+        for f, expect in zip(inputs, expects):
+            print("vacuum full size", bc, shape, precision, flush=True)
+            assert p.solve_vacuum(dev(f), u) == gps.GPS_OK
+            err = np.abs(host(u) - expect).max() / np.abs(expect).max()
+            print("  rel err %.3e" % err)
+            assert err <= tol
+        p.close()
 
 
 def test_charged_solute_mpb_recipe_coarse_parity():

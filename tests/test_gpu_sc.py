@@ -1,7 +1,9 @@
 """GPU parity of Algorithm SC and the PSD minimization (Sec. II.A) through
 gps_solve_sc, against the oracle: iterates after a fixed number of steps
-(FP64, 1e-10 of max|phi|), converged solutions (iterations within one,
-1e-7), mixed precision (1e-5 Ha/e), and the argument checks."""
+(FP64, 1e-10 of max|phi|) for SC, PSD with Algorithm PCG's step and PSD with
+the weighted step; converged solutions (iterations within one, 1e-7); the
+paper's step reported as not converged where the oracle stalls; mixed
+precision (1e-5 Ha/e); and the argument checks."""
 import numpy as np
 import pytest
 
@@ -17,8 +19,13 @@ def _problem(bc):
     return W.molecule(16, 0.5, seed=4, n_atoms=5, ball=1.5, bc=bc)
 
 
+def _oracle_psd(p, bc, tol, maxit, method):
+    step = "paper" if method == "psd" else "weighted"
+    return sc.psd_solve(p.rho, p.eps, p.h, bc, tol=tol, maxit=maxit, step=step)
+
+
 @pytest.mark.parametrize("bc", ["free", "surface", "wire"])
-@pytest.mark.parametrize("method", ["sc", "psd"])
+@pytest.mark.parametrize("method", ["sc", "psd", "psd_weighted"])
 def test_iterates_match_oracle(bc, method):
     require_gpu()
     p = _problem(bc)
@@ -26,7 +33,7 @@ def test_iterates_match_oracle(bc, method):
     if method == "sc":
         ref, _, _ = sc.sc_solve(p.rho, p.eps, p.h, bc, 0.6, tol=0.0, maxit=steps)
     else:
-        ref, _, _ = sc.psd_solve(p.rho, p.eps, p.h, bc, tol=0.0, maxit=steps)
+        ref, _, _ = _oracle_psd(p, bc, 0.0, steps, method)
     pl = plan(p.shape, p.h, bc, "fp64", maxit=steps)
     phi = empty(p.shape)
     print("sc iterates", bc, method, flush=True)
@@ -37,14 +44,14 @@ def test_iterates_match_oracle(bc, method):
 
 
 @pytest.mark.parametrize("bc", ["free", "wire"])
-@pytest.mark.parametrize("method", ["sc", "psd"])
+@pytest.mark.parametrize("method", ["sc", "psd_weighted"])
 def test_converged_solution_matches_oracle(bc, method):
     require_gpu()
     p = _problem(bc)
     if method == "sc":
         ref, it, _ = sc.sc_solve(p.rho, p.eps, p.h, bc, 0.6, tol=1e-9, maxit=2000)
     else:
-        ref, it, _ = sc.psd_solve(p.rho, p.eps, p.h, bc, tol=1e-9, maxit=2000)
+        ref, it, _ = _oracle_psd(p, bc, 1e-9, 2000, method)
     pl = plan(p.shape, p.h, bc, "fp64", maxit=2000)
     phi = empty(p.shape)
     print("sc converged", bc, method, flush=True)
@@ -56,6 +63,25 @@ def test_converged_solution_matches_oracle(bc, method):
         pm = plan(p.shape, p.h, bc, "mixed", maxit=2000)
         assert pm.solve_sc(dev(p.rho), dev(p.eps), phi, 1e-6, method="sc", eta=0.6) == gps.GPS_OK
         assert np.abs(host(phi) - ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("bc", ["free", "wire"])
+def test_paper_step_not_converged_like_the_oracle(bc):
+    # Algorithm PCG's step with beta = 0 stalls on this discretization: the
+    # oracle ends "not_converged" at maxit, the GPU with GPS_E_NOT_CONVERGED
+    # and the same iterate
+    require_gpu()
+    p = _problem(bc)
+    ref, it, st = _oracle_psd(p, bc, 1e-6, 60, "psd")
+    assert st == "not_converged" and it == 60
+    pl = plan(p.shape, p.h, bc, "fp64", maxit=60)
+    phi = empty(p.shape)
+    print("psd paper step", bc, flush=True)
+    assert pl.solve_sc(dev(p.rho), dev(p.eps), phi, 1e-6, method="psd") == \
+        gps.GPS_E_NOT_CONVERGED
+    info = pl.info()
+    assert info["iterations"] == 60 and info["rel_residual"] > 0.5
+    assert np.abs(host(phi) - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
 def test_sc_arguments_checked():
@@ -77,9 +103,9 @@ def test_sc_arguments_checked():
 
 def test_paper_gaussian_test_pcg_faster_than_sc():
     # the Gaussian test of Sec. II.C (box 10, sigma 0.5, d0 1.7, Delta 0.3):
-    # PCG reaches 1e-10 in about ten iterations, SC (eta 0.6) and PSD need
-    # about twice as many; all three approach the analytic potential to the
-    # kernel's discretization error
+    # PCG reaches 1e-10 in about ten iterations, SC (eta 0.6) and PSD with the
+    # weighted step need about twice as many; all three approach the analytic
+    # potential to the kernel's discretization error
     require_gpu()
     prob, exact = W.manufactured_gaussian(64, box=10.0, sigma=0.5, d0=1.7, delta=0.3)
     pl = plan(prob.shape, prob.h, "free", "fp64", maxit=500)
@@ -91,9 +117,13 @@ def test_paper_gaussian_test_pcg_faster_than_sc():
     assert pl.solve_sc(rho, eps, phi, 1e-10, method="sc", eta=0.6) == gps.GPS_OK
     it_sc = pl.info()["iterations"]
     err_sc = np.abs(host(phi) - exact).max()
-    assert pl.solve_sc(rho, eps, phi, 1e-10, method="psd") == gps.GPS_OK
+    assert pl.solve_sc(rho, eps, phi, 1e-10, method="psd_weighted") == gps.GPS_OK
     it_psd = pl.info()["iterations"]
-    print("  iterations pcg %d sc %d psd %d" % (it_pcg, it_sc, it_psd))
+    print("  iterations pcg %d sc %d psd (weighted step) %d" % (it_pcg, it_sc, it_psd))
     assert it_pcg <= 15 and it_sc >= 1.5 * it_pcg and it_psd >= 1.5 * it_pcg
+    # the paper's own PSD step does not contract here (as in the oracle)
+    pl2 = plan(prob.shape, prob.h, "free", "fp64", maxit=40)
+    assert pl2.solve_sc(rho, eps, phi, 1e-10, method="psd") == gps.GPS_E_NOT_CONVERGED
+    assert pl2.info()["rel_residual"] > 0.9
     # second-order kernel: 1.2e-2 of max|phi| at h = 10/64
     assert err_pcg < 3e-2 * np.abs(exact).max() and err_sc < 3e-2 * np.abs(exact).max()

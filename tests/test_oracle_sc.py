@@ -1,11 +1,14 @@
 """Pins of the oracle's Algorithm SC and PSD minimization (Sec. II.A):
 SC equals PSD with the fixed step -eta/(4 pi) iterate by iterate, both reach
-the dense solve of the operator they discretize, and constant eps is solved
-at once."""
+the dense solve of the operator they discretize, constant eps is solved at
+once, the operator's stencil term matches its closed form, SC and the
+weighted PSD step converge to the analytic potential of the paper's Gaussian
+test (Sec. II.C) at second order, and the paper's own PSD step (Algorithm PCG
+with beta = 0) is the line formula of Algorithm PCG and stalls on that test."""
 import numpy as np
 import pytest
 
-from oracle import green, sc
+from oracle import green, pcg, sc
 from paper_1509_00680_amd import workloads as W
 
 
@@ -35,18 +38,95 @@ def test_fixed_points_are_the_dense_solve(bc):
     a = sc.dense_sc_operator(p.eps, p.h, bc)
     ref = np.linalg.solve(a, -4 * np.pi * p.rho.ravel()).reshape(p.shape)
     phi_sc, it_sc, _ = sc.sc_solve(p.rho, p.eps, p.h, bc, 0.6, tol=1e-13, maxit=2000)
-    phi_psd, it_psd, st = sc.psd_solve(p.rho, p.eps, p.h, bc, tol=1e-13, maxit=2000)
+    phi_psd, it_psd, st = sc.psd_solve(p.rho, p.eps, p.h, bc, tol=1e-13, maxit=2000,
+                                       step="weighted")
     assert st == "ok"
     scale = np.abs(ref).max()
     assert np.abs(phi_sc - ref).max() <= 1e-9 * scale
     assert np.abs(phi_psd - ref).max() <= 1e-9 * scale
 
 
-def test_constant_eps_one_step():
+@pytest.mark.parametrize("step", ["paper", "weighted"])
+def test_constant_eps_one_step(step):
     p = _problem("free", 8, 0.5)
     eps = np.full(p.shape, 7.0)
     u = green.VacuumSolver(p.shape, p.h, "free").apply(p.rho) / 7.0
     phi, it, _ = sc.sc_solve(p.rho, eps, p.h, "free", 0.6, tol=1e-12)
     assert it == 1 and np.abs(phi - u).max() <= 1e-13 * np.abs(u).max()
-    phi, it, st = sc.psd_solve(p.rho, eps, p.h, "free", tol=1e-12)
+    phi, it, st = sc.psd_solve(p.rho, eps, p.h, "free", tol=1e-12, step=step)
     assert st == "ok" and it == 1 and np.abs(phi - u).max() <= 1e-12 * np.abs(u).max()
+
+
+def _smooth_case(n, mutate=None, box=10.0, a=2.5, s=1.0, c=(0.7, -0.4, 0.3), e0=3.0):
+    h = box / n
+    x, y, z = W.grid_coords((n, n, n), h)
+    r2 = x * x + y * y + z * z
+    eps = 1.0 + (e0 - 1.0) * (1.0 - np.exp(-r2 / (a * a)))
+    dx, dy, dz = x - c[0], y - c[1], z - c[2]
+    phi = np.exp(-(dx * dx + dy * dy + dz * dz) / (2 * s * s))
+    # closed form of grad ln eps . grad phi (eps radial, phi an off-centre Gaussian)
+    geps_over_r = (e0 - 1.0) * np.exp(-r2 / (a * a)) * 2.0 / (a * a)
+    exact = geps_over_r / eps * -(x * dx + y * dy + z * dz) / (s * s) * phi
+    f = np.transpose(phi, (0, 2, 1)) if mutate == "transpose" else phi
+    got = sc.grad_dot(np.log(eps), f, h, 8, "free")
+    return float(np.abs(got - exact).max() / np.abs(exact).max())
+
+
+def test_stencil_term_against_closed_form():
+    # the operator's only stencil term, grad_h ln eps . grad_h phi (Eq.
+    # rhoiter), on a smooth cavity with an off-centre Gaussian: order 16
+    # converges fast; exchanging two axes of one operand is an O(1) error
+    e24, e32 = _smooth_case(24), _smooth_case(32)
+    assert e24 < 1e-3 and e32 < 1e-4 and e24 / e32 > 4.0
+    assert _smooth_case(32, "transpose") > 0.5
+
+
+def test_sc_and_weighted_psd_converge_to_the_analytic_potential():
+    # Sec. II.C: Gaussian potential (sigma 0.5) in the erf cavity (d0 1.7,
+    # Delta 0.3, eps0 78.36) of a cube of side 10; rho from the analytic
+    # operator.  SC (eta = 0.6, as in the paper) and PSD with the weighted step
+    # approach the analytic phi at second order, and their discrete operator
+    # differs from Algorithm PCG's by O(h^2)
+    errs, diffs = [], []
+    for n in (40, 80):
+        p, exact = W.manufactured_gaussian(n)
+        solver = green.VacuumSolver(p.shape, p.h, "free")
+        scale = np.abs(exact).max()
+        phi_sc, it_sc, _ = sc.sc_solve(p.rho, p.eps, p.h, "free", 0.6, 1e-10, solver=solver)
+        phi_w, it_w, st = sc.psd_solve(p.rho, p.eps, p.h, "free", 1e-10, solver=solver,
+                                       step="weighted")
+        ref = pcg.pcg_solve(p.rho, p.eps, p.h, "free", tol=1e-11, solver=solver)
+        assert st == "ok" and it_sc <= 40 and it_w <= 40 and ref.converged
+        assert np.abs(phi_sc - phi_w).max() <= 1e-8 * scale
+        errs.append(np.abs(phi_sc - exact).max() / scale)
+        diffs.append(np.abs(phi_sc - ref.phi).max() / scale)
+    assert errs[1] < 1e-2 and errs[0] / errs[1] > 3.0
+    assert diffs[0] / diffs[1] > 3.0
+
+
+def test_paper_step_is_the_line_formula_of_algorithm_pcg():
+    # first step of the paper's PSD: alpha_0 = (v_0, r_0)/(v_0, A v_0) with A
+    # the dense operator and v_0 = G(r_0/eps)
+    p = _problem("free", 6, 0.6)
+    a = sc.dense_sc_operator(p.eps, p.h, "free")
+    r0 = -4 * np.pi * p.rho
+    v0 = green.VacuumSolver(p.shape, p.h, "free").apply(r0 / p.eps)
+    alpha0 = float(v0.ravel() @ r0.ravel()) / float(v0.ravel() @ (a @ v0.ravel()))
+    rec = []
+    sc.psd_solve(p.rho, p.eps, p.h, "free", tol=0.0, maxit=1, record=rec)
+    assert np.abs(rec[0] - alpha0 * v0).max() <= 1e-11 * np.abs(alpha0 * v0).max()
+
+
+def test_paper_step_stalls_on_the_paper_gaussian():
+    # the reported result: the paper's step does not contract on this
+    # non-symmetric discretization (the relative residual stays near 1), while
+    # SC on the same problem converges (previous test)
+    p, _ = W.manufactured_gaussian(32)
+    solver = green.VacuumSolver(p.shape, p.h, "free")
+    hist = []
+    phi, it, st = sc.psd_solve(p.rho, p.eps, p.h, "free", 1e-6, solver=solver, maxit=60,
+                               res_hist=hist)
+    assert st == "not_converged" and it == 60 and len(hist) == 60
+    assert min(hist) > 0.9 and min(hist[30:]) > 0.9
+    v = solver.apply(-4 * np.pi * p.rho / p.eps)
+    assert np.isfinite(phi).all() and np.abs(phi).max() < 10 * np.abs(v).max()
