@@ -283,6 +283,23 @@ gps_status gps_rigid_cavity(gps_plan *plan, int natoms, const double *atoms, dou
 gps_status gps_polarization_charge(gps_plan *plan, const double *rho, const double *eps,
                                    const double *phi, double *rho_pol);
 
+/* As gps_polarization_charge, but allocates nothing: for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The ln eps field it needs lives in a
+ * static device array of GPS_NOALLOC_MAX_POINTS doubles (32 MiB) that the
+ * library holds on each GPU it runs on until the process ends; its device
+ * address is looked up on the first call on each device.  Every call on a GPU
+ * shares that GPU's array, so calls that overlap on one GPU (several host
+ * threads, or plans on different streams) race and must be serialized by the
+ * caller.  The result is bit for bit that of gps_polarization_charge.
+ * Runs on the plan's stream and returns when it has finished.  Errors:
+ * GPS_E_INVALID (null pointer, or a plan of more than GPS_NOALLOC_MAX_POINTS
+ * grid points), GPS_E_DEVICE. */
+#define GPS_NOALLOC_MAX_POINTS 4194304
+gps_status gps_polarization_charge_noalloc(gps_plan *plan, const double *rho,
+                                           const double *eps, const double *phi,
+                                           double *rho_pol);
+
 /* Information about the last solve of this plan. */
 gps_status gps_last_info(const gps_plan *plan, gps_info *out);
 

@@ -1320,6 +1320,31 @@ gps_status gps_polarization_charge(gps_plan* pl, const double* rho, const double
   return GPS_OK;
 }
 
+gps_status gps_polarization_charge_noalloc(gps_plan* pl, const double* rho, const double* eps,
+                                           const double* phi, double* rho_pol) {
+  if (!pl || !rho || !eps || !phi || !rho_pol) return GPS_E_INVALID;
+  if (pl->npts() > GPS_NOALLOC_MAX_POINTS) return GPS_E_INVALID;
+  static_assert(GPS_NOALLOC_MAX_POINTS == kNoAllocMaxPoints, "scratch size");
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) return GPS_E_DEVICE;
+  if (prev != pl->device && hipSetDevice(pl->device) != hipSuccess) return GPS_E_DEVICE;
+  gps_status status = GPS_OK;
+  try {
+    double* lne = nullptr;
+    ck(noalloc_scratch(pl->device, &lne));
+    launch_log_field(pl->npts(), eps, lne, pl->stream());
+    launch_polarization(pl->g, pl->opt.fd_order / 2, rho, eps, lne, phi, rho_pol,
+                        pl->stream());
+    ck(hipGetLastError());
+    ck(hipStreamSynchronize(pl->stream()));
+  } catch (const DevError& d) {
+    pl->info.device_error = (int)d.e;
+    status = GPS_E_DEVICE;
+  }
+  if (prev != pl->device) (void)hipSetDevice(prev);
+  return status;
+}
+
 gps_status gps_solve_pb(gps_plan* pl, const double* rho, const double* eps, const gps_ions* ions,
                         double* phi, double tol) {
   if (!pl || !rho || !eps || !phi || !ions || !(tol > 0.0) || !std::isfinite(tol))

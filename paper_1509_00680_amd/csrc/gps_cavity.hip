@@ -7,6 +7,8 @@
 //    the one Eq. remap implies; Eq. rhopol prints a plus);
 //  * the operator and pointwise steps of Algorithm SC and the PSD minimization
 //    (Sec. II.A, Eq. PrePSD).
+#include <mutex>
+
 #include "gps_device.h"
 #include "gps_launch.h"
 
@@ -272,6 +274,37 @@ __global__ __launch_bounds__(kThreads) void k_log_field(long long n, const doubl
                                                         double* __restrict__ lne) {
   const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
   if (i < n) lne[i] = log(eps[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Polarization charge without allocation: the ln eps field lives in a
+// file-scope device array of kNoAllocMaxPoints doubles (32 MiB), one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel (in host code it is only a stand-in for the symbol); it uses the
+// device address that hipGetSymbolAddress returns, looked up once per device
+// with that device current.  Every call on a GPU shares that GPU's array:
+// calls that overlap on one GPU race on it.  ln eps is written in full before
+// it is read, so nothing has to start at zero.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kNoAllocMaxPoints];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 void launch_log_field(long long n, const double* eps, double* lne, hipStream_t s) {

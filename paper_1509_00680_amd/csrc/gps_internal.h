@@ -53,6 +53,10 @@ __device__ __forceinline__ unsigned fast_div(unsigned n, FastDiv f) {
   return (__umulhi(n, f.m) + n) >> f.s;
 }
 
+// Largest grid (points) of gps_polarization_charge_noalloc; its scratch array
+// holds this many doubles (32 MiB) per GPU.
+constexpr long long kNoAllocMaxPoints = 4194304;
+
 constexpr int kMaxStages = 16;
 constexpr int kMaxLen = 1024;        // longest supported FFT length
 

@@ -172,6 +172,10 @@ template <typename T> void launch_refine(const SlotTable<T>& tab, const Batch& b
 void launch_rigid_cavity(const Geom& g, const double* atoms, int natoms, double delta,
                          double eps0, double* eps, double* q, hipStream_t s);
 void launch_log_field(long long n, const double* eps, double* lne, hipStream_t s);
+// Device address of the no-allocation scratch array (kNoAllocMaxPoints
+// doubles) on `device`, which must be the current device; looked up once per
+// device with hipGetSymbolAddress.
+hipError_t noalloc_scratch(int device, double** out);
 void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
                          const double* lne, const double* phi, double* out, hipStream_t s);
 int polarization_groups(const Geom& g);

@@ -24,13 +24,15 @@ STATUS = {0: "GPS_OK", 1: "GPS_E_INVALID", 2: "GPS_E_NOMEM", 3: "GPS_E_NOT_CONVE
 GPS_OK, GPS_E_INVALID, GPS_E_NOMEM, GPS_E_NOT_CONVERGED = 0, 1, 2, 3
 GPS_E_BREAKDOWN, GPS_E_NONFINITE, GPS_E_DEVICE, GPS_E_UNSUPPORTED = 4, 5, 6, 7
 GPS_PENDING = 8
+NOALLOC_MAX_POINTS = 4194304          # GPS_NOALLOC_MAX_POINTS
 
 # every symbol include/gps.h declares
 EXPORTED = ("gps_plan_create", "gps_plan_set_options", "gps_plan_get_options",
             "gps_plan_device_bytes", "gps_plan_destroy", "gps_solve_generalized",
             "gps_solve_pb", "gps_solve_vacuum", "gps_solve_generalized_q", "gps_solve_sc",
             "gps_rigid_cavity",
-            "gps_polarization_charge", "gps_last_info", "gps_last_history",
+            "gps_polarization_charge", "gps_polarization_charge_noalloc",
+            "gps_last_info", "gps_last_history",
             "gps_plan_set_timing", "gps_plan_timing", "gps_status_string",
             "gps_plan_footprint", "gps_plan_release_buffers", "gps_server_create", "gps_server_submit", "gps_server_poll",
             "gps_server_wait", "gps_server_get_stats", "gps_server_destroy")
@@ -137,6 +139,8 @@ def load(path=LIB_PATH):
     lib.gps_rigid_cavity.restype = I
     lib.gps_polarization_charge.argtypes = [P, P, P, P, P]
     lib.gps_polarization_charge.restype = I
+    lib.gps_polarization_charge_noalloc.argtypes = [P, P, P, P, P]
+    lib.gps_polarization_charge_noalloc.restype = I
     lib.gps_last_info.argtypes = [P, ctypes.POINTER(gps_info)]
     lib.gps_last_info.restype = I
     lib.gps_last_history.argtypes = [P, ctypes.POINTER(D), I]
@@ -296,6 +300,14 @@ class Plan:
             _check_field(t, self.shape)
         return load().gps_polarization_charge(self.handle, _ptr(rho), _ptr(eps), _ptr(phi),
                                               _ptr(rho_pol))
+
+    def polarization_charge_noalloc(self, rho, eps, phi, rho_pol):
+        """gps_polarization_charge_noalloc: as polarization_charge, with the ln eps
+        scratch in the library's static device array (no allocation)."""
+        for t in (rho, eps, phi, rho_pol):
+            _check_field(t, self.shape)
+        return load().gps_polarization_charge_noalloc(self.handle, _ptr(rho), _ptr(eps),
+                                                      _ptr(phi), _ptr(rho_pol))
 
     def solve_vacuum(self, f, u):
         for t in (f, u):

@@ -56,6 +56,8 @@ def test_null_plan_rejected(lib):
     assert lib.gps_solve_generalized(None, None, None, None, 1e-6) == gps.GPS_E_INVALID
     assert lib.gps_plan_set_timing(None, 1) == gps.GPS_E_INVALID
     assert lib.gps_last_info(None, None) == gps.GPS_E_INVALID
+    assert lib.gps_polarization_charge_noalloc(None, None, None, None, None) == \
+        gps.GPS_E_INVALID
     assert lib.gps_plan_device_bytes(None) == 0
     lib.gps_plan_destroy(None)
 
