@@ -157,27 +157,82 @@ struct RegFFT<T, INV, N, Ns, R, Rest...> {
   }
 };
 
-// Radix lists of the codelet lengths.
+// ---- prime-factor (Good-Thomas) codelet for N = N1 N2 with gcd(N1, N2) = 1 --
+// Input n = (N2 n1 + N1 n2) mod N is read as a N1 x N2 array; N1-point DFTs
+// along n1, then N2-point DFTs along n2, and output (k1, k2) is X[k] with
+// k = k1 mod N1 = k2 mod N2 (Chinese remainder theorem).  The exponent of
+// w_N factors exactly into w_N1^(n1 k1) w_N2^(n2 k2), so no twiddle factor
+// sits between the two stages.  All indices are compile-time after unrolling.
+// Inverse of a modulo m (gcd(a, m) = 1), evaluated in constant expressions.
+__host__ __device__ constexpr int ce_modinv(int a, int m) {
+  int r = 1;
+  while ((a * r) % m != 1 % m) ++r;
+  return r;
+}
+// CRT idempotents: E1 = 1 mod N1, 0 mod N2; E2 = 0 mod N1, 1 mod N2.  The
+// output index of (k1, k2) is (k1 E1 + k2 E2) mod N, plain arithmetic on
+// unrolled constants.
+template <int N1, int N2> struct PfaMap {
+  static constexpr int E1 = N2 * ce_modinv(N2 % N1, N1);
+  static constexpr int E2 = N1 * ce_modinv(N1 % N2, N2);
+};
+
 template <typename T, bool INV, int N> struct Codelet;
+
+template <typename T, bool INV, int N1, int N2> struct PfaFFT {
+  static __device__ __forceinline__ void run(cplx<T>* x) {
+    constexpr int N = N1 * N2;
+    cplx<T> y[N];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) {
+      cplx<T> v[N1];
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) v[n1] = x[(N2 * n1 + N1 * n2) % N];
+      Codelet<T, INV, N1>::run(v);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) y[k1 * N2 + n2] = v[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      cplx<T> v[N2];
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) v[n2] = y[k1 * N2 + n2];
+      Codelet<T, INV, N2>::run(v);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2)
+        x[(k1 * PfaMap<N1, N2>::E1 + k2 * PfaMap<N1, N2>::E2) % N] = v[k2];
+    }
+  }
+};
+
+// Radix lists of the codelet lengths (prime-factor form where N splits into
+// coprime factors).
 #define GPS_CODELET(N, ...)                                                         \
   template <typename T, bool INV> struct Codelet<T, INV, N> {                       \
     static __device__ __forceinline__ void run(cplx<T>* x) {                        \
       RegFFT<T, INV, N, 1, __VA_ARGS__>::run(x);                                    \
     }                                                                               \
   };
+#define GPS_PFA_CODELET(N, N1, N2)                                                  \
+  template <typename T, bool INV> struct Codelet<T, INV, N> {                       \
+    static __device__ __forceinline__ void run(cplx<T>* x) {                        \
+      PfaFFT<T, INV, N1, N2>::run(x);                                               \
+    }                                                                               \
+  };
 GPS_CODELET(2, 2)
 GPS_CODELET(3, 3)
 GPS_CODELET(4, 4)
 GPS_CODELET(5, 5)
-GPS_CODELET(6, 3, 2)
 GPS_CODELET(8, 4, 2)
-GPS_CODELET(10, 5, 2)
-GPS_CODELET(12, 4, 3)
 GPS_CODELET(16, 4, 4)
-GPS_CODELET(20, 4, 5)
-GPS_CODELET(24, 4, 3, 2)
 GPS_CODELET(32, 4, 4, 2)
+GPS_PFA_CODELET(6, 2, 3)
+GPS_PFA_CODELET(10, 2, 5)
+GPS_PFA_CODELET(12, 4, 3)
+GPS_PFA_CODELET(20, 4, 5)
+GPS_PFA_CODELET(24, 8, 3)
 #undef GPS_CODELET
+#undef GPS_PFA_CODELET
 
 // Natural-order DFT of N values held in registers.
 template <typename T, bool INV, int N>
