@@ -74,12 +74,17 @@ def parse():
                     help="sc workload: the molecule, or the Gaussian test of Sec. II.C "
                          "(box 10, sigma 0.5, d0 1.7, Delta 0.3) with its analytic potential")
     ap.add_argument("--requests", type=int, default=512, help="serving: stream length")
-    ap.add_argument("--max-active", type=int, default=4, help="serving: concurrent solves")
+    ap.add_argument("--max-active", type=int, default=4, help="serving: worker streams")
+    ap.add_argument("--batch-slots", type=int, default=4,
+                    help="serving: problems per batched launch on small grids (1: no batching)")
     ap.add_argument("--budget-frac", type=float, default=0.75,
                     help="serving: admission budget as a fraction of the distinct plans' "
                          "total resident bytes")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving: arrival rate as a fraction of the closed-loop capacity")
+    ap.add_argument("--rate", type=float, default=450.0,
+                    help="serving: arrival rate in requests/s (0: --load times the closed-loop "
+                         "capacity)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (10 times) and exit: the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -269,7 +274,10 @@ def serving_bench(args, torch, gps, W):
     fps = {}
     for prm in prms:
         n = prm["n"]
-        fps[(n, prm["bc"])] = gps.plan_footprint((n, n, n), prm["bc"], "mixed")
+        tb, b, t = gps.plan_footprint((n, n, n), prm["bc"], "mixed")
+        if args.batch_slots > 1 and n ** 3 <= 64 ** 3:
+            b *= args.batch_slots                    # a batched plan holds batch_slots problems
+        fps[(n, prm["bc"])] = (tb, b, t)
     total = sum(tb + b for tb, b, _ in fps.values())
     budget = max(int(args.budget_frac * total), max(tb + b + t for tb, b, t in fps.values()))
     npts = [prm["n"] ** 3 for prm in prms]
@@ -288,10 +296,22 @@ def serving_bench(args, torch, gps, W):
 
     def summarize(results, srv):
         lat = np.array([r["done_ms"] - r["submit_ms"] for r in results])
+        wait = np.array([r["start_ms"] - r["submit_ms"] for r in results])
+        run = np.array([r["done_ms"] - r["start_ms"] for r in results])
+        by_grid = {}
+        for prm, l, w, u in zip(prms, lat, wait, run):
+            by_grid.setdefault(prm["n"], []).append((l, w, u))
+        per_grid = {str(n): {"requests": len(v),
+                             "p50_ms": float(np.percentile([x[0] for x in v], 50)),
+                             "p99_ms": float(np.percentile([x[0] for x in v], 99)),
+                             "mean_wait_ms": float(np.mean([x[1] for x in v])),
+                             "mean_run_ms": float(np.mean([x[2] for x in v]))}
+                    for n, v in sorted(by_grid.items())}
         bad = [r["status"] for r in results if r["status"] != gps.GPS_OK]
         wall = (max(r["done_ms"] for r in results) - min(r["submit_ms"] for r in results)) / 1e3
         iters = sum(r["iterations"] for r in results)
         return {"solves_per_s": len(results) / wall, "p50_ms": float(np.percentile(lat, 50)),
+                "per_grid": per_grid, "wait_p99_ms": float(np.percentile(wait, 99)),
                 "p99_ms": float(np.percentile(lat, 99)), "wall_s": wall,
                 "mgridpts_iter_per_s": sum(n * r["iterations"] for n, r in zip(npts, results))
                 / wall / 1e6, "iterations": iters, "failed": len(bad), "stats": srv.stats()}
@@ -300,14 +320,22 @@ def serving_bench(args, torch, gps, W):
     # after one closed-loop pass that creates the plans and graphs; the open-loop
     # arrival rate is a fraction of it, so the server is not overloaded
     nreq = len(reqs)
-    srv = gps.Server(budget_bytes=budget, max_active=args.max_active, precision="mixed")
+    srv = gps.Server(budget_bytes=budget, max_active=args.max_active, precision="mixed",
+                     batch_slots=args.batch_slots)
     closed_loop(srv, nreq, phis)
     capacity = closed_loop(srv, nreq, phis)
-    rate = args.load * capacity
+    rate = args.rate if args.rate > 0 else args.load * capacity
     arrivals = np.cumsum(gaps / rate)
     res_mixed = run_stream(torch, gps, srv, reqs, arrivals, phis)
     mixed = summarize(res_mixed, srv)
     srv.close()
+
+    # closed-loop capacity without batched launches, for comparison
+    srv1 = gps.Server(budget_bytes=budget, max_active=args.max_active, precision="mixed",
+                      batch_slots=1)
+    closed_loop(srv1, nreq, phis)
+    capacity_unbatched = closed_loop(srv1, nreq, phis)
+    srv1.close()
 
     srv64 = gps.Server(budget_bytes=0, max_active=1, precision="fp64")
     closed_loop(srv64, nreq, phis64)
@@ -336,10 +364,13 @@ def serving_bench(args, torch, gps, W):
         "config": {"workload": "serving_stream_%d" % len(reqs), "grids": list(W.SERVING_GRIDS),
                    "box_bohr": W.SERVING_BOX, "bc": "free/surface/periodic", "kinds": kinds,
                    "seed": 5, "tol": 1e-6, "max_active": args.max_active,
+                   "batch_slots": args.batch_slots,
                    "budget_bytes": budget, "distinct_plans_bytes": total,
                    "arrival_rate_per_s": rate, "closed_loop_capacity_per_s": capacity,
+                   "closed_loop_capacity_unbatched_per_s": capacity_unbatched,
                    "precision": "mixed (fp32 bulk, fp64 dots/solution)"},
         "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"],
+        "per_grid": mixed["per_grid"], "wait_p99_ms": mixed["wait_p99_ms"],
         "utilization": {"offered_load": rate / capacity,
                         "served_over_arrival_rate": mixed["solves_per_s"] / rate},
         "mgridpts_iter_per_s": mixed["mgridpts_iter_per_s"],

@@ -355,7 +355,19 @@ const char *gps_status_string(int status);
  * graphs) stay resident between requests and are reused by any request of
  * the same nx, ny, nz, h and bc.
  *
- * Admission is by device footprint (gps_plan_footprint).  A request is
+ * Batched launches: generalized Poisson and linear Poisson-Boltzmann requests
+ * on grids of at most 64^3 points (whose solves are bound by launch latency)
+ * run in continuous batches.  Their plan holds batch_slots problems, and every
+ * kernel of an iteration is one launch over all of them, each with its own
+ * buffers, coefficients and device-side stop decision.  A waiting request of
+ * the same plan (and, for periodic boundaries, the same kind) joins a free
+ * slot between two replays of the captured iteration graphs, and a request
+ * leaves as soon as the host reads its state as done; other workers leave such
+ * requests to the running batch.  Larger grids and nonlinear Poisson-Boltzmann
+ * requests get one solve per plan.
+ *
+ * Admission is by device footprint (gps_plan_footprint; a batched plan counts
+ * batch_slots times the buffers of one solve).  A request is
  * admitted when the bytes that the server's plans hold, plus what its own solve
  * adds (new tables, buffers and the transient of a new plan; only the
  * buffers if a resident plan has released them), fit in budget_bytes.  To make
@@ -366,8 +378,9 @@ const char *gps_status_string(int status);
  * ahead of older ones that need a new plan.  No request is passed over more
  * than 8 times.
  *
- * A result is the same whether its request runs alone or among others.  Each
- * solve uses one plan, and the kernels reduce in a fixed order.
+ * A result is the same whether its request runs alone or among others: each
+ * problem has its own buffers and state, and the kernels reduce in a fixed
+ * order that does not depend on the other problems of a launch.
  *
  * Fields are device pointers, as for the plan calls.  They must hold their
  * final values when gps_server_submit is called (the workers' streams do not
@@ -379,10 +392,12 @@ typedef struct gps_server gps_server;
 typedef struct {
   size_t budget_bytes;  /* device bytes the server's plans may hold, transients
                            included; 0 = no limit */
-  int max_active;       /* solves in flight at once, 1..16 (default 4) */
+  int max_active;       /* worker streams, 1..16 (default 4) */
   int precision;        /* gps_precision of every solve (default GPS_PREC_MIXED) */
   int fd_order;         /* as gps_options (default 16) */
   int maxit;            /* as gps_options (default 1000) */
+  int batch_slots;      /* problems per batched launch on grids of at most 64^3
+                           points, 1..8 (0 = default 4; 1 = no batching) */
 } gps_server_options;
 
 typedef struct {
@@ -422,6 +437,8 @@ typedef struct {
   int max_in_flight;     /* largest number of solves running at once */
   long long submitted;
   long long completed;
+  long long batched;     /* requests solved in a slot of a batched plan */
+  int max_batch;         /* most problems in flight in one batched launch */
 } gps_server_stats;
 
 /* Start a server on the current device.  opt may be NULL (defaults).

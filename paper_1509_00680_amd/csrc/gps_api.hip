@@ -17,6 +17,7 @@
 #include "gps.h"
 #include "gps_internal.h"
 #include "gps_launch.h"
+#include "gps_batch.h"
 
 using namespace gps;
 
@@ -109,12 +110,14 @@ int ilog2(int v) {
   return l;
 }
 
-// Per-precision buffers of one problem in flight.
+// Per-precision buffers of the problems in flight on a plan: slot 0 for the
+// single-solve calls, slots 0..nslots-1 when the plan serves a batch.
 template <typename T> struct Res {
   bool ready = false;
   size_t bytes = 0;          // device bytes of this precision's buffers
-  SlotTable<T> tab{};        // passed by value to every kernel; entry 0 is this plan's problem
-  Slot<T>& slot() { return tab.s[0]; }
+  SlotTable<T> tab{};        // passed by value to every kernel
+  int nslots = 1;            // slots with buffers
+  Slot<T>& slot(int i = 0) { return tab.s[i]; }
   SolveState* h_state = nullptr;   // pinned
   double* h_parts = nullptr;       // pinned, >= 4 * groups
   int hist_cap = 0;
@@ -130,6 +133,11 @@ template <typename T> struct Res {
   hipGraphExec_t graphs[kGraphs] = {};
   int graph_iters[kGraphs] = {};
   int graph_neutral = -1, graph_timing = -1, graph_chunk = 0, graph_refine = -1;
+  // batch mode: the same graph lengths over all nslots slots (grid.y = nslots)
+  hipGraphExec_t bgraphs[kGraphs] = {};
+  int bgraph_iters[kGraphs] = {};
+  int bgraph_neutral = -1, bgraph_chunk = 0, bgraph_n = 0;
+  SolveState* h_states = nullptr;  // pinned, one per slot
 };
 
 template <typename T>
@@ -138,6 +146,11 @@ void drop_graphs(Res<T>& R) {
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
   }
+  for (hipGraphExec_t& g : R.bgraphs) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  R.bgraph_n = 0;
 }
 
 }  // namespace
@@ -355,6 +368,43 @@ void build_green(gps_plan* pl) {
 // ---------------------------------------------------------------------------
 // per-precision solve resources
 // ---------------------------------------------------------------------------
+// The buffers of one problem in flight (PCG vectors, fields, FFT work buffer,
+// partial sums, state, solution); history and optional buffers separately.
+template <typename T>
+void alloc_slot(gps_plan* pl, Slot<T>& s, size_t* bytes) {
+  const long long n = pl->npts();
+  const int nvg = vec_groups(n);
+  const Geom& g = pl->g;
+  const int nxg = part_caps(g).x;
+  const int nzg = part_caps(g).z;
+  const size_t nb = (size_t)n * sizeof(T);
+  dalloc(&s.r, nb, bytes);
+  dalloc(&s.p, nb, bytes);
+  dalloc(&s.ap, nb, bytes);
+  dalloc(&s.isq, nb, bytes);
+  dalloc(&s.qk, nb, bytes);
+  if (pl->bc == GPS_BC_PERIODIC) dalloc(&s.s, nb, bytes);
+  dalloc(&s.sq64, (size_t)n * sizeof(double), bytes);
+  dalloc(&s.work, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<T>), bytes);
+  dalloc(&s.part_init, (size_t)4 * nvg * sizeof(double), bytes);
+  dalloc(&s.part_rr, (size_t)nxg * sizeof(double), bytes);
+  dalloc(&s.part_delta, (size_t)nzg * sizeof(double), bytes);
+  dalloc(&s.part_pap, (size_t)nxg * sizeof(double), bytes);
+  dalloc(&s.part_mu, (size_t)nxg * sizeof(double), bytes);
+  dalloc(&s.part_aux, (size_t)kVec * nvg * sizeof(double), bytes);
+  dalloc(&s.st, sizeof(SolveState), bytes);
+  dalloc(&s.phi, (size_t)n * sizeof(double), bytes);
+}
+
+template <typename T>
+void free_slot(Slot<T>& s) {
+  dfree(s.r); dfree(s.p); dfree(s.ap); dfree(s.isq); dfree(s.qk); dfree(s.s);
+  dfree(s.ion); dfree(s.sq64); dfree(s.work); dfree(s.part_init); dfree(s.part_rr);
+  dfree(s.part_delta); dfree(s.part_pap); dfree(s.part_mu); dfree(s.part_aux); dfree(s.hist);
+  dfree(s.st); dfree(s.phi);
+  dfree(s.sig64); dfree(s.src64); dfree(s.qk64);
+}
+
 template <typename T>
 void ensure_res(gps_plan* pl, bool need_ion, bool need_refine = false) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -362,28 +412,9 @@ void ensure_res(gps_plan* pl, bool need_ion, bool need_refine = false) {
   const long long n = pl->npts();
   const int nvg = vec_groups(n);
   const Geom& g = pl->g;
-  const int nxg = part_caps(g).x;
-  const int nzg = part_caps(g).z;
   if (!R.ready) {
-    Slot<T>& s = R.slot();
-    s = Slot<T>{};
-    const size_t nb = (size_t)n * sizeof(T);
-    dalloc(&s.r, nb, &R.bytes);
-    dalloc(&s.p, nb, &R.bytes);
-    dalloc(&s.ap, nb, &R.bytes);
-    dalloc(&s.isq, nb, &R.bytes);
-    dalloc(&s.qk, nb, &R.bytes);
-    if (pl->bc == GPS_BC_PERIODIC) dalloc(&s.s, nb, &R.bytes);
-    dalloc(&s.sq64, (size_t)n * sizeof(double), &R.bytes);
-    dalloc(&s.work, (size_t)g.nz * g.Ly * g.Kx * sizeof(cplx<T>), &R.bytes);
-    dalloc(&s.part_init, (size_t)4 * nvg * sizeof(double), &R.bytes);
-    dalloc(&s.part_rr, (size_t)nxg * sizeof(double), &R.bytes);
-    dalloc(&s.part_delta, (size_t)nzg * sizeof(double), &R.bytes);
-    dalloc(&s.part_pap, (size_t)nxg * sizeof(double), &R.bytes);
-    dalloc(&s.part_mu, (size_t)nxg * sizeof(double), &R.bytes);
-    dalloc(&s.part_aux, (size_t)kVec * nvg * sizeof(double), &R.bytes);
-    dalloc(&s.st, sizeof(SolveState), &R.bytes);
-    dalloc(&s.phi, (size_t)n * sizeof(double), &R.bytes);
+    R.slot() = Slot<T>{};
+    alloc_slot<T>(pl, R.slot(), &R.bytes);
     if (pl->bc == GPS_BC_PERIODIC) {
       dalloc(&R.lap64, (size_t)n * sizeof(double), &R.bytes);
       if (sizeof(T) != sizeof(double))
@@ -397,9 +428,11 @@ void ensure_res(gps_plan* pl, bool need_ion, bool need_refine = false) {
     R.ready = true;
   }
   if (R.hist_cap < pl->opt.maxit + 1) {
-    if (R.slot().hist) R.bytes -= (size_t)4 * R.hist_cap * sizeof(double);
-    dfree(R.slot().hist);
-    dalloc(&R.slot().hist, (size_t)4 * (pl->opt.maxit + 1) * sizeof(double), &R.bytes);
+    for (int i = 0; i < R.nslots; ++i) {
+      if (R.slot(i).hist) R.bytes -= (size_t)4 * R.hist_cap * sizeof(double);
+      dfree(R.slot(i).hist);
+      dalloc(&R.slot(i).hist, (size_t)4 * (pl->opt.maxit + 1) * sizeof(double), &R.bytes);
+    }
     R.hist_cap = pl->opt.maxit + 1;
   }
   bool changed = false;
@@ -420,22 +453,21 @@ void ensure_res(gps_plan* pl, bool need_ion, bool need_refine = false) {
   // the table is captured by value in graphs: rebuild them when it changes
   if (changed || R.slot().hist_cap != R.hist_cap || R.slot().maxit != pl->opt.maxit)
     drop_graphs(R);
-  R.slot().hist_cap = R.hist_cap;
-  R.slot().maxit = pl->opt.maxit;
+  for (int i = 0; i < R.nslots; ++i) {
+    R.slot(i).hist_cap = R.hist_cap;
+    R.slot(i).maxit = pl->opt.maxit;
+  }
 }
 
 template <typename T>
 void free_res(gps_plan* pl) {
   Res<T>& R = pl->res<T>();
   drop_graphs(R);
-  Slot<T>& s = R.slot();
-  dfree(s.r); dfree(s.p); dfree(s.ap); dfree(s.isq); dfree(s.qk); dfree(s.s);
-  dfree(s.ion); dfree(s.sq64); dfree(s.work); dfree(s.part_init); dfree(s.part_rr);
-  dfree(s.part_delta); dfree(s.part_pap); dfree(s.part_mu); dfree(s.part_aux); dfree(s.hist);
-  dfree(s.st); dfree(s.phi); dfree(R.lap64); dfree(R.work64q);
-  dfree(s.sig64); dfree(s.src64); dfree(s.qk64); dfree(R.u64); dfree(R.work64r);
+  for (int i = 0; i < R.nslots; ++i) free_slot(R.slot(i));
+  dfree(R.lap64); dfree(R.work64q); dfree(R.u64); dfree(R.work64r);
   if (R.h_state) (void)hipHostFree(R.h_state);
   if (R.h_parts) (void)hipHostFree(R.h_parts);
+  if (R.h_states) (void)hipHostFree(R.h_states);
   R = Res<T>{};
 }
 
@@ -606,10 +638,11 @@ void apply64(gps_plan* pl, const double* in, double* out, cplx<double>* work,
 
 // Spectral Laplacian of sqrt(eps) (periodic q) with the FP64 FFT passes.
 template <typename T>
-void spectral_laplacian(gps_plan* pl) {
+void spectral_laplacian(gps_plan* pl, int slot = 0) {
   Res<T>& R = pl->res<T>();
-  cplx<double>* work = R.work64q ? R.work64q : reinterpret_cast<cplx<double>*>(R.slot().work);
-  apply64(pl, R.slot().sq64, R.lap64, work, pl->lap64t);
+  cplx<double>* work =
+      R.work64q ? R.work64q : reinterpret_cast<cplx<double>*>(R.slot(slot).work);
+  apply64(pl, R.slot(slot).sq64, R.lap64, work, pl->lap64t);
 }
 
 // One true-residual refinement (final: only phi from the source s).
@@ -1023,7 +1056,259 @@ gps_status sc_impl(gps_plan* pl, const double* rho, const double* eps, double* p
   return status;
 }
 
+gps_status parse_electrolyte(const gps_plan* pl, const gps_ions* ions, Electrolyte* out) {
+  if (ions->nspecies < 1 || ions->nspecies > 4 || !ions->Z || !ions->c_bulk) return GPS_E_INVALID;
+  if (!(ions->kT > 0.0)) return GPS_E_INVALID;
+  if (!ions->gamma && !(ions->eps_bulk > 1.0)) return GPS_E_INVALID;
+  Electrolyte el;
+  el.present = true;
+  el.linear = ions->linear != 0;
+  IonParams& ip = el.ip;
+  ip.nspecies = ions->nspecies;
+  ip.kT = ions->kT;
+  ip.eta = ions->eta;
+  ip.eps_bulk = ions->eps_bulk;
+  ip.gamma = ions->gamma;
+  ip.steric = ions->c_max != nullptr;
+  double z2c = 0.0;
+  for (int i = 0; i < ions->nspecies; ++i) {
+    const double c = ions->c_bulk[i];
+    if (!(c > 0.0) || !std::isfinite(ions->Z[i])) return GPS_E_INVALID;
+    ip.Z[i] = ions->Z[i];
+    ip.c[i] = c;
+    ip.a[i] = 0.0;
+    if (ip.steric) {
+      const double cm = ions->c_max[i];
+      if (!(cm > c)) return GPS_E_INVALID;
+      ip.a[i] = c / cm;
+    }
+    z2c += ions->Z[i] * ions->Z[i] * c;
+  }
+  el.kappa_coef = kFourPi / ions->kT * z2c;
+  if (!el.linear) {
+    if (!(ions->eta > 0.0 && ions->eta <= 1.0) || ions->outer_maxit < 1) return GPS_E_INVALID;
+    if (pl->bc == GPS_BC_PERIODIC) return GPS_E_UNSUPPORTED;
+    el.outer_maxit = ions->outer_maxit;
+  }
+  *out = el;
+  return GPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// continuous batching (gps_batch.h)
+// ---------------------------------------------------------------------------
+template <typename T>
+void ensure_batch(gps_plan* pl, int K) {
+  ensure_res<T>(pl, false);
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  Res<T>& R = pl->res<T>();
+  if (R.nslots < K) {
+    for (int i = R.nslots; i < K; ++i) {
+      Slot<T>& sl = R.slot(i);
+      sl = Slot<T>{};
+      R.nslots = i + 1;            // free_res frees it even if an allocation below fails
+      alloc_slot<T>(pl, sl, &R.bytes);
+      dalloc(&sl.hist, (size_t)4 * R.hist_cap * sizeof(double), &R.bytes);
+      sl.hist_cap = R.hist_cap;
+      sl.maxit = pl->opt.maxit;
+    }
+    drop_graphs(R);                // the slot table changed
+  }
+  if (!R.h_states &&
+      hipHostMalloc(reinterpret_cast<void**>(&R.h_states), kArgSlots * sizeof(SolveState)) !=
+          hipSuccess) {
+    R.h_states = nullptr;
+    throw NoMem{};
+  }
+}
+
+template <typename T>
+void build_batch_graphs(gps_plan* pl, int K, int check_neutral, int chunk) {
+  Res<T>& R = pl->res<T>();
+  if (R.bgraphs[0] && R.bgraph_n == K && R.bgraph_neutral == check_neutral &&
+      R.bgraph_chunk == chunk)
+    return;
+  for (hipGraphExec_t& g : R.bgraphs) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  if (!pl->cap_stream) ck(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+  Batch b{};
+  b.n = K;
+  for (int i = 0; i < K; ++i) b.slot[i] = i;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  const int sizes[Res<T>::kGraphs] = {4 * chunk, 2 * chunk, chunk, 4, 2, 1};
+  for (int i = 0; i < Res<T>::kGraphs; ++i) {
+    R.bgraph_iters[i] = sizes[i];
+    ck(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < sizes[i]; ++j)
+      enqueue_iteration<T>(pl, R.tab, b, check_neutral, pl->cap_stream, j, 0);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (e != hipSuccess) throw DevError{e};
+    const hipError_t e2 = hipGraphInstantiate(&R.bgraphs[i], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) throw DevError{e2};
+  }
+  R.bgraph_n = K;
+  R.bgraph_neutral = check_neutral;
+  R.bgraph_chunk = chunk;
+}
+
+template <typename T>
+void batch_open_impl(gps_plan* pl, int K, int check_neutral) {
+  ensure_batch<T>(pl, K);
+  build_batch_graphs<T>(pl, K, check_neutral, pl->opt.check_every);
+  Res<T>& R = pl->res<T>();
+  Batch b{};
+  b.n = K;
+  for (int i = 0; i < K; ++i) b.slot[i] = i;
+  launch_idle_state<T>(R.tab, b, pl->stream());
+  ck(hipGetLastError());
+  ck(hipStreamSynchronize(pl->stream()));
+}
+
+template <typename T>
+void batch_join_impl(gps_plan* pl, int j, const BatchJoin& q, const Electrolyte& el) {
+  Res<T>& R = pl->res<T>();
+  hipStream_t s = pl->stream();
+  const long long n = pl->npts();
+  const int periodic = pl->bc == GPS_BC_PERIODIC;
+  Batch b{};
+  b.n = 1;
+  b.slot[0] = j;
+  launch_reset_state<T>(R.tab, b, 0.0, q.tol, 0, s);
+  launch_init<T>(R.tab, b, q.rho, q.eps, n, 0, s);
+  const double kcoef = el.present ? el.kappa_coef : 0.0;
+  const double* lap = nullptr;
+  if (periodic) {
+    spectral_laplacian<T>(pl, j);
+    lap = R.lap64;
+  }
+  launch_qfield<T>(R.tab, b, pl->g, pl->opt.fd_order / 2, lap, kcoef, q.eps, el.ip.gamma,
+                   el.ip.eps_bulk, s);
+  if (periodic && kcoef != 0.0) {
+    const Geom& g = pl->g;
+    launch_set_g0<T>(R.tab, b, n, 1.0 / ((double)g.Lx * g.Ly * g.Lz), s);
+  }
+  ck(hipGetLastError());
+}
+
+template <typename T>
+void batch_advance_impl(gps_plan* pl, int iters, BatchSlot* out) {
+  Res<T>& R = pl->res<T>();
+  hipStream_t s = pl->stream();
+  int left = iters;
+  for (int i = 0; i < Res<T>::kGraphs; ++i)
+    for (; left >= R.bgraph_iters[i]; left -= R.bgraph_iters[i])
+      ck(hipGraphLaunch(R.bgraphs[i], s));
+  const int K = R.bgraph_n;
+  for (int i = 0; i < K; ++i)
+    ck(hipMemcpyAsync(R.h_states + i, R.slot(i).st, sizeof(SolveState), hipMemcpyDeviceToHost,
+                      s));
+  ck(hipStreamSynchronize(s));
+  for (int i = 0; i < K; ++i) {
+    const SolveState& st = R.h_states[i];
+    out[i] = BatchSlot{st.done, st.status, st.iters, st.rr, st.thr2, st.rr0};
+  }
+}
+
+template <typename T>
+double batch_finish_impl(gps_plan* pl, int j, const double* rho, double* phi) {
+  Res<T>& R = pl->res<T>();
+  hipStream_t s = pl->stream();
+  const long long n = pl->npts();
+  Batch b{};
+  b.n = 1;
+  b.slot[0] = j;
+  ck(hipMemcpyAsync(phi, R.slot(j).phi, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_energy<T>(R.tab, b, rho, n, s);
+  ck(hipGetLastError());
+  const int groups = vec_groups(n);
+  ck(hipMemcpyAsync(R.h_parts, R.slot(j).part_aux, (size_t)groups * 2 * sizeof(double),
+                    hipMemcpyDeviceToHost, s));
+  ck(hipStreamSynchronize(s));
+  double e = 0.0;
+  for (int i = 0; i < groups; ++i) e += R.h_parts[(size_t)i * 2];
+  return 0.5 * pl->g.h * pl->g.h * pl->g.h * e;
+}
+
 }  // namespace
+
+
+// ===========================================================================
+// continuous batching entry points (internal API, gps_batch.h)
+// ===========================================================================
+namespace gps {
+
+template <typename F>
+static gps_status batch_guard(gps_plan* pl, F&& f) {
+  pl->info.device_error = 0;
+  try {
+    f();
+  } catch (const NoMem&) {
+    return GPS_E_NOMEM;
+  } catch (const DevError& d) {
+    pl->info.device_error = (int)d.e;
+    return GPS_E_DEVICE;
+  }
+  return GPS_OK;
+}
+
+static int batch_width(gps_plan* pl) {
+  return pl->opt.precision == GPS_PREC_MIXED ? pl->res<float>().bgraph_n
+                                             : pl->res<double>().bgraph_n;
+}
+
+gps_status batch_open(gps_plan* pl, int nslots, int check_neutral) {
+  if (!pl || nslots < 1 || nslots > kArgSlots) return GPS_E_INVALID;
+  if (pl->opt.refine_every > 0 || pl->opt.warm_start) return GPS_E_INVALID;
+  if (pl->timing_kind != GPS_K_NONE) return GPS_E_INVALID;
+  const bool mixed = pl->opt.precision == GPS_PREC_MIXED;
+  return batch_guard(pl, [&] {
+    if (mixed) batch_open_impl<float>(pl, nslots, check_neutral);
+    else batch_open_impl<double>(pl, nslots, check_neutral);
+  });
+}
+
+gps_status batch_join(gps_plan* pl, int slot, const BatchJoin& q) {
+  if (!pl || slot < 0 || slot >= batch_width(pl) || !q.rho || !q.eps || !(q.tol > 0.0) ||
+      !std::isfinite(q.tol))
+    return GPS_E_INVALID;
+  Electrolyte el;
+  if (q.ions) {
+    const gps_status st = parse_electrolyte(pl, q.ions, &el);
+    if (st != GPS_OK) return st;
+    if (!el.linear) return GPS_E_INVALID;
+  }
+  const bool mixed = pl->opt.precision == GPS_PREC_MIXED;
+  return batch_guard(pl, [&] {
+    if (mixed) batch_join_impl<float>(pl, slot, q, el);
+    else batch_join_impl<double>(pl, slot, q, el);
+  });
+}
+
+gps_status batch_advance(gps_plan* pl, int iters, BatchSlot* out) {
+  if (!pl || iters < 1 || !out || batch_width(pl) < 1) return GPS_E_INVALID;
+  const bool mixed = pl->opt.precision == GPS_PREC_MIXED;
+  return batch_guard(pl, [&] {
+    if (mixed) batch_advance_impl<float>(pl, iters, out);
+    else batch_advance_impl<double>(pl, iters, out);
+  });
+}
+
+gps_status batch_finish(gps_plan* pl, int slot, const double* rho, double* phi,
+                        double* energy) {
+  if (!pl || slot < 0 || slot >= batch_width(pl) || !rho || !phi || !energy)
+    return GPS_E_INVALID;
+  const bool mixed = pl->opt.precision == GPS_PREC_MIXED;
+  return batch_guard(pl, [&] {
+    *energy = mixed ? batch_finish_impl<float>(pl, slot, rho, phi)
+                    : batch_finish_impl<double>(pl, slot, rho, phi);
+  });
+}
+
+}  // namespace gps
 
 // ===========================================================================
 // C ABI
@@ -1349,41 +1634,12 @@ gps_status gps_solve_pb(gps_plan* pl, const double* rho, const double* eps, cons
                         double* phi, double tol) {
   if (!pl || !rho || !eps || !phi || !ions || !(tol > 0.0) || !std::isfinite(tol))
     return GPS_E_INVALID;
-  if (ions->nspecies < 1 || ions->nspecies > 4 || !ions->Z || !ions->c_bulk) return GPS_E_INVALID;
-  if (!(ions->kT > 0.0)) return GPS_E_INVALID;
-  if (!ions->gamma && !(ions->eps_bulk > 1.0)) return GPS_E_INVALID;
   Electrolyte el;
-  el.present = true;
-  el.linear = ions->linear != 0;
-  IonParams& ip = el.ip;
-  ip.nspecies = ions->nspecies;
-  ip.kT = ions->kT;
-  ip.eta = ions->eta;
-  ip.eps_bulk = ions->eps_bulk;
-  ip.gamma = ions->gamma;
-  ip.steric = ions->c_max != nullptr;
-  double z2c = 0.0;
-  for (int i = 0; i < ions->nspecies; ++i) {
-    const double c = ions->c_bulk[i];
-    if (!(c > 0.0) || !std::isfinite(ions->Z[i])) return GPS_E_INVALID;
-    ip.Z[i] = ions->Z[i];
-    ip.c[i] = c;
-    ip.a[i] = 0.0;
-    if (ip.steric) {
-      const double cm = ions->c_max[i];
-      if (!(cm > c)) return GPS_E_INVALID;
-      ip.a[i] = c / cm;
-    }
-    z2c += ions->Z[i] * ions->Z[i] * c;
-  }
-  el.kappa_coef = kFourPi / ions->kT * z2c;
-  if (!el.linear) {
-    if (!(ions->eta > 0.0 && ions->eta <= 1.0) || ions->outer_maxit < 1) return GPS_E_INVALID;
-    if (pl->bc == GPS_BC_PERIODIC) return GPS_E_UNSUPPORTED;
-    el.outer_maxit = ions->outer_maxit;
-  }
+  const gps_status st = parse_electrolyte(pl, ions, &el);
+  if (st != GPS_OK) return st;
   return run_guarded(pl, pl->opt.precision == GPS_PREC_MIXED, rho, eps, phi, tol, el);
 }
+
 
 gps_status gps_solve_vacuum(gps_plan* pl, const double* f, double* u) {
   if (!pl || !f || !u) return GPS_E_INVALID;

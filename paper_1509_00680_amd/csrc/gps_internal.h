@@ -128,7 +128,7 @@ template <typename T> struct Slot {
 // Problems per launch.  The slot table travels by value in the kernel
 // arguments (constant memory), so a work-group finds its buffers without a
 // dependent global load, and a captured graph stays valid across solves.
-constexpr int kArgSlots = 1;
+constexpr int kArgSlots = 8;
 template <typename T> struct SlotTable {
   Slot<T> s[kArgSlots];
 };

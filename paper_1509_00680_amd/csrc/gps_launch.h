@@ -147,6 +147,8 @@ struct IonParams {
 template <typename T> void launch_reset_state(const SlotTable<T>& tab, const Batch& b,
                                               double abs_thr, double rel_thr, int rel_from_b,
                                               hipStream_t s);
+template <typename T> void launch_idle_state(const SlotTable<T>& tab, const Batch& b,
+                                             hipStream_t s);
 template <typename T> void launch_set_g0(const SlotTable<T>& tab, const Batch& b, long long n,
                                          double norm, hipStream_t s);
 template <typename T> void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho,

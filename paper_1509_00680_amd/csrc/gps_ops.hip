@@ -263,6 +263,21 @@ void launch_reset_state(const SlotTable<T>& tab, const Batch& b, double abs_thr,
   GPS_LAUNCH((k_reset_state<T>), dim3(b.n), dim3(64), 0, s, tab, b, abs_thr, rel_thr, rel_from_b);
 }
 
+// A free batch slot: its state says done, so every pass returns at once.
+template <typename T>
+__global__ void k_idle_state(SlotTable<T> tab, Batch b) {
+  if (threadIdx.x == 0) {
+    SolveState z{};
+    z.done = 1;
+    *tab.s[b.slot[blockIdx.x]].st = z;
+  }
+}
+
+template <typename T>
+void launch_idle_state(const SlotTable<T>& tab, const Batch& b, hipStream_t s) {
+  GPS_LAUNCH((k_idle_state<T>), dim3(b.n), dim3(64), 0, s, tab, b);
+}
+
 // Periodic boundaries with ions: the k = 0 multiplier 4 pi / mean(kappa2/eps)
 // (divided by the transform size) from the partials of the q kernel (one per
 // q work-group).
@@ -720,6 +735,7 @@ void launch_refine(const SlotTable<T>& tab, const Batch& b, const double* rho, c
 #define GPS_INST(T)                                                                              \
   template void launch_reset_state<T>(const SlotTable<T>&, const Batch&, double, double, int,       \
                                       hipStream_t);                                              \
+  template void launch_idle_state<T>(const SlotTable<T>&, const Batch&, hipStream_t);             \
   template void launch_set_g0<T>(const SlotTable<T>&, const Batch&, long long, double,            \
                                  hipStream_t);                                                   \
   template void launch_init<T>(const SlotTable<T>&, const Batch&, const double*, const double*,       \

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -16,6 +17,7 @@
 #include <vector>
 
 #include "gps.h"
+#include "gps_batch.h"
 
 namespace {
 
@@ -25,6 +27,12 @@ using Clock = std::chrono::steady_clock;
 // often the oldest request may be passed over for one of them.
 constexpr int kLookahead = 16;
 constexpr int kMaxBypass = 8;
+// Grids of at most this many points are served in continuous batches (their
+// solves are bound by launch latency, so one launch covering several of them
+// costs about as much as one alone); larger grids get one solve per plan.
+constexpr long long kBatchMaxPoints = 64LL * 64 * 64;
+// PCG iterations per replayed graph in the serving plans.
+constexpr int kServeChunk = 8;
 
 struct PlanKey {
   int nx, ny, nz, bc;
@@ -38,6 +46,8 @@ struct Request {
   long long ticket = 0;
   gps_request req{};
   PlanKey key{};
+  bool batchable = false;  // small grid, generalized Poisson or linear PB
+  int neutral = 0;         // periodic generalized Poisson (input neutrality checked)
   bool has_ions = false;
   gps_ions ions{};
   double Z[4]{}, c[4]{}, cmax[4]{};
@@ -52,6 +62,8 @@ struct PlanEntry {
   PlanKey key{};
   size_t bytes = 0;
   bool busy = false;
+  int batch_neutral = -1;  // while a batch runs on it: its neutrality class
+  int free_slots = 0;      // while a batch runs on it: slots a request may join
   bool released = false;   // buffers released (tables kept)
   unsigned long long last_use = 0;
 };
@@ -85,6 +97,14 @@ struct gps_server {
   }
   void refund(size_t b) { stats.bytes_in_use -= std::min(b, stats.bytes_in_use); }
 
+  // A running batch that request R can join at its next poll.
+  bool joinable(const Request* R) const {
+    if (!R->batchable) return false;
+    for (const PlanEntry* e : plans)
+      if (e->busy && e->key == R->key && e->batch_neutral == R->neutral && e->free_slots > 0)
+        return true;
+    return false;
+  }
   PlanEntry* idle_plan(const PlanKey& k) {
     PlanEntry* best = nullptr;
     for (PlanEntry* e : plans)
@@ -139,12 +159,12 @@ struct gps_server {
 
 namespace {
 
-// Runs one admitted request on stream st with plan e (created here when
-// e->plan is null).  Called without the server lock.
-void run_request(gps_server* S, Request* R, PlanEntry* e, hipStream_t st) {
+// Creates plan e for `key` when e->plan is null and applies the server's
+// options with stream st.  Called without the server lock.
+gps_status prepare_plan(gps_server* S, PlanEntry* e, const PlanKey& key, hipStream_t st) {
   gps_status status = GPS_OK;
   if (!e->plan) {
-    status = gps_plan_create(R->key.nx, R->key.ny, R->key.nz, R->key.h, R->key.bc, &e->plan);
+    status = gps_plan_create(key.nx, key.ny, key.nz, key.h, key.bc, &e->plan);
     if (status != GPS_OK) e->plan = nullptr;
   }
   if (status == GPS_OK) {
@@ -153,9 +173,17 @@ void run_request(gps_server* S, Request* R, PlanEntry* e, hipStream_t st) {
     o.precision = S->opt.precision;
     o.fd_order = S->opt.fd_order;
     o.maxit = S->opt.maxit;
+    o.check_every = kServeChunk;
     o.stream = st;
     status = gps_plan_set_options(e->plan, &o);
   }
+  return status;
+}
+
+// Runs one admitted request on stream st with plan e (created here when
+// e->plan is null).  Called without the server lock.
+void run_request(gps_server* S, Request* R, PlanEntry* e, hipStream_t st) {
+  gps_status status = prepare_plan(S, e, R->key, st);
   if (status == GPS_OK) {
     const gps_request& q = R->req;
     status = R->has_ions ? gps_solve_pb(e->plan, q.rho, q.eps, &R->ions, q.phi, q.tol)
@@ -170,6 +198,147 @@ void run_request(gps_server* S, Request* R, PlanEntry* e, hipStream_t st) {
     R->res.device_error = info.device_error;
   }
   R->res.status = status;
+}
+
+// Marks request R finished (status and figures already in R->res).
+void publish(gps_server* S, Request* R) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  --S->in_flight;
+  R->res.done_ms = S->now_ms();
+  R->done = true;
+  ++S->stats.completed;
+  S->cv_done.notify_all();
+}
+
+// PCG iterations a slot is predicted to need before its stop decision:
+// log-linear extrapolation of ||r||^2 from its last two polls.
+int predict_iters(const gps::BatchSlot& b, double prev_rr, int prev_it) {
+  int n = 2 * kServeChunk;
+  if (prev_rr > 0.0 && b.rr > 0.0 && b.iterations > prev_it && b.rr < prev_rr) {
+    const double rate = std::log(b.rr / prev_rr) / double(b.iterations - prev_it);
+    const double left = std::log(b.thr2 / b.rr) / rate;
+    n = (int)std::ceil(std::max(1.0, left));
+  }
+  return std::max(1, std::min(n, 8 * kServeChunk));
+}
+
+// Continuous batch on plan e, started with the admitted request `first`:
+// requests of the same plan (and neutrality class) that wait in the queue
+// join free slots between graph replays, and each request is published as
+// soon as its slot's state says done.  Ends when no slot is busy and no such
+// request waits.  Called without the server lock; publishes every request it
+// took, `first` included.
+void run_batch(gps_server* S, Request* first, PlanEntry* e, hipStream_t st, int w) {
+  const int K = S->opt.batch_slots;
+  gps_status status = prepare_plan(S, e, first->key, st);
+  if (status == GPS_OK) status = gps::batch_open(e->plan, K, first->neutral);
+  if (status != GPS_OK) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      e->free_slots = 0;
+      e->batch_neutral = -1;
+    }
+    first->res.status = status;
+    publish(S, first);
+    return;
+  }
+  Request* slot[gps::kArgSlots] = {};
+  double prev_rr[gps::kArgSlots] = {};
+  int prev_it[gps::kArgSlots] = {};
+  gps::BatchSlot info[gps::kArgSlots] = {};
+  auto join = [&](int i, Request* R) {
+    const gps::BatchJoin q{R->req.rho, R->req.eps, R->has_ions ? &R->ions : nullptr,
+                           R->req.tol};
+    const gps_status js = gps::batch_join(e->plan, i, q);
+    if (js != GPS_OK) {
+      R->res.status = js;
+      publish(S, R);
+      return;
+    }
+    slot[i] = R;
+    prev_rr[i] = -1.0;
+    prev_it[i] = 0;
+    int busy = 0;
+    for (int k = 0; k < K; ++k) busy += slot[k] != nullptr;
+    std::lock_guard<std::mutex> lk(S->mu);
+    ++S->stats.batched;
+    S->stats.max_batch = std::max(S->stats.max_batch, busy);
+    info[i] = gps::BatchSlot{0, 0, 0, -1.0, 0.0, 0.0};
+  };
+  Request* incoming[gps::kArgSlots] = {};
+  incoming[0] = first;
+  for (;;) {
+    for (int i = 0; i < K; ++i)
+      if (incoming[i]) {
+        join(i, incoming[i]);
+        incoming[i] = nullptr;
+      }
+    int active = 0;
+    for (int i = 0; i < K; ++i) active += slot[i] != nullptr;
+    if (active > 0) {
+      int n = 8 * kServeChunk;
+      for (int i = 0; i < K; ++i)
+        if (slot[i]) n = std::min(n, predict_iters(info[i], prev_rr[i], prev_it[i]));
+      for (int i = 0; i < K; ++i)
+        if (slot[i]) {
+          prev_rr[i] = info[i].rr;
+          prev_it[i] = info[i].iterations;
+        }
+      status = gps::batch_advance(e->plan, n, info);
+      for (int i = 0; i < K; ++i) {
+        Request* R = slot[i];
+        if (!R || (status == GPS_OK && !info[i].done)) continue;
+        gps_status rs = status;
+        if (rs == GPS_OK) {
+          double energy = 0.0;
+          rs = gps::batch_finish(e->plan, i, R->req.rho, R->req.phi, &energy);
+          if (rs == GPS_OK) rs = (gps_status)info[i].status;
+          R->res.iterations = info[i].iterations;
+          R->res.energy = energy;
+          R->res.rel_residual = info[i].rr0 > 0.0 ? std::sqrt(info[i].rr / info[i].rr0) : 0.0;
+        }
+        gps_info pi{};
+        gps_last_info(e->plan, &pi);
+        R->res.device_error = pi.device_error;
+        R->res.status = rs;
+        slot[i] = nullptr;
+        publish(S, R);
+      }
+      if (status != GPS_OK) break;      // the plan's stream failed: end the batch
+    }
+    // waiting requests of this plan take the free slots
+    std::lock_guard<std::mutex> lk(S->mu);
+    int busy = 0;
+    for (int i = 0; i < K; ++i) {
+      if (slot[i]) {
+        ++busy;
+        continue;
+      }
+      auto it = std::find_if(S->queue.begin(), S->queue.end(), [&](const Request* q) {
+        return q->batchable && q->key == e->key && q->neutral == first->neutral;
+      });
+      if (it == S->queue.end()) continue;
+      Request* R = *it;
+      S->queue.erase(it);
+      R->res.start_ms = S->now_ms();
+      R->res.worker = w;
+      R->res.plan_reused = 1;
+      ++S->in_flight;
+      S->stats.max_in_flight = std::max(S->stats.max_in_flight, S->in_flight);
+      incoming[i] = R;
+      ++busy;
+    }
+    e->free_slots = K - busy;
+    e->batch_neutral = busy ? first->neutral : -1;
+    if (!busy) {
+      e->free_slots = 0;
+      break;
+    }
+  }
+  // a failed batch leaves its waiting joiners (none taken after the failure)
+  std::lock_guard<std::mutex> lk(S->mu);
+  e->free_slots = 0;
+  e->batch_neutral = -1;
 }
 
 void worker_main(gps_server* S, int w) {
@@ -187,19 +356,28 @@ void worker_main(gps_server* S, int w) {
         S->cv_work.wait(lk);
         continue;
       }
+      // requests that a running batch of their plan takes at its next poll
+      // are left to it
+      size_t head = 0;
+      while (head < S->queue.size() && S->joinable(S->queue[head])) ++head;
+      if (head == S->queue.size()) {
+        S->cv_work.wait(lk);
+        continue;
+      }
       // a waiting request whose plan is resident and idle goes first (no plan
       // build); the oldest request is passed over at most kMaxBypass times
-      size_t pick = 0;
-      R = S->queue.front();
+      R = S->queue[head];
       e = S->idle_plan(R->key);
       if (!e && R->bypassed < kMaxBypass) {
-        const size_t look = std::min(S->queue.size(), (size_t)kLookahead);
-        for (size_t i = 1; i < look && !e; ++i) {
+        const size_t look = std::min(S->queue.size(), head + (size_t)kLookahead);
+        size_t pick = head;
+        for (size_t i = head + 1; i < look && !e; ++i) {
+          if (S->joinable(S->queue[i])) continue;
           e = S->idle_plan(S->queue[i]->key);
           pick = i;
         }
         if (e) {
-          for (size_t i = 0; i < pick; ++i) ++S->queue[i]->bypassed;
+          for (size_t i = head; i < pick; ++i) ++S->queue[i]->bypassed;
           R = S->queue[pick];
         }
       }
@@ -221,7 +399,7 @@ void worker_main(gps_server* S, int w) {
           }
         }
         if (!S->in_flight) {   // nothing will free memory: fail the request
-          S->queue.pop_front();
+          S->queue.erase(std::find(S->queue.begin(), S->queue.end(), R));
           R->res.status = GPS_E_NOMEM;
           R->res.start_ms = R->res.done_ms = S->now_ms();
           R->res.worker = w;
@@ -241,12 +419,22 @@ void worker_main(gps_server* S, int w) {
     R->res.start_ms = S->now_ms();
     R->res.worker = w;
     R->res.plan_reused = fresh ? 0 : 1;
+    const bool batch = R->batchable;
+    if (batch) {
+      e->batch_neutral = R->neutral;
+      e->free_slots = S->opt.batch_slots - 1;
+    }
     lk.unlock();
 
-    run_request(S, R, e, st);
+    if (batch) {
+      run_batch(S, R, e, st, w);       // publishes R and every request that joined
+      R = nullptr;
+    } else {
+      run_request(S, R, e, st);
+    }
 
     lk.lock();
-    --S->in_flight;
+    if (R) --S->in_flight;
     S->refund(reserved);
     if (e->plan) {
       if (fresh) ++S->stats.plans_created;
@@ -262,10 +450,12 @@ void worker_main(gps_server* S, int w) {
       --S->stats.plans_resident;
       delete e;
     }
-    R->res.done_ms = S->now_ms();
-    R->done = true;
-    ++S->stats.completed;
-    S->cv_done.notify_all();
+    if (R) {
+      R->res.done_ms = S->now_ms();
+      R->done = true;
+      ++S->stats.completed;
+      S->cv_done.notify_all();
+    }
     S->cv_work.notify_all();
   }
 }
@@ -283,8 +473,11 @@ gps_status gps_server_create(const gps_server_options* opt, gps_server** out) {
   o.precision = GPS_PREC_MIXED;
   o.fd_order = 16;
   o.maxit = 1000;
+  o.batch_slots = 4;
   if (opt) o = *opt;
+  if (o.batch_slots == 0) o.batch_slots = 4;
   if (o.max_active < 1 || o.max_active > 16) return GPS_E_INVALID;
+  if (o.batch_slots < 1 || o.batch_slots > gps::kArgSlots) return GPS_E_INVALID;
   if (o.precision != GPS_PREC_FP64 && o.precision != GPS_PREC_MIXED) return GPS_E_INVALID;
   if (o.fd_order < 2 || o.fd_order > 16 || (o.fd_order & 1) || o.maxit < 1) return GPS_E_INVALID;
   gps_server* S = new (std::nothrow) gps_server();
@@ -344,6 +537,10 @@ gps_status gps_server_submit(gps_server* S, const gps_request* q, long long* tic
     delete R;
     return GPS_E_INVALID;
   }
+  R->neutral = q->bc == GPS_BC_PERIODIC && !R->has_ions;
+  R->batchable = S->opt.batch_slots > 1 && !nonlinear &&
+                 (long long)q->nx * q->ny * q->nz <= kBatchMaxPoints;
+  if (R->batchable) R->buffers *= (size_t)S->opt.batch_slots;   // a plan of batch_slots slots
   if (S->opt.budget_bytes && R->tables + R->buffers + R->transient > S->opt.budget_bytes) {
     delete R;
     return GPS_E_NOMEM;

@@ -68,7 +68,8 @@ class gps_info(ctypes.Structure):
 
 class gps_server_options(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int),
-                ("precision", ctypes.c_int), ("fd_order", ctypes.c_int), ("maxit", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("fd_order", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("batch_slots", ctypes.c_int)]
 
 
 class gps_request(ctypes.Structure):
@@ -95,7 +96,8 @@ class gps_server_stats(ctypes.Structure):
                 ("plans_resident", ctypes.c_int), ("plans_created", ctypes.c_int),
                 ("plans_evicted", ctypes.c_int), ("buffers_released", ctypes.c_int),
                 ("max_in_flight", ctypes.c_int),
-                ("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong)]
+                ("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong),
+                ("batched", ctypes.c_longlong), ("max_batch", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -368,9 +370,9 @@ class Server:
     been taken by poll() or wait()."""
 
     def __init__(self, budget_bytes=0, max_active=4, precision="mixed", fd_order=16,
-                 maxit=1000):
+                 maxit=1000, batch_slots=4):
         o = gps_server_options(int(budget_bytes), int(max_active), PRECISIONS[precision],
-                               int(fd_order), int(maxit))
+                               int(fd_order), int(maxit), int(batch_slots))
         h = ctypes.c_void_p()
         st = load().gps_server_create(ctypes.byref(o), ctypes.byref(h))
         if st != GPS_OK:

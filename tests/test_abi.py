@@ -87,8 +87,10 @@ def test_footprint_host_side(lib):
 def test_server_argument_checks_need_no_device(lib):
     t = ctypes.c_longlong()
     assert lib.gps_server_create(None, None) == gps.GPS_E_INVALID
-    bad = gps.gps_server_options(0, 0, 1, 16, 100)          # max_active 0
+    bad = gps.gps_server_options(0, 0, 1, 16, 100, 4)       # max_active 0
     h = ctypes.c_void_p()
+    assert lib.gps_server_create(ctypes.byref(bad), ctypes.byref(h)) == gps.GPS_E_INVALID
+    bad = gps.gps_server_options(0, 4, 1, 16, 100, 9)       # batch_slots beyond 8
     assert lib.gps_server_create(ctypes.byref(bad), ctypes.byref(h)) == gps.GPS_E_INVALID
     assert lib.gps_server_submit(None, None, ctypes.byref(t)) == gps.GPS_E_INVALID
     assert lib.gps_server_poll(None, 1, None) == gps.GPS_E_INVALID

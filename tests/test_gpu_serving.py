@@ -1,8 +1,10 @@
 """Serving (gps_server_*): a stream of independent requests of different grids,
 boundary conditions and kinds, admitted by device footprint and run
-concurrently on several streams.  Each result must equal, bit for bit, the
-same request solved alone on a fresh plan; one request is checked against the
-FP64 oracle; footprints agree with what plans actually hold."""
+concurrently on several streams, small grids in continuous batches (several
+problems per launch, joining and leaving between graph replays).  Each result
+must equal, bit for bit, the same request solved alone on a fresh plan;
+served requests, batched ones included, are checked against the FP64 oracle;
+footprints agree with what plans actually hold."""
 import numpy as np
 import pytest
 
@@ -63,30 +65,20 @@ def test_footprint_matches_plan_bytes(bc, precision):
         assert p.device_bytes() == tables + buffers_nl
 
 
-def test_mix_equals_alone_bitwise():
+def _mix(reqs, srv):
     torch = require_gpu()
-    reqs = _requests(18, seed=7)
-    fp = {(p.shape, p.bc): gps.plan_footprint(p.shape, p.bc, "mixed") for p, _, _ in reqs}
-    # every request fits alone, the distinct plans together do not
-    budget = (max(tb + b + t for tb, b, t in fp.values())
-              + sum(tb + b for tb, b, _ in fp.values()) // 4)
-    assert sum(tb + b for tb, b, _ in fp.values()) > budget
-    srv = gps.Server(budget_bytes=budget, max_active=4, precision="mixed")
     phis, tickets = [], []
-    print("serving mix of", len(reqs), "requests, budget", budget, flush=True)
     for prob, rho, eps in reqs:
         phi = torch.full(prob.shape, float("nan"), dtype=torch.float64, device="cuda")
         st, t = srv.submit(rho, eps, phi, prob.h, prob.bc, prob.tol, ions=prob.ions)
         assert st == gps.GPS_OK
         phis.append(phi)
         tickets.append(t)
-    results = [srv.wait(t) for t in tickets]
-    stats = srv.stats()
-    srv.close()
-    assert stats["completed"] == len(reqs)
-    assert stats["max_in_flight"] >= 2
-    assert stats["bytes_peak"] <= budget
-    assert stats["plans_evicted"] + stats["buffers_released"] >= 1   # the budget binds
+    return phis, [srv.wait(t) for t in tickets]
+
+
+def _check_alone(reqs, phis, results):
+    torch = require_gpu()
     for (prob, rho, eps), phi, res in zip(reqs, phis, results):
         print("alone", prob.name, flush=True)
         st, phi1, info = _solve_alone(prob, rho, eps)
@@ -95,6 +87,59 @@ def test_mix_equals_alone_bitwise():
         assert res["energy"] == info["energy"]
         assert torch.equal(phi, phi1), prob.name
         assert res["submit_ms"] <= res["start_ms"] <= res["done_ms"]
+
+
+@pytest.mark.parametrize("slots", [1, 4])
+def test_mix_equals_alone_bitwise(slots):
+    torch = require_gpu()
+    reqs = _requests(18, seed=7)
+    fp = {(p.shape, p.bc): gps.plan_footprint(p.shape, p.bc, "mixed") for p, _, _ in reqs}
+    fp = {k: (tb, b * slots, t) for k, (tb, b, t) in fp.items()}
+    # every request fits alone, the distinct plans together do not
+    budget = (max(tb + b + t for tb, b, t in fp.values())
+              + sum(tb + b for tb, b, _ in fp.values()) // 4)
+    assert sum(tb + b for tb, b, _ in fp.values()) > budget
+    srv = gps.Server(budget_bytes=budget, max_active=4, precision="mixed", batch_slots=slots)
+    print("serving mix of", len(reqs), "requests, budget", budget, "slots", slots, flush=True)
+    phis, results = _mix(reqs, srv)
+    stats = srv.stats()
+    srv.close()
+    assert stats["completed"] == len(reqs)
+    assert stats["max_in_flight"] >= 2
+    assert stats["bytes_peak"] <= budget
+    assert stats["plans_evicted"] + stats["buffers_released"] >= 1   # the budget binds
+    assert stats["batched"] == (len(reqs) if slots > 1 else 0)
+    _check_alone(reqs, phis, results)
+
+
+def test_batched_stream_joins_and_matches_oracle():
+    # many requests on few plans: batches fill, requests join freed slots, and
+    # each result equals its solve alone (bitwise) and the oracle (1e-5 Ha/e,
+    # relative energy 1e-6)
+    require_gpu()
+    prms, _ = W.serving_stream_params(24, seed=11, grids=(24,), box=BOX)
+    for i, prm in enumerate(prms):
+        prm["bc"] = ("free", "surface")[i % 2]
+        prm["kind"], prm["ions"] = "gpe", None
+    reqs = []
+    for prm in prms:
+        prob = W.request_problem(prm)
+        reqs.append((prob, dev(prob.rho), dev(prob.eps)))
+    srv = gps.Server(max_active=2, precision="mixed", batch_slots=4)
+    print("batched stream of", len(reqs), "requests", flush=True)
+    phis, results = _mix(reqs, srv)
+    stats = srv.stats()
+    srv.close()
+    assert stats["completed"] == stats["batched"] == len(reqs)
+    assert stats["max_batch"] == 4
+    assert stats["plans_created"] <= 2 * 2
+    _check_alone(reqs, phis, results)
+    for (prob, _, _), phi, res in list(zip(reqs, phis, results))[::6]:
+        print("oracle", prob.name, flush=True)
+        ref = pcg.pcg_solve(prob.rho, prob.eps, prob.h, prob.bc, tol=1e-10)
+        assert np.abs(host(phi) - ref.phi).max() <= 1e-5
+        e_ref = pcg.electrostatic_energy(prob.rho, ref.phi, prob.h)
+        assert abs(res["energy"] / e_ref - 1.0) <= 1e-6
 
 
 def test_served_request_matches_oracle():
@@ -124,7 +169,7 @@ def test_server_errors_and_polling():
     prob = W.molecule(16, 0.5, seed=1, n_atoms=4, ball=2.0)
     rho, eps = dev(prob.rho), dev(prob.eps)
     small = gps.plan_footprint((16, 16, 16), "free", "mixed")
-    srv = gps.Server(budget_bytes=sum(small), max_active=1, precision="mixed")
+    srv = gps.Server(budget_bytes=sum(small), max_active=1, precision="mixed", batch_slots=1)
     big = torch.zeros((32, 32, 32), dtype=torch.float64, device="cuda")
     st, _ = srv.submit(big, big, big.clone(), 0.5, "free", 1e-6)
     assert st == gps.GPS_E_NOMEM                    # can never fit the budget
