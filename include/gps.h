@@ -411,6 +411,15 @@ typedef struct {
                            else Poisson-Boltzmann (gps_solve_pb).  The struct
                            and its host arrays are copied at submission. */
   double tol;
+  unsigned long long eps_key;  /* 0, or the caller's identity of this request's
+                           dielectric: requests with the same nonzero key
+                           promise the same eps (bit for bit).  Warm-start cache:
+                           such a request (free, surface or wire boundaries,
+                           generalized Poisson or linear PB) runs on a plan that
+                           keeps the FP64 source of its final iterate, and when
+                           the last solve on that plan had the same key (and the
+                           same electrolyte) it starts from that iterate
+                           (gps_options.warm_start) instead of from phi = 0. */
 } gps_request;
 
 typedef struct {
@@ -425,6 +434,7 @@ typedef struct {
   int worker;            /* index of the worker that ran it */
   int plan_reused;       /* 1 if an existing resident plan served it */
   int device_error;      /* as gps_info.device_error */
+  int warm_started;      /* 1 if it started from a cached iterate (eps_key) */
 } gps_result;
 
 typedef struct {

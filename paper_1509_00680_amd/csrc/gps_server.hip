@@ -42,10 +42,31 @@ struct PlanKey {
   }
 };
 
+// The electrolyte a cached iterate was computed with (none for Poisson).
+struct IonSig {
+  bool present = false;
+  gps_ions ions{};
+  double Z[4]{}, c[4]{}, cmax[4]{};
+  bool operator==(const IonSig& o) const {
+    if (present != o.present) return false;
+    if (!present) return true;
+    const gps_ions& a = ions;
+    const gps_ions& b = o.ions;
+    if (a.nspecies != b.nspecies || a.kT != b.kT || a.gamma != b.gamma ||
+        a.eps_bulk != b.eps_bulk || a.linear != b.linear || (a.c_max == nullptr) != (b.c_max == nullptr))
+      return false;
+    for (int i = 0; i < a.nspecies; ++i)
+      if (Z[i] != o.Z[i] || c[i] != o.c[i] || cmax[i] != o.cmax[i]) return false;
+    return true;
+  }
+};
+
 struct Request {
   long long ticket = 0;
   gps_request req{};
   PlanKey key{};
+  bool tracked = false;    // eps_key given: warm-start cache
+  IonSig sig{};
   bool batchable = false;  // small grid, generalized Poisson or linear PB
   int neutral = 0;         // periodic generalized Poisson (input neutrality checked)
   bool has_ions = false;
@@ -64,6 +85,8 @@ struct PlanEntry {
   bool busy = false;
   int batch_neutral = -1;  // while a batch runs on it: its neutrality class
   int free_slots = 0;      // while a batch runs on it: slots a request may join
+  unsigned long long warm_key = 0;   // eps_key of the iterate the plan keeps (0: none)
+  IonSig warm_sig{};
   bool released = false;   // buffers released (tables kept)
   unsigned long long last_use = 0;
 };
@@ -105,10 +128,15 @@ struct gps_server {
         return true;
     return false;
   }
-  PlanEntry* idle_plan(const PlanKey& k) {
+  // An idle resident plan for R: one that keeps R's cached iterate first,
+  // else the most recently used.
+  PlanEntry* idle_plan(const Request* R) {
     PlanEntry* best = nullptr;
-    for (PlanEntry* e : plans)
-      if (!e->busy && e->key == k && (!best || e->last_use > best->last_use)) best = e;
+    for (PlanEntry* e : plans) {
+      if (e->busy || !(e->key == R->key)) continue;
+      if (R->tracked && e->warm_key == R->req.eps_key && e->warm_sig == R->sig) return e;
+      if (!best || e->last_use > best->last_use) best = e;
+    }
     return best;
   }
   // Releases the buffers of the least recently used idle plan that holds
@@ -119,6 +147,7 @@ struct gps_server {
       if (!e->busy && e != keep && !e->released && (!v || e->last_use < v->last_use)) v = e;
     if (!v) return false;
     gps_plan_release_buffers(v->plan);
+    v->warm_key = 0;                 // the cached iterate went with the buffers
     const size_t now = gps_plan_device_bytes(v->plan);
     refund(v->bytes - std::min(now, v->bytes));
     v->bytes = now;
@@ -161,7 +190,8 @@ namespace {
 
 // Creates plan e for `key` when e->plan is null and applies the server's
 // options with stream st.  Called without the server lock.
-gps_status prepare_plan(gps_server* S, PlanEntry* e, const PlanKey& key, hipStream_t st) {
+gps_status prepare_plan(gps_server* S, PlanEntry* e, const PlanKey& key, hipStream_t st,
+                        int warm_start = 0, int refine_every = 0) {
   gps_status status = GPS_OK;
   if (!e->plan) {
     status = gps_plan_create(key.nx, key.ny, key.nz, key.h, key.bc, &e->plan);
@@ -175,6 +205,8 @@ gps_status prepare_plan(gps_server* S, PlanEntry* e, const PlanKey& key, hipStre
     o.maxit = S->opt.maxit;
     o.check_every = kServeChunk;
     o.stream = st;
+    o.warm_start = warm_start;
+    o.refine_every = refine_every;
     status = gps_plan_set_options(e->plan, &o);
   }
   return status;
@@ -183,7 +215,14 @@ gps_status prepare_plan(gps_server* S, PlanEntry* e, const PlanKey& key, hipStre
 // Runs one admitted request on stream st with plan e (created here when
 // e->plan is null).  Called without the server lock.
 void run_request(gps_server* S, Request* R, PlanEntry* e, hipStream_t st) {
-  gps_status status = prepare_plan(S, e, R->key, st);
+  // warm-start cache: a tracked request keeps the FP64 source of its iterate
+  // (refine_every past maxit: tracked, never refined) and starts from the
+  // plan's cached iterate when it was computed for the same eps and ions
+  const bool warm = R->tracked && e->plan && e->warm_key == R->req.eps_key && e->warm_sig == R->sig;
+  gps_status status = prepare_plan(S, e, R->key, st, warm ? 1 : 0,
+                                   R->tracked && !warm ? S->opt.maxit + 1 : 0);
+  R->res.warm_started = warm ? 1 : 0;
+  e->warm_key = 0;
   if (status == GPS_OK) {
     const gps_request& q = R->req;
     status = R->has_ions ? gps_solve_pb(e->plan, q.rho, q.eps, &R->ions, q.phi, q.tol)
@@ -196,6 +235,10 @@ void run_request(gps_server* S, Request* R, PlanEntry* e, hipStream_t st) {
     R->res.rel_residual = info.rel_residual;
     R->res.energy = info.energy;
     R->res.device_error = info.device_error;
+    if (R->tracked && (status == GPS_OK || status == GPS_E_NOT_CONVERGED)) {
+      e->warm_key = R->req.eps_key;
+      e->warm_sig = R->sig;
+    }
   }
   R->res.status = status;
 }
@@ -230,6 +273,7 @@ int predict_iters(const gps::BatchSlot& b, double prev_rr, int prev_it) {
 // took, `first` included.
 void run_batch(gps_server* S, Request* first, PlanEntry* e, hipStream_t st, int w) {
   const int K = S->opt.batch_slots;
+  e->warm_key = 0;                   // slot 0's initialisation clears a cached iterate
   gps_status status = prepare_plan(S, e, first->key, st);
   if (status == GPS_OK) status = gps::batch_open(e->plan, K, first->neutral);
   if (status != GPS_OK) {
@@ -367,13 +411,13 @@ void worker_main(gps_server* S, int w) {
       // a waiting request whose plan is resident and idle goes first (no plan
       // build); the oldest request is passed over at most kMaxBypass times
       R = S->queue[head];
-      e = S->idle_plan(R->key);
+      e = S->idle_plan(R);
       if (!e && R->bypassed < kMaxBypass) {
         const size_t look = std::min(S->queue.size(), head + (size_t)kLookahead);
         size_t pick = head;
         for (size_t i = head + 1; i < look && !e; ++i) {
           if (S->joinable(S->queue[i])) continue;
-          e = S->idle_plan(S->queue[i]->key);
+          e = S->idle_plan(S->queue[i]);
           pick = i;
         }
         if (e) {
@@ -530,15 +574,23 @@ gps_status gps_server_submit(gps_server* S, const gps_request* q, long long* tic
     R->ions.c_bulk = R->c;
     R->ions.c_max = in.c_max ? R->cmax : nullptr;
     R->req.ions = &R->ions;
+    R->sig.present = true;
+    R->sig.ions = in;
+    for (int i = 0; i < in.nspecies; ++i) {
+      R->sig.Z[i] = R->Z[i];
+      R->sig.c[i] = R->c[i];
+      R->sig.cmax[i] = R->cmax[i];
+    }
   }
   const int nonlinear = R->has_ions && !R->ions.linear;
-  if (gps_plan_footprint(q->nx, q->ny, q->nz, q->bc, S->opt.precision, S->opt.maxit, nonlinear, 0,
-                         &R->tables, &R->buffers, &R->transient) != GPS_OK) {
+  R->tracked = q->eps_key != 0 && q->bc != GPS_BC_PERIODIC && !nonlinear;
+  if (gps_plan_footprint(q->nx, q->ny, q->nz, q->bc, S->opt.precision, S->opt.maxit, nonlinear,
+                         R->tracked ? 1 : 0, &R->tables, &R->buffers, &R->transient) != GPS_OK) {
     delete R;
     return GPS_E_INVALID;
   }
   R->neutral = q->bc == GPS_BC_PERIODIC && !R->has_ions;
-  R->batchable = S->opt.batch_slots > 1 && !nonlinear &&
+  R->batchable = S->opt.batch_slots > 1 && !nonlinear && !R->tracked &&
                  (long long)q->nx * q->ny * q->nz <= kBatchMaxPoints;
   if (R->batchable) R->buffers *= (size_t)S->opt.batch_slots;   // a plan of batch_slots slots
   if (S->opt.budget_bytes && R->tables + R->buffers + R->transient > S->opt.budget_bytes) {

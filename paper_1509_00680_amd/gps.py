@@ -76,7 +76,8 @@ class gps_request(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("h", ctypes.c_double), ("bc", ctypes.c_int), ("rho", ctypes.c_void_p),
                 ("eps", ctypes.c_void_p), ("phi", ctypes.c_void_p),
-                ("ions", ctypes.POINTER(gps_ions)), ("tol", ctypes.c_double)]
+                ("ions", ctypes.POINTER(gps_ions)), ("tol", ctypes.c_double),
+                ("eps_key", ctypes.c_ulonglong)]
 
 
 class gps_result(ctypes.Structure):
@@ -85,7 +86,7 @@ class gps_result(ctypes.Structure):
                 ("energy", ctypes.c_double), ("submit_ms", ctypes.c_double),
                 ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
                 ("worker", ctypes.c_int), ("plan_reused", ctypes.c_int),
-                ("device_error", ctypes.c_int)]
+                ("device_error", ctypes.c_int), ("warm_started", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -380,9 +381,10 @@ class Server:
         self.handle = h
         self._live = {}
 
-    def submit(self, rho, eps, phi, h, bc, tol, ions=None, gamma=None, sync=True):
+    def submit(self, rho, eps, phi, h, bc, tol, ions=None, gamma=None, sync=True, eps_key=0):
         """Queue one solve; returns (status, ticket).  With sync, the current
-        torch stream is synchronized first so that the inputs are complete."""
+        torch stream is synchronized first so that the inputs are complete.
+        eps_key: 0, or the caller's identity of eps (the warm-start cache)."""
         shape = tuple(rho.shape)
         for t in (rho, eps, phi):
             _check_field(t, shape)
@@ -392,7 +394,8 @@ class Server:
         nz, ny, nx = shape
         s = ions_struct(ions, gamma) if ions is not None else None
         req = gps_request(nx, ny, nz, float(h), BC_CODES[bc], _ptr(rho), _ptr(eps), _ptr(phi),
-                          ctypes.pointer(s) if s is not None else None, float(tol))
+                          ctypes.pointer(s) if s is not None else None, float(tol),
+                          int(eps_key))
         ticket = ctypes.c_longlong()
         st = load().gps_server_submit(self.handle, ctypes.byref(req), ctypes.byref(ticket))
         if st == GPS_OK:

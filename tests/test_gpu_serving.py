@@ -188,3 +188,34 @@ def test_server_errors_and_polling():
     stats = srv.stats()
     srv.close()
     assert stats["submitted"] == stats["completed"] == 2
+
+
+def test_warm_start_cache_by_eps_key():
+    # requests that name the same dielectric (eps_key) reuse the plan's cached
+    # iterate: a re-solve of the same rho needs a few iterations, a perturbed
+    # rho fewer than cold; results match the oracle; another key starts cold
+    require_gpu()
+    prob = W.molecule(32, 0.4, seed=5, n_atoms=8, ball=2.0)
+    other = W.molecule(32, 0.4, seed=6, n_atoms=8, ball=2.0)
+    rho, eps = dev(prob.rho), dev(prob.eps)
+    rho2 = dev(prob.rho + 0.02 * other.rho)
+    srv = gps.Server(max_active=1, precision="mixed")
+    out = []
+    print("warm-start cache", flush=True)
+    for r, key in ((rho, 7), (rho, 7), (rho2, 7), (rho, 8)):
+        phi = empty(prob.shape)
+        st, t = srv.submit(r, eps, phi, prob.h, "free", 1e-6, eps_key=key)
+        assert st == gps.GPS_OK
+        out.append((srv.wait(t), phi))
+    srv.close()
+    (c0, p0), (w1, p1), (w2, p2), (c3, p3) = out
+    assert [x["status"] for x, _ in out] == [gps.GPS_OK] * 4
+    assert [x["warm_started"] for x, _ in out] == [0, 1, 1, 0]
+    print("  iterations cold %d, same rho %d, perturbed %d, other key %d"
+          % (c0["iterations"], w1["iterations"], w2["iterations"], c3["iterations"]))
+    assert w1["iterations"] <= c0["iterations"] // 4
+    assert w2["iterations"] < c0["iterations"]
+    ref = pcg.pcg_solve(prob.rho, prob.eps, prob.h, "free", tol=1e-10)
+    ref2 = pcg.pcg_solve(prob.rho + 0.02 * other.rho, prob.eps, prob.h, "free", tol=1e-10)
+    for phi, r in ((p0, ref), (p1, ref), (p2, ref2), (p3, ref)):
+        assert np.abs(host(phi) - r.phi).max() <= 1e-5
