@@ -178,6 +178,19 @@ struct gps_plan {
   double* lap64t = nullptr;     // spectral Laplacian table (periodic)
   double* pol_lne = nullptr;    // ln eps scratch of gps_polarization_charge (n doubles)
   size_t pol_bytes = 0;
+  // Algorithm SC / PSD (gps_solve_sc): FP64 fields, partials, device state and
+  // captured iteration graphs of 8, 4, 2 and 1 steps
+  struct ScRes {
+    double *r = nullptr, *v = nullptr, *av = nullptr, *f = nullptr, *lne = nullptr;
+    double *eps = nullptr, *phi = nullptr, *part_op = nullptr, *part = nullptr;
+    ScState* st = nullptr;
+    ScState* h_st = nullptr;      // pinned
+    double* h_part = nullptr;     // pinned, 2 vec_groups(n)
+    size_t bytes = 0;
+    hipGraphExec_t graphs[4] = {};
+    int graph_iters[4] = {8, 4, 2, 1};
+    int graph_key = -1;           // paper_step + 2 (fd_order/2) + 64 (mixed)
+  } sc;
   float* lap32t = nullptr;
   Res<float> r32;
   Res<double> r64;
@@ -469,6 +482,19 @@ void free_res(gps_plan* pl) {
   if (R.h_parts) (void)hipHostFree(R.h_parts);
   if (R.h_states) (void)hipHostFree(R.h_states);
   R = Res<T>{};
+}
+
+void free_sc(gps_plan* pl) {
+  gps_plan::ScRes& S = pl->sc;
+  for (hipGraphExec_t& g : S.graphs) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  dfree(S.r); dfree(S.v); dfree(S.av); dfree(S.f); dfree(S.lne); dfree(S.eps); dfree(S.phi);
+  dfree(S.part_op); dfree(S.part); dfree(S.st);
+  if (S.h_st) (void)hipHostFree(S.h_st);
+  if (S.h_part) (void)hipHostFree(S.h_part);
+  S = gps_plan::ScRes{};
 }
 
 template <typename T>
@@ -937,122 +963,175 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
   return result;
 }
 
-// Algorithm SC and the PSD minimization (Sec. II.A), driven from the host:
-// per step one vacuum solve (the plan's passes, bulk precision) of f = r/eps,
-// the operator A v = -4 pi r + eps grad ln eps . grad v with the two inner
-// products of the step, and the update phi += alpha v, r -= alpha A v (FP64).
-// PSD takes Algorithm PCG's step with beta = 0, (v, r)/(v, A v), and stops on
-// ||r||_2; its weighted variant takes the step that minimizes ||r/eps||_2,
-// (A v, r/eps^2)/(A v, A v/eps^2), and stops on ||r/eps||_2.  SC is the same
-// recurrence with the fixed steps -1/(4 pi) (first) and -eta/(4 pi), and its
-// residual ||rho_iter_{k+1} - rho_iter_k|| equals (eta/4 pi) ||r/eps|| at the
-// current iterate.
-struct ScBuffers {
-  double *r = nullptr, *v = nullptr, *av = nullptr, *f = nullptr, *part = nullptr;
-  double* lne = nullptr;
-  ~ScBuffers() {
-    dfree(lne);
-    dfree(r);
-    dfree(v);
-    dfree(av);
-    dfree(f);
-    dfree(part);
+// Algorithm SC and the PSD minimization (Sec. II.A), on the device: per step
+// one vacuum solve (the plan's passes, bulk precision) of f = r/eps, the
+// operator A v = -4 pi r + eps grad ln eps . grad v with the two inner
+// products of the step, then the update phi += alpha v, r -= alpha A v (FP64)
+// with alpha taken on the device from the operator's partials, and a
+// one-work-group stop decision.  PSD takes Algorithm PCG's step with beta =
+// 0, (v, r)/(v, A v), and stops on ||r||_2; its weighted variant takes the
+// step that minimizes ||r/eps||_2, (A v, r/eps^2)/(A v, A v/eps^2), and stops
+// on ||r/eps||_2.  SC is the same recurrence with the fixed steps -1/(4 pi)
+// (first) and -eta/(4 pi), and its residual ||rho_iter_{k+1} - rho_iter_k||
+// equals (eta/4 pi) ||r/eps|| at the current iterate.  Steps are captured as
+// graphs of 8, 4, 2 and 1 steps over plan-owned buffers (eps and phi are
+// copied in and out), replayed for a predicted number of steps between polls
+// of the device state; steps after the stop decision return at once.
+template <typename T>
+void ensure_sc(gps_plan* pl) {
+  ensure_res<T>(pl, false);
+  gps_plan::ScRes& S = pl->sc;
+  if (S.st) return;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  const long long n = pl->npts();
+  const size_t nd = (size_t)n * sizeof(double);
+  const int gv = vec_groups(n), gp = polarization_groups(pl->g);
+  dalloc(&S.r, nd, &S.bytes);
+  dalloc(&S.v, nd, &S.bytes);
+  dalloc(&S.av, nd, &S.bytes);
+  dalloc(&S.f, nd, &S.bytes);
+  dalloc(&S.lne, nd, &S.bytes);
+  dalloc(&S.eps, nd, &S.bytes);
+  dalloc(&S.phi, nd, &S.bytes);
+  dalloc(&S.part_op, (size_t)2 * gp * sizeof(double), &S.bytes);
+  dalloc(&S.part, (size_t)2 * gv * sizeof(double), &S.bytes);
+  dalloc(&S.st, sizeof(ScState), &S.bytes);
+  if (hipHostMalloc(reinterpret_cast<void**>(&S.h_st), sizeof(ScState)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&S.h_part), (size_t)2 * gv * sizeof(double)) !=
+          hipSuccess)
+    throw NoMem{};
+}
+
+// u = G f with the bulk-precision passes, enqueued on stream s (no wait).
+template <typename T>
+void enqueue_vacuum(gps_plan* pl, const double* f, double* u, hipStream_t s) {
+  Res<T>& R = pl->res<T>();
+  const Geom& g = pl->g;
+  cplx<T>* work = R.slot().work;
+  XParams<T> xp = xparams<T>(pl, g.ny * g.nz, g.ny, g.nx, g.nx, (long long)g.Ly * g.Kx, g.nx);
+  xp.in_real = f;
+  xp.out_real = u;
+  xp.work = work;
+  launch_xfwd<T>(XF_REAL, xp, s);
+  SParams<T> yf = sparams<T>(pl, 1, g.Ly, g.ny, g.Ly, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
+                             g.Kx);
+  yf.work = work;
+  launch_strided<T>(ST_FWD, yf, s);
+  SParams<T> zc = sparams<T>(pl, 2, g.Lz, g.nz, g.nz, g.Ly * g.Kx, g.Ly * g.Kx, 0,
+                             (long long)g.Ly * g.Kx);
+  zc.work = work;
+  zc.table = pl->green<T>();
+  launch_strided<T>(ST_CONV, zc, s);
+  SParams<T> yi = sparams<T>(pl, 1, g.Ly, g.Ly, g.ny, g.nz * g.Kx, g.Kx, (long long)g.Ly * g.Kx,
+                             g.Kx);
+  yi.work = work;
+  launch_strided<T>(ST_INV, yi, s);
+  launch_xinv<T>(XI_REAL, xp, s);
+}
+
+template <typename T>
+void enqueue_sc_step(gps_plan* pl, int paper_step, hipStream_t s) {
+  gps_plan::ScRes& S = pl->sc;
+  const long long n = pl->npts();
+  enqueue_vacuum<T>(pl, S.f, S.v, s);
+  launch_sc_operator(pl->g, pl->opt.fd_order / 2, paper_step, S.r, S.eps, S.lne, S.v, S.av,
+                     S.part_op, &S.st->done, s);
+  launch_sc_advance(n, S.eps, S.phi, S.r, S.v, S.av, S.f, S.part_op, polarization_groups(pl->g),
+                    S.part, S.st, s);
+}
+
+template <typename T>
+void build_sc_graphs(gps_plan* pl, int paper_step) {
+  gps_plan::ScRes& S = pl->sc;
+  const int key = paper_step + 2 * (pl->opt.fd_order / 2) + 64 * (sizeof(T) == sizeof(float));
+  if (S.graphs[0] && S.graph_key == key) return;
+  for (hipGraphExec_t& g : S.graphs) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
   }
-};
+  if (!pl->cap_stream) ck(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  for (int i = 0; i < 4; ++i) {
+    ck(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < S.graph_iters[i]; ++j) enqueue_sc_step<T>(pl, paper_step, pl->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (e != hipSuccess) throw DevError{e};
+    const hipError_t e2 = hipGraphInstantiate(&S.graphs[i], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) throw DevError{e2};
+  }
+  S.graph_key = key;
+}
+
+ScState read_sc_state(gps_plan* pl) {
+  gps_plan::ScRes& S = pl->sc;
+  ck(hipMemcpyAsync(S.h_st, S.st, sizeof(ScState), hipMemcpyDeviceToHost, pl->stream()));
+  ck(hipStreamSynchronize(pl->stream()));
+  return *S.h_st;
+}
 
 template <typename T>
 gps_status sc_impl(gps_plan* pl, const double* rho, const double* eps, double* phi, double tol,
                    int method, double eta) {
+  ensure_sc<T>(pl);
+  gps_plan::ScRes& S = pl->sc;
   const long long n = pl->npts();
-  const Geom& g = pl->g;
   hipStream_t s = pl->stream();
-  ScBuffers b;
-  size_t bytes = 0;
-  dalloc(&b.r, (size_t)n * sizeof(double), &bytes);
-  dalloc(&b.v, (size_t)n * sizeof(double), &bytes);
-  dalloc(&b.av, (size_t)n * sizeof(double), &bytes);
-  dalloc(&b.f, (size_t)n * sizeof(double), &bytes);
-  dalloc(&b.lne, (size_t)n * sizeof(double), &bytes);
-  launch_log_field(n, eps, b.lne, s);
-  const int gv = vec_groups(n), gp = polarization_groups(g);
-  dalloc(&b.part, (size_t)2 * std::max(gv, gp) * sizeof(double), &bytes);
-  std::vector<double> hp((size_t)2 * std::max(gv, gp));
-  auto sums = [&](int groups, double* a0, double* a1) {
-    ck(hipMemcpyAsync(hp.data(), b.part, (size_t)2 * groups * sizeof(double),
-                      hipMemcpyDeviceToHost, s));
-    ck(hipStreamSynchronize(s));
-    double x = 0.0, y = 0.0;
-    for (int i = 0; i < groups; ++i) {
-      x += hp[(size_t)2 * i];
-      y += hp[(size_t)2 * i + 1];
-    }
-    *a0 = x;
-    *a1 = y;
-  };
-  launch_sc_step(0, n, 0.0, rho, eps, phi, b.r, nullptr, nullptr, b.f, b.part, s);
+  const int paper_step = method == GPS_METHOD_PSD;
+  build_sc_graphs<T>(pl, paper_step);
+  const int max_steps = method == GPS_METHOD_SC ? pl->opt.maxit + 1 : pl->opt.maxit;
+  launch_sc_begin(n, rho, eps, S.r, S.f, S.phi, S.eps, S.lne, S.part, S.st, method, eta, tol,
+                  max_steps, s);
   ck(hipGetLastError());
-  double rr0 = 0.0, ff = 0.0;
-  sums(gv, &rr0, &ff);
   std::memset(&pl->info, 0, sizeof(pl->info));
   pl->hist.clear();
-  if (!std::isfinite(rr0) || !std::isfinite(ff)) return GPS_E_NONFINITE;
-  const double thr_w = tol * std::sqrt(ff);                   // tol ||4 pi rho/eps||
-  const double thr_r = tol * std::sqrt(rr0);                  // tol ||4 pi rho||
-  const double thr_sc = tol * std::sqrt(rr0) / kFourPi;      // tol ||rho||
-  const int paper_step = method == GPS_METHOD_PSD;
-  gps_status status = GPS_E_NOT_CONVERGED;
-  int iters = 0;
-  double rr = rr0;
-  if (rr0 == 0.0) status = GPS_OK;
-  const int max_steps = method == GPS_METHOD_SC ? pl->opt.maxit + 1 : pl->opt.maxit;
-  for (int step = 0; status == GPS_E_NOT_CONVERGED && step < max_steps; ++step) {
-    vacuum_apply<T>(pl, b.f, b.v);
-    launch_sc_operator(g, pl->opt.fd_order / 2, paper_step, b.r, eps, b.lne, b.v, b.av,
-                       b.part, s);
-    ck(hipGetLastError());
-    double vr = 0.0, vav = 0.0;
-    sums(gp, &vr, &vav);
-    double alpha;
-    if (method == GPS_METHOD_SC) {
-      alpha = (step == 0 ? -1.0 : -eta) / kFourPi;
-    } else {
-      if (!std::isfinite(vr) || !std::isfinite(vav)) {
-        status = GPS_E_NONFINITE;
-        break;
-      }
-      if (paper_step ? vav == 0.0 : !(vav > 0.0)) {
-        status = GPS_E_BREAKDOWN;
-        break;
-      }
-      alpha = vr / vav;
+  ScState st = read_sc_state(pl);
+  // steps before the next poll: log-linear extrapolation of the stopping norm
+  auto norm2 = [&](const ScState& z) {
+    return method == GPS_METHOD_PSD ? z.rr : z.ff;
+  };
+  auto thr2 = [&](const ScState& z) {
+    if (method == GPS_METHOD_PSD) return z.thr_r * z.thr_r;
+    if (method == GPS_METHOD_PSD_WEIGHTED) return z.thr_w * z.thr_w;
+    const double t = z.thr_sc * kFourPi / z.eta;     // SC: on ||r/eps||
+    return t * t;
+  };
+  int n_next = 4;
+  double prev = -1.0;
+  int prev_step = 0;
+  while (!st.done && st.step <= max_steps + 8) {
+    int left = n_next;
+    for (int i = 0; i < 4; ++i)
+      for (; left >= S.graph_iters[i]; left -= S.graph_iters[i])
+        ck(hipGraphLaunch(S.graphs[i], s));
+    st = read_sc_state(pl);
+    if (st.done) break;
+    n_next = 4;
+    const double cur = norm2(st);
+    if (prev > 0.0 && cur > 0.0 && cur < prev && st.step > prev_step) {
+      const double rate = std::log(cur / prev) / double(st.step - prev_step);
+      const double need = std::log(thr2(st) / cur) / rate;
+      n_next = (int)std::ceil(std::max(1.0, need));
     }
-    const double ff_before = ff;
-    launch_sc_step(1, n, alpha, rho, eps, phi, b.r, b.v, b.av, b.f, b.part, s);
-    ck(hipGetLastError());
-    sums(gv, &rr, &ff);
-    if (!std::isfinite(rr) || !std::isfinite(ff)) {
-      status = GPS_E_NONFINITE;
-      break;
-    }
-    if (method == GPS_METHOD_SC) {
-      if (step >= 1) {
-        iters = step;
-        if (eta / kFourPi * std::sqrt(ff_before) <= thr_sc) status = GPS_OK;
-      }
-    } else {
-      iters = step + 1;
-      if (paper_step ? std::sqrt(rr) <= thr_r : std::sqrt(ff) <= thr_w) status = GPS_OK;
-    }
+    n_next = std::max(1, std::min(n_next, 32));
+    prev = cur;
+    prev_step = st.step;
   }
-  launch_sc_step(2, n, 0.0, rho, eps, phi, b.r, b.v, b.av, b.f, b.part, s);
+  launch_sc_energy(n, rho, S.phi, S.part, s);
   ck(hipGetLastError());
-  double e = 0.0, unused = 0.0;
-  sums(gv, &e, &unused);
+  ck(hipMemcpyAsync(phi, S.phi, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const int gv = vec_groups(n);
+  ck(hipMemcpyAsync(S.h_part, S.part, (size_t)2 * gv * sizeof(double), hipMemcpyDeviceToHost, s));
+  ck(hipStreamSynchronize(s));
+  double e = 0.0;
+  for (int i = 0; i < gv; ++i) e += S.h_part[(size_t)2 * i];
+  const gps_status status = st.done ? (gps_status)st.status : GPS_E_NOT_CONVERGED;
   pl->info.status = status;
-  pl->info.iterations = iters;
-  pl->info.rnorm0 = std::sqrt(rr0);
-  pl->info.rel_residual = rr0 > 0.0 ? std::sqrt(rr / rr0) : 0.0;
-  pl->info.energy = 0.5 * g.h * g.h * g.h * e;
+  pl->info.iterations = st.iters;
+  pl->info.rnorm0 = std::sqrt(st.rr0);
+  pl->info.rel_residual = st.rr0 > 0.0 ? std::sqrt(st.rr / st.rr0) : 0.0;
+  pl->info.energy = 0.5 * pl->g.h * pl->g.h * pl->g.h * e;
   return status;
 }
 
@@ -1348,6 +1427,7 @@ static void plan_release(gps_plan* pl) {
   dfree(pl->lap32t);
   dfree(pl->pol_lne);
   pl->pol_bytes = 0;
+  free_sc(pl);
 }
 
 gps_status gps_plan_create(int nx, int ny, int nz, double h, int bc, gps_plan** out) {
@@ -1443,7 +1523,7 @@ gps_status gps_plan_get_options(const gps_plan* pl, gps_options* o) {
 }
 
 size_t gps_plan_device_bytes(const gps_plan* pl) {
-  return pl ? pl->bytes + pl->r32.bytes + pl->r64.bytes + pl->pol_bytes : 0;
+  return pl ? pl->bytes + pl->r32.bytes + pl->r64.bytes + pl->pol_bytes + pl->sc.bytes : 0;
 }
 
 gps_status gps_plan_release_buffers(gps_plan* pl) {
@@ -1453,6 +1533,7 @@ gps_status gps_plan_release_buffers(gps_plan* pl) {
   free_res<double>(pl);
   dfree(pl->pol_lne);
   pl->pol_bytes = 0;
+  free_sc(pl);
   return GPS_OK;
 }
 

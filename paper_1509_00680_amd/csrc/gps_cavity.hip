@@ -9,6 +9,7 @@
 //    (Sec. II.A, Eq. PrePSD).
 #include <mutex>
 
+#include "gps.h"
 #include "gps_device.h"
 #include "gps_launch.h"
 
@@ -119,7 +120,7 @@ constexpr int kPThreads = kPTX * kPTY;
 // (A v, A v/eps^2) (the step that minimizes ||r/eps||_2).
 template <int M, bool AV>
 __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, int ntx, int nty,
-                                                            int paper,
+                                                            int paper, const int* stop,
                                                             const double* __restrict__ rho,
                                                             const double* __restrict__ eps,
                                                             const double* __restrict__ lne,
@@ -133,6 +134,7 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
   constexpr int HS = (NH + kPThreads - 1) / kPThreads;
   __shared__ double te[TH * TW];
   __shared__ double tp[TH * TW];
+  if (stop && *stop) return;
   const int tid = threadIdx.x;
   const int tx = tid % kPTX, ty = tid / kPTX;
   const int t = xcd_tile(blockIdx.x, gridDim.x);   // x fastest, then y, then z chunk
@@ -315,14 +317,14 @@ void launch_log_field(long long n, const double* eps, double* lne, hipStream_t s
 template <bool AV>
 static void launch_graddot(const Geom& g, int fd_half, int paper, const double* rho,
                            const double* eps, const double* lne, const double* phi, double* out,
-                           double* part, hipStream_t s) {
+                           double* part, const int* stop, hipStream_t s) {
   const int ntx = (g.nx + kPTX - 1) / kPTX, nty = (g.ny + kPTY - 1) / kPTY;
   const dim3 grid(polarization_groups(g));
   const FdFirst w = fd_first_weights(fd_half);
 #define GPS_PF(MM)                                                                        \
   case MM:                                                                                \
     GPS_LAUNCH((k_polarization<MM, AV>), grid, dim3(kPThreads), 0, s, g, w, ntx, nty,     \
-               paper, rho, eps, lne, phi, out, part);                                     \
+               paper, stop, rho, eps, lne, phi, out, part);                               \
     break;
   switch (fd_half) {
     GPS_PF(1) GPS_PF(2) GPS_PF(3) GPS_PF(4) GPS_PF(5) GPS_PF(6) GPS_PF(7) GPS_PF(8)
@@ -333,53 +335,41 @@ static void launch_graddot(const Geom& g, int fd_half, int paper, const double* 
 
 void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
                          const double* lne, const double* phi, double* out, hipStream_t s) {
-  launch_graddot<false>(g, fd_half, 0, rho, eps, lne, phi, out, nullptr, s);
+  launch_graddot<false>(g, fd_half, 0, rho, eps, lne, phi, out, nullptr, nullptr, s);
 }
 
 void launch_sc_operator(const Geom& g, int fd_half, int paper_step, const double* r,
                         const double* eps, const double* lne, const double* v, double* av,
-                        double* part, hipStream_t s) {
-  launch_graddot<true>(g, fd_half, paper_step, r, eps, lne, v, av, part, s);
+                        double* part, const int* stop, hipStream_t s) {
+  launch_graddot<true>(g, fd_half, paper_step, r, eps, lne, v, av, part, stop, s);
 }
 
 // ---------------------------------------------------------------------------
-// Pointwise steps of Algorithm SC / PSD (FP64), two partials per work-group.
-// init:   r = -4 pi rho, f = r/eps, phi = 0;       partials ||r||^2, ||r/eps||^2
-// update: phi += alpha v, r -= alpha A v, f = r/eps; partials ||r||^2, ||r/eps||^2
-// energy: partials sum rho phi, 0
+// Pointwise steps and decisions of Algorithm SC / PSD (FP64), device-resident:
+// the host only replays captured iterations and polls the state.
 // ---------------------------------------------------------------------------
-constexpr int kScInit = 0, kScUpdate = 1, kScEnergy = 2;
-
-__global__ __launch_bounds__(kThreads) void k_sc_step(int mode, long long n, double alpha,
-                                                      const double* __restrict__ rho,
-                                                      const double* __restrict__ eps,
-                                                      double* __restrict__ phi,
-                                                      double* __restrict__ r,
-                                                      const double* __restrict__ v,
-                                                      const double* __restrict__ av,
-                                                      double* __restrict__ f,
-                                                      double* __restrict__ part) {
+__global__ __launch_bounds__(kThreads) void k_sc_begin(long long n, const double* __restrict__ rho,
+                                                       const double* __restrict__ eps,
+                                                       double* __restrict__ r,
+                                                       double* __restrict__ f,
+                                                       double* __restrict__ phi,
+                                                       double* __restrict__ eps_c,
+                                                       double* __restrict__ lne,
+                                                       double* __restrict__ part) {
   const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
   double a0 = 0.0, a1 = 0.0;
 #pragma unroll
   for (int j = 0; j < kVec; ++j) {
     const long long i = base + (long long)j * kThreads;
     if (i < n) {
-      if (mode == kScEnergy) {
-        a0 += rho[i] * phi[i];
-        continue;
-      }
-      double ri;
-      if (mode == kScInit) {
-        ri = -4.0 * kPi * rho[i];
-        phi[i] = 0.0;
-      } else {
-        phi[i] += alpha * v[i];
-        ri = r[i] - alpha * av[i];
-      }
+      const double ev = eps[i];
+      const double ri = -4.0 * kPi * rho[i];
+      const double fi = ri / ev;
       r[i] = ri;
-      const double fi = ri / eps[i];
       f[i] = fi;
+      phi[i] = 0.0;
+      eps_c[i] = ev;
+      lne[i] = log(ev);
       a0 += ri * ri;
       a1 += fi * fi;
     }
@@ -392,11 +382,159 @@ __global__ __launch_bounds__(kThreads) void k_sc_step(int mode, long long n, dou
   }
 }
 
-void launch_sc_step(int mode, long long n, double alpha, const double* rho, const double* eps,
-                    double* phi, double* r, const double* v, const double* av, double* f,
-                    double* part, hipStream_t s) {
-  GPS_LAUNCH(k_sc_step, dim3(vec_groups(n)), dim3(kThreads), 0, s, mode, n, alpha, rho, eps,
-             phi, r, v, av, f, part);
+__global__ __launch_bounds__(kThreads) void k_sc_start(const double* __restrict__ part, int nparts,
+                                                       ScState* st, int method, double eta,
+                                                       double tol, int max_steps) {
+  const double rr0 = sum_partials(part, nparts, 2);
+  const double ff0 = sum_partials(part + 1, nparts, 2);
+  if (threadIdx.x == 0) {
+    ScState z{};
+    z.method = method;
+    z.eta = eta;
+    z.max_steps = max_steps;
+    z.status = GPS_E_NOT_CONVERGED;
+    z.rr0 = rr0;
+    z.rr = rr0;
+    z.ff = ff0;
+    z.ff_prev = ff0;
+    z.thr_w = tol * sqrt(ff0);
+    z.thr_r = tol * sqrt(rr0);
+    z.thr_sc = tol * sqrt(rr0) / kFourPi;
+    if (!isfinite(rr0) || !isfinite(ff0)) {
+      z.status = GPS_E_NONFINITE;
+      z.done = 1;
+    } else if (rr0 == 0.0 || max_steps < 1) {
+      z.status = rr0 == 0.0 ? GPS_OK : GPS_E_NOT_CONVERGED;
+      z.done = 1;
+    }
+    *st = z;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sc_update(long long n, const double* __restrict__ eps,
+                                                        double* __restrict__ phi,
+                                                        double* __restrict__ r,
+                                                        const double* __restrict__ v,
+                                                        const double* __restrict__ av,
+                                                        double* __restrict__ f,
+                                                        const double* __restrict__ op_part,
+                                                        int n_op, double* __restrict__ part,
+                                                        ScState* st) {
+  if (st->done) return;
+  // alpha, identical in every work-group (fixed-order sums of the operator's partials)
+  const double vr = sum_partials(op_part, n_op, 2);
+  const double vav = sum_partials(op_part + 1, n_op, 2);
+  const int method = st->method;
+  double alpha;
+  int fail = 0;
+  if (method == GPS_METHOD_SC) {
+    alpha = (st->step == 0 ? -1.0 : -st->eta) / kFourPi;
+  } else {
+    if (!isfinite(vr) || !isfinite(vav)) fail = GPS_E_NONFINITE;
+    else if (method == GPS_METHOD_PSD ? vav == 0.0 : !(vav > 0.0)) fail = GPS_E_BREAKDOWN;
+    alpha = fail ? 0.0 : vr / vav;
+  }
+  if (fail) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->status = fail;   // the decision ends the solve
+    return;
+  }
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) {
+      phi[i] += alpha * v[i];
+      const double ri = r[i] - alpha * av[i];
+      const double fi = ri / eps[i];
+      r[i] = ri;
+      f[i] = fi;
+      a0 += ri * ri;
+      a1 += fi * fi;
+    }
+  }
+  a0 = block_sum(a0);
+  a1 = block_sum(a1);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a0;
+    part[2 * blockIdx.x + 1] = a1;
+    if (blockIdx.x == 0) st->alpha = alpha;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sc_decide(const double* __restrict__ part,
+                                                        int nparts, ScState* st) {
+  if (st->done) return;
+  const double rr = sum_partials(part, nparts, 2);
+  const double ff = sum_partials(part + 1, nparts, 2);
+  if (threadIdx.x != 0) return;
+  ScState z = *st;
+  if (z.status != GPS_E_NOT_CONVERGED) {          // breakdown or non-finite step
+    z.done = 1;
+    *st = z;
+    return;
+  }
+  const int step = z.step;
+  z.ff_prev = z.ff;
+  z.rr = rr;
+  z.ff = ff;
+  z.step = step + 1;
+  if (!isfinite(rr) || !isfinite(ff)) {
+    z.status = GPS_E_NONFINITE;
+  } else if (z.method == GPS_METHOD_SC) {
+    // SC's residual ||rho_iter_{k+1} - rho_iter_k|| = (eta/4 pi) ||r_k/eps|| of
+    // the iterate before this step; the first step is the unmixed phi_0
+    if (step >= 1) {
+      z.iters = step;
+      if (z.eta / kFourPi * sqrt(z.ff_prev) <= z.thr_sc) z.status = GPS_OK;
+    }
+  } else {
+    z.iters = step + 1;
+    if (z.method == GPS_METHOD_PSD ? sqrt(rr) <= z.thr_r : sqrt(ff) <= z.thr_w) z.status = GPS_OK;
+  }
+  if (z.status != GPS_E_NOT_CONVERGED || z.step >= z.max_steps) z.done = 1;
+  *st = z;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sc_energy(long long n, const double* __restrict__ rho,
+                                                        const double* __restrict__ phi,
+                                                        double* __restrict__ part) {
+  const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
+  double a0 = 0.0;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const long long i = base + (long long)j * kThreads;
+    if (i < n) a0 += rho[i] * phi[i];
+  }
+  a0 = block_sum(a0);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a0;
+    part[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+void launch_sc_begin(long long n, const double* rho, const double* eps, double* r, double* f,
+                     double* phi, double* eps_c, double* lne, double* part, ScState* st,
+                     int method, double eta, double tol, int max_steps, hipStream_t s) {
+  const int gv = vec_groups(n);
+  GPS_LAUNCH(k_sc_begin, dim3(gv), dim3(kThreads), 0, s, n, rho, eps, r, f, phi, eps_c, lne,
+             part);
+  GPS_LAUNCH(k_sc_start, dim3(1), dim3(kThreads), 0, s, part, gv, st, method, eta, tol,
+             max_steps);
+}
+
+void launch_sc_advance(long long n, const double* eps, double* phi, double* r, const double* v,
+                       const double* av, double* f, const double* op_part, int n_op,
+                       double* part, ScState* st, hipStream_t s) {
+  const int gv = vec_groups(n);
+  GPS_LAUNCH(k_sc_update, dim3(gv), dim3(kThreads), 0, s, n, eps, phi, r, v, av, f, op_part,
+             n_op, part, st);
+  GPS_LAUNCH(k_sc_decide, dim3(1), dim3(kThreads), 0, s, part, gv, st);
+}
+
+void launch_sc_energy(long long n, const double* rho, const double* phi, double* part,
+                      hipStream_t s) {
+  GPS_LAUNCH(k_sc_energy, dim3(vec_groups(n)), dim3(kThreads), 0, s, n, rho, phi, part);
 }
 
 }  // namespace gps

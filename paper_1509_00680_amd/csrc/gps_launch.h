@@ -181,11 +181,45 @@ hipError_t noalloc_scratch(int device, double** out);
 void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
                          const double* lne, const double* phi, double* out, hipStream_t s);
 int polarization_groups(const Geom& g);
+// Device state of a solve by Algorithm SC or PSD (gps_solve_sc).
+struct ScState {
+  int done;          // 1 once the solve has stopped
+  int status;        // gps_status (GPS_E_NOT_CONVERGED while running)
+  int step;          // steps taken
+  int iters;         // iterations reported (SC: steps after the first)
+  int method;        // gps_sc_method
+  int max_steps;
+  double eta;        // SC mixing
+  double thr_w;      // tol ||4 pi rho / eps||
+  double thr_r;      // tol ||4 pi rho||
+  double thr_sc;     // tol ||rho||
+  double rr0;        // ||4 pi rho||^2
+  double rr;         // ||r||^2 after the last step
+  double ff;         // ||r/eps||^2 after the last step
+  double ff_prev;    // ||r/eps||^2 before the last step
+  double alpha;      // step of the last iteration
+};
+// SC/PSD operator A v = -4 pi r + eps grad ln eps . grad v and two partials
+// per work-group (paper_step: (v, r) and (v, A v); else (A v, r/eps^2) and
+// (A v, A v/eps^2)); returns at once when *stop != 0 (stop may be null).
 void launch_sc_operator(const Geom& g, int fd_half, int paper_step, const double* r,
                         const double* eps, const double* lne, const double* v, double* av,
-                        double* part, hipStream_t s);
-void launch_sc_step(int mode, long long n, double alpha, const double* rho, const double* eps,
-                    double* phi, double* r, const double* v, const double* av, double* f,
-                    double* part, hipStream_t s);
+                        double* part, const int* stop, hipStream_t s);
+// Start of an SC/PSD solve: r = -4 pi rho, f = r/eps, phi = 0, eps_c = eps,
+// lne = ln eps, and the state (thresholds; done at once for rho = 0 or
+// non-finite input).  part: 2 vec_groups(n) doubles of scratch.
+void launch_sc_begin(long long n, const double* rho, const double* eps, double* r, double* f,
+                     double* phi, double* eps_c, double* lne, double* part, ScState* st,
+                     int method, double eta, double tol, int max_steps, hipStream_t s);
+// One SC/PSD step after the operator: every work-group takes alpha from the
+// operator's n_op partial pairs, then phi += alpha v, r -= alpha A v, f =
+// r/eps with the ||r||^2, ||f||^2 partials; a one-work-group kernel then takes
+// the stop decision.  Both return at once once the state says done.
+void launch_sc_advance(long long n, const double* eps, double* phi, double* r, const double* v,
+                       const double* av, double* f, const double* op_part, int n_op,
+                       double* part, ScState* st, hipStream_t s);
+// (1/2) h^3 sum rho phi partials (one per work-group, stride 2) into part.
+void launch_sc_energy(long long n, const double* rho, const double* phi, double* part,
+                      hipStream_t s);
 
 }  // namespace gps
