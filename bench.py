@@ -47,7 +47,8 @@ def parse():
                     help="timed solves (default: 10 for charged_solute, 20 otherwise)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="charged_solute",
-                    choices=("charged_solute", "molecule", "slab", "serving", "rigid", "sc"),
+                    choices=("charged_solute", "molecule", "slab", "serving", "rigid", "sc",
+                             "micro"),
                     help="charged_solute: nonlinear PB at 160^3 (default); molecule: "
                          "generalized Poisson at 96^3; slab: linear PB, surface BC, "
                          "128x128x192; serving: a request stream through the serving loop")
@@ -624,6 +625,77 @@ def pcg_line(args, torch, gps, W, prob, name, steps, warmup, cpu=True, pass_time
     return out
 
 
+def micro_bench(args, torch):
+    """Measurements behind the FFT design (libgps_micro.so): the FP32 issue
+    rate of the 16-point register codelet, the same DFT as a dense real GEMM on
+    the matrix cores (checked against numpy's FFT, then timed with register
+    operands only: an upper bound for any MFMA form of the stage), and the
+    floor of a 5-read / 2-write pointwise pass at 96^3 and 160^3 points."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1509_00680_amd", "libgps_micro.so"))
+    vp, ci, cl = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong
+    lib.micro_codelet16.argtypes = [ci, ci, vp, vp]
+    lib.micro_mfma_dft16_check.argtypes = [vp, vp, vp]
+    lib.micro_mfma_dft16_rate.argtypes = [ci, ci, vp, vp]
+    lib.micro_stream5.argtypes = [cl, vp, vp, vp, vp, vp, vp, vp, vp]
+    stream = vp(torch.cuda.current_stream().cuda_stream)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    # the GEMM form computes the DFT
+    rng = np.random.default_rng(0)
+    xh = rng.normal(size=(32, 16)).astype(np.float32)
+    x = torch.from_numpy(xh).cuda()
+    y = torch.empty_like(x)
+    if lib.micro_mfma_dft16_check(vp(x.data_ptr()), vp(y.data_ptr()), stream) != 0:
+        raise RuntimeError("micro_mfma_dft16_check launch failed")
+    z = np.fft.fft(xh[:16].astype(np.float64) + 1j * xh[16:].astype(np.float64), axis=0)
+    ref = np.concatenate([z.real, z.imag])
+    mfma_err = float(np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max())
+
+    blocks, reps = 4096, 400
+    out = torch.empty(blocks * 256, device="cuda")
+    t_cod = timed(lambda: lib.micro_codelet16(blocks, reps, vp(out.data_ptr()), stream), 5)
+    t_mf = timed(lambda: lib.micro_mfma_dft16_rate(blocks, reps, vp(out.data_ptr()), stream), 5)
+    lanes = blocks * 256
+    cod_rate = lanes * reps / t_cod                  # pencils/s, one pencil per lane
+    waves = lanes // 64
+    mf_inst = waves * 16 * reps / t_mf               # MFMA instructions/s
+    mf_rate = mf_inst                                # 16 MFMAs per 16 pencils
+
+    streams = {}
+    for n in (96, 160):
+        npts = n ** 3
+        bufs = [torch.rand(npts, device="cuda") for _ in range(7)]
+        t = timed(lambda: lib.micro_stream5(npts, *[vp(b.data_ptr()) for b in bufs], stream), 20)
+        streams["%d^3" % n] = {"bytes": 28 * npts, "us": t * 1e6, "gbs": 28 * npts / t / 1e9}
+    return {
+        "metric": "FFT design micro-benchmarks: 16-point DFT per second as register codelet "
+                  "and as MFMA GEMM; pointwise-pass floor",
+        "value": cod_rate / 1e9, "unit": "G 16-point DFTs/s (register codelet)",
+        "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": t_cod * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "micro_fft_design", "codelet_lanes": lanes, "reps": reps,
+                   "mfma": "v_mfma_f32_16x16x4_f32, 16 per 16 pencils (32x32 real DFT matrix)"},
+        "codelet_dft16_per_s": cod_rate,
+        "mfma_dft16_per_s_upper_bound": mf_rate,
+        "mfma_tflops": mf_inst * 2048 / 1e12,
+        "codelet_over_mfma": cod_rate / mf_rate,
+        "mfma_dft_check_max_rel_err": mfma_err,
+        "pointwise_5r2w": streams,
+    }
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -640,6 +712,9 @@ def main():
     from paper_1509_00680_amd import gps, workloads as W
     if args.workload == "serving":
         print(json.dumps(serving_bench(args, torch, gps, W)))
+        return
+    if args.workload == "micro":
+        print(json.dumps(micro_bench(args, torch)))
         return
     if args.workload == "rigid":
         args.n = args.n or 96

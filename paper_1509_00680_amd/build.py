@@ -3,7 +3,8 @@
     python -m paper_1509_00680_amd.build        # or build() from Python
 
 Every source is compiled on each call; the objects go to _build/ beside the
-sources and the shared library to paper_1509_00680_amd/libgps.so.
+sources, the library to paper_1509_00680_amd/libgps.so and the benchmark's
+measurement kernels to paper_1509_00680_amd/libgps_micro.so.
 """
 import os
 import subprocess
@@ -17,6 +18,9 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgps.so")
 SOURCES = ["gps_fft.hip", "gps_fft_fast.hip", "gps_ops.hip", "gps_cavity.hip", "gps_api.hip",
            "gps_server.hip"]
+# measurement kernels of the benchmark (a library of their own, outside the C ABI)
+MICRO_SOURCE = "gps_micro.hip"
+MICRO_LIB = os.path.join(PKG, "libgps_micro.so")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -38,18 +42,23 @@ def _compile(src):
     return out
 
 
-def build(verbose=False):
-    os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose=False):
+    os.makedirs(OBJ, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        objs = list(ex.map(_compile, SOURCES + [MICRO_SOURCE]))
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], MICRO_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", MICRO_LIB)
     return LIB
 
 
