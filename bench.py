@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (10 times) and exit: the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--source-digest", action="store_true",
+                    help="only print the digest of the FFT passes' sources and exit")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = 10 if args.workload == "charged_solute" else 20
@@ -119,23 +121,31 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_mib": mib, "copies": 10}))
 
 
+# the translation unit of the FFT passes (the kernels whose counters are
+# recorded): their source file and every header it includes
+FFT_PASS_SOURCES = ("gps_fft_fast.hip", "gps_fft_reg.h", "gps_iter.h", "gps_launch.h",
+                    "gps_device.h", "gps_internal.h")
+
+
 def kernel_source_digest():
-    """sha256 over the HIP sources (names and contents, sorted by name)."""
+    """sha256 over the FFT passes' sources (names and contents, in name order)
+    and the public header they include."""
     import hashlib
     d = os.path.join(ROOT, "paper_1509_00680_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in sorted(FFT_PASS_SOURCES):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "gps.h"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic(name):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE passes
-    (scaled by a plain copy's counts), or None once the kernel sources have
-    changed since the counters were taken."""
+    (scaled by a plain copy's counts), or None once the FFT passes' sources
+    have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -698,6 +708,9 @@ def micro_bench(args, torch):
 
 def main():
     args = parse()
+    if args.source_digest:
+        print(kernel_source_digest())
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
