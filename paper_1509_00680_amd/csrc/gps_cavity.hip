@@ -101,7 +101,7 @@ void launch_rigid_cavity(const Geom& g, const double* atoms, int natoms, double 
 //   c_m = (-1)^(m+1) (M!)^2 / (m (M - m)! (M + m)!),
 // with the ghosts of the q stencil (edge-replicated on free axes, wrapped on
 // periodic ones).  2.5D like the q stencil: a kPTX x kPTY column tile marches
-// along z over kPZC planes; x and y neighbours of ln eps and phi come from
+// along z over zlen planes (stencil_zlen); x and y neighbours of ln eps and phi come from
 // two LDS tiles with an M-wide halo, z neighbours from two register queues of
 // 2M+1 planes, and the next plane's loads are in flight while the current
 // one is differenced.  ln eps comes precomputed (k_log_field), and eps itself
@@ -109,7 +109,7 @@ void launch_rigid_cavity(const Geom& g, const double* atoms, int natoms, double 
 // ---------------------------------------------------------------------------
 struct FdFirst { double c[9]; };
 
-constexpr int kPTX = 32, kPTY = 8, kPZC = 8;
+constexpr int kPTX = 32, kPTY = 8;
 constexpr int kPThreads = kPTX * kPTY;
 
 // AV = false: out = rho_pol from (rho, eps, phi).  AV = true (PSD / SC
@@ -120,7 +120,7 @@ constexpr int kPThreads = kPTX * kPTY;
 // (A v, A v/eps^2) (the step that minimizes ||r/eps||_2).
 template <int M, bool AV>
 __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, int ntx, int nty,
-                                                            int paper, const int* stop,
+                                                            int zlen, int paper, const int* stop,
                                                             const double* __restrict__ rho,
                                                             const double* __restrict__ eps,
                                                             const double* __restrict__ lne,
@@ -142,8 +142,8 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
   const int zc = t / ntxy;
   const int yt = (t - zc * ntxy) / ntx;
   const int xt = t - zc * ntxy - yt * ntx;
-  const int x0 = xt * kPTX, y0 = yt * kPTY, z0 = zc * kPZC;
-  const int z1 = min(z0 + kPZC, g.nz);
+  const int x0 = xt * kPTX, y0 = yt * kPTY, z0 = zc * zlen;
+  const int z1 = min(z0 + zlen, g.nz);
   const int X = x0 + tx, Y = y0 + ty;
   const int plane = g.nx * g.ny;
   const int cxy = ghost_index(Y, g.ny, g.periodic_y) * g.nx + ghost_index(X, g.nx, g.periodic_x);
@@ -267,8 +267,13 @@ static FdFirst fd_first_weights(int M) {
   return w;
 }
 
+static int polarization_zlen(const Geom& g) {
+  return stencil_zlen((long long)((g.nx + kPTX - 1) / kPTX) * ((g.ny + kPTY - 1) / kPTY), g.nz);
+}
+
 int polarization_groups(const Geom& g) {
-  return ((g.nx + kPTX - 1) / kPTX) * ((g.ny + kPTY - 1) / kPTY) * ((g.nz + kPZC - 1) / kPZC);
+  const int zlen = polarization_zlen(g);
+  return ((g.nx + kPTX - 1) / kPTX) * ((g.ny + kPTY - 1) / kPTY) * ((g.nz + zlen - 1) / zlen);
 }
 
 // lne = ln eps, pointwise
@@ -319,12 +324,13 @@ static void launch_graddot(const Geom& g, int fd_half, int paper, const double* 
                            const double* eps, const double* lne, const double* phi, double* out,
                            double* part, const int* stop, hipStream_t s) {
   const int ntx = (g.nx + kPTX - 1) / kPTX, nty = (g.ny + kPTY - 1) / kPTY;
+  const int zlen = polarization_zlen(g);
   const dim3 grid(polarization_groups(g));
   const FdFirst w = fd_first_weights(fd_half);
 #define GPS_PF(MM)                                                                        \
   case MM:                                                                                \
     GPS_LAUNCH((k_polarization<MM, AV>), grid, dim3(kPThreads), 0, s, g, w, ntx, nty,     \
-               paper, stop, rho, eps, lne, phi, out, part);                               \
+               zlen, paper, stop, rho, eps, lne, phi, out, part);                         \
     break;
   switch (fd_half) {
     GPS_PF(1) GPS_PF(2) GPS_PF(3) GPS_PF(4) GPS_PF(5) GPS_PF(6) GPS_PF(7) GPS_PF(8)

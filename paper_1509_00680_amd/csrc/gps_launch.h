@@ -181,6 +181,8 @@ hipError_t noalloc_scratch(int device, double** out);
 void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
                          const double* lne, const double* phi, double* out, hipStream_t s);
 int polarization_groups(const Geom& g);
+// Planes per z march of the 2.5D stencils over ntxy column tiles.
+int stencil_zlen(long long ntxy, int nz);
 // Device state of a solve by Algorithm SC or PSD (gps_solve_sc).
 struct ScState {
   int done;          // 1 once the solve has stopped

@@ -366,19 +366,29 @@ void launch_init(const SlotTable<T>& tab, const Batch& b, const double* rho, con
 struct FdWeights { double c[9]; };
 
 // Stencil form (free and surface boundaries), 2.5D: a work-group owns a
-// kQTX x kQTY column tile and marches along z over kQZC planes.  The x and y
+// kQTX x kQTY column tile and marches along z over zlen planes.  The x and y
 // neighbours of a plane come from an LDS tile with an M-wide halo (no
 // corners), the z neighbours from a register queue of 2M+1 planes per
-// thread, so a point costs about (2M + kQZC)/kQZC + 1.5 global loads instead
+// thread, so a point costs about (2M + zlen)/zlen + 1.5 global loads instead
 // of 6M + 1.  The next plane's halo and queue entry are loaded while the
-// current plane is differenced.
-constexpr int kQTX = 32, kQTY = 16, kQZC = 4;
+// current plane is differenced.  zlen is chosen per grid (stencil_zlen): as
+// long as the launch still has about two work-groups per CU, so the queue
+// refill is amortized over long marches on large grids.
+constexpr int kQTX = 32, kQTY = 16;
 constexpr int kQThreads = kQTX * kQTY;
+
+// Planes per z march of a 2.5D stencil over ntxy column tiles: the longest
+// (up to 32, at least 4) that keeps about 512 work-groups.
+int stencil_zlen(long long ntxy, int nz) {
+  long long z = (ntxy * nz + 511) / 512;
+  z = std::max<long long>(4, std::min<long long>(32, z));
+  return (int)std::min<long long>(z, nz);
+}
 
 template <typename T, int M>
 __global__ __launch_bounds__(kQThreads) void k_qstencil(SlotTable<T> tab, Batch b, Geom g,
                                                         FdWeights w, int ntx, int nty,
-                                                        double kappa_coef,
+                                                        int zlen, double kappa_coef,
                                                         const double* __restrict__ eps,
                                                         const double* __restrict__ gamma,
                                                         double eps_bulk) {
@@ -397,8 +407,8 @@ __global__ __launch_bounds__(kQThreads) void k_qstencil(SlotTable<T> tab, Batch 
   const int zc = t / ntxy;
   const int yt = (t - zc * ntxy) / ntx;
   const int xt = t - zc * ntxy - yt * ntx;
-  const int x0 = xt * kQTX, y0 = yt * kQTY, z0 = zc * kQZC;
-  const int z1 = min(z0 + kQZC, g.nz);
+  const int x0 = xt * kQTX, y0 = yt * kQTY, z0 = zc * zlen;
+  const int z1 = min(z0 + zlen, g.nz);
   const int X = x0 + tx, Y = y0 + ty;
   const int plane = g.nx * g.ny;
   const int cxy = ghost_index(Y, g.ny, g.periodic_y) * g.nx + ghost_index(X, g.nx, g.periodic_x);
@@ -554,13 +564,14 @@ void launch_qfield(const SlotTable<T>& tab, const Batch& b, const Geom& g, int f
     return;
   }
   const int ntx = (g.nx + kQTX - 1) / kQTX, nty = (g.ny + kQTY - 1) / kQTY;
-  const int nzc = (g.nz + kQZC - 1) / kQZC;
+  const int zlen = stencil_zlen((long long)ntx * nty, g.nz);
+  const int nzc = (g.nz + zlen - 1) / zlen;
   const dim3 grid(ntx * nty * nzc, b.n);
   const FdWeights w = fd_weights(fd_half);
 #define GPS_QF(MM)                                                                        \
   case MM:                                                                                \
     GPS_LAUNCH((k_qstencil<T, MM>), grid, dim3(kQThreads), 0, s, tab, b, g, w, ntx, nty,  \
-               kappa_coef, eps, gamma, eps_bulk);                                         \
+               zlen, kappa_coef, eps, gamma, eps_bulk);                                   \
     break;
   switch (fd_half) {
     GPS_QF(1) GPS_QF(2) GPS_QF(3) GPS_QF(4) GPS_QF(5) GPS_QF(6) GPS_QF(7) GPS_QF(8)

@@ -226,17 +226,31 @@ def test_fast_division_matches_integer_division():
 
 
 # ---- the 2.5D stencil kernel of q (k_qstencil in gps_ops.hip) -------------------------
-QTX, QTY, QZC, QTHREADS = 32, 16, 4, 512
+QTX, QTY, QTHREADS = 32, 16, 512
+
+
+def stencil_zlen(ntxy, nz):
+    """Planes per z march of the 2.5D stencils (stencil_zlen in gps_ops.hip):
+    the longest, from 4 to 32, that keeps about 512 work-groups."""
+    z = max(4, min(32, -(-(ntxy * nz) // 512)))
+    return min(z, nz)
+
+
+def test_stencil_zlen_rule():
+    assert stencil_zlen(18, 96) == 4            # 96^3, 32x16 tiles
+    assert stencil_zlen(50, 160) == 16          # 160^3
+    assert stencil_zlen(1, 3) == 3 and stencil_zlen(10000, 400) == 32
 
 
 def _ghost(i, n, periodic):
     return np.mod(i, n) if periodic else np.clip(i, 0, n - 1)
 
 
-def qstencil_replay(sq, h, M, per, weights):
+def qstencil_replay(sq, h, M, per, weights, zlen=None):
     """Every work-group and thread of k_qstencil, restated on the CPU: tile
     decomposition, ghosted halo slots, LDS tile, register queue.  Returns q
-    without the kappa term and asserts every access in bounds."""
+    without the kappa term and asserts every access in bounds.  zlen: planes
+    per z march (default: the launcher's rule)."""
     nz, ny, nx = sq.shape
     px, py, pz = per
     flat = sq.ravel()
@@ -245,7 +259,9 @@ def qstencil_replay(sq, h, M, per, weights):
     NXH = 2 * M * QTY
     NH = NXH + 2 * M * QTX
     HS = (NH + QTHREADS - 1) // QTHREADS
-    ntx, nty, nzc = -(-nx // QTX), -(-ny // QTY), -(-nz // QZC)
+    ntx, nty = -(-nx // QTX), -(-ny // QTY)
+    QZC = zlen or stencil_zlen(ntx * nty, nz)
+    nzc = -(-nz // QZC)
     q = np.full(sq.shape, np.nan)
     tid = np.arange(QTHREADS)
     tx, ty = tid % QTX, tid // QTX
@@ -296,10 +312,14 @@ def qstencil_replay(sq, h, M, per, weights):
     return q
 
 
-@pytest.mark.parametrize("shape,bc,order", [((13, 17, 20), "free", 16), ((13, 17, 20), "surface", 16),
-                                            ((9, 40, 35), "free", 6), ((21, 18, 33), "surface", 2),
-                                            ((5, 6, 7), "free", 16)])
-def test_qstencil_replay_matches_oracle(shape, bc, order):
+@pytest.mark.parametrize("shape,bc,order,zlen", [((13, 17, 20), "free", 16, None),
+                                                 ((13, 17, 20), "surface", 16, None),
+                                                 ((9, 40, 35), "free", 6, None),
+                                                 ((21, 18, 33), "surface", 2, None),
+                                                 ((5, 6, 7), "free", 16, None),
+                                                 ((37, 17, 20), "free", 16, 16),
+                                                 ((30, 18, 33), "surface", 8, 7)])
+def test_qstencil_replay_matches_oracle(shape, bc, order, zlen):
     from oracle import stencil
     rng = np.random.default_rng(3)
     eps = 1.0 + 77.0 * rng.random(shape)
@@ -307,7 +327,7 @@ def test_qstencil_replay_matches_oracle(shape, bc, order):
     per = (bc != "free", bc != "free", False)
     M = order // 2
     w = stencil.fd_second_derivative_weights(M)
-    got = qstencil_replay(np.sqrt(eps), h, M, per, w)
+    got = qstencil_replay(np.sqrt(eps), h, M, per, w, zlen)
     ref = stencil.q_field(eps, h, bc, order)
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
@@ -324,12 +344,13 @@ def _source_constants(name, keys):
     return out
 
 
-def polarization_replay(rho, eps, phi, h, M, per, w):
+def polarization_replay(rho, eps, phi, h, M, per, w, zlen=None):
     """Every work-group and thread of k_polarization, restated on the CPU
     (tiles, ghosted halo slots, the two LDS tiles and register queues);
-    asserts every access in bounds and returns rho_pol."""
-    c = _source_constants("gps_cavity.hip", ["kPTX", "kPTY", "kPZC"])
-    PTX, PTY, PZC = c["kPTX"], c["kPTY"], c["kPZC"]
+    asserts every access in bounds and returns rho_pol.  zlen: planes per z
+    march (default: the launcher's rule)."""
+    c = _source_constants("gps_cavity.hip", ["kPTX", "kPTY"])
+    PTX, PTY = c["kPTX"], c["kPTY"]
     PTHREADS = PTX * PTY
     nz, ny, nx = eps.shape
     px, py, pz = per
@@ -339,7 +360,9 @@ def polarization_replay(rho, eps, phi, h, M, per, w):
     NXH = 2 * M * PTY
     NH = NXH + 2 * M * PTX
     HS = (NH + PTHREADS - 1) // PTHREADS
-    ntx, nty, nzc = -(-nx // PTX), -(-ny // PTY), -(-nz // PZC)
+    ntx, nty = -(-nx // PTX), -(-ny // PTY)
+    PZC = zlen or stencil_zlen(ntx * nty, nz)
+    nzc = -(-nz // PZC)
     out = np.full(eps.shape, np.nan)
     tid = np.arange(PTHREADS)
     tx, ty = tid % PTX, tid // PTX
@@ -400,10 +423,14 @@ def polarization_replay(rho, eps, phi, h, M, per, w):
     return out
 
 
-@pytest.mark.parametrize("shape,bc,order", [((13, 17, 20), "free", 16), ((13, 17, 40), "surface", 16),
-                                            ((9, 40, 35), "periodic", 6), ((6, 5, 7), "free", 2),
-                                            ((18, 20, 24), "wire", 12)])
-def test_polarization_replay_matches_oracle(shape, bc, order):
+@pytest.mark.parametrize("shape,bc,order,zlen", [((13, 17, 20), "free", 16, None),
+                                                 ((13, 17, 40), "surface", 16, None),
+                                                 ((9, 40, 35), "periodic", 6, None),
+                                                 ((6, 5, 7), "free", 2, None),
+                                                 ((18, 20, 24), "wire", 12, None),
+                                                 ((37, 17, 20), "free", 16, 16),
+                                                 ((29, 20, 24), "wire", 12, 9)])
+def test_polarization_replay_matches_oracle(shape, bc, order, zlen):
     from oracle import cavity
     rng = np.random.default_rng(5)
     eps = 1.0 + 77.0 * rng.random(shape)
@@ -413,6 +440,7 @@ def test_polarization_replay_matches_oracle(shape, bc, order):
     per = {"free": (False, False, False), "surface": (True, True, False),
            "periodic": (True, True, True), "wire": (False, False, True)}[bc]
     M = order // 2
-    got = polarization_replay(rho, eps, phi, h, M, per, cavity.fd_first_derivative_weights(M))
+    got = polarization_replay(rho, eps, phi, h, M, per, cavity.fd_first_derivative_weights(M),
+                              zlen)
     ref = cavity.polarization_charge(rho, eps, phi, h, bc, order)
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
