@@ -754,10 +754,14 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk, int refine) {
 // polls the host enqueues n iterations, n predicted from the recent residual
 // decay, as replays of graphs of 4, 2, 1 chunks and 4, 2, 1 iterations, so
 // that a solve runs few iterations past its stop decision (those launches
-// exit at once, but each still costs a dispatch) with few graph launches
-// (each costs about as much idle GPU time as an early-exit iteration).
+// exit early, but each still loads its operands) with few polls (each leaves
+// the GPU idle for about a third of an iteration at 160^3).  The decay rate
+// at the first poll is taken from ||r_0||; first_n > 0 is the caller's guess
+// of the iterations needed (the nonlinear outer loop passes the previous
+// inner solve's count), else the first batch is two chunks.
 template <typename T>
-SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nullptr) {
+SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nullptr,
+                   int first_n = 0) {
   Res<T>& R = pl->res<T>();
   const int chunk = pl->opt.check_every;
   // track_rho (the right-hand side): the x passes keep the FP64 source s of
@@ -775,7 +779,7 @@ SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nu
   b.n = 1;
   b.slot[0] = 0;
   int k = 0;              // iterations enqueued
-  int n = 2 * chunk;      // iterations before the next poll
+  int n = first_n > 0 ? std::min(first_n, 8 * chunk) : 2 * chunk;   // before the next poll
   double prev_rr = -1.0;
   int prev_it = 0;
   SolveState st{};
@@ -806,12 +810,23 @@ SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nu
       refine_step<T>(pl, track_rho, false);
       next_ref += m;
     }
-    // predicted iterations left: log-linear extrapolation of ||r||^2
-    n = 2 * chunk;
+    // predicted iterations left: log-linear extrapolation of ||r||^2 (from
+    // ||r_0||^2 at iteration 0 at the first poll)
+    // (no usable rate, the residual having risen: half the iterations done)
+    n = std::max(1, std::min(2 * chunk, st.iters / 2));
+    const bool from_start = prev_rr < 0.0;
+    if (from_start) {
+      prev_rr = st.rr0;
+      prev_it = 0;
+    }
     if (prev_rr > 0.0 && st.rr > 0.0 && st.iters > prev_it && st.rr < prev_rr) {
       const double rate = std::log(st.rr / prev_rr) / double(st.iters - prev_it);
       const double left = std::log(st.thr2 / st.rr) / rate;
       n = (int)std::ceil(std::max(1.0, left));
+      // PCG's residual falls faster after its first iterations, so a rate
+      // measured from iteration 0 overstates what is left: at most half the
+      // iterations done, then a poll with a rate from two polls
+      if (from_start) n = std::min(n, std::max(1, st.iters / 2));
       n = std::max(1, std::min(n, 8 * chunk));
     }
     prev_rr = st.rr;
@@ -935,7 +950,8 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
   for (int k = 1; k <= el.outer_maxit; ++k) {
     outer = k;
     if (k > 1) reset_state<T>(pl, kFourPi * tol * rho_norm, k <= 2 ? 1e-2 : 0.0);
-    st = run_pcg<T>(pl, 0);
+    // inner solves of consecutive outer steps need similar iteration counts
+    st = run_pcg<T>(pl, 0, nullptr, k > 1 ? std::max(1, st.iters - 1) : 0);
     total += st.iters;
     if (st.status != GPS_OK) {
       result = (gps_status)st.status;
