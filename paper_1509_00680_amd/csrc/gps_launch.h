@@ -96,6 +96,7 @@ template <typename T> struct SParams {
   int k0_from_slot;         // periodic: the k = 0 multiplier is the solve state's g0
   int Lx;                   // ST_CONV with slots: x length (weights of the (v, r) partials)
   int decide;               // ST_INV with slots: work-group 0 takes the stop decision
+  int plain_store;          // ST_FWD: ordinary stores (the output stays cached for the next pass)
   DecideArgs dec;
   cplx<T>* work;            // explicit buffer, or null to use the slots
   SlotTable<T> tab;
