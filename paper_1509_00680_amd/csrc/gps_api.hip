@@ -264,9 +264,9 @@ SParams<T> sparams(const gps_plan* pl, int axis, int L, int Lin, int Lout, int n
   p.Kx = pl->g.Kx;
   p.Ly = pl->g.Ly;
   p.Lz = pl->g.Lz;
-  // y-forward outputs of 32 MiB and more are stored plainly (they stay in the
-  // last-level cache for the z pass)
-  p.plain_store = axis == 1 && (long long)Lout * npencils * (long long)sizeof(cplx<T>) >= (32ll << 20);
+  // y-forward and z passes over 32 MiB and more of data store plainly (the
+  // output stays in the last-level cache for the next pass)
+  p.plain_store = axis >= 1 && (long long)Lout * npencils * (long long)sizeof(cplx<T>) >= (32ll << 20);
   return p;
 }
 

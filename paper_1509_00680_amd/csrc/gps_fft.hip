@@ -460,7 +460,7 @@ template <typename T> void launch_xinv(int mode, const XParams<T>& p, hipStream_
 }
 
 template <typename T> int strided_parts(const SParams<T>& p) {
-  if (fast_length(p.L)) return fast_strided_parts<T>(p.L, p.npencils);
+  if (fast_length(p.L)) return fast_strided_parts<T>(p);
   return (p.npencils + p.B - 1) / p.B;
 }
 

@@ -25,6 +25,15 @@ namespace gps {
 template <typename T> struct FastTile;
 template <> struct FastTile<float> { static constexpr int B = 16; };
 template <> struct FastTile<double> { static constexpr int B = 8; };
+// Pencils per tile of a strided pass: FastTile<T>::B, except for FP32 z
+// passes of length 320 and 384, which take 8.  Their 16-pencil LDS tile
+// (L x 17 values, 46-55 KB) fits 2-3 work-groups per CU; the 8-pencil tile
+// fits 5-6, which hides more of the latency of the two transforms (160^3:
+// 52.5 -> 41.5 us; 128 x 128 x 192 slab, length 384: 22.3 -> 16.2 us).  At
+// the shorter lengths the 16-pencil tile already fits 4 or more.
+template <typename T> int strided_tile(int mode, int L) {
+  return (mode == ST_CONV && L >= 320 && FastTile<T>::B == 16) ? 8 : FastTile<T>::B;
+}
 constexpr int kXPairs = 6;             // row pairs per work-group of the x passes
 
 constexpr int round64(int v) { return (v + 63) / 64 * 64; }
@@ -34,11 +43,11 @@ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return cmk(a.x, -a.y); }
 
 // Store of a value that the next kernel reads on other XCDs (the transposes
 // around the z pass): non-temporal, so the line does not stay dirty in this
-// XCD's L2 until the end-of-kernel write-back.  A large y-forward output
-// (plain_store: 32 MiB and more, 66 MB at 160^3) is stored plainly instead:
-// it then stays in the last-level cache for the z pass, which reads it about
-// 10% faster than from HBM; below that size the write-back costs more than
-// the z pass gains.
+// XCD's L2 until the end-of-kernel write-back.  Large outputs of the y-forward
+// and z passes (plain_store: 32 MiB and more, 66 MB at 160^3) are stored
+// plainly instead: they then stay in the last-level cache for the next pass
+// (160^3: z pass 57.8 -> 52.5 us after a plain y forward; y inverse 25.3 ->
+// 22.3 us after a plain z pass).
 template <typename T>
 __device__ __forceinline__ void store_stream(cplx<T>* dst, cplx<T> v) {
   __builtin_nontemporal_store(v.x, &dst->x);
@@ -54,10 +63,9 @@ __device__ __forceinline__ void store_stream(cplx<T>* dst, cplx<T> v) {
 // (Hockney zero padding): the forward and z passes read, and the inverse and z
 // passes write, only the first L/2 elements, and the zero half is a
 // compile-time constant.
-template <typename T, int L1, int L2, int MODE, bool PAD, int NTILE>
-__global__ __launch_bounds__(round64(FastTile<T>::B * L1))
+template <typename T, int L1, int L2, int MODE, bool PAD, int NTILE, int B>
+__global__ __launch_bounds__(round64(B * L1))
 void k_fstrided(SParams<T> p) {
-  constexpr int B = FastTile<T>::B;
   constexpr int L = L1 * L2;
   constexpr int PITCH = B + 1;
   constexpr int NT = round64(B * L1);
@@ -284,7 +292,10 @@ void k_fstrided(SParams<T> p) {
           const int e = q + L2 * nb;
           const bool out = PAD ? (nb < L1 / 2) : (e < lout);
           if (out) {
-            if constexpr (MODE == ST_CONV) store_stream(&at_bytes(work, qb[t] + (unsigned)nb * s2), x[nb]);
+            if constexpr (MODE == ST_CONV) {
+              if (p.plain_store) at_bytes(work, qb[t] + (unsigned)nb * s2) = x[nb];
+              else store_stream(&at_bytes(work, qb[t] + (unsigned)nb * s2), x[nb]);
+            }
             else at_bytes(work, qb[t] + (unsigned)nb * s2) = x[nb];
           }
         }
@@ -735,26 +746,27 @@ int fast_xpass_parts(int, int nrows) { return fast_xpass_groups(nrows); }
 // Tiles per work-group of the strided passes.
 constexpr int kStridedTiles = 1;
 
-template <typename T> int fast_strided_groups(int npencils) {
-  constexpr int W = FastTile<T>::B * kStridedTiles;
+template <typename T> int fast_strided_groups(int npencils, int B) {
+  const int W = B * kStridedTiles;
   return (npencils + W - 1) / W;
 }
 
-template <typename T> int fast_strided_parts(int L, int npencils) {
-  switch (L) {
+// z pass (solve mode): one partial per wavefront
+template <typename T> int fast_strided_parts(const SParams<T>& p) {
+  const int B = strided_tile<T>(ST_CONV, p.L);
+  switch (p.L) {
 #define GPS_CASE(LL, A, BB) \
-  case LL: return fast_strided_groups<T>(npencils) * (round64(FastTile<T>::B * A) / 64);
+  case LL: return fast_strided_groups<T>(p.npencils, B) * (round64(B * A) / 64);
     GPS_FAST_LENGTHS(GPS_CASE)
 #undef GPS_CASE
     default: return 0;
   }
 }
-template int fast_strided_parts<float>(int, int);
-template int fast_strided_parts<double>(int, int);
+template int fast_strided_parts<float>(const SParams<float>&);
+template int fast_strided_parts<double>(const SParams<double>&);
 
 template <typename T>
 bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
-  constexpr int B = FastTile<T>::B;
   constexpr int NTL = kStridedTiles;
   // PAD when the pencil's data half is L/2: forward reads, z pass reads and
   // writes, inverse writes that half only
@@ -762,19 +774,24 @@ bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
                    (mode == ST_CONV && 2 * p.Lin == p.L && p.Lout == p.Lin) ||
                    (mode == ST_INV && 2 * p.Lout == p.L && p.Lin == p.L);
   const int dec = mode == ST_INV && p.decide ? 1 : 0;   // the decision work-group
-  const dim3 grid(fast_strided_groups<T>(p.npencils) + dec, p.work ? 1 : p.batch.n);
+  constexpr int BT = FastTile<T>::B;
+  constexpr int BS = 8;                                  // FP32 z pass at lengths 320, 384
+  const int B = strided_tile<T>(mode, p.L);
+  const dim3 grid(fast_strided_groups<T>(p.npencils, B) + dec, p.work ? 1 : p.batch.n);
   switch (p.L) {
 #define GPS_CASE(LL, A, BB)                                                                    \
   case LL: {                                                                                   \
     const dim3 blk(round64(B * A));                                                            \
     if (pad) {                                                                                 \
-      if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD, true, NTL>), grid, blk, 0, s, p);   \
-      else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV, true, NTL>), grid, blk, 0, s, p); \
-      else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, true, NTL>), grid, blk, 0, s, p);             \
+      if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD, true, NTL, BT>), grid, blk, 0, s, p);   \
+      else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV, true, NTL, BT>), grid, blk, 0, s, p); \
+      else if (B == BT) GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, true, NTL, BT>), grid, blk, 0, s, p);   \
+      else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, true, NTL, BS>), grid, blk, 0, s, p);             \
     } else {                                                                                   \
-      if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD, false, NTL>), grid, blk, 0, s, p);  \
-      else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV, false, NTL>), grid, blk, 0, s, p); \
-      else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, false, NTL>), grid, blk, 0, s, p);            \
+      if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD, false, NTL, BT>), grid, blk, 0, s, p);  \
+      else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV, false, NTL, BT>), grid, blk, 0, s, p); \
+      else if (B == BT) GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, false, NTL, BT>), grid, blk, 0, s, p);  \
+      else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, false, NTL, BS>), grid, blk, 0, s, p);            \
     }                                                                                          \
     return true;                                                                               \
   }

@@ -96,7 +96,8 @@ template <typename T> struct SParams {
   int k0_from_slot;         // periodic: the k = 0 multiplier is the solve state's g0
   int Lx;                   // ST_CONV with slots: x length (weights of the (v, r) partials)
   int decide;               // ST_INV with slots: work-group 0 takes the stop decision
-  int plain_store;          // ST_FWD: ordinary stores (the output stays cached for the next pass)
+  int plain_store;          // y forward, z pass over 32 MiB and more: ordinary stores (the output
+                            // stays in the last-level cache for the next pass)
   DecideArgs dec;
   cplx<T>* work;            // explicit buffer, or null to use the slots
   SlotTable<T> tab;
@@ -111,8 +112,8 @@ template <typename T> int strided_parts(const SParams<T>& p);
 bool fast_length(int L);
 int fast_xpass_groups(int nrows);
 int fast_xpass_parts(int L, int nrows);
-template <typename T> int fast_strided_groups(int npencils);
-template <typename T> int fast_strided_parts(int L, int npencils);
+template <typename T> int fast_strided_groups(int npencils, int B);
+template <typename T> int fast_strided_parts(const SParams<T>& p);   // z pass (solve mode)
 template <typename T> bool fast_strided(int mode, const SParams<T>& p, hipStream_t s);
 template <typename T> bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s);
 template <typename T> bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s);
