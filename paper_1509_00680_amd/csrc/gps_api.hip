@@ -758,10 +758,10 @@ void build_graph(gps_plan* pl, int check_neutral, int chunk, int refine) {
 // decay, as replays of graphs of 4, 2, 1 chunks and 4, 2, 1 iterations, so
 // that a solve runs few iterations past its stop decision (those launches
 // exit early, but each still loads its operands) with few polls (each leaves
-// the GPU idle for about a third of an iteration at 160^3).  The decay rate
-// at the first poll is taken from ||r_0||; first_n > 0 is the caller's guess
-// of the iterations needed (the nonlinear outer loop passes the previous
-// inner solve's count), else the first batch is two chunks.
+// the GPU idle for about a third of an iteration at 160^3).  first_n > 0 is
+// the caller's guess of the iterations needed (the nonlinear outer loop
+// passes the previous inner solve's count), else the first batch is two
+// chunks.
 template <typename T>
 SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nullptr,
                    int first_n = 0) {
@@ -815,9 +815,14 @@ SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nu
     }
     // predicted iterations left: log-linear extrapolation of ||r||^2 (from
     // ||r_0||^2 at iteration 0 at the first poll)
-    // (no usable rate, the residual having risen: half the iterations done)
-    n = std::max(1, std::min(2 * chunk, st.iters / 2));
-    const bool from_start = prev_rr < 0.0;
+    // With a prior (first_n > 0: the solve restarts from a nearby iterate)
+    // the first poll already extrapolates, from ||r_0||^2 at iteration 0,
+    // and a poll without a usable rate (the residual having risen) is
+    // followed by half the iterations done; a solve from scratch waits for
+    // a rate between two polls, two chunks apart.
+    const bool prior = first_n > 0;
+    n = prior ? std::max(1, std::min(2 * chunk, st.iters / 2)) : 2 * chunk;
+    const bool from_start = prior && prev_rr < 0.0;
     if (from_start) {
       prev_rr = st.rr0;
       prev_it = 0;

@@ -63,7 +63,7 @@ __device__ __forceinline__ void store_stream(cplx<T>* dst, cplx<T> v) {
 // (Hockney zero padding): the forward and z passes read, and the inverse and z
 // passes write, only the first L/2 elements, and the zero half is a
 // compile-time constant.
-template <typename T, int L1, int L2, int MODE, bool PAD, int NTILE, int B>
+template <typename T, int L1, int L2, int MODE, bool PAD, int NTILE, int B, bool PLAIN>
 __global__ __launch_bounds__(round64(B * L1))
 void k_fstrided(SParams<T> p) {
   constexpr int L = L1 * L2;
@@ -240,7 +240,7 @@ void k_fstrided(SParams<T> p) {
           for (int k2 = 0; k2 < L2; ++k2) {
             const int kk = q + L1 * k2;
             if (kk < lout) {
-              if (p.plain_store) at_bytes(work, qb[t] + (unsigned)k2 * s1) = y[k2];
+              if constexpr (PLAIN) at_bytes(work, qb[t] + (unsigned)k2 * s1) = y[k2];
               else store_stream(&at_bytes(work, qb[t] + (unsigned)k2 * s1), y[k2]);
             }
           }
@@ -293,7 +293,7 @@ void k_fstrided(SParams<T> p) {
           const bool out = PAD ? (nb < L1 / 2) : (e < lout);
           if (out) {
             if constexpr (MODE == ST_CONV) {
-              if (p.plain_store) at_bytes(work, qb[t] + (unsigned)nb * s2) = x[nb];
+              if constexpr (PLAIN) at_bytes(work, qb[t] + (unsigned)nb * s2) = x[nb];
               else store_stream(&at_bytes(work, qb[t] + (unsigned)nb * s2), x[nb]);
             }
             else at_bytes(work, qb[t] + (unsigned)nb * s2) = x[nb];
@@ -777,26 +777,38 @@ bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
   constexpr int BT = FastTile<T>::B;
   constexpr int BS = 8;                                  // FP32 z pass at lengths 320, 384
   const int B = strided_tile<T>(mode, p.L);
+  const bool plain = p.plain_store != 0;
   const dim3 grid(fast_strided_groups<T>(p.npencils, B) + dec, p.work ? 1 : p.batch.n);
+// k_fstrided<T, L1, L2, mode, pad, NTL, B, plain>
+#define GPS_K(A, BB, M, P, BX, PL) k_fstrided<T, A, BB, M, P, NTL, BX, PL>
+#define GPS_PASS(A, BB, P)                                                                     \
+  if (mode == ST_FWD) {                                                                        \
+    if (plain) GPS_LAUNCH((GPS_K(A, BB, ST_FWD, P, BT, true)), grid, blk, 0, s, p);            \
+    else GPS_LAUNCH((GPS_K(A, BB, ST_FWD, P, BT, false)), grid, blk, 0, s, p);                 \
+  } else if (mode == ST_INV) {                                                                 \
+    GPS_LAUNCH((GPS_K(A, BB, ST_INV, P, BT, false)), grid, blk, 0, s, p);                      \
+  } else if (B == BT) {                                                                        \
+    if (plain) GPS_LAUNCH((GPS_K(A, BB, ST_CONV, P, BT, true)), grid, blk, 0, s, p);           \
+    else GPS_LAUNCH((GPS_K(A, BB, ST_CONV, P, BT, false)), grid, blk, 0, s, p);                \
+  } else {                                                                                     \
+    if (plain) GPS_LAUNCH((GPS_K(A, BB, ST_CONV, P, BS, true)), grid, blk, 0, s, p);           \
+    else GPS_LAUNCH((GPS_K(A, BB, ST_CONV, P, BS, false)), grid, blk, 0, s, p);                \
+  }
   switch (p.L) {
 #define GPS_CASE(LL, A, BB)                                                                    \
   case LL: {                                                                                   \
     const dim3 blk(round64(B * A));                                                            \
     if (pad) {                                                                                 \
-      if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD, true, NTL, BT>), grid, blk, 0, s, p);   \
-      else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV, true, NTL, BT>), grid, blk, 0, s, p); \
-      else if (B == BT) GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, true, NTL, BT>), grid, blk, 0, s, p);   \
-      else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, true, NTL, BS>), grid, blk, 0, s, p);             \
+      GPS_PASS(A, BB, true)                                                                    \
     } else {                                                                                   \
-      if (mode == ST_FWD) GPS_LAUNCH((k_fstrided<T, A, BB, ST_FWD, false, NTL, BT>), grid, blk, 0, s, p);  \
-      else if (mode == ST_INV) GPS_LAUNCH((k_fstrided<T, A, BB, ST_INV, false, NTL, BT>), grid, blk, 0, s, p); \
-      else if (B == BT) GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, false, NTL, BT>), grid, blk, 0, s, p);  \
-      else GPS_LAUNCH((k_fstrided<T, A, BB, ST_CONV, false, NTL, BS>), grid, blk, 0, s, p);            \
+      GPS_PASS(A, BB, false)                                                                   \
     }                                                                                          \
     return true;                                                                               \
   }
     GPS_FAST_LENGTHS(GPS_CASE)
 #undef GPS_CASE
+#undef GPS_PASS
+#undef GPS_K
     default: return false;
   }
 }
