@@ -25,14 +25,15 @@ namespace gps {
 template <typename T> struct FastTile;
 template <> struct FastTile<float> { static constexpr int B = 16; };
 template <> struct FastTile<double> { static constexpr int B = 8; };
-// Pencils per tile of a strided pass: FastTile<T>::B, except for FP32 z
-// passes of length 320 and 384, which take 8.  Their 16-pencil LDS tile
-// (L x 17 values, 46-55 KB) fits 2-3 work-groups per CU; the 8-pencil tile
-// fits 5-6, which hides more of the latency of the two transforms (160^3:
-// 52.5 -> 41.5 us; 128 x 128 x 192 slab, length 384: 22.3 -> 16.2 us).  At
-// the shorter lengths the 16-pencil tile already fits 4 or more.
-template <typename T> int strided_tile(int mode, int L) {
-  return (mode == ST_CONV && L >= 320 && FastTile<T>::B == 16) ? 8 : FastTile<T>::B;
+// Pencils per tile of a strided pass: FastTile<T>::B, except for FP32 passes
+// of length 320 and 384, which take 8.  Their 16-pencil LDS tile (L x 17
+// values, 46-55 KB) fits 2-3 work-groups per CU; the 8-pencil tile fits 5-6,
+// which hides more of the latency of the transforms (160^3: z pass 52.5 ->
+// 41.5 us, y passes 23.8 / 22.4 -> 21.7 / 21.8 us; 128 x 128 x 192 slab, z
+// length 384: 22.3 -> 16.2 us).  At the shorter lengths the 16-pencil tile
+// already fits 4 or more, and its 128-byte rows are whole cache lines.
+template <typename T> int strided_tile(int, int L) {
+  return (L >= 320 && FastTile<T>::B == 16) ? 8 : FastTile<T>::B;
 }
 constexpr int kXPairs = 6;             // row pairs per work-group of the x passes
 
@@ -775,7 +776,7 @@ bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
                    (mode == ST_INV && 2 * p.Lout == p.L && p.Lin == p.L);
   const int dec = mode == ST_INV && p.decide ? 1 : 0;   // the decision work-group
   constexpr int BT = FastTile<T>::B;
-  constexpr int BS = 8;                                  // FP32 z pass at lengths 320, 384
+  constexpr int BS = 8;                                  // FP32 passes at lengths 320, 384
   const int B = strided_tile<T>(mode, p.L);
   const bool plain = p.plain_store != 0;
   const dim3 grid(fast_strided_groups<T>(p.npencils, B) + dec, p.work ? 1 : p.batch.n);
@@ -783,10 +784,13 @@ bool fast_strided(int mode, const SParams<T>& p, hipStream_t s) {
 #define GPS_K(A, BB, M, P, BX, PL) k_fstrided<T, A, BB, M, P, NTL, BX, PL>
 #define GPS_PASS(A, BB, P)                                                                     \
   if (mode == ST_FWD) {                                                                        \
-    if (plain) GPS_LAUNCH((GPS_K(A, BB, ST_FWD, P, BT, true)), grid, blk, 0, s, p);            \
+    if (B != BT) { if (plain) GPS_LAUNCH((GPS_K(A, BB, ST_FWD, P, BS, true)), grid, blk, 0, s, p); \
+      else GPS_LAUNCH((GPS_K(A, BB, ST_FWD, P, BS, false)), grid, blk, 0, s, p); }           \
+    else if (plain) GPS_LAUNCH((GPS_K(A, BB, ST_FWD, P, BT, true)), grid, blk, 0, s, p);       \
     else GPS_LAUNCH((GPS_K(A, BB, ST_FWD, P, BT, false)), grid, blk, 0, s, p);                 \
   } else if (mode == ST_INV) {                                                                 \
-    GPS_LAUNCH((GPS_K(A, BB, ST_INV, P, BT, false)), grid, blk, 0, s, p);                      \
+    if (B != BT) GPS_LAUNCH((GPS_K(A, BB, ST_INV, P, BS, false)), grid, blk, 0, s, p);         \
+    else GPS_LAUNCH((GPS_K(A, BB, ST_INV, P, BT, false)), grid, blk, 0, s, p);                 \
   } else if (B == BT) {                                                                        \
     if (plain) GPS_LAUNCH((GPS_K(A, BB, ST_CONV, P, BT, true)), grid, blk, 0, s, p);           \
     else GPS_LAUNCH((GPS_K(A, BB, ST_CONV, P, BT, false)), grid, blk, 0, s, p);                \

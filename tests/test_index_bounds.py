@@ -36,7 +36,7 @@ def strided_violations(T, mode, L, Lin, Lout, npen, per_group, group_stride, ele
                        B=None):
     """decide: the solve's y inverse, whose work-group 0 only takes the stop
     decision; the tiles are numbered from work-group 1 on.  B: pencils per
-    tile (16 in FP32, 8 in FP64; a large FP32 z pass takes 8)."""
+    tile (16 in FP32, 8 in FP64 and in FP32 passes of length 320 and 384)."""
     L1, L2 = FAST[L]
     if B is None:
         B = 16 if T == "f" else 8
@@ -145,7 +145,7 @@ def test_strided_passes_stay_in_bounds(bc):
         for tag, T, args, kw in launches(shape, bc):
             if args[1] not in FAST:
                 continue
-            tiles = (16, 8) if (tag == "z pass" and T == "f") else (None,)
+            tiles = (16, 8) if T == "f" else (None,)
             for ntile in (1, 2):
                 for decide in ((False, True) if tag == "y inverse" else (False,)):
                     for B in tiles:
