@@ -35,7 +35,13 @@ template <> struct FastTile<double> { static constexpr int B = 8; };
 template <typename T> int strided_tile(int, int L) {
   return (L >= 320 && FastTile<T>::B == 16) ? 8 : FastTile<T>::B;
 }
-constexpr int kXPairs = 6;             // row pairs per work-group of the x passes
+// Row pairs per work-group of the x passes: 6, and 10 at length 320 (L1 =
+// 20).  Every x-forward work-group re-sums the x-inverse's partials, one per
+// work-group, so that head costs the square of the work-group count; at
+// 160^3 (12,800 row pairs) 10 pairs take the x forward from 39.1 to 32.2 us
+// (8 and 12 pairs: 36.1 us); on the 96^3 and 128 x 128 x 192 grids 6 pairs
+// are fastest.
+template <int L1> constexpr int xpairs() { return L1 == 20 ? 10 : 6; }
 
 constexpr int round64(int v) { return (v + 63) / 64 * 64; }
 
@@ -318,7 +324,7 @@ void k_fstrided(SParams<T> p) {
 // (PAD: the box holds L/2 points of the padded length L, else L), so every
 // loop has a fixed trip count and all global loads of a thread are issued
 // before the first one is used.
-template <int L1> constexpr int xthreads() { return round64(kXPairs * L1); }
+template <int L1> constexpr int xthreads() { return round64(xpairs<L1>() * L1); }
 
 // Work-group sum for a compile-time block of NT threads: one wavefront needs
 // no barrier.
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(xthreads<L1>())
 void k_fxfwd(XParams<T> p) {
   constexpr bool SOLVE = MODE == XF_SOLVE || MODE == XF_SOLVE_REF;
   constexpr bool REF = MODE == XF_SOLVE_REF;     // also s += alpha sigma (refinement)
-  constexpr int P = kXPairs;
+  constexpr int P = xpairs<L1>();
   constexpr int L = L1 * L2;
   constexpr int PITCH = P + 1;
   constexpr int NT = xthreads<L1>();
@@ -566,7 +572,7 @@ void k_fxinv(XParams<T> p) {
   constexpr bool SOLVE = MODE != XI_REAL;
   constexpr bool PER = MODE == XI_SOLVE_PERIODIC;
   constexpr bool REF = MODE == XI_SOLVE_REF;
-  constexpr int P = kXPairs;
+  constexpr int P = xpairs<L1>();
   constexpr int L = L1 * L2;
   constexpr int PITCH = P + 1;
   constexpr int NT = xthreads<L1>();
@@ -739,10 +745,22 @@ bool fast_length(int L) {
   }
 }
 
-int fast_xpass_groups(int nrows) { return ((nrows + 1) / 2 + kXPairs - 1) / kXPairs; }
+static int xpass_pairs(int L) {
+  switch (L) {
+#define GPS_CASE(LL, A, BB) case LL: return xpairs<A>();
+    GPS_FAST_LENGTHS(GPS_CASE)
+#undef GPS_CASE
+    default: return 6;
+  }
+}
+
+int fast_xpass_groups(int L, int nrows) {
+  const int P = xpass_pairs(L);
+  return ((nrows + 1) / 2 + P - 1) / P;
+}
 
 // Partials of the solve-mode x passes: one per work-group.
-int fast_xpass_parts(int, int nrows) { return fast_xpass_groups(nrows); }
+int fast_xpass_parts(int L, int nrows) { return fast_xpass_groups(L, nrows); }
 
 // Tiles per work-group of the strided passes.
 constexpr int kStridedTiles = 1;
@@ -824,7 +842,7 @@ bool fast_xfwd(int mode, const XParams<T>& p, hipStream_t s) {
   const bool pad = 2 * p.Lin == p.g.Lx;
   if (!pad && p.Lin != p.g.Lx) return false;
   if (p.in_row_stride != p.Lin) return false;        // the kernels assume contiguous rows
-  const dim3 grid(fast_xpass_groups(p.nrows), p.has_slots ? p.batch.n : 1);
+  const dim3 grid(fast_xpass_groups(p.g.Lx, p.nrows), p.has_slots ? p.batch.n : 1);
   switch (p.g.Lx) {
 #define GPS_CASE(LL, A, BB)                                                                      \
   case LL: {                                                                                     \
@@ -852,7 +870,7 @@ bool fast_xinv(int mode, const XParams<T>& p, hipStream_t s) {
   const bool pad = 2 * p.Lout == p.g.Lx;
   if (!pad && p.Lout != p.g.Lx) return false;
   if (p.in_row_stride != p.Lout) return false;       // the kernels assume contiguous rows
-  const dim3 grid(fast_xpass_groups(p.nrows), p.has_slots ? p.batch.n : 1);
+  const dim3 grid(fast_xpass_groups(p.g.Lx, p.nrows), p.has_slots ? p.batch.n : 1);
   switch (p.g.Lx) {
 #define GPS_CASE(LL, A, BB)                                                                      \
   case LL: {                                                                                     \

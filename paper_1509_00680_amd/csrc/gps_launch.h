@@ -110,7 +110,7 @@ template <typename T> int strided_parts(const SParams<T>& p);
 
 // Two-level passes for the common lengths (32 ... 384); false if L has none.
 bool fast_length(int L);
-int fast_xpass_groups(int nrows);
+int fast_xpass_groups(int L, int nrows);
 int fast_xpass_parts(int L, int nrows);
 template <typename T> int fast_strided_groups(int npencils, int B);
 template <typename T> int fast_strided_parts(const SParams<T>& p);   // z pass (solve mode)

@@ -156,12 +156,16 @@ def test_strided_passes_stay_in_bounds(bc):
 
 
 def _x_pairs():
-    """Row pairs per work-group of the two-level x passes, read from the source."""
+    """Row pairs per work-group of the two-level x passes as a function of
+    the first factor L1 of the length, read from the source."""
     import os
     import re
     src = os.path.join(os.path.dirname(__file__), "..", "paper_1509_00680_amd", "csrc",
                        "gps_fft_fast.hip")
-    return int(re.search(r"constexpr int kXPairs = (\d+);", open(src).read()).group(1))
+    m = re.search(r"constexpr int xpairs\(\) \{ return L1 == (\d+) \? (\d+) : (\d+); \}",
+                  open(src).read())
+    l1, special, default = (int(g) for g in m.groups())
+    return lambda L1: special if L1 == l1 else default
 
 
 X_PAIRS = _x_pairs()
@@ -181,7 +185,8 @@ def test_partial_sums_fit_their_arrays():
             if Lx in FAST:
                 L1 = FAST[Lx][0]
                 nrows = ny * nz
-                groups = ((nrows + 1) // 2 + X_PAIRS - 1) // X_PAIRS
+                P = X_PAIRS(L1)
+                groups = ((nrows + 1) // 2 + P - 1) // P
                 assert groups <= (nrows + 1) // 2 + 1, (shape, bc)
             if Lz in FAST:
                 L1 = FAST[Lz][0]
