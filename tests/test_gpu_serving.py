@@ -142,6 +142,48 @@ def test_batched_stream_joins_and_matches_oracle():
         assert abs(res["energy"] / e_ref - 1.0) <= 1e-6
 
 
+def test_bench_stream_sample_matches_oracle():
+    # the stream the serving bench replays (512 requests, seed 5, grids 32-128
+    # in a 19.2-bohr box): its requests of at most 48^3 among the first 60 (both
+    # kinds, the three BCs), served in batches under the mixed server, each
+    # against the oracle at 1e-10 -- max |dphi| <= 1e-5 Ha/e and relative
+    # energy 1e-6 (periodic GPe: up to the constant)
+    require_gpu()
+    from oracle import pb
+    from gpu_util import oracle_ions
+    prms, _ = W.serving_stream_params(512, seed=5)
+    picked = [prm for prm in prms[:60] if prm["n"] <= 48]
+    reqs = []
+    for prm in picked:
+        prob = W.request_problem(prm)
+        reqs.append((prob, dev(prob.rho), dev(prob.eps)))
+    kinds = {(prob.bc, prob.kind) for prob, _, _ in reqs}
+    assert len(reqs) >= 10 and len(kinds) >= 5, kinds
+    srv = gps.Server(max_active=4, precision="mixed", batch_slots=4)
+    print("bench stream sample of", len(reqs), "requests", flush=True)
+    phis, results = _mix(reqs, srv)
+    stats = srv.stats()
+    srv.close()
+    assert stats["completed"] == len(reqs) and stats["batched"] >= 1
+    worst_phi = worst_e = 0.0
+    for (prob, _, _), phi, res in zip(reqs, phis, results):
+        print("oracle", prob.name, flush=True)
+        assert res["status"] == gps.GPS_OK, (prob.name, res)
+        if prob.ions is None:
+            ref = pcg.pcg_solve(prob.rho, prob.eps, prob.h, prob.bc, tol=1e-10).phi
+        else:
+            ref = pb.solve_linear_pb(prob.rho, prob.eps, prob.h, prob.bc, oracle_ions(prob.ions),
+                                     1e-10).phi
+        got = host(phi)
+        if prob.bc == "periodic" and prob.ions is None:
+            got, ref = got - got.mean(), ref - ref.mean()
+        worst_phi = max(worst_phi, float(np.abs(got - ref).max()))
+        e_ref = pcg.electrostatic_energy(prob.rho, ref, prob.h)
+        worst_e = max(worst_e, abs(res["energy"] / e_ref - 1.0))
+    print("served vs oracle: max |dphi| %.2e, max rel dE %.2e" % (worst_phi, worst_e), flush=True)
+    assert worst_phi <= 1e-5 and worst_e <= 1e-6
+
+
 def test_served_request_matches_oracle():
     require_gpu()
     prm = W.serving_params(np.random.default_rng(3), grids=(24,), box=BOX)
