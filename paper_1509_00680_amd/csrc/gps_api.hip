@@ -949,17 +949,22 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
     pl->info.status = st.status;
     return (gps_status)st.status;
   }
-  // Algorithm SCPBimproved
+  // Algorithm SCPBimproved.  After each inner solve the ionic update and the
+  // outer decision run on the device (k_outer_decide: outer residual, stop
+  // test, and the reset of the inner state for the next step), and the next
+  // inner solve's first iterations are queued behind them without a host
+  // round trip; its first poll also returns the outer decision.  When the
+  // outer loop has stopped, those queued iterations find the inner state
+  // stopped and return at once.
   int total = 0;
   SolveState st{};
   gps_status result = GPS_E_NOT_CONVERGED;
   double outer_res = 0.0;
-  int outer = 0;
-  for (int k = 1; k <= el.outer_maxit; ++k) {
+  int outer = 1;
+  const double abs_thr = kFourPi * tol * rho_norm;
+  st = run_pcg<T>(pl, 0);
+  for (int k = 1;; ++k) {
     outer = k;
-    if (k > 1) reset_state<T>(pl, kFourPi * tol * rho_norm, k <= 2 ? 1e-2 : 0.0);
-    // inner solves of consecutive outer steps need similar iteration counts
-    st = run_pcg<T>(pl, 0, nullptr, k > 1 ? std::max(1, st.iters - 1) : 0);
     total += st.iters;
     if (st.status != GPS_OK) {
       result = (gps_status)st.status;
@@ -968,17 +973,17 @@ gps_status solve_impl(gps_plan* pl, const double* rho, const double* eps, double
     IonParams ip = el.ip;
     ip.eps = eps;
     launch_ion_update<T>(R.tab, b, n, ip, k == 1, s);
+    launch_outer_decide<T>(R.tab, b, vec_groups(n), rho_norm, tol, abs_thr,
+                           k + 1 <= 2 ? 1e-2 : 0.0, k == el.outer_maxit, s);
     ck(hipGetLastError());
-    const double d2 = read_sum<T>(pl, sl.part_init, vec_groups(n), 4, 3);
-    outer_res = rho_norm > 0 ? std::sqrt(d2) / rho_norm : std::sqrt(d2);
-    if (!std::isfinite(d2)) {
-      result = GPS_E_NONFINITE;
+    // inner solves of consecutive outer steps need similar iteration counts
+    const SolveState next = run_pcg<T>(pl, 0, nullptr, std::max(1, st.iters - 1));
+    outer_res = next.outer_res;
+    if (next.outer_done) {
+      result = (gps_status)next.outer_status;
       break;
     }
-    if (std::sqrt(d2) <= tol * rho_norm) {
-      result = GPS_OK;
-      break;
-    }
+    st = next;
   }
   finish_info<T>(pl, st, rho, phi, total);
   pl->info.outer_iterations = outer;

@@ -94,6 +94,11 @@ struct SolveState {
                      // starts a new direction (cleared by the y-inverse decision)
   int fresh;         // this iteration starts a direction: p = v (y-inverse decision)
   int rel_from_b;    // warm start: the relative threshold is taken on ||4 pi rho||, not ||r_0||
+  // nonlinear outer loop (Algorithm SCPBimproved), decided on the device after
+  // each inner solve (k_outer_decide); kept across the reset of the inner state
+  int outer_done;    // 1 once the outer loop has stopped (status in outer_status)
+  int outer_status;
+  double outer_res;  // ||rho_ion,k+1 - rho_ion,k||_2 / ||rho||_2 of the last outer step
 };
 
 // Input-check flags (SolveState::err)

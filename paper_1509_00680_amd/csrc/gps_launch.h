@@ -164,6 +164,14 @@ template <typename T> void launch_qcopy(const SlotTable<T>& tab, const Batch& b,
                                         const double* q, hipStream_t s);
 template <typename T> void launch_ion_update(const SlotTable<T>& tab, const Batch& b, long long n,
                                              const IonParams& ip, int first, hipStream_t s);
+// One work-group after the ionic update: the outer residual from the update's
+// partials (fixed order), the outer decision, and, when the loop goes on, the
+// inner state reset for the next outer step (abs_thr, rel_thr_next); when it
+// stops, the inner state stays stopped so the launches already queued return.
+template <typename T> void launch_outer_decide(const SlotTable<T>& tab, const Batch& b,
+                                               int n_parts, double rho_norm, double tol,
+                                               double abs_thr, double rel_thr_next, int last,
+                                               hipStream_t s);
 template <typename T> void launch_energy(const SlotTable<T>& tab, const Batch& b, const double* rho,
                                          long long n, hipStream_t s);
 template <typename T> void launch_zero_ion(const SlotTable<T>& tab, const Batch& b, long long n,

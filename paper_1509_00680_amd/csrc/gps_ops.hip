@@ -656,6 +656,43 @@ void launch_ion_update(const SlotTable<T>& tab, const Batch& b, long long n, con
 }
 
 template <typename T>
+__global__ __launch_bounds__(kThreads) void k_outer_decide(SlotTable<T> tab, Batch b, int n_parts,
+                                                           double rho_norm, double tol,
+                                                           double abs_thr, double rel_thr_next,
+                                                           int last) {
+  const Slot<T> sl = tab.s[b.slot[blockIdx.x]];
+  const double d2 = sum_partials(sl.part_init + 3, n_parts, 4);
+  if (threadIdx.x == 0) {
+    SolveState* st = sl.st;
+    const double dn = sqrt(d2);
+    int status = -1;
+    if (!isfinite(d2)) status = GPS_E_NONFINITE;
+    else if (dn <= tol * rho_norm) status = GPS_OK;
+    else if (last) status = GPS_E_NOT_CONVERGED;
+    const double res = rho_norm > 0.0 ? dn / rho_norm : dn;
+    if (status >= 0) {
+      st->outer_done = 1;
+      st->outer_status = status;
+      st->outer_res = res;
+    } else {
+      SolveState z{};
+      z.abs_thr = abs_thr;
+      z.rel_thr = rel_thr_next;
+      z.outer_res = res;
+      *st = z;
+    }
+  }
+}
+
+template <typename T>
+void launch_outer_decide(const SlotTable<T>& tab, const Batch& b, int n_parts, double rho_norm,
+                         double tol, double abs_thr, double rel_thr_next, int last,
+                         hipStream_t s) {
+  GPS_LAUNCH((k_outer_decide<T>), dim3(b.n), dim3(kThreads), 0, s, tab, b, n_parts, rho_norm,
+             tol, abs_thr, rel_thr_next, last);
+}
+
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_zero_ion(SlotTable<T> tab, Batch b,
                                                        long long n) {
   const Slot<T> sl = tab.s[b.slot[blockIdx.y]];
@@ -758,6 +795,8 @@ void launch_refine(const SlotTable<T>& tab, const Batch& b, const double* rho, c
   template void launch_ion_update<T>(const SlotTable<T>&, const Batch&, long long, const IonParams&,  \
                                      int, hipStream_t);                                          \
   template void launch_zero_ion<T>(const SlotTable<T>&, const Batch&, long long, hipStream_t);        \
+  template void launch_outer_decide<T>(const SlotTable<T>&, const Batch&, int, double, double, double, \
+                                       double, int, hipStream_t);                                \
   template void launch_energy<T>(const SlotTable<T>&, const Batch&, const double*, long long,         \
                                  hipStream_t);                                                   \
   template void launch_refine<T>(const SlotTable<T>&, const Batch&, const double*, const double*,    \
