@@ -805,7 +805,10 @@ SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nu
     k += n;
     st = read_state<T>(pl);
     if (timing) {
-      collect_timing(pl, pl->ev_pending, k_base, st.done ? st.iters : k);
+      // launches that did work: up to the stop decision; none when the
+      // nonlinear outer loop had stopped before this solve (the state still
+      // holds the previous inner solve, and every launch returned at once)
+      collect_timing(pl, pl->ev_pending, k_base, st.outer_done ? 0 : st.done ? st.iters : k);
       pl->timing_bytes = pass_bytes(pl, pl->timing_kind, sizeof(T));
     }
     if (st.done || k > pl->opt.maxit + 1) break;
