@@ -816,13 +816,12 @@ SolveState run_pcg(gps_plan* pl, int check_neutral, const double* track_rho = nu
       refine_step<T>(pl, track_rho, false);
       next_ref += m;
     }
-    // predicted iterations left: log-linear extrapolation of ||r||^2 (from
-    // ||r_0||^2 at iteration 0 at the first poll)
-    // With a prior (first_n > 0: the solve restarts from a nearby iterate)
-    // the first poll already extrapolates, from ||r_0||^2 at iteration 0,
-    // and a poll without a usable rate (the residual having risen) is
-    // followed by half the iterations done; a solve from scratch waits for
-    // a rate between two polls, two chunks apart.
+    // predicted iterations left: log-linear extrapolation of ||r||^2 between
+    // two polls.  With a prior (first_n > 0: the solve restarts from a nearby
+    // iterate) the first poll already extrapolates, from ||r_0||^2 at
+    // iteration 0, and a poll without a usable rate (the residual having
+    // risen) is followed by half the iterations done; a solve from scratch
+    // waits for a rate between two polls, two chunks apart.
     const bool prior = first_n > 0;
     n = prior ? std::max(1, std::min(2 * chunk, st.iters / 2)) : 2 * chunk;
     const bool from_start = prior && prev_rr < 0.0;
