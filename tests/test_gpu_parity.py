@@ -35,6 +35,55 @@ def test_vacuum_solver_matches_oracle(bc, shape, precision):
     assert np.abs(got - expect).max() <= tol * np.abs(expect).max()
 
 
+# Extreme grids: the smallest accepted (two points per axis: FFT lengths 2 and
+# 4) and the longest FFT length the plan accepts (1024, reached by 512 points
+# on an isolated axis or 1024 on a periodic one), on each axis in turn.
+EXTREME = [("free", (2, 2, 2)), ("surface", (2, 2, 2)), ("periodic", (2, 2, 2)),
+           ("wire", (2, 2, 2)), ("free", (4, 3, 512)), ("free", (3, 512, 4)),
+           ("free", (512, 4, 3)), ("periodic", (2, 3, 1024)), ("surface", (512, 3, 2)),
+           ("wire", (1024, 2, 3))]
+
+
+@pytest.mark.parametrize("bc,shape", EXTREME)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_vacuum_solver_extreme_grids(bc, shape, precision):
+    require_gpu()
+    h = 0.45
+    rng = np.random.default_rng(13)
+    f = rng.normal(size=shape)
+    if bc == "periodic":
+        f -= f.mean()
+    expect = green.VacuumSolver(shape, h, bc).apply(f)
+    p = plan(shape, h, bc, precision)
+    u = empty(shape)
+    print("vacuum extreme", bc, shape, precision, flush=True)
+    assert p.solve_vacuum(dev(f), u) == gps.GPS_OK
+    err = np.abs(host(u) - expect).max() / np.abs(expect).max()
+    print("  max error / max |u|: %.2e" % err, flush=True)
+    assert err <= (1e-12 if precision == "fp64" else 3e-6)
+
+
+@pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
+def test_gpe_smallest_grid_fp64(bc):
+    """The generalized Poisson solve on a 2x2x2 grid (the order-16 stencil's
+    ghosts cover the whole grid) against the oracle."""
+    require_gpu()
+    rng = np.random.default_rng(17)
+    shape, h = (2, 2, 2), 0.5
+    eps = 1.0 + 77.0 * rng.random(shape)
+    rho = rng.normal(size=shape)
+    if bc == "periodic":
+        rho -= rho.mean()
+    ref = pcg.pcg_solve(rho, eps, h, bc, tol=1e-11)
+    p = plan(shape, h, bc, "fp64")
+    phi = empty(shape)
+    print("gpe smallest grid", bc, flush=True)
+    st = p.solve_generalized(dev(rho), dev(eps), phi, 1e-11)
+    assert st == gps.GPS_OK, gps.STATUS[st]
+    assert abs(p.info()["iterations"] - ref.iterations) <= 1
+    assert np.abs(host(phi) - ref.phi).max() <= 1e-8 * np.abs(ref.phi).max()
+
+
 @pytest.mark.parametrize("bc", ["free", "surface", "periodic", "wire"])
 def test_gpe_fp64_matches_oracle(bc):
     require_gpu()
