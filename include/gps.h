@@ -191,8 +191,11 @@ gps_status gps_solve_generalized(gps_plan *plan, const double *rho, const double
  * outer steps which stop at 1e-2 of their initial residual.  Errors: as
  * gps_solve_generalized, plus GPS_E_INVALID for a bad electrolyte
  * (nspecies outside 1..4, kT <= 0, c <= 0, c_max <= c, eta outside (0, 1],
- * eps_bulk <= 1 when gamma is NULL) and GPS_E_NONFINITE when the ionic
- * charge overflows (Boltzmann law at large |phi|/kT). */
+ * eps_bulk <= 1 when gamma is NULL), GPS_E_NONFINITE when the ionic
+ * charge overflows (Boltzmann law at large |phi|/kT), and GPS_E_UNSUPPORTED
+ * for a nonlinear law on a periodic plan (there the potential's constant,
+ * which sets the net ionic charge, is fixed by nothing in the algorithm: each
+ * inner solve drops the zero mode of its source). */
 gps_status gps_solve_pb(gps_plan *plan, const double *rho, const double *eps,
                         const gps_ions *ions, double *phi, double tol);
 

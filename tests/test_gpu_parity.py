@@ -185,20 +185,23 @@ def test_linear_pb_matches_oracle(bc, precision):
     assert np.abs(got - ref.phi).max() <= bound
 
 
+# Algorithm SCPBimproved under the boundary conditions with an isolated axis
+# (free, surface, wire); periodic cells are refused (next test).
+@pytest.mark.parametrize("bc", ["free", "surface", "wire"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("steric", [True, False])
-def test_nonlinear_pb_matches_oracle(precision, steric):
+def test_nonlinear_pb_matches_oracle(precision, steric, bc):
     require_gpu()
     prob = W.charged_solute_mpb(n=24, h=0.5, n_atoms=8, ball=2.0, net_charge=1.0,
                                 molar=0.1, steric=steric)
     if not steric:       # the Boltzmann law overflows at full charge (see below)
         prob.rho = prob.rho * 0.1
     oi = oracle_ions(prob.ions)
-    ref = pb.scpb_improved(prob.rho, prob.eps, prob.h, "free", oi, 1e-9, eta=prob.ions["eta"])
+    ref = pb.scpb_improved(prob.rho, prob.eps, prob.h, bc, oi, 1e-9, eta=prob.ions["eta"])
     assert ref.converged
-    p = plan(prob.shape, prob.h, "free", precision)
+    p = plan(prob.shape, prob.h, bc, precision)
     phi = empty(prob.shape)
-    print("nonlinear pb", precision, steric, flush=True)
+    print("nonlinear pb", bc, precision, steric, flush=True)
     tol = 1e-9 if precision == "fp64" else 1e-6
     st = p.solve_pb(dev(prob.rho), dev(prob.eps), prob.ions, phi, tol)
     assert st == gps.GPS_OK, gps.STATUS[st]
@@ -209,6 +212,19 @@ def test_nonlinear_pb_matches_oracle(precision, steric):
         assert np.abs(got - ref.phi).max() <= 1e-7 * np.abs(ref.phi).max()
     else:
         assert np.abs(got - ref.phi).max() <= 1e-5
+
+
+@pytest.mark.parametrize("steric", [True, False])
+def test_nonlinear_pb_periodic_unsupported(steric):
+    # the potential's constant sets the net ionic charge on a periodic cell and
+    # Algorithm SCPBimproved does not fix it: the library refuses the case
+    require_gpu()
+    prob = W.charged_solute_mpb(n=16, h=0.5, n_atoms=4, ball=1.5, net_charge=1.0,
+                                molar=0.1, steric=steric)
+    rho = prob.rho - prob.rho.mean()
+    p = plan(prob.shape, prob.h, "periodic", "mixed")
+    st = p.solve_pb(dev(rho), dev(prob.eps), prob.ions, empty(prob.shape), 1e-6)
+    assert st == gps.GPS_E_UNSUPPORTED, gps.STATUS[st]
 
 
 def test_boltzmann_overflow_reported():
