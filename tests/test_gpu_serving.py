@@ -8,10 +8,10 @@ footprints agree with what plans actually hold."""
 import numpy as np
 import pytest
 
-from oracle import pcg
+from oracle import pb, pcg
 from paper_1509_00680_amd import gps
 from paper_1509_00680_amd import workloads as W
-from gpu_util import dev, host, empty, plan, require_gpu
+from gpu_util import dev, host, empty, plan, oracle_ions, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -204,6 +204,34 @@ def test_served_request_matches_oracle():
     assert np.abs(d).max() <= 1e-5
     e_ref = pcg.electrostatic_energy(prob.rho, ref.phi, prob.h)
     assert abs(res["energy"] / e_ref - 1.0) <= 1e-6
+
+
+def test_served_nonlinear_pb_matches_oracle():
+    # a nonlinear PB request (Algorithm SCPBimproved, steric ions) served beside a
+    # batchable GPe request, both against the oracle
+    require_gpu()
+    prob = W.charged_solute_mpb(n=24, h=0.5, n_atoms=8, ball=2.0, net_charge=1.0,
+                                molar=0.1, steric=True)
+    ref = pb.scpb_improved(prob.rho, prob.eps, prob.h, "free", oracle_ions(prob.ions), 1e-9,
+                           eta=prob.ions["eta"])
+    assert ref.converged
+    small = W.molecule(16, 0.5, seed=6, n_atoms=4, ball=2.0)
+    ref_small = pcg.pcg_solve(small.rho, small.eps, small.h, "free", tol=1e-10)
+    srv = gps.Server(max_active=2, precision="mixed")
+    phi, phi_small = empty(prob.shape), empty(small.shape)
+    print("served nonlinear pb beside a gpe request", flush=True)
+    st, t = srv.submit(dev(prob.rho), dev(prob.eps), phi, prob.h, "free", 1e-6, ions=prob.ions)
+    assert st == gps.GPS_OK
+    st, t_small = srv.submit(dev(small.rho), dev(small.eps), phi_small, small.h, "free", 1e-6)
+    assert st == gps.GPS_OK
+    res, res_small = srv.wait(t), srv.wait(t_small)
+    srv.close()
+    assert res["status"] == gps.GPS_OK and res_small["status"] == gps.GPS_OK
+    assert res["outer_iterations"] > 2
+    assert np.abs(host(phi) - ref.phi).max() <= 1e-5
+    assert np.abs(host(phi_small) - ref_small.phi).max() <= 1e-5
+    e_ref = pcg.electrostatic_energy(small.rho, ref_small.phi, small.h)
+    assert abs(res_small["energy"] / e_ref - 1.0) <= 1e-6
 
 
 def test_server_errors_and_polling():
