@@ -1065,8 +1065,9 @@ void enqueue_sc_step(gps_plan* pl, int paper_step, hipStream_t s) {
   gps_plan::ScRes& S = pl->sc;
   const long long n = pl->npts();
   enqueue_vacuum<T>(pl, S.f, S.v, s);
+  // the operator launch also takes the previous step's stop decision
   launch_sc_operator(pl->g, pl->opt.fd_order / 2, paper_step, S.r, S.eps, S.lne, S.v, S.av,
-                     S.part_op, &S.st->done, s);
+                     S.part_op, &S.st->done, ScDecide{S.part, vec_groups(n), S.st}, s);
   launch_sc_advance(n, S.eps, S.phi, S.r, S.v, S.av, S.f, S.part_op, polarization_groups(pl->g),
                     S.part, S.st, s);
 }
@@ -1085,6 +1086,8 @@ void build_sc_graphs(gps_plan* pl, int paper_step) {
   for (int i = 0; i < 4; ++i) {
     ck(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < S.graph_iters[i]; ++j) enqueue_sc_step<T>(pl, paper_step, pl->cap_stream);
+    // the last step's decision, so that the state read between replays is current
+    launch_sc_decide(ScDecide{S.part, vec_groups(pl->npts()), S.st}, pl->cap_stream);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
     if (e != hipSuccess) throw DevError{e};

@@ -96,6 +96,47 @@ void launch_rigid_cavity(const Geom& g, const double* atoms, int natoms, double 
 }
 
 // ---------------------------------------------------------------------------
+// Stop decision of an SC/PSD step (one work-group): from the update's partial
+// pairs (||r||^2, ||r/eps||^2) it records the step, its norms and the status,
+// and sets done on convergence, failure or the step limit.  It acts only when
+// the update has marked a decision pending, so every update is decided once,
+// whether by the next step's operator launch or by a launch of its own.
+// ---------------------------------------------------------------------------
+__device__ void sc_decide_group(const double* __restrict__ part, int nparts, ScState* st) {
+  if (st->done || !st->pending) return;          // the same for every thread
+  const double rr = sum_partials(part, nparts, 2);
+  const double ff = sum_partials(part + 1, nparts, 2);
+  if (threadIdx.x != 0) return;
+  ScState z = *st;
+  z.pending = 0;
+  if (z.status != GPS_E_NOT_CONVERGED) {          // breakdown or non-finite step
+    z.done = 1;
+    *st = z;
+    return;
+  }
+  const int step = z.step;
+  z.ff_prev = z.ff;
+  z.rr = rr;
+  z.ff = ff;
+  z.step = step + 1;
+  if (!isfinite(rr) || !isfinite(ff)) {
+    z.status = GPS_E_NONFINITE;
+  } else if (z.method == GPS_METHOD_SC) {
+    // SC's residual ||rho_iter_{k+1} - rho_iter_k|| = (eta/4 pi) ||r_k/eps|| of
+    // the iterate before this step; the first step is the unmixed phi_0
+    if (step >= 1) {
+      z.iters = step;
+      if (z.eta / kFourPi * sqrt(z.ff_prev) <= z.thr_sc) z.status = GPS_OK;
+    }
+  } else {
+    z.iters = step + 1;
+    if (z.method == GPS_METHOD_PSD ? sqrt(rr) <= z.thr_r : sqrt(ff) <= z.thr_w) z.status = GPS_OK;
+  }
+  if (z.status != GPS_E_NOT_CONVERGED || z.step >= z.max_steps) z.done = 1;
+  *st = z;
+}
+
+// ---------------------------------------------------------------------------
 // Polarization charge.  First differences of order 2M:
 //   f'(x) ~ (1/h) sum_{m=1..M} c_m (f(x + m h) - f(x - m h)),
 //   c_m = (-1)^(m+1) (M!)^2 / (m (M - m)! (M + m)!),
@@ -126,7 +167,8 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
                                                             const double* __restrict__ lne,
                                                             const double* __restrict__ phi,
                                                             double* __restrict__ out,
-                                                            double* __restrict__ part) {
+                                                            double* __restrict__ part,
+                                                            ScDecide dec) {
   constexpr int TW = kPTX + 2 * M;
   constexpr int TH = kPTY + 2 * M;
   constexpr int NXH = 2 * M * kPTY;                // halo slots left and right of the tile
@@ -134,10 +176,17 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
   constexpr int HS = (NH + kPThreads - 1) / kPThreads;
   __shared__ double te[TH * TW];
   __shared__ double tp[TH * TW];
+  // SC/PSD: work-group 0 takes the previous update's stop decision, the
+  // tiles start at work-group 1
+  const int d0 = dec.st ? 1 : 0;
+  if (d0 && blockIdx.x == 0) {
+    sc_decide_group(dec.part, dec.nparts, dec.st);
+    return;
+  }
   if (stop && *stop) return;
   const int tid = threadIdx.x;
   const int tx = tid % kPTX, ty = tid / kPTX;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);   // x fastest, then y, then z chunk
+  const int t = xcd_tile(blockIdx.x - d0, gridDim.x - d0);   // x fastest, then y, then z chunk
   const int ntxy = ntx * nty;
   const int zc = t / ntxy;
   const int yt = (t - zc * ntxy) / ntx;
@@ -248,8 +297,8 @@ __global__ __launch_bounds__(kPThreads) void k_polarization(Geom g, FdFirst w, i
     vr = block_sum(vr);
     vav = block_sum(vav);
     if (tid == 0) {
-      part[2 * blockIdx.x] = vr;
-      part[2 * blockIdx.x + 1] = vav;
+      part[2 * (blockIdx.x - d0)] = vr;
+      part[2 * (blockIdx.x - d0) + 1] = vav;
     }
   }
 }
@@ -322,15 +371,15 @@ void launch_log_field(long long n, const double* eps, double* lne, hipStream_t s
 template <bool AV>
 static void launch_graddot(const Geom& g, int fd_half, int paper, const double* rho,
                            const double* eps, const double* lne, const double* phi, double* out,
-                           double* part, const int* stop, hipStream_t s) {
+                           double* part, const int* stop, const ScDecide& dec, hipStream_t s) {
   const int ntx = (g.nx + kPTX - 1) / kPTX, nty = (g.ny + kPTY - 1) / kPTY;
   const int zlen = polarization_zlen(g);
-  const dim3 grid(polarization_groups(g));
+  const dim3 grid(polarization_groups(g) + (dec.st ? 1 : 0));
   const FdFirst w = fd_first_weights(fd_half);
 #define GPS_PF(MM)                                                                        \
   case MM:                                                                                \
     GPS_LAUNCH((k_polarization<MM, AV>), grid, dim3(kPThreads), 0, s, g, w, ntx, nty,     \
-               zlen, paper, stop, rho, eps, lne, phi, out, part);                         \
+               zlen, paper, stop, rho, eps, lne, phi, out, part, dec);                     \
     break;
   switch (fd_half) {
     GPS_PF(1) GPS_PF(2) GPS_PF(3) GPS_PF(4) GPS_PF(5) GPS_PF(6) GPS_PF(7) GPS_PF(8)
@@ -341,13 +390,14 @@ static void launch_graddot(const Geom& g, int fd_half, int paper, const double* 
 
 void launch_polarization(const Geom& g, int fd_half, const double* rho, const double* eps,
                          const double* lne, const double* phi, double* out, hipStream_t s) {
-  launch_graddot<false>(g, fd_half, 0, rho, eps, lne, phi, out, nullptr, nullptr, s);
+  launch_graddot<false>(g, fd_half, 0, rho, eps, lne, phi, out, nullptr, nullptr, ScDecide{},
+                        s);
 }
 
 void launch_sc_operator(const Geom& g, int fd_half, int paper_step, const double* r,
                         const double* eps, const double* lne, const double* v, double* av,
-                        double* part, const int* stop, hipStream_t s) {
-  launch_graddot<true>(g, fd_half, paper_step, r, eps, lne, v, av, part, stop, s);
+                        double* part, const int* stop, const ScDecide& dec, hipStream_t s) {
+  launch_graddot<true>(g, fd_half, paper_step, r, eps, lne, v, av, part, stop, dec, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -441,7 +491,10 @@ __global__ __launch_bounds__(kThreads) void k_sc_update(long long n, const doubl
     alpha = fail ? 0.0 : vr / vav;
   }
   if (fail) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->status = fail;   // the decision ends the solve
+    if (blockIdx.x == 0 && threadIdx.x == 0) {   // the decision ends the solve
+      st->status = fail;
+      st->pending = 1;
+    }
     return;
   }
   const long long base = (long long)blockIdx.x * kThreads * kVec + threadIdx.x;
@@ -464,42 +517,15 @@ __global__ __launch_bounds__(kThreads) void k_sc_update(long long n, const doubl
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = a0;
     part[2 * blockIdx.x + 1] = a1;
-    if (blockIdx.x == 0) st->alpha = alpha;
+    if (blockIdx.x == 0) {
+      st->alpha = alpha;
+      st->pending = 1;
+    }
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_sc_decide(const double* __restrict__ part,
-                                                        int nparts, ScState* st) {
-  if (st->done) return;
-  const double rr = sum_partials(part, nparts, 2);
-  const double ff = sum_partials(part + 1, nparts, 2);
-  if (threadIdx.x != 0) return;
-  ScState z = *st;
-  if (z.status != GPS_E_NOT_CONVERGED) {          // breakdown or non-finite step
-    z.done = 1;
-    *st = z;
-    return;
-  }
-  const int step = z.step;
-  z.ff_prev = z.ff;
-  z.rr = rr;
-  z.ff = ff;
-  z.step = step + 1;
-  if (!isfinite(rr) || !isfinite(ff)) {
-    z.status = GPS_E_NONFINITE;
-  } else if (z.method == GPS_METHOD_SC) {
-    // SC's residual ||rho_iter_{k+1} - rho_iter_k|| = (eta/4 pi) ||r_k/eps|| of
-    // the iterate before this step; the first step is the unmixed phi_0
-    if (step >= 1) {
-      z.iters = step;
-      if (z.eta / kFourPi * sqrt(z.ff_prev) <= z.thr_sc) z.status = GPS_OK;
-    }
-  } else {
-    z.iters = step + 1;
-    if (z.method == GPS_METHOD_PSD ? sqrt(rr) <= z.thr_r : sqrt(ff) <= z.thr_w) z.status = GPS_OK;
-  }
-  if (z.status != GPS_E_NOT_CONVERGED || z.step >= z.max_steps) z.done = 1;
-  *st = z;
+__global__ __launch_bounds__(kThreads) void k_sc_decide(ScDecide dec) {
+  sc_decide_group(dec.part, dec.nparts, dec.st);
 }
 
 __global__ __launch_bounds__(kThreads) void k_sc_energy(long long n, const double* __restrict__ rho,
@@ -535,7 +561,10 @@ void launch_sc_advance(long long n, const double* eps, double* phi, double* r, c
   const int gv = vec_groups(n);
   GPS_LAUNCH(k_sc_update, dim3(gv), dim3(kThreads), 0, s, n, eps, phi, r, v, av, f, op_part,
              n_op, part, st);
-  GPS_LAUNCH(k_sc_decide, dim3(1), dim3(kThreads), 0, s, part, gv, st);
+}
+
+void launch_sc_decide(const ScDecide& dec, hipStream_t s) {
+  GPS_LAUNCH(k_sc_decide, dim3(1), dim3(kThreads), 0, s, dec);
 }
 
 void launch_sc_energy(long long n, const double* rho, const double* phi, double* part,

@@ -201,6 +201,7 @@ struct ScState {
   int iters;         // iterations reported (SC: steps after the first)
   int method;        // gps_sc_method
   int max_steps;
+  int pending;       // 1 while the last update waits for its stop decision
   double eta;        // SC mixing
   double thr_w;      // tol ||4 pi rho / eps||
   double thr_r;      // tol ||4 pi rho||
@@ -211,22 +212,34 @@ struct ScState {
   double ff_prev;    // ||r/eps||^2 before the last step
   double alpha;      // step of the last iteration
 };
+// Stop decision of an SC/PSD step from the update's partials (part, nparts
+// pairs); st == nullptr: none.
+struct ScDecide {
+  const double* part;
+  int nparts;
+  ScState* st;
+};
 // SC/PSD operator A v = -4 pi r + eps grad ln eps . grad v and two partials
 // per work-group (paper_step: (v, r) and (v, A v); else (A v, r/eps^2) and
-// (A v, A v/eps^2)); returns at once when *stop != 0 (stop may be null).
+// (A v, A v/eps^2)); returns at once when *stop != 0 (stop may be null).  With
+// dec.st, one extra work-group takes the stop decision of the previous step's
+// update (if one is pending) while the others apply the operator.
 void launch_sc_operator(const Geom& g, int fd_half, int paper_step, const double* r,
                         const double* eps, const double* lne, const double* v, double* av,
-                        double* part, const int* stop, hipStream_t s);
+                        double* part, const int* stop, const ScDecide& dec, hipStream_t s);
+// The stop decision alone (the last update of a replayed chunk of steps).
+void launch_sc_decide(const ScDecide& dec, hipStream_t s);
 // Start of an SC/PSD solve: r = -4 pi rho, f = r/eps, phi = 0, eps_c = eps,
 // lne = ln eps, and the state (thresholds; done at once for rho = 0 or
 // non-finite input).  part: 2 vec_groups(n) doubles of scratch.
 void launch_sc_begin(long long n, const double* rho, const double* eps, double* r, double* f,
                      double* phi, double* eps_c, double* lne, double* part, ScState* st,
                      int method, double eta, double tol, int max_steps, hipStream_t s);
-// One SC/PSD step after the operator: every work-group takes alpha from the
+// The update of one SC/PSD step: every work-group takes alpha from the
 // operator's n_op partial pairs, then phi += alpha v, r -= alpha A v, f =
-// r/eps with the ||r||^2, ||f||^2 partials; a one-work-group kernel then takes
-// the stop decision.  Both return at once once the state says done.
+// r/eps with the ||r||^2, ||f||^2 partials, and marks the step's stop decision
+// pending (taken by the next operator launch or launch_sc_decide).  Returns
+// at once once the state says done.
 void launch_sc_advance(long long n, const double* eps, double* phi, double* r, const double* v,
                        const double* av, double* f, const double* op_part, int n_op,
                        double* part, ScState* st, hipStream_t s);
