@@ -153,6 +153,24 @@ def test_polarization_charge_matches_oracle(bc, order, shape):
     assert np.abs(host(out) - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.timeout(300)
+def test_polarization_charge_full_size():
+    # the 160^3 launch (32-plane z marches, 500 work-groups) of the rigid-cavity
+    # workload, every point against the oracle
+    require_gpu()
+    shape, h = (160, 160, 160), 0.3
+    rng = np.random.default_rng(19)
+    eps = 1.0 + 77.0 * rng.random(shape)
+    phi = rng.normal(size=shape)
+    rho = rng.normal(size=shape)
+    ref = cavity.polarization_charge(rho, eps, phi, h, "free", 16)
+    p = plan(shape, h, "free", "fp64")
+    out = empty(shape)
+    print("polarization 160^3", flush=True)
+    assert p.polarization_charge(dev(rho), dev(eps), dev(phi), out) == gps.GPS_OK
+    assert np.abs(host(out) - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
 def test_polarization_charge_gauss_law_on_gpu_solution():
     # a unit charge in a spherical cavity: the solvent's bound charge totals
     # -(1 - 1/eps0) Q; phi from the GPU solve, rho_pol from the GPU
